@@ -1,0 +1,263 @@
+/*
+ * sgwave.h -- C ABI of the MI355X (gfx950) acoustic finite-difference
+ * propagator: the seismic-data path of SubsurfaceGen (arXiv 2605.30541).
+ *
+ * Problem statement followed (Sec. 2 and App. E): a 2D velocity slice on a
+ * regular grid, the grid spacing, the time step and the number of steps, a
+ * source wavelet with source positions, and receiver positions go in; the
+ * wavefield p(x,t) (snapshots) and/or the shot gather R p come out.  The
+ * scheme is the constant-density acoustic equation (eq. "acoustic_2d"),
+ * 8th order in space and 2nd order in time (Table "params"), with a free
+ * surface on top (eq. "free_surface") and a Cerjan sponge on the other three
+ * sides (eqs. "cerjan_pde", "cerjan_damp").  The velocity gradient of an L2
+ * gather misfit is the exact adjoint of that discrete scheme.
+ *
+ * Conventions shared by every call
+ *   - Arrays are row-major with x fastest: a velocity slice is [nz][nx], a
+ *     gather is [nshot][nrows][nrec], snapshots are [nshot][snap_count][nz][nx].
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory read during the call only.
+ *   - The caller owns every buffer.  The library owns only plans; it never
+ *     allocates or frees device memory.  Scratch device memory is passed in as
+ *     a workspace whose size the *_workspace_size calls report.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their work on it and return without waiting for the device.  Host
+ *     tables are staged in pinned host memory owned by the plan and copied to
+ *     the workspace with hipMemcpyAsync; a plan's staging buffer is reused
+ *     only after its previous copy has completed.
+ *   - Inputs are validated before anything is enqueued: on an error return
+ *     no output and no workspace byte is touched.  No C++ exception crosses
+ *     the ABI.  sg_last_error() returns a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Time levels are t_n = n*dt, n = 0..nt-1; the initial state is zero
+ *     (App. E.2) so level 0 of every output is exactly 0.
+ */
+#ifndef SGWAVE_H
+#define SGWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_ABI_VERSION 1
+
+typedef int32_t sg_status;
+enum {
+    SG_OK = 0,
+    SG_EINVAL = 1,        /* bad argument, size, pointer or position */
+    SG_ECFL = 2,          /* dt above the CFL bound of App. E.3.2 */
+    SG_ENOSPACE = 3,      /* workspace smaller than required */
+    SG_EHIP = 4,          /* a HIP runtime call failed */
+    SG_EDIVERGED = 5,     /* non-finite values found by sg_check_finite */
+    SG_EUNSUPPORTED = 6   /* valid but not implemented (e.g. a tuning variant) */
+};
+
+/* sg_geometry.top */
+enum { SG_TOP_FREE = 0, SG_TOP_ABSORBING = 1 };
+
+/* sg_plan_create flags */
+enum { SG_ALLOW_UNSTABLE = 1u << 0 };
+
+/* sg_plan_warnings bits */
+enum { SG_WARN_DISPERSION = 1u << 0 };
+
+/*
+ * Grid, time axis, boundary and output sampling of one velocity slice.
+ *   nz, nx        physical nodes; node (iz,ix) is at z = iz*dz, x = ix*dx [m]
+ *   dz, dx, dt    spacing [m] and time step [s]
+ *   nt            number of time levels (nt-1 updates); >= 2
+ *   nbl           sponge width in cells added left, right, bottom (and top
+ *                 when top = SG_TOP_ABSORBING); 0 = rigid p = 0 just outside
+ *   top           SG_TOP_FREE (p = 0 at z = 0, App. E.2) or SG_TOP_ABSORBING
+ *   damp_R        target reflection coefficient R of eq. "cerjan_damp" (1e-3)
+ *   vmax_hint     largest velocity [m/s] used for the CFL check
+ *                 dt <= s_max h / v_max, s_max = (sqrt(2 sum|c_m|))^-1 (App. E.3.2)
+ *   vmin_hint, fmax_hint   for the dispersion warning h <= v_min/(4 f_max)
+ *                 (App. E.3.1); 0 skips it
+ *   rec_every     gather rows keep levels n = 0, k, 2k, ... (k >= 1, App. E.3.3)
+ *   snap_every, snap_count   snapshots at n = j*snap_every, j < snap_count
+ *                 (snap_count 0 = none); (snap_count-1)*snap_every <= nt-1
+ */
+typedef struct {
+    int32_t nz, nx;
+    double dz, dx, dt;
+    int32_t nt;
+    int32_t nbl;
+    int32_t top;
+    double damp_R;
+    double vmax_hint;
+    double vmin_hint;
+    double fmax_hint;
+    int32_t rec_every;
+    int32_t snap_every;
+    int32_t snap_count;
+} sg_geometry;
+
+/*
+ * Acquisition of one call (Sec. 2, App. E.5): nshot independent shots, each
+ * one point source, and one receiver spread shared by every shot.
+ *   src_zx    host [nshot][2] source (z, x) [m] inside the physical grid
+ *   rec_zx    host [nrec][2]  receiver (z, x) [m] inside the physical grid
+ *   wavelet   device [wavelet_per_shot ? nshot : 1][nt] float source time
+ *             functions w(t_n)
+ * Off-grid positions use bilinear weights; a point source adds
+ * weight * w(t_n) / (dx dz) at its nodes into the step n -> n+1, receivers
+ * sample p^n with the same weights.  A node on the free-surface row
+ * carries no source (p is pinned to 0 there) and reads 0.
+ */
+typedef struct {
+    int32_t nshot;
+    const double *src_zx;
+    int32_t nrec;
+    const double *rec_zx;
+    const float *wavelet;
+    int32_t wavelet_per_shot;
+} sg_shots;
+
+/*
+ * Kernel tuning of the time-stepping launches.
+ *   variant      0 = library default; 1 = one launch per time step with the
+ *                stencil read from global memory; 2 = LDS-tiled, time-blocked
+ *                launches
+ *   tile_x, tile_z   cells (x by z) of the LDS tile one workgroup loads
+ *                (variant 2), one of the built shapes 128x64, 64x128, 64x64;
+ *                the output tile is that minus a halo of 4*time_block per side
+ *                (under a free top the top tile row trades halo for ghost rows)
+ *   time_block   time steps per launch (variant 2), 1..8
+ *   rows_per_thread   rows of the tile column each thread keeps in registers
+ *                (variant 2): 8 or 16 for 128x64, 16 for 64x128, 8 for 64x64;
+ *                0 = the first built one
+ * All zeros ask for the library's default.  sg_plan_set_tuning rejects
+ * shapes that are not built with SG_EUNSUPPORTED.
+ */
+typedef struct {
+    int32_t variant;
+    int32_t tile_x;
+    int32_t tile_z;
+    int32_t time_block;
+    int32_t rows_per_thread;
+} sg_tuning;
+
+typedef struct sg_plan sg_plan;
+
+/* ABI version of the loaded library (SG_ABI_VERSION of its header). */
+int32_t sg_abi_version(void);
+
+/* Name of a status code; never NULL. */
+const char *sg_status_string(sg_status s);
+
+/* Message of the last failing call on this thread ("" if none); never NULL. */
+const char *sg_last_error(void);
+
+/*
+ * Validate a geometry and create a plan (host only, no device work).
+ * Returns SG_EINVAL for bad sizes, SG_ECFL when dt > s_max h / vmax_hint
+ * unless flags has SG_ALLOW_UNSTABLE.  *out is NULL on error.
+ */
+sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out);
+
+/* Destroy a plan; NULL is accepted. */
+sg_status sg_plan_destroy(sg_plan *p);
+
+/* Warning bits (SG_WARN_*) raised by sg_plan_create. */
+uint32_t sg_plan_warnings(const sg_plan *p);
+
+/* Padded grid of the plan: rows and columns including the sponge. */
+sg_status sg_plan_padded_shape(const sg_plan *p, int32_t *Nz, int32_t *Nx);
+
+/* Set the tuning used by later calls on this plan (NULL = library default).
+ * Returns SG_EINVAL for values outside the documented ranges. */
+sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t);
+
+/* Tuning the plan will use for nshot shots (after defaults are resolved). */
+sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t);
+
+/*
+ * Kernel timing of the time-stepping launches.  With profiling on, later
+ * calls on this plan bracket every time-stepping launch with a pair of HIP
+ * events on the call's stream; sg_plan_profile waits for the last recorded
+ * event and returns the summed kernel time [ms] and the launch count of the
+ * most recent call.  Used by the benchmark to price the dominant kernel.
+ */
+sg_status sg_plan_set_profiling(sg_plan *p, int32_t on);
+sg_status sg_plan_profile(sg_plan *p, double *kernel_ms, int32_t *launches);
+
+/*
+ * Ricker pulse of App. E.4 evaluated in double precision and rounded to
+ * float: w(t_n) = (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2), tau = n dt - t0.
+ * t0 <= 0 selects t0 = 1/f0.  `out` is host memory of nt floats.
+ */
+sg_status sg_ricker(double f0, double dt, int32_t nt, double t0, float *out);
+
+/* CFL time-step limit s_max h / vmax of App. E.3.2 for this stencil, with
+ * h = min(dz, dx). */
+double sg_cfl_dt_max(double dz, double dx, double vmax);
+
+/* Bytes of device workspace sg_forward needs for nshot shots and nrec
+ * receivers. */
+sg_status sg_forward_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec, size_t *bytes);
+
+/*
+ * Forward modelling (the hot path).
+ *   vp        device [nz][nx] float velocity [m/s], > 0
+ *   shots     host description, see sg_shots
+ *   gathers   device [nshot][ceil(nt/rec_every)][nrec] float, or NULL
+ *   snaps     device [nshot][snap_count][nz][nx] float, or NULL
+ *   ws        device workspace of ws_bytes >= sg_forward_workspace_size
+ * Every element of the non-NULL outputs is written.
+ */
+sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots,
+                     float *gathers, float *snaps, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Differentiation (adjoint-state velocity gradient).
+ * sg_grad_workspace_size: bytes for nshot shots and nrec receivers with
+ * checkpoints every ckpt_every levels (<= 0: ceil(sqrt(nt))).  sg_forward_ckpt runs the forward
+ * like sg_forward (gathers, no snapshots) and keeps checkpoints in ws;
+ * sg_adjoint_gradient then consumes them:
+ *   resid     device [nshot][ceil(nt/rec_every)][nrec] float, dJ/dd for any
+ *             misfit J (for J = 1/2 |d - d_obs|^2 this is d - d_obs)
+ *   grad      device [nz][nx] float, overwritten with dJ/dv summed over shots
+ * Both calls must get the same plan, vp, shots, ckpt_every and ws.
+ */
+sg_status sg_grad_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec,
+                                 int32_t ckpt_every, size_t *bytes);
+sg_status sg_forward_ckpt(sg_plan *p, const float *vp, const sg_shots *shots,
+                          int32_t ckpt_every, float *gathers, void *ws, size_t ws_bytes,
+                          void *stream);
+sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots,
+                              int32_t ckpt_every, const float *resid, float *grad,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched forward over several slices of uneven size (one item per slice,
+ * all with the same dt and nt); every time block of every shot of every item
+ * runs in one launch.
+ */
+typedef struct {
+    sg_plan *plan;
+    const float *vp;
+    const sg_shots *shots;
+    float *gathers;
+    float *snaps;
+} sg_batch_item;
+
+sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes);
+sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Scan `n` device floats for NaN/Inf.  Synchronises the stream; returns
+ * SG_EDIVERGED if any is found (used to flag blow-ups).
+ */
+sg_status sg_check_finite(const float *x, size_t n, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGWAVE_H */

@@ -1,0 +1,100 @@
+// Internal declarations shared by the host runtime (sg_runtime.cpp) and the
+// HIP kernels (sg_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sg {
+
+// Stencil half width: the 8th-order central difference reaches 4 cells on
+// each side (M = 4, App. E.3 / Table "params").
+constexpr int kHalo = 4;
+
+// Guard cells kept at zero around every stored field (rows above and below,
+// columns left and right).  They let the one-step kernel read neighbours of
+// any padded cell without a bounds test.
+constexpr int kGuard = 4;
+
+// Up to four bilinear nodes per source or receiver.
+constexpr int kNodes = 4;
+
+// Device-side description of one padded slice and its fields.  All offsets
+// are in floats relative to a field's base; node (Iz, Ix) of the padded grid
+// lives at (Iz + kGuard) * pitch + (Ix + kGuard).
+struct SliceDesc {
+    int32_t Nz, Nx;          // padded grid
+    int32_t pitch;           // floats per stored row
+    int32_t nz, nx;          // physical grid
+    int32_t ztop, xleft;     // padded index of physical (0, 0)
+    int32_t free_top;        // 1: row 0 pinned to 0, odd mirror above
+    int32_t nshot;
+    int32_t nrec;
+    int32_t nrow;            // gather rows = ceil(nt / rec_every)
+    int32_t rec_every;
+    int32_t snap_every, snap_count;
+    int32_t wavelet_stride;  // 0 if one wavelet is shared, else nt
+    int64_t frame;           // floats per stored field = (Nz + 2 kGuard) * pitch
+    float cz[kHalo + 1];     // c_m / dz^2
+    float cx[kHalo + 1];     // c_m / dx^2
+    const float *V2;         // (v dt)^2 on the padded grid, stored-field layout
+    const float *gx;         // [Nx] eta_x / (2 dt); gamma = (gx + gz) * V2
+    const float *gz;         // [Nz]
+    const int32_t *src_off;  // [nshot][kNodes] stored-field offsets, -1 = unused
+    const int32_t *src_iz;   // [nshot][kNodes] padded row of each node (-1 << 20 = unused)
+    const int32_t *src_ix;   // [nshot][kNodes] padded column
+    const float *src_w;      // [nshot][kNodes] weight / (dx dz), 0 = unused
+    const int32_t *rec_off;  // [nrec][kNodes] stored-field offsets, -1 = unused
+    const int32_t *rec_iz;   // [nrec] padded row of the base node (weights in rec_w
+    const int32_t *rec_ix;   // [nrec]   for (0,0), (0,1), (1,0), (1,1))
+    const float *rec_w;      // [nrec][kNodes], 0 = unused
+    const int32_t *tile_rec; // tiled path: [tiles + 1] CSR start per tile, then receiver ids
+    const float *wavelet;    // [nshot or 1][nt]
+    float *fields;           // [nshot][kFramesPerShot][frame]
+    float *gathers;          // [nshot][nrow][nrec] or null
+    float *snaps;            // [nshot][snap_count][nz][nx] or null
+};
+
+// Each shot owns two pairs of fields.  The one-step kernel keeps level m in
+// frame m & 1 of pair 0.  The tiled kernel reads a pair (frame 0 = level m-1,
+// frame 1 = level m) and writes the other, so no workgroup overwrites a level
+// another workgroup still reads as halo.
+constexpr int kFramesPerShot = 4;
+
+// Tiling of the time-blocked kernel for one launch.
+struct TileArgs {
+    int32_t n;          // first level of the launch (levels n-1, n are read)
+    int32_t nsteps;     // levels advanced by this launch (<= tb)
+    int32_t tb;         // time block the tiling was sized for: halo = 4 * tb
+    int32_t tx, tz;     // output tile
+    int32_t tz_top;     // output rows of the top tile row under a free top
+    int32_t ntx, ntz;   // tiles per row / column
+    int32_t in_pair, out_pair;
+};
+
+// Output tiling of the time-blocked kernel for an extended (LDS) tile of
+// ex x ez cells with time block tb and k rows per thread.
+struct Tiling {
+    int ex, ez, k;
+    int tx, tz, tz_top, ntx, ntz;
+    bool ok;
+};
+Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb);
+
+// Instantiated shapes of the time-blocked kernel (extended tile ex x ez,
+// k rows per thread); `config` indexes this list.
+struct TiledShape { int ex, ez, k; };
+constexpr int kTiledShapes = 4;
+TiledShape tiled_shape(int config);
+
+// Kernel launchers (sg_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_prepare(const SliceDesc &s, const float *vp, float dt2, hipStream_t st);
+hipError_t launch_zero(float *p, size_t n, hipStream_t st);
+hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);
+hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
+hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st);
+hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st);
+
+}  // namespace sg

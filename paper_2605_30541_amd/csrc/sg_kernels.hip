@@ -1,0 +1,453 @@
+// HIP kernels of the acoustic finite-difference propagator for gfx950.
+//
+// Scheme (SubsurfaceGen, arXiv 2605.30541; eqs. "acoustic_2d", "cerjan_pde",
+// "free_surface"; App. E.3): for every padded cell,
+//   p^{n+1} = 2a p^n + W (L p^n + S^n) - b p^{n-1},
+//   gamma = eta v^2 dt / 2, a = 1/(1+gamma), b = (1-gamma) a, W = a (v dt)^2,
+// with L the 8th-order Laplacian, p = 0 outside the padded grid, and under a
+// free top row 0 pinned to 0 with the odd mirror p(-m) = -p(m) above it.
+// S^n is the point-source term w(t_n) * weight / (dx dz) on bilinear nodes.
+// Receivers read p^n with the same bilinear weights.
+//
+// Storage: a field is (Nz + 2G) rows of `pitch` floats, padded node (Iz, Ix)
+// at (Iz + G) * pitch + Ix + G, G = 4 zero guard cells on every side.  Each
+// shot owns two such fields; time level m lives in field m & 1, so a step
+// overwrites level n-1 with level n+1 in place.
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+__device__ inline float wavelet_at(const SliceDesc &s, int shot, int n)
+{
+    return s.wavelet[(int64_t)shot * s.wavelet_stride + n];
+}
+
+// One term pair of the 8th-order Laplacian in difference form:
+//   L p = sum_{m=1..4} cz_m (p(z+m) + p(z-m) - 2p) + cx_m (p(x+m) + p(x-m) - 2p),
+// the same operator as c_0 p + sum_m c_m (...) with c_0 = -2 sum_m c_m, but a
+// constant field gives exactly 0 whatever the rounding of the weights, and each
+// term stays small on smooth fields.  Over 10^4 steps this keeps the FP32
+// round-off two orders of magnitude below the summed form.
+__device__ inline float lap_pair(float acc, float cz, float cx, float zsum, float xsum, float c2)
+{
+    acc = fmaf(cz, zsum - c2, acc);
+    return fmaf(cx, xsum - c2, acc);
+}
+
+// Leapfrog update with b = 2a - 1:
+//   p^{n+1} = 2a p^n + W L p^n - b p^{n-1} = W L p^n + (2a (p^n - p^{n-1}) + p^{n-1}).
+__device__ inline float leapfrog(float W, float lap, float a2, float c, float prev)
+{
+    return fmaf(W, lap, fmaf(a2, c - prev, prev));
+}
+
+// Records level n of one shot: gather row n / rec_every (when n is a multiple
+// of rec_every) and snapshot n / snap_every (when due).  `tid`/`nthr` spread
+// the receivers and the physical cells over the calling threads.
+__device__ inline void record_level(const SliceDesc &s, const float *cur, int shot, int n,
+                                    int tid, int nthr)
+{
+    if (s.gathers && n % s.rec_every == 0) {
+        float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+        for (int r = tid; r < s.nrec; r += nthr) {
+            float d = 0.f;
+#pragma unroll
+            for (int k = 0; k < kNodes; ++k) {
+                int off = s.rec_off[r * kNodes + k];
+                if (off >= 0) d += s.rec_w[r * kNodes + k] * cur[off];
+            }
+            row[r] = d;
+        }
+    }
+    if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count) {
+        float *fr = s.snaps + ((int64_t)shot * s.snap_count + n / s.snap_every) * s.nz * s.nx;
+        const int npts = s.nz * s.nx;
+        for (int q = tid; q < npts; q += nthr) {
+            int iz = q / s.nx, ix = q - iz * s.nx;
+            fr[q] = cur[(int64_t)(iz + s.ztop + kGuard) * s.pitch + ix + s.xleft + kGuard];
+        }
+    }
+}
+
+// Velocity -> (v dt)^2 on the padded grid (edge replication into the sponge),
+// zero on the guard cells.
+__global__ void __launch_bounds__(256) k_prepare(SliceDesc s, const float *vp, float dt2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= s.frame) return;
+    const int r = (int)(q / s.pitch), c = (int)(q - (int64_t)r * s.pitch);
+    const int Iz = r - kGuard, Ix = c - kGuard;
+    float out = 0.f;
+    if (Iz >= 0 && Iz < s.Nz && Ix >= 0 && Ix < s.Nx) {
+        int iz = min(max(Iz - s.ztop, 0), s.nz - 1);
+        int ix = min(max(Ix - s.xleft, 0), s.nx - 1);
+        float v = vp[(int64_t)iz * s.nx + ix];
+        out = v * v * dt2;
+    }
+    ((float *)s.V2)[q] = out;
+}
+
+__global__ void __launch_bounds__(256) k_zero(float *p, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.f;
+}
+
+// One time step n -> n+1 for every shot (blockIdx.z), one thread per padded
+// cell, operands straight from global memory.  Also records level n.
+__global__ void __launch_bounds__(256) k_step_naive(SliceDesc s, int n)
+{
+    const int Ix = blockIdx.x * 64 + threadIdx.x;
+    const int Iz = blockIdx.y * 4 + threadIdx.y;
+    const int shot = blockIdx.z;
+    float *base = s.fields + (int64_t)shot * kFramesPerShot * s.frame;
+    const float *cur = base + (n & 1) * s.frame;
+    float *nxt = base + ((n + 1) & 1) * s.frame;   // level n-1 on entry
+
+    const int tid = ((blockIdx.y * gridDim.x + blockIdx.x) * 4 + threadIdx.y) * 64 + threadIdx.x;
+    const int nthr = gridDim.x * gridDim.y * 256;
+    record_level(s, cur, shot, n, tid, nthr);
+
+    if (Ix >= s.Nx || Iz >= s.Nz) return;
+    if (s.free_top && Iz == 0) return;             // p = 0 on the free surface
+
+    const int64_t i = (int64_t)(Iz + kGuard) * s.pitch + Ix + kGuard;
+    const float c = cur[i], c2 = c + c;
+    float lap = 0.f;
+#pragma unroll
+    for (int m = 1; m <= kHalo; ++m) {
+        // above row 0 of a free top: odd mirror, p(Iz - m) = -p(m - Iz)
+        const float up = (s.free_top && Iz - m < 0) ? -cur[i + (int64_t)(m - 2 * Iz) * s.pitch]
+                                                    : cur[i - (int64_t)m * s.pitch];
+        lap = lap_pair(lap, s.cz[m], s.cx[m], cur[i + (int64_t)m * s.pitch] + up, cur[i + m] + cur[i - m], c2);
+    }
+    float amp = 0.f;
+#pragma unroll
+    for (int k = 0; k < kNodes; ++k)
+        if (s.src_off[shot * kNodes + k] == (int32_t)i) amp += s.src_w[shot * kNodes + k];
+
+    const float V2 = s.V2[i];
+    const float gam = (s.gx[Ix] + s.gz[Iz]) * V2;
+    const float a = 1.f / (1.f + gam);
+    const float W = a * V2;
+    float v = leapfrog(W, lap, 2.f * a, c, nxt[i]);
+    if (amp != 0.f) v = fmaf(W, amp * wavelet_at(s, shot, n), v);
+    nxt[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_record(SliceDesc s, int n, int slot)
+{
+    const int shot = blockIdx.y;
+    const float *cur = s.fields + ((int64_t)shot * kFramesPerShot + slot) * s.frame;
+    record_level(s, cur, shot, n, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
+}
+
+// Maps a launch-order block index to a logical tile so that consecutive
+// logical tiles (neighbours in one shot) land on the same XCD: the hardware
+// deals workgroups round-robin over the 8 XCDs, each with its own L2.
+__device__ inline int xcd_remap(int b, int nblocks)
+{
+    const int per = nblocks >> 3;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Time-blocked step (overlapped tiling).  One workgroup advances one tile of
+// one shot by t.nsteps levels.  It loads the tile plus a halo of 4*tb cells
+// (levels n-1 and n) once, runs the sub-steps out of LDS, and writes the
+// output tile (levels n+nsteps-1 and n+nsteps) to the other field pair.
+// Validity shrinks by 4 cells per sub-step from the edges of the loaded
+// region that are not edges of the padded grid, so after tb sub-steps the
+// output tile is exact.  Cells outside the padded grid are held at 0.  Under
+// a free top the top tile row loads k ghost rows above row 0 and keeps rows
+// -1..-4 equal to minus rows 1..4 after every sub-step.
+//
+// Threads: 64 lanes across x (one wave covers 64 adjacent columns), waves
+// stacked as NWX x NWZ; each thread owns one column and K consecutive rows,
+// whose values stay in registers (z neighbours inside the column come from
+// registers, only the 4 rows above and below and the x neighbours from LDS).
+template <int K, int NWX, int NWZ>
+__global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, TileArgs t)
+{
+    constexpr int EX = 64 * NWX, EZ = K * NWZ;
+    constexpr int LW = EX + 2 * kHalo;           // LDS row: 4 pad cells each side
+    constexpr int LH = EZ + 2 * kHalo;
+    __shared__ float lds[2][LH * LW];
+
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tiles = t.ntx * t.ntz;
+    const int shot = b / tiles;
+    const int tile = b - shot * tiles;
+    const int tzi = tile / t.ntx, txi = tile - tzi * t.ntx;
+    const int halo = kHalo * t.tb;
+    const bool top_tile = s.free_top && tzi == 0;
+    int oz, oz_end, ez0;
+    if (s.free_top) {
+        oz = tzi == 0 ? 0 : t.tz_top + (tzi - 1) * t.tz;
+        oz_end = tzi == 0 ? t.tz_top : oz + t.tz;
+        ez0 = tzi == 0 ? -K : oz - halo;
+    } else {
+        oz = tzi * t.tz;
+        oz_end = oz + t.tz;
+        ez0 = oz - halo;
+    }
+    oz_end = min(oz_end, s.Nz);
+    const int ox = txi * t.tx, ox_end = min(ox + t.tx, s.Nx), ex0 = ox - halo;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lx = (w % NWX) * 64 + lane;        // local column in [0, EX)
+    const int lz0 = (w / NWX) * K;               // first local row of this thread
+    const int X = ex0 + lx, Z0 = ez0 + lz0;      // padded coordinates
+    const bool xin = X >= 0 && X < s.Nx;
+
+    const float *fbase = s.fields + (int64_t)shot * kFramesPerShot * s.frame;
+    const float *in_prev = fbase + (int64_t)(2 * t.in_pair) * s.frame;
+    const float *in_cur = in_prev + s.frame;
+    float *out_prev = (float *)fbase + (int64_t)(2 * t.out_pair) * s.frame;
+    float *out_cur = out_prev + s.frame;
+
+    // ---- zero the LDS pad ring of both buffers (read only by cells whose
+    // results are discarded; zero keeps every value finite)
+    for (int q = threadIdx.x; q < 2 * kHalo * (LW + EZ); q += 64 * NWX * NWZ) {
+        int r, c;
+        if (q < 2 * kHalo * LW) {              // 4 rows on top, 4 at the bottom
+            r = q / LW;
+            c = q - r * LW;
+            if (r >= kHalo) r += EZ;
+        } else {                               // 4 columns left and right of each row
+            const int q2 = q - 2 * kHalo * LW;
+            r = kHalo + q2 / (2 * kHalo);
+            c = q2 % (2 * kHalo);
+            if (c >= kHalo) c += EX;
+        }
+        lds[0][r * LW + c] = 0.f;
+        lds[1][r * LW + c] = 0.f;
+    }
+
+    // ---- load levels n-1 (registers) and n (registers + LDS), coefficients.
+    // Cells the scheme does not update (outside the padded grid, the pinned
+    // free-surface row) get a2 = W = 0 and p = 0, so the update keeps them 0.
+    float cur[K], prev[K], a2[K], W[K];
+    const float gxX = xin ? s.gx[X] : 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Z = Z0 + k;
+        const bool in = xin && Z >= 0 && Z < s.Nz;
+        float c = 0.f, pv = 0.f, v2 = 0.f;
+        if (in) {
+            const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+            c = in_cur[i];
+            pv = in_prev[i];
+            v2 = s.V2[i];
+        } else if (top_tile && xin && Z < 0 && Z >= -kHalo) {
+            c = -in_cur[(int64_t)(-Z + kGuard) * s.pitch + X + kGuard];   // odd mirror
+        }
+        const bool upd = in && !(s.free_top && Z == 0);
+        const float gam = upd ? (gxX + s.gz[Z]) * v2 : 0.f;
+        const float a = 1.f / (1.f + gam);
+        a2[k] = upd ? 2.f * a : 0.f;
+        W[k] = upd ? a * v2 : 0.f;
+        cur[k] = c;
+        prev[k] = upd ? pv : 0.f;
+        lds[0][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
+    }
+
+    // sources of this shot that fall inside the loaded region (uniform test)
+    bool has_src = false;
+#pragma unroll
+    for (int j = 0; j < kNodes; ++j) {
+        const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
+        has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
+    }
+    const int32_t rbeg = s.tile_rec ? s.tile_rec[tile] : 0;
+    const int32_t rend = s.tile_rec ? s.tile_rec[tile + 1] : 0;
+    const int32_t *rids = s.tile_rec + (tiles + 1);
+    __syncthreads();
+
+    for (int st = 0; st < t.nsteps; ++st) {
+        const int n = t.n + st;                  // level held in `cur`
+        const float *Lc = lds[st & 1];
+        float *Ln = lds[(st + 1) & 1];
+
+        // record level n: receivers whose base node is in this output tile
+        if (s.gathers && n % s.rec_every == 0) {
+            float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+            for (int q = rbeg + (int)threadIdx.x; q < rend; q += 64 * NWX * NWZ) {
+                const int r = rids[q];
+                const int rz = s.rec_iz[r] - ez0 + kHalo, rx = s.rec_ix[r] - ex0 + kHalo;
+                const float *wr = s.rec_w + r * kNodes;
+                row[r] = wr[0] * Lc[rz * LW + rx] + wr[1] * Lc[rz * LW + rx + 1] +
+                         wr[2] * Lc[(rz + 1) * LW + rx] + wr[3] * Lc[(rz + 1) * LW + rx + 1];
+            }
+        }
+        if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count &&
+            X >= max(ox, s.xleft) && X < min(ox_end, s.xleft + s.nx)) {
+            float *fr = s.snaps + ((int64_t)shot * s.snap_count + n / s.snap_every) * s.nz * s.nx;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int Z = Z0 + k;
+                if (Z >= max(oz, s.ztop) && Z < min(oz_end, s.ztop + s.nz))
+                    fr[(int64_t)(Z - s.ztop) * s.nx + (X - s.xleft)] = cur[k];
+            }
+        }
+
+        // the 4 rows above and below this thread's column segment
+        float up[kHalo], dn[kHalo];
+#pragma unroll
+        for (int j = 0; j < kHalo; ++j) {
+            up[j] = Lc[(lz0 + j) * LW + lx + kHalo];
+            dn[j] = Lc[(lz0 + K + kHalo + j) * LW + lx + kHalo];
+        }
+        const float wav = has_src ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
+
+        // Row k needs rows k-4..k+4 of level n; once row k is done, row k-4
+        // of level n is dead and is replaced by its new value (the register
+        // window of new values stays 5 rows deep).
+        float nw[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float *rowp = Lc + (lz0 + k + kHalo) * LW + lx + kHalo;
+            const float c2 = cur[k] + cur[k];
+            float lap = 0.f;
+#pragma unroll
+            for (int m = 1; m <= kHalo; ++m) {
+                const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
+                const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
+                lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, rowp[m] + rowp[-m], c2);
+            }
+            float v = leapfrog(W[k], lap, a2[k], cur[k], prev[k]);
+            if (has_src) {
+                float amp = 0.f;
+#pragma unroll
+                for (int j = 0; j < kNodes; ++j)
+                    if (s.src_ix[shot * kNodes + j] == X && s.src_iz[shot * kNodes + j] == Z0 + k)
+                        amp += s.src_w[shot * kNodes + j];
+                if (amp != 0.f) v = fmaf(W[k], amp * wav, v);
+            }
+            nw[k] = v;
+            const int Z = Z0 + k;
+            if (!(top_tile && Z < 0)) Ln[(lz0 + k + kHalo) * LW + lx + kHalo] = v;
+            if (top_tile && Z >= 1 && Z <= kHalo)   // ghost row -Z of the new level
+                Ln[(-Z - ez0 + kHalo) * LW + lx + kHalo] = -v;
+            if (k >= kHalo) {
+                prev[k - kHalo] = cur[k - kHalo];
+                cur[k - kHalo] = nw[k - kHalo];
+            }
+        }
+#pragma unroll
+        for (int k = K - kHalo; k < K; ++k) {
+            prev[k] = cur[k];
+            cur[k] = nw[k];
+        }
+        __syncthreads();
+    }
+
+    // ---- write the output tile: levels n+nsteps-1 and n+nsteps
+    if (X >= ox && X < ox_end) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int Z = Z0 + k;
+            if (Z >= oz && Z < oz_end) {
+                const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+                out_cur[i] = cur[k];
+                out_prev[i] = prev[k];
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_count_nonfinite(const float *x, size_t n, unsigned int *count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    unsigned int bad = 0;
+    for (; i < n; i += stride) bad += !isfinite(x[i]);
+    if (bad) atomicAdd(count, bad);
+}
+
+}  // namespace
+
+hipError_t launch_prepare(const SliceDesc &s, const float *vp, float dt2, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((s.frame + 255) / 256);
+    hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, s, vp, dt2);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(float *p, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st)
+{
+    dim3 grid((s.Nx + 63) / 64, (s.Nz + 3) / 4, s.nshot);
+    hipLaunchKernelGGL(k_step_naive, grid, dim3(64, 4), 0, st, s, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st)
+{
+    int work = s.nrec;
+    if (s.snaps && s.nz * s.nx > work) work = s.nz * s.nx;
+    unsigned blocks = (unsigned)((work + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_record, dim3(blocks, s.nshot), dim3(256), 0, st, s, n, slot);
+    return hipGetLastError();
+}
+
+namespace {
+// (ex, ez, k) of the instantiations below; every one fits its register
+// budget without spilling.
+constexpr TiledShape kShapes[kTiledShapes] = {{128, 64, 8}, {64, 128, 16}, {64, 64, 8}, {128, 64, 16}};
+}
+
+TiledShape tiled_shape(int config) { return kShapes[config]; }
+
+Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
+{
+    Tiling T{};
+    T.ex = ex;
+    T.ez = ez;
+    T.k = k;
+    const int halo = kHalo * tb;
+    T.tx = ex - 2 * halo;
+    T.tz = ez - 2 * halo;
+    T.tz_top = free_top ? ez - k - halo : T.tz;
+    T.ok = T.tx >= 1 && T.tz >= 1 && T.tz_top >= 1 && k >= kHalo;
+    if (!T.ok) return T;
+    T.ntx = (Nx + T.tx - 1) / T.tx;
+    T.ntz = free_top ? 1 + (Nz > T.tz_top ? (Nz - T.tz_top + T.tz - 1) / T.tz : 0) : (Nz + T.tz - 1) / T.tz;
+    return T;
+}
+
+hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
+    switch (config) {
+    case 0: hipLaunchKernelGGL((k_step_tiled<8, 2, 8>), dim3(blocks), dim3(1024), 0, st, s, t); break;
+    case 1: hipLaunchKernelGGL((k_step_tiled<16, 1, 8>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 2: hipLaunchKernelGGL((k_step_tiled<8, 1, 8>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 3: hipLaunchKernelGGL((k_step_tiled<16, 2, 4>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st)
+{
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)blocks), dim3(256), 0, st, x, n, count);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,657 @@
+// Host runtime of the acoustic propagator: plan validation, coefficient
+// tables, acquisition tables, workspace layout and launch orchestration behind
+// the C ABI of include/sgwave.h.
+#include "sgwave.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sg_status fail(sg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define SG_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+// Central second-derivative weights of the 8th-order stencil (M = 4):
+// the unique symmetric weights exact for polynomials up to degree 9
+// (Fornberg 1988, cited for a_m in App. E.3.2).
+constexpr double kC8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+constexpr double kPi = 3.14159265358979323846;
+
+// s_max = (sqrt(d sum_{m>=1} |a_m|))^-1 with d = 2 (App. E.3.2).
+double cfl_smax()
+{
+    double s = 0.0;
+    for (int m = 1; m <= 4; ++m) s += std::fabs(kC8[m]);
+    return 1.0 / std::sqrt(2.0 * s);
+}
+
+// Cerjan damping of one sponge side at depth d = 1..nbl cells (eq. "cerjan_damp"),
+// returned in SI units (s/m^2): the paper's eta is in the solver's km/s-ms
+// units, so eta_SI = eta * 1e-3; rho = d / nbl.
+double sponge_eta(int d, int nbl, double h, double R)
+{
+    if (d <= 0 || nbl <= 0) return 0.0;
+    const double cdamp = 1.5 * std::log(1.0 / R) / nbl;
+    const double rho = (double)d / nbl;
+    return cdamp / h * (rho - std::sin(2.0 * kPi * rho) / (2.0 * kPi)) * 1e-3;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct sg_plan {
+    sg_geometry g;
+    int32_t Nz, Nx, ztop, xleft, pitch, nrow;
+    int64_t frame;
+    uint32_t warnings;
+    sg_tuning tuning;          // zeros = library choice
+    std::vector<float> gx, gz; // eta / (2 dt) per padded column / row
+    // pinned staging for the per-call tables, reused across calls
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
+    std::mutex mu;
+    // optional per-launch timing of the time-stepping kernels
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used = 0;
+};
+
+namespace {
+
+// Workspace layout of one slice with nshot shots and nrec receivers
+// (byte offsets).  Everything from gx to tile_rec is uploaded from the
+// plan's pinned staging buffer in one copy.
+struct Layout {
+    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec,
+        tables_end, fields, total;
+};
+
+// Upper bound on the tiles of one shot over every tiling the plan may use
+// (the smallest output tile is 8 x 8 with a free top).
+int64_t max_tiles(const sg_plan *p) { return ((int64_t)p->Nz / 8 + 2) * ((int64_t)p->Nx / 8 + 2); }
+
+Layout layout_of(const sg_plan *p, int nshot, int nrec)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    const size_t ns = (size_t)nshot * sg::kNodes, nr = (size_t)std::max(nrec, 1);
+    L.v2 = take((size_t)p->frame * sizeof(float));
+    L.gx = take((size_t)p->Nx * sizeof(float));
+    L.gz = take((size_t)p->Nz * sizeof(float));
+    L.src_off = take(ns * sizeof(int32_t));
+    L.src_iz = take(ns * sizeof(int32_t));
+    L.src_ix = take(ns * sizeof(int32_t));
+    L.src_w = take(ns * sizeof(float));
+    L.rec_off = take(nr * sg::kNodes * sizeof(int32_t));
+    L.rec_iz = take(nr * sizeof(int32_t));
+    L.rec_ix = take(nr * sizeof(int32_t));
+    L.rec_w = take(nr * sg::kNodes * sizeof(float));
+    L.tile_rec = take(((size_t)max_tiles(p) + 1 + nr) * sizeof(int32_t));
+    L.tables_end = o;
+    L.fields = take((size_t)nshot * sg::kFramesPerShot * p->frame * sizeof(float));
+    L.total = o;
+    return L;
+}
+
+// Bilinear nodes of a point at (z, x) metres, in the order (0,0), (0,1),
+// (1,0), (1,1) from the base node: stored-field offsets, padded (row, col)
+// and weights times `scale`.  Nodes with zero weight, and nodes on a pinned
+// free-surface row, are dropped (offset -1, weight 0).  Returns false outside
+// the physical grid.
+constexpr int32_t kNoNode = -(1 << 20);
+
+struct Nodes {
+    int32_t base_iz, base_ix;
+    int32_t off[sg::kNodes], iz[sg::kNodes], ix[sg::kNodes];
+    float w[sg::kNodes];
+};
+
+bool bilinear(const sg_plan *p, double z, double x, double scale, Nodes *out)
+{
+    const sg_geometry &g = p->g;
+    if (!std::isfinite(z) || !std::isfinite(x)) return false;
+    const double fz = z / g.dz, fx = x / g.dx;
+    if (!(fz >= 0.0 && fx >= 0.0 && fz <= g.nz - 1 && fx <= g.nx - 1)) return false;
+    int iz = (int)std::floor(fz), ix = (int)std::floor(fx);
+    iz = std::min(iz, g.nz - 1);
+    ix = std::min(ix, g.nx - 1);
+    const double rz = fz - iz, rx = fx - ix;
+    out->base_iz = iz + p->ztop;
+    out->base_ix = ix + p->xleft;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int k = 2 * a + b;
+            const double wt = (a ? rz : 1.0 - rz) * (b ? rx : 1.0 - rx);
+            const int Iz = iz + a + p->ztop, Ix = ix + b + p->xleft;
+            out->off[k] = -1;
+            out->iz[k] = kNoNode;
+            out->ix[k] = kNoNode;
+            out->w[k] = 0.f;
+            if (wt != 0.0 && !(g.top == SG_TOP_FREE && Iz == 0)) {
+                out->off[k] = (int32_t)((int64_t)(Iz + sg::kGuard) * p->pitch + Ix + sg::kGuard);
+                out->iz[k] = Iz;
+                out->ix[k] = Ix;
+                out->w[k] = (float)(wt * scale);
+            }
+        }
+    return true;
+}
+
+sg_status check_shots(const sg_plan *p, const sg_shots *sh)
+{
+    if (!sh) return fail(SG_EINVAL, "shots is NULL");
+    if (sh->nshot < 1) return fail(SG_EINVAL, "nshot must be >= 1 (got %d)", sh->nshot);
+    if (sh->nrec < 0) return fail(SG_EINVAL, "nrec must be >= 0");
+    if (!sh->src_zx) return fail(SG_EINVAL, "src_zx is NULL");
+    if (sh->nrec > 0 && !sh->rec_zx) return fail(SG_EINVAL, "rec_zx is NULL");
+    if (!sh->wavelet) return fail(SG_EINVAL, "wavelet is NULL");
+    Nodes nd;
+    for (int i = 0; i < sh->nshot; ++i)
+        if (!bilinear(p, sh->src_zx[2 * i], sh->src_zx[2 * i + 1], 1.0, &nd))
+            return fail(SG_EINVAL, "source %d at (%g, %g) m is outside the physical grid", i,
+                        sh->src_zx[2 * i], sh->src_zx[2 * i + 1]);
+    for (int i = 0; i < sh->nrec; ++i)
+        if (!bilinear(p, sh->rec_zx[2 * i], sh->rec_zx[2 * i + 1], 1.0, &nd))
+            return fail(SG_EINVAL, "receiver %d at (%g, %g) m is outside the physical grid", i,
+                        sh->rec_zx[2 * i], sh->rec_zx[2 * i + 1]);
+    return SG_OK;
+}
+
+sg::SliceDesc describe(const sg_plan *p, const Layout &L, char *ws, const sg_shots *sh,
+                       float *gathers, float *snaps)
+{
+    const sg_geometry &g = p->g;
+    sg::SliceDesc s{};
+    s.Nz = p->Nz;
+    s.Nx = p->Nx;
+    s.pitch = p->pitch;
+    s.nz = g.nz;
+    s.nx = g.nx;
+    s.ztop = p->ztop;
+    s.xleft = p->xleft;
+    s.free_top = g.top == SG_TOP_FREE;
+    s.nshot = sh->nshot;
+    s.nrec = sh->nrec;
+    s.nrow = p->nrow;
+    s.rec_every = g.rec_every;
+    s.snap_every = g.snap_every > 0 ? g.snap_every : 1;
+    s.snap_count = g.snap_count;
+    s.wavelet_stride = sh->wavelet_per_shot ? g.nt : 0;
+    s.frame = p->frame;
+    for (int m = 0; m <= sg::kHalo; ++m) {
+        s.cz[m] = (float)(kC8[m] / (g.dz * g.dz));
+        s.cx[m] = (float)(kC8[m] / (g.dx * g.dx));
+    }
+    s.V2 = (const float *)(ws + L.v2);
+    s.gx = (const float *)(ws + L.gx);
+    s.gz = (const float *)(ws + L.gz);
+    s.src_off = (const int32_t *)(ws + L.src_off);
+    s.src_iz = (const int32_t *)(ws + L.src_iz);
+    s.src_ix = (const int32_t *)(ws + L.src_ix);
+    s.src_w = (const float *)(ws + L.src_w);
+    s.rec_off = (const int32_t *)(ws + L.rec_off);
+    s.rec_iz = (const int32_t *)(ws + L.rec_iz);
+    s.rec_ix = (const int32_t *)(ws + L.rec_ix);
+    s.rec_w = (const float *)(ws + L.rec_w);
+    s.tile_rec = (const int32_t *)(ws + L.tile_rec);
+    s.wavelet = sh->wavelet;
+    s.fields = (float *)(ws + L.fields);
+    s.gathers = sh->nrec > 0 ? gathers : nullptr;
+    s.snaps = g.snap_count > 0 ? snaps : nullptr;
+    return s;
+}
+
+// Instantiated kernel shape matching a tuning's extended tile; -1 if none.
+int shape_of(const sg_tuning &t)
+{
+    for (int c = 0; c < sg::kTiledShapes; ++c) {
+        const sg::TiledShape sh = sg::tiled_shape(c);
+        if (sh.ex == t.tile_x && sh.ez == t.tile_z && (t.rows_per_thread == 0 || t.rows_per_thread == sh.k))
+            return c;
+    }
+    return -1;
+}
+
+// Tuning of a call: the plan's setting with zeros replaced by defaults.
+sg_tuning resolve_tuning(const sg_plan *p, int nshot)
+{
+    (void)nshot;
+    sg_tuning t = p->tuning;
+    if (t.variant == 0) t.variant = 2;
+    if (t.variant == 1) {
+        t.tile_x = t.tile_z = t.rows_per_thread = 0;
+        t.time_block = 1;
+        return t;
+    }
+    if (t.tile_x == 0 || t.tile_z == 0) {
+        t.tile_x = 128;
+        t.tile_z = 64;
+    }
+    if (t.time_block <= 0) t.time_block = 2;
+    const int c = shape_of(t);
+    if (c >= 0) t.rows_per_thread = sg::tiled_shape(c).k;
+    return t;
+}
+
+sg_status tiling_for(const sg_plan *p, const sg_tuning &t, int *config, sg::Tiling *T)
+{
+    *config = shape_of(t);
+    if (*config < 0) return fail(SG_EUNSUPPORTED, "no kernel built for a %d x %d tile", t.tile_x, t.tile_z);
+    const sg::TiledShape sh = sg::tiled_shape(*config);
+    *T = sg::make_tiling(p->Nz, p->Nx, p->g.top == SG_TOP_FREE, sh.ex, sh.ez, sh.k, t.time_block);
+    if (!T->ok) return fail(SG_EUNSUPPORTED, "time block %d leaves no output tile in %d x %d", t.time_block,
+                            sh.ex, sh.ez);
+    if ((int64_t)T->ntx * T->ntz > max_tiles(p)) return fail(SG_EUNSUPPORTED, "tiling too fine");
+    return SG_OK;
+}
+
+// Copy the 1D damping tables and the acquisition tables of `sh` into the
+// workspace (pinned staging + async copy; the staging buffer is reused only
+// after the previous copy out of it has finished).  `T` (may be null) gives
+// the tiling whose per-tile receiver lists are built.
+sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *sh, const sg::Tiling *T,
+                        hipStream_t st)
+{
+    const size_t bytes = L.tables_end - L.gx;
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->stage_done) SG_HIP(hipEventSynchronize(p->stage_done));
+    if (p->stage_bytes < bytes) {
+        if (p->stage) SG_HIP(hipHostFree(p->stage));
+        p->stage = nullptr;
+        p->stage_bytes = 0;
+        SG_HIP(hipHostMalloc(&p->stage, bytes, hipHostMallocDefault));
+        p->stage_bytes = bytes;
+    }
+    if (!p->stage_done) SG_HIP(hipEventCreateWithFlags(&p->stage_done, hipEventDisableTiming));
+    char *h = (char *)p->stage;
+    auto at = [&](size_t off) { return h + (off - L.gx); };
+    std::memset(h, 0, bytes);
+    std::memcpy(at(L.gx), p->gx.data(), p->gx.size() * sizeof(float));
+    std::memcpy(at(L.gz), p->gz.data(), p->gz.size() * sizeof(float));
+    const double inv_cell = 1.0 / (p->g.dx * p->g.dz);
+    Nodes nd;
+    for (int i = 0; i < sh->nshot; ++i) {
+        bilinear(p, sh->src_zx[2 * i], sh->src_zx[2 * i + 1], inv_cell, &nd);
+        for (int k = 0; k < sg::kNodes; ++k) {
+            ((int32_t *)at(L.src_off))[i * sg::kNodes + k] = nd.off[k];
+            ((int32_t *)at(L.src_iz))[i * sg::kNodes + k] = nd.iz[k];
+            ((int32_t *)at(L.src_ix))[i * sg::kNodes + k] = nd.ix[k];
+            ((float *)at(L.src_w))[i * sg::kNodes + k] = nd.w[k];
+        }
+    }
+    std::vector<int32_t> rtile(std::max(sh->nrec, 0));
+    for (int k = 0; k < std::max(sh->nrec, 1) * sg::kNodes; ++k) ((int32_t *)at(L.rec_off))[k] = -1;
+    for (int i = 0; i < sh->nrec; ++i) {
+        bilinear(p, sh->rec_zx[2 * i], sh->rec_zx[2 * i + 1], 1.0, &nd);
+        for (int k = 0; k < sg::kNodes; ++k) {
+            ((int32_t *)at(L.rec_off))[i * sg::kNodes + k] = nd.off[k];
+            ((float *)at(L.rec_w))[i * sg::kNodes + k] = nd.w[k];
+        }
+        ((int32_t *)at(L.rec_iz))[i] = nd.base_iz;
+        ((int32_t *)at(L.rec_ix))[i] = nd.base_ix;
+        if (T) {   // tile holding the base node
+            int tz;
+            if (p->g.top == SG_TOP_FREE)
+                tz = nd.base_iz < T->tz_top ? 0 : 1 + (nd.base_iz - T->tz_top) / T->tz;
+            else
+                tz = nd.base_iz / T->tz;
+            rtile[i] = tz * T->ntx + nd.base_ix / T->tx;
+        }
+    }
+    if (T) {   // CSR: start offsets per tile, then receiver ids grouped by tile
+        const int tiles = T->ntx * T->ntz;
+        int32_t *csr = (int32_t *)at(L.tile_rec);
+        std::vector<int32_t> count(tiles + 1, 0);
+        for (int i = 0; i < sh->nrec; ++i) ++count[rtile[i] + 1];
+        for (int q = 0; q < tiles; ++q) count[q + 1] += count[q];
+        for (int q = 0; q <= tiles; ++q) csr[q] = count[q];
+        int32_t *ids = csr + tiles + 1;
+        for (int i = 0; i < sh->nrec; ++i) ids[count[rtile[i]]++] = i;
+    }
+    SG_HIP(hipMemcpyAsync(ws + L.gx, h, bytes, hipMemcpyHostToDevice, st));
+    SG_HIP(hipEventRecord(p->stage_done, st));
+    return SG_OK;
+}
+
+// Event pair i of the profiling buffer (created on first use).
+sg_status prof_pair(sg_plan *p, int i, hipEvent_t *a, hipEvent_t *b)
+{
+    while ((int)p->prof_ev.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        SG_HIP(hipEventCreate(&e));
+        p->prof_ev.push_back(e);
+    }
+    *a = p->prof_ev[2 * i];
+    *b = p->prof_ev[2 * i + 1];
+    return SG_OK;
+}
+
+// Runs levels 0 .. nt-1 of every shot: records each level while stepping
+// from it, then records the last level.
+sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
+                      const sg::Tiling &T, hipStream_t st)
+{
+    const int nt = p->g.nt;
+    const int step = t.variant == 1 ? 1 : t.time_block;
+    p->prof_used = 0;
+    int pair = 0;
+    for (int n = 0; n < nt - 1; n += step) {
+        const int k = std::min(step, nt - 1 - n);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p->profiling) {
+            sg_status rc = prof_pair(p, p->prof_used, &e0, &e1);
+            if (rc != SG_OK) return rc;
+            SG_HIP(hipEventRecord(e0, st));
+        }
+        if (t.variant == 1) {
+            SG_HIP(sg::launch_step_naive(s, n, st));
+        } else {
+            sg::TileArgs a{};
+            a.n = n;
+            a.nsteps = k;
+            a.tb = t.time_block;
+            a.tx = T.tx;
+            a.tz = T.tz;
+            a.tz_top = T.tz_top;
+            a.ntx = T.ntx;
+            a.ntz = T.ntz;
+            a.in_pair = pair;
+            a.out_pair = pair ^ 1;
+            SG_HIP(sg::launch_step_tiled(s, a, config, st));
+            pair ^= 1;
+        }
+        if (p->profiling) {
+            SG_HIP(hipEventRecord(e1, st));
+            ++p->prof_used;
+        }
+    }
+    const int last_slot = t.variant == 1 ? (nt - 1) & 1 : 2 * pair + 1;
+    SG_HIP(sg::launch_record_slot(s, nt - 1, last_slot, st));
+    return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sg_abi_version(void) { return SG_ABI_VERSION; }
+
+const char *sg_status_string(sg_status s)
+{
+    switch (s) {
+    case SG_OK: return "SG_OK";
+    case SG_EINVAL: return "SG_EINVAL";
+    case SG_ECFL: return "SG_ECFL";
+    case SG_ENOSPACE: return "SG_ENOSPACE";
+    case SG_EHIP: return "SG_EHIP";
+    case SG_EDIVERGED: return "SG_EDIVERGED";
+    case SG_EUNSUPPORTED: return "SG_EUNSUPPORTED";
+    default: return "SG_UNKNOWN";
+    }
+}
+
+const char *sg_last_error(void) { return g_last_error.c_str(); }
+
+double sg_cfl_dt_max(double dz, double dx, double vmax)
+{
+    return cfl_smax() * std::min(dz, dx) / vmax;
+}
+
+sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out)
+{
+    if (!out) return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(SG_EINVAL, "geometry is NULL");
+    if (g->nz < 1 || g->nx < 1) return fail(SG_EINVAL, "nz, nx must be >= 1 (got %d, %d)", g->nz, g->nx);
+    if (!(g->dz > 0 && g->dx > 0 && g->dt > 0) || !std::isfinite(g->dz) || !std::isfinite(g->dx) ||
+        !std::isfinite(g->dt))
+        return fail(SG_EINVAL, "dz, dx, dt must be finite and > 0");
+    if (g->nt < 2) return fail(SG_EINVAL, "nt must be >= 2 (got %d)", g->nt);
+    if (g->nbl < 0) return fail(SG_EINVAL, "nbl must be >= 0");
+    if (g->top != SG_TOP_FREE && g->top != SG_TOP_ABSORBING) return fail(SG_EINVAL, "bad top mode %d", g->top);
+    if (g->nbl > 0 && !(g->damp_R > 0 && g->damp_R < 1)) return fail(SG_EINVAL, "damp_R must be in (0, 1)");
+    if (!(g->vmax_hint > 0) || !std::isfinite(g->vmax_hint)) return fail(SG_EINVAL, "vmax_hint must be > 0");
+    if (g->rec_every < 1) return fail(SG_EINVAL, "rec_every must be >= 1");
+    if (g->snap_count < 0) return fail(SG_EINVAL, "snap_count must be >= 0");
+    if (g->snap_count > 0) {
+        if (g->snap_every < 1) return fail(SG_EINVAL, "snap_every must be >= 1");
+        if ((int64_t)(g->snap_count - 1) * g->snap_every > g->nt - 1)
+            return fail(SG_EINVAL, "snapshots reach beyond level nt-1");
+    }
+    const double dtmax = sg_cfl_dt_max(g->dz, g->dx, g->vmax_hint);
+    if (g->dt > dtmax && !(flags & SG_ALLOW_UNSTABLE))
+        return fail(SG_ECFL, "dt = %g s exceeds the CFL bound %g s at vmax = %g m/s", g->dt, dtmax,
+                    g->vmax_hint);
+    const int ztop = g->top == SG_TOP_FREE ? 0 : g->nbl;
+    const int64_t Nz = (int64_t)g->nz + ztop + g->nbl, Nx = (int64_t)g->nx + 2 * g->nbl;
+    const int64_t pitch = (int64_t)align_up((size_t)(Nx + 2 * sg::kGuard), 32);
+    const int64_t frame = (Nz + 2 * sg::kGuard) * pitch;
+    if (frame >= ((int64_t)1 << 31)) return fail(SG_EINVAL, "grid too large (%lld x %lld)", (long long)Nz,
+                                                 (long long)Nx);
+    sg_plan *p = new (std::nothrow) sg_plan();
+    if (!p) return fail(SG_EINVAL, "out of host memory");
+    p->g = *g;
+    if (p->g.snap_count == 0) p->g.snap_every = 0;
+    p->Nz = (int32_t)Nz;
+    p->Nx = (int32_t)Nx;
+    p->ztop = ztop;
+    p->xleft = g->nbl;
+    p->pitch = (int32_t)pitch;
+    p->frame = frame;
+    p->nrow = (g->nt + g->rec_every - 1) / g->rec_every;
+    p->warnings = 0;
+    if (g->vmin_hint > 0 && g->fmax_hint > 0 && std::max(g->dz, g->dx) > g->vmin_hint / (4.0 * g->fmax_hint))
+        p->warnings |= SG_WARN_DISPERSION;
+    // gamma = eta v^2 dt / 2 = (eta / (2 dt)) * (v dt)^2; corners add the sides
+    p->gx.assign(Nx, 0.f);
+    p->gz.assign(Nz, 0.f);
+    for (int Ix = 0; Ix < Nx; ++Ix) {
+        const int dl = p->xleft - Ix, dr = Ix - (p->xleft + g->nx - 1);
+        const double eta = sponge_eta(dl, g->nbl, g->dx, g->damp_R) + sponge_eta(dr, g->nbl, g->dx, g->damp_R);
+        p->gx[Ix] = (float)(eta / (2.0 * g->dt));
+    }
+    for (int Iz = 0; Iz < Nz; ++Iz) {
+        const int db = Iz - (ztop + g->nz - 1), dtp = ztop - Iz;
+        const double eta = sponge_eta(db, g->nbl, g->dz, g->damp_R) + sponge_eta(dtp, g->nbl, g->dz, g->damp_R);
+        p->gz[Iz] = (float)(eta / (2.0 * g->dt));
+    }
+    *out = p;
+    return SG_OK;
+}
+
+sg_status sg_plan_destroy(sg_plan *p)
+{
+    if (!p) return SG_OK;
+    if (p->stage_done) {
+        (void)hipEventSynchronize(p->stage_done);
+        (void)hipEventDestroy(p->stage_done);
+    }
+    if (p->stage) (void)hipHostFree(p->stage);
+    for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+    delete p;
+    return SG_OK;
+}
+
+uint32_t sg_plan_warnings(const sg_plan *p) { return p ? p->warnings : 0u; }
+
+sg_status sg_plan_set_profiling(sg_plan *p, int32_t on)
+{
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    p->profiling = on != 0;
+    return SG_OK;
+}
+
+sg_status sg_plan_profile(sg_plan *p, double *kernel_ms, int32_t *launches)
+{
+    if (!p || !kernel_ms || !launches) return fail(SG_EINVAL, "NULL argument");
+    double total = 0.0;
+    if (p->prof_used > 0) SG_HIP(hipEventSynchronize(p->prof_ev[2 * p->prof_used - 1]));
+    for (int i = 0; i < p->prof_used; ++i) {
+        float ms = 0.f;
+        SG_HIP(hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]));
+        total += ms;
+    }
+    *kernel_ms = total;
+    *launches = p->prof_used;
+    return SG_OK;
+}
+
+sg_status sg_plan_padded_shape(const sg_plan *p, int32_t *Nz, int32_t *Nx)
+{
+    if (!p || !Nz || !Nx) return fail(SG_EINVAL, "NULL argument");
+    *Nz = p->Nz;
+    *Nx = p->Nx;
+    return SG_OK;
+}
+
+sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t)
+{
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    if (!t) {
+        p->tuning = sg_tuning{};
+        return SG_OK;
+    }
+    if (t->variant < 0 || t->variant > 2) return fail(SG_EINVAL, "variant must be 0, 1 or 2");
+    if (t->time_block < 0 || t->time_block > 8) return fail(SG_EINVAL, "time_block must be in 0..8");
+    if (t->tile_x < 0 || t->tile_z < 0) return fail(SG_EINVAL, "tile sizes must be >= 0");
+    if (t->rows_per_thread < 0) return fail(SG_EINVAL, "rows_per_thread must be >= 0");
+    if (t->variant != 1 && (t->tile_x || t->tile_z) && shape_of(*t) < 0)
+        return fail(SG_EUNSUPPORTED, "no kernel built for a %d x %d tile with %d rows per thread", t->tile_x,
+                    t->tile_z, t->rows_per_thread);
+    p->tuning = *t;
+    return SG_OK;
+}
+
+sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t)
+{
+    if (!p || !t) return fail(SG_EINVAL, "NULL argument");
+    *t = resolve_tuning(p, nshot);
+    return SG_OK;
+}
+
+sg_status sg_ricker(double f0, double dt, int32_t nt, double t0, float *out)
+{
+    if (!out || nt < 0 || !(f0 > 0) || !(dt > 0)) return fail(SG_EINVAL, "bad Ricker arguments");
+    if (t0 <= 0) t0 = 1.0 / f0;
+    for (int n = 0; n < nt; ++n) {
+        const double tau = n * dt - t0;
+        const double q = kPi * kPi * f0 * f0 * tau * tau;
+        out[n] = (float)((1.0 - 2.0 * q) * std::exp(-q));
+    }
+    return SG_OK;
+}
+
+sg_status sg_forward_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SG_EINVAL, "NULL argument");
+    if (nshot < 1 || nrec < 0) return fail(SG_EINVAL, "nshot must be >= 1 and nrec >= 0");
+    *bytes = layout_of(p, nshot, nrec).total;
+    return SG_OK;
+}
+
+sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers,
+                     float *snaps, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    if (!vp) return fail(SG_EINVAL, "vp is NULL");
+    if (!ws) return fail(SG_EINVAL, "workspace is NULL");
+    sg_status rc = check_shots(p, shots);
+    if (rc != SG_OK) return rc;
+    const Layout L = layout_of(p, shots->nshot, shots->nrec);
+    if (ws_bytes < L.total)
+        return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+    const sg_tuning t = resolve_tuning(p, shots->nshot);
+    int config = -1;
+    sg::Tiling T{};
+    if (t.variant == 2 && (rc = tiling_for(p, t, &config, &T)) != SG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    if ((rc = upload_tables(p, L, w, shots, t.variant == 2 ? &T : nullptr, st)) != SG_OK) return rc;
+    const sg::SliceDesc s = describe(p, L, w, shots, gathers, snaps);
+    SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
+    SG_HIP(sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st));
+    return run_forward(p, s, t, config, T, st);
+}
+
+sg_status sg_check_finite(const float *x, size_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!x || !ws) return fail(SG_EINVAL, "NULL argument");
+    if (ws_bytes < sizeof(unsigned int)) return fail(SG_ENOSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int *cnt = (unsigned int *)ws;
+    SG_HIP(sg::launch_zero((float *)cnt, 1, st));
+    SG_HIP(sg::launch_count_nonfinite(x, n, cnt, st));
+    unsigned int h = 0;
+    SG_HIP(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    if (h) return fail(SG_EDIVERGED, "%u non-finite values", h);
+    return SG_OK;
+}
+
+sg_status sg_grad_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec, int32_t ckpt_every,
+                                 size_t *bytes)
+{
+    (void)p; (void)nshot; (void)nrec; (void)ckpt_every; (void)bytes;
+    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+}
+
+sg_status sg_forward_ckpt(sg_plan *p, const float *vp, const sg_shots *shots, int32_t ckpt_every,
+                          float *gathers, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)p; (void)vp; (void)shots; (void)ckpt_every; (void)gathers; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+}
+
+sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots, int32_t ckpt_every,
+                              const float *resid, float *grad, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)p; (void)vp; (void)shots; (void)ckpt_every; (void)resid; (void)grad; (void)ws; (void)ws_bytes;
+    (void)stream;
+    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+}
+
+sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes)
+{
+    (void)items; (void)nitems; (void)bytes;
+    return fail(SG_EUNSUPPORTED, "batched path not built yet");
+}
+
+sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    (void)items; (void)nitems; (void)tuning; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(SG_EUNSUPPORTED, "batched path not built yet");
+}
+
+}  // extern "C"

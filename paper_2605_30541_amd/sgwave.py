@@ -1,0 +1,320 @@
+"""Python binding of libsgwave (the C ABI of include/sgwave.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch supplies device memory and the stream; arrays cross the
+boundary as raw pointers.  The ``sg_*`` functions mirror the C calls one for
+one; ``Plan`` and the helpers below them only allocate the caller-owned
+buffers the C calls expect.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libsgwave.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgwave.h")
+
+SG_OK, SG_EINVAL, SG_ECFL, SG_ENOSPACE, SG_EHIP, SG_EDIVERGED, SG_EUNSUPPORTED = range(7)
+SG_TOP_FREE, SG_TOP_ABSORBING = 0, 1
+SG_ALLOW_UNSTABLE = 1
+SG_WARN_DISPERSION = 1
+
+
+class SGError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+_STATUS_NAMES = {0: "SG_OK", 1: "SG_EINVAL", 2: "SG_ECFL", 3: "SG_ENOSPACE", 4: "SG_EHIP",
+                 5: "SG_EDIVERGED", 6: "SG_EUNSUPPORTED"}
+
+
+class sg_geometry(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("dz", ctypes.c_double), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nt", ctypes.c_int32), ("nbl", ctypes.c_int32), ("top", ctypes.c_int32),
+                ("damp_R", ctypes.c_double), ("vmax_hint", ctypes.c_double),
+                ("vmin_hint", ctypes.c_double), ("fmax_hint", ctypes.c_double),
+                ("rec_every", ctypes.c_int32), ("snap_every", ctypes.c_int32),
+                ("snap_count", ctypes.c_int32)]
+
+
+class sg_shots(ctypes.Structure):
+    _fields_ = [("nshot", ctypes.c_int32), ("src_zx", ctypes.POINTER(ctypes.c_double)),
+                ("nrec", ctypes.c_int32), ("rec_zx", ctypes.POINTER(ctypes.c_double)),
+                ("wavelet", ctypes.c_void_p), ("wavelet_per_shot", ctypes.c_int32)]
+
+
+class sg_tuning(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_z", ctypes.c_int32), ("time_block", ctypes.c_int32),
+                ("rows_per_thread", ctypes.c_int32)]
+
+
+class sg_batch_item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("vp", ctypes.c_void_p),
+                ("shots", ctypes.POINTER(sg_shots)), ("gathers", ctypes.c_void_p),
+                ("snaps", ctypes.c_void_p)]
+
+
+_lib = None
+_SIGS = {
+    "sg_abi_version": (ctypes.c_int32, []),
+    "sg_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "sg_last_error": (ctypes.c_char_p, []),
+    "sg_plan_create": (ctypes.c_int32, [ctypes.POINTER(sg_geometry), ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "sg_plan_warnings": (ctypes.c_uint32, [ctypes.c_void_p]),
+    "sg_plan_padded_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
+    "sg_plan_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sg_tuning)]),
+    "sg_plan_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sg_tuning)]),
+    "sg_plan_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "sg_plan_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "sg_ricker": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_float)]),
+    "sg_cfl_dt_max": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "sg_forward_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]),
+    "sg_grad_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_forward_ckpt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+    "sg_adjoint_gradient": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
+                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "sg_batch_workspace_size": (ctypes.c_int32, [ctypes.POINTER(sg_batch_item), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_batch_forward": (ctypes.c_int32, [ctypes.POINTER(sg_batch_item), ctypes.c_int32,
+                                          ctypes.POINTER(sg_tuning), ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p]),
+    "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded libsgwave.  Raises if the library has not been built: there
+    is no fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsgwave.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/sgwave.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", text)) - {"sg_shots"})
+
+
+def _check(status: int):
+    if status != SG_OK:
+        raise SGError(status, lib().sg_last_error().decode())
+
+
+# ------------------------------------------------------------------ C calls
+
+def sg_abi_version() -> int:
+    return lib().sg_abi_version()
+
+
+def sg_status_string(s: int) -> str:
+    return lib().sg_status_string(s).decode()
+
+
+def sg_last_error() -> str:
+    return lib().sg_last_error().decode()
+
+
+def sg_ricker(f0: float, dt: float, nt: int, t0: float = 0.0) -> np.ndarray:
+    out = np.empty(nt, np.float32)
+    _check(lib().sg_ricker(f0, dt, nt, t0, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def sg_cfl_dt_max(dz: float, dx: float, vmax: float) -> float:
+    return lib().sg_cfl_dt_max(dz, dx, vmax)
+
+
+@dataclass
+class Geometry:
+    """Mirror of sg_geometry (include/sgwave.h)."""
+    nz: int
+    nx: int
+    dz: float
+    dx: float
+    dt: float
+    nt: int
+    nbl: int = 40
+    top: int = SG_TOP_FREE
+    damp_R: float = 1e-3
+    vmax_hint: float = 5000.0
+    vmin_hint: float = 0.0
+    fmax_hint: float = 0.0
+    rec_every: int = 1
+    snap_every: int = 0
+    snap_count: int = 0
+
+    def c(self) -> sg_geometry:
+        return sg_geometry(self.nz, self.nx, self.dz, self.dx, self.dt, self.nt, self.nbl, self.top,
+                           self.damp_R, self.vmax_hint, self.vmin_hint, self.fmax_hint,
+                           self.rec_every, self.snap_every, self.snap_count)
+
+    @property
+    def nrow(self) -> int:
+        return -(-self.nt // self.rec_every)
+
+
+class Plan:
+    """Owner of one sg_plan*."""
+
+    def __init__(self, geom: Geometry, flags: int = 0):
+        self.geom = geom
+        self._g = geom.c()
+        h = ctypes.c_void_p()
+        _check(lib().sg_plan_create(ctypes.byref(self._g), flags, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.sg_plan_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def warnings(self) -> int:
+        return lib().sg_plan_warnings(self.handle)
+
+    @property
+    def padded_shape(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sg_plan_padded_shape(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_tuning(self, variant=0, tile_x=0, tile_z=0, time_block=0, rows_per_thread=0):
+        t = sg_tuning(variant, tile_x, tile_z, time_block, rows_per_thread)
+        _check(lib().sg_plan_set_tuning(self.handle, ctypes.byref(t)))
+
+    def clear_tuning(self):
+        _check(lib().sg_plan_set_tuning(self.handle, None))
+
+    def set_profiling(self, on: bool):
+        _check(lib().sg_plan_set_profiling(self.handle, 1 if on else 0))
+
+    def profile(self):
+        """(summed kernel ms, launches) of the time-stepping kernels of the last call."""
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().sg_plan_profile(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def get_tuning(self, nshot: int = 1):
+        t = sg_tuning()
+        _check(lib().sg_plan_get_tuning(self.handle, nshot, ctypes.byref(t)))
+        return dict(variant=t.variant, tile_x=t.tile_x, tile_z=t.tile_z, time_block=t.time_block,
+                    rows_per_thread=t.rows_per_thread)
+
+
+@dataclass
+class Shots:
+    """Host side of sg_shots; `wavelet` is a float32 CUDA tensor [1 or nshot, nt]."""
+    src_zx: np.ndarray
+    rec_zx: np.ndarray
+    wavelet: object
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c(self) -> sg_shots:
+        src = np.ascontiguousarray(np.asarray(self.src_zx, np.float64).reshape(-1, 2))
+        rec = np.ascontiguousarray(np.asarray(self.rec_zx, np.float64).reshape(-1, 2))
+        self._keep = [src, rec]
+        w = self.wavelet
+        per_shot = 1 if (w.dim() == 2 and w.shape[0] > 1) else 0
+        if per_shot and w.shape[0] != src.shape[0]:
+            raise ValueError("wavelet rows must be 1 or nshot")
+        return sg_shots(src.shape[0], src.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        rec.shape[0], rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        ctypes.c_void_p(w.data_ptr()), per_shot)
+
+    @property
+    def nshot(self) -> int:
+        return int(np.asarray(self.src_zx).reshape(-1, 2).shape[0])
+
+    @property
+    def nrec(self) -> int:
+        return int(np.asarray(self.rec_zx).reshape(-1, 2).shape[0])
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def sg_forward_workspace_size(plan: Plan, nshot: int, nrec: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sg_forward_workspace_size(plan.handle, nshot, nrec, ctypes.byref(n)))
+    return n.value
+
+
+def sg_forward(plan: Plan, vp, shots: Shots, gathers, snaps, ws, stream=None):
+    sh = shots.c()
+    _check(lib().sg_forward(plan.handle, _ptr(vp), ctypes.byref(sh), _ptr(gathers), _ptr(snaps),
+                            _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def sg_check_finite(x, ws, stream=None):
+    _check(lib().sg_check_finite(_ptr(x), x.numel(), _ptr(ws), ws.numel() * ws.element_size(),
+                                 _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------------ helpers
+
+def ricker_tensor(f0: float, dt: float, nt: int, device="cuda"):
+    """Ricker wavelet from sg_ricker as a [1, nt] float32 tensor."""
+    import torch
+    return torch.from_numpy(sg_ricker(f0, dt, nt)).reshape(1, nt).to(device)
+
+
+def forward(plan: Plan, vp, shots: Shots, want_gathers=True, want_snaps=None, ws=None, stream=None):
+    """Allocate outputs (and the workspace unless given) with torch, run
+    sg_forward, return (gathers, snaps)."""
+    import torch
+    g = plan.geom
+    dev = vp.device
+    gathers = torch.empty((shots.nshot, g.nrow, shots.nrec), dtype=torch.float32, device=dev) \
+        if want_gathers and shots.nrec > 0 else None
+    if want_snaps is None:
+        want_snaps = g.snap_count > 0
+    snaps = torch.empty((shots.nshot, g.snap_count, g.nz, g.nx), dtype=torch.float32, device=dev) \
+        if want_snaps and g.snap_count > 0 else None
+    if ws is None:
+        ws = torch.empty(sg_forward_workspace_size(plan, shots.nshot, shots.nrec), dtype=torch.uint8,
+                         device=dev)
+    sg_forward(plan, vp, shots, gathers, snaps, ws, stream)
+    return gathers, snaps

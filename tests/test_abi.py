@@ -1,0 +1,139 @@
+"""Host-side tests of the C ABI (no GPU): the library loads, exports every
+function the header declares, and its host-only calls validate and compute
+what they document."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_30541_amd import sgwave
+from paper_2605_30541_amd.sgwave import Geometry, Plan, SGError
+
+
+def test_library_exports_every_header_function():
+    names = sgwave.header_functions()
+    assert "sg_forward" in names and "sg_adjoint_gradient" in names and "sg_batch_forward" in names
+    L = sgwave.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sgwave.sg_abi_version() == 1
+    assert set(names) == set(sgwave._SIGS)
+
+
+def test_status_strings():
+    assert sgwave.sg_status_string(0) == "SG_OK"
+    assert sgwave.sg_status_string(2) == "SG_ECFL"
+    assert sgwave.sg_status_string(99) == "SG_UNKNOWN"
+
+
+def test_ricker_matches_oracle():
+    for f0, dt, nt in ((15.0, 1e-3, 500), (12.0, 8e-4, 10000), (4.5, 1e-3, 8001)):
+        a = sgwave.sg_ricker(f0, dt, nt)
+        b = oracle.ricker(f0, dt, nt)
+        assert np.abs(a - b).max() <= 6e-8 * np.abs(b).max()
+
+
+def test_cfl_limit_matches_paper_constant():
+    assert sgwave.sg_cfl_dt_max(10.0, 10.0, 5000.0) == pytest.approx(oracle.cfl_dt_max(10.0, 5000.0), rel=1e-14)
+
+
+def _geom(**kw):
+    base = dict(nz=64, nx=128, dz=10.0, dx=10.0, dt=1e-3, nt=500, nbl=20, vmax_hint=3500.0)
+    base.update(kw)
+    return Geometry(**base)
+
+
+def test_plan_validation_errors():
+    Plan(_geom())
+    bad = [dict(nz=0), dict(nx=-1), dict(dt=0.0), dict(dz=float("nan")), dict(nt=1), dict(nbl=-1),
+           dict(top=7), dict(damp_R=0.0), dict(damp_R=1.5), dict(vmax_hint=0.0), dict(rec_every=0),
+           dict(snap_count=3, snap_every=0), dict(snap_count=6, snap_every=100)]
+    for kw in bad:
+        with pytest.raises(SGError) as e:
+            Plan(_geom(**kw))
+        assert e.value.status == sgwave.SG_EINVAL, kw
+        assert e.value.message
+    Plan(_geom(snap_count=5, snap_every=100, nt=401))
+    with pytest.raises(SGError):
+        Plan(_geom(snap_count=5, snap_every=100, nt=400))
+
+
+def test_plan_cfl_rejection_and_override():
+    dtmax = oracle.cfl_dt_max(10.0, 5000.0)
+    Plan(_geom(dt=dtmax * 0.999, vmax_hint=5000.0))
+    with pytest.raises(SGError) as e:
+        Plan(_geom(dt=dtmax * 1.001, vmax_hint=5000.0))
+    assert e.value.status == sgwave.SG_ECFL
+    Plan(_geom(dt=dtmax * 1.001, vmax_hint=5000.0), flags=sgwave.SG_ALLOW_UNSTABLE)
+
+
+def test_dispersion_warning():
+    # h <= vmin / (4 fmax): 10 m passes at 1500 m/s, 25 Hz (15 m) and fails at 50 Hz (7.5 m)
+    assert Plan(_geom(vmin_hint=1500.0, fmax_hint=25.0)).warnings == 0
+    assert Plan(_geom(vmin_hint=1500.0, fmax_hint=50.0)).warnings & sgwave.SG_WARN_DISPERSION
+
+
+def test_padded_shape_and_workspace_size():
+    p = Plan(_geom())
+    assert p.padded_shape == (84, 168)                     # 64+20 x 128+40
+    p2 = Plan(_geom(top=sgwave.SG_TOP_ABSORBING))
+    assert p2.padded_shape == (104, 168)
+    w1 = sgwave.sg_forward_workspace_size(p, 1, 128)
+    w4 = sgwave.sg_forward_workspace_size(p, 4, 128)
+    assert w4 > w1 > 2 * 84 * 168 * 4
+    # fields dominate: 3 more shots add at least 3 x 2 padded fields
+    assert w4 - w1 >= 3 * 2 * 84 * 168 * 4
+
+
+def test_tuning_validation():
+    p = Plan(_geom())
+    assert p.get_tuning(1)["variant"] == 2                 # default: tiled
+    p.set_tuning(variant=2, tile_x=128, tile_z=64, time_block=4)
+    assert p.get_tuning(1) == dict(variant=2, tile_x=128, tile_z=64, time_block=4, rows_per_thread=8)
+    p.set_tuning(variant=2, tile_x=128, tile_z=64, time_block=3, rows_per_thread=16)
+    assert p.get_tuning(1)["rows_per_thread"] == 16
+    with pytest.raises(SGError) as e:
+        p.set_tuning(variant=2, tile_x=64, tile_z=32, time_block=4)
+    assert e.value.status == sgwave.SG_EUNSUPPORTED
+    with pytest.raises(SGError):
+        p.set_tuning(variant=2, tile_x=64, tile_z=64, rows_per_thread=16)
+    p.set_tuning(variant=1)
+    assert p.get_tuning(1) == dict(variant=1, tile_x=0, tile_z=0, time_block=1, rows_per_thread=0)
+    with pytest.raises(SGError):
+        p.set_tuning(variant=5)
+    with pytest.raises(SGError):
+        p.set_tuning(variant=2, time_block=9)
+    p.clear_tuning()
+
+
+def test_forward_argument_errors_touch_nothing():
+    """Validation happens before any device work: these calls fail on the
+    host with null device pointers and never reach the GPU."""
+    p = Plan(_geom())
+    L = sgwave.lib()
+    src = np.array([[20.0, 640.0]])
+    rec = np.stack([np.full(128, 10.0), np.arange(128) * 10.0], 1)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def shots(src_, rec_, wavelet=1):
+        return sgwave.sg_shots(len(src_), src_.ctypes.data_as(dp), len(rec_), rec_.ctypes.data_as(dp),
+                               ctypes.c_void_p(wavelet), 0)
+    fake = ctypes.c_void_p(0x1000)
+    cases = [
+        (None, shots(src, rec), fake, 1 << 30, sgwave.SG_EINVAL),          # vp NULL
+        (fake, shots(src, rec), None, 1 << 30, sgwave.SG_EINVAL),          # ws NULL
+        (fake, shots(np.array([[20.0, 1280.0]]), rec), fake, 1 << 30, sgwave.SG_EINVAL),  # src outside
+        (fake, shots(src, np.array([[-1.0, 5.0]])), fake, 1 << 30, sgwave.SG_EINVAL),    # rec outside
+        (fake, shots(src, rec, wavelet=0), fake, 1 << 30, sgwave.SG_EINVAL),            # no wavelet
+        (fake, shots(src, rec), fake, 16, sgwave.SG_ENOSPACE),                          # small ws
+    ]
+    for vp, sh, ws, nbytes, want in cases:
+        st = L.sg_forward(p.handle, vp, ctypes.byref(sh), None, None, ws, nbytes, None)
+        assert st == want, (st, want, sgwave.sg_last_error())
+        assert sgwave.sg_last_error()
+
+
+def test_destroy_null_is_ok():
+    assert sgwave.lib().sg_plan_destroy(None) == 0
