@@ -177,10 +177,11 @@ sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t);
 
 /*
  * Kernel timing of the time-stepping launches.  With profiling on, later
- * calls on this plan bracket every time-stepping launch with a pair of HIP
- * events on the call's stream; sg_plan_profile waits for the last recorded
- * event and returns the summed kernel time [ms] and the launch count of the
- * most recent call.  Used by the benchmark to price the dominant kernel.
+ * calls on this plan bracket their back-to-back run of time-stepping
+ * launches with a pair of HIP events on the call's stream; sg_plan_profile
+ * waits for the second event and returns the elapsed time [ms] and the
+ * number of launches in between for the most recent call.  Used by the
+ * benchmark to price the dominant kernel (time / launches = average launch).
  */
 sg_status sg_plan_set_profiling(sg_plan *p, int32_t on);
 sg_status sg_plan_profile(sg_plan *p, double *kernel_ms, int32_t *launches);

@@ -83,7 +83,8 @@ struct sg_plan {
     // optional per-launch timing of the time-stepping kernels
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;
-    int prof_used = 0;
+    int prof_used = 0;       // event pairs recorded by the last call
+    int prof_launches = 0;   // time-stepping launches they bracket
 };
 
 namespace {
@@ -258,7 +259,7 @@ sg_tuning resolve_tuning(const sg_plan *p, int nshot)
         t.tile_x = 128;
         t.tile_z = 64;
     }
-    if (t.time_block <= 0) t.time_block = 2;
+    if (t.time_block <= 0) t.time_block = 4;
     const int c = shape_of(t);
     if (c >= 0) t.rows_per_thread = sg::tiled_shape(c).k;
     return t;
@@ -358,22 +359,23 @@ sg_status prof_pair(sg_plan *p, int i, hipEvent_t *a, hipEvent_t *b)
 }
 
 // Runs levels 0 .. nt-1 of every shot: records each level while stepping
-// from it, then records the last level.
+// from it, then records the last level.  With profiling on, one event pair
+// brackets the whole run of time-stepping launches.
 sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
                       const sg::Tiling &T, hipStream_t st)
 {
     const int nt = p->g.nt;
     const int step = t.variant == 1 ? 1 : t.time_block;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     p->prof_used = 0;
-    int pair = 0;
-    for (int n = 0; n < nt - 1; n += step) {
+    if (p->profiling) {
+        sg_status rc = prof_pair(p, 0, &e0, &e1);
+        if (rc != SG_OK) return rc;
+        SG_HIP(hipEventRecord(e0, st));
+    }
+    int pair = 0, launches = 0;
+    for (int n = 0; n < nt - 1; n += step, ++launches) {
         const int k = std::min(step, nt - 1 - n);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (p->profiling) {
-            sg_status rc = prof_pair(p, p->prof_used, &e0, &e1);
-            if (rc != SG_OK) return rc;
-            SG_HIP(hipEventRecord(e0, st));
-        }
         if (t.variant == 1) {
             SG_HIP(sg::launch_step_naive(s, n, st));
         } else {
@@ -391,10 +393,11 @@ sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
             SG_HIP(sg::launch_step_tiled(s, a, config, st));
             pair ^= 1;
         }
-        if (p->profiling) {
-            SG_HIP(hipEventRecord(e1, st));
-            ++p->prof_used;
-        }
+    }
+    if (p->profiling) {
+        SG_HIP(hipEventRecord(e1, st));
+        p->prof_used = 1;
+        p->prof_launches = launches;
     }
     const int last_slot = t.variant == 1 ? (nt - 1) & 1 : 2 * pair + 1;
     SG_HIP(sg::launch_record_slot(s, nt - 1, last_slot, st));
@@ -523,7 +526,7 @@ sg_status sg_plan_profile(sg_plan *p, double *kernel_ms, int32_t *launches)
         total += ms;
     }
     *kernel_ms = total;
-    *launches = p->prof_used;
+    *launches = p->prof_launches;
     return SG_OK;
 }
 

@@ -89,7 +89,7 @@ def test_padded_shape_and_workspace_size():
 
 def test_tuning_validation():
     p = Plan(_geom())
-    assert p.get_tuning(1)["variant"] == 2                 # default: tiled
+    assert p.get_tuning(1) == dict(variant=2, tile_x=128, tile_z=64, time_block=4, rows_per_thread=8)
     p.set_tuning(variant=2, tile_x=128, tile_z=64, time_block=4)
     assert p.get_tuning(1) == dict(variant=2, tile_x=128, tile_z=64, time_block=4, rows_per_thread=8)
     p.set_tuning(variant=2, tile_x=128, tile_z=64, time_block=3, rows_per_thread=16)
