@@ -63,21 +63,48 @@ struct SliceDesc {
 // another workgroup still reads as halo.
 constexpr int kFramesPerShot = 4;
 
-// Tiling of the time-blocked kernel for one launch.
+// Residual injection tables of the adjoint (one tiling): for tile t the cells
+// tile_start[t] .. tile_start[t+1]-1 are the receiver nodes inside its loaded
+// region; cell e sits at LDS index lds[e] (padded row iz[e], column ix[e]) and
+// gets sum_q w[q] r[rid[q]] for q in pstart[e] .. pstart[e+1]-1.
+struct InjTables {
+    const int32_t *tile_start;
+    const int32_t *lds;
+    const int32_t *iz;
+    const int32_t *ix;
+    const int32_t *pstart;
+    const int32_t *rid;
+    const float *w;
+};
+
+// One launch of the time-blocked kernel.
 struct TileArgs {
-    int32_t n;          // first level of the launch (levels n-1, n are read)
+    int32_t n;          // forward: levels n-1, n are read, n+1.. computed;
+                        // adjoint: mu^{n+2}, mu^{n+1} are read, mu^n, mu^{n-1}.. computed
     int32_t nsteps;     // levels advanced by this launch (<= tb)
     int32_t tb;         // time block the tiling was sized for: halo = 4 * tb
     int32_t tx, tz;     // output tile
     int32_t tz_top;     // output rows of the top tile row under a free top
     int32_t ntx, ntz;   // tiles per row / column
     int32_t in_pair, out_pair;
+    float *fields;      // [nshot][kFramesPerShot][frame]
+    // forward: each new level of the output tile is also stored in ring slot
+    // (level - ring_lo) when ring != null; adjoint: the ring holds the forward
+    // levels ring_lo .. ring_hi read by the imaging term
+    float *ring;
+    int32_t ring_lo, ring_hi;
+    int64_t ring_shot;  // floats per shot in the ring
+    // adjoint only
+    const float *resid; // [nshot][nrow][nrec], dJ/dd at the recorded levels
+    float *hsum, *hcomp;// [nshot][frame] Kahan pair of sum_n mu^{n+1} (p^{n+1} - 2p^n + p^{n-1})
+    int32_t nt;
+    InjTables inj;
 };
 
 // Output tiling of the time-blocked kernel for an extended (LDS) tile of
 // ex x ez cells with time block tb and k rows per thread.
 struct Tiling {
-    int ex, ez, k;
+    int ex, ez, k, tb;
     int tx, tz, tz_top, ntx, ntz;
     bool ok;
 };
@@ -94,6 +121,14 @@ hipError_t launch_prepare(const SliceDesc &s, const float *vp, float dt2, hipStr
 hipError_t launch_zero(float *p, size_t n, hipStream_t st);
 hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);
 hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
+hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
+// dst[shot][0..n) = src[shot][0..n) for every shot (strides in floats)
+hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
+                       hipStream_t st);
+// grad[iz][ix] = 2 / (dt^2 v^3) * sum over shots and over the padded cells whose
+// velocity is copied from (iz, ix) of (hsum - hcomp)
+hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
+                                int64_t shot_stride, float dt, float *grad, hipStream_t st);
 hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st);
 hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st);
 

@@ -155,24 +155,36 @@ __device__ inline int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
-// Time-blocked step (overlapped tiling).  One workgroup advances one tile of
-// one shot by t.nsteps levels.  It loads the tile plus a halo of 4*tb cells
-// (levels n-1 and n) once, runs the sub-steps out of LDS, and writes the
-// output tile (levels n+nsteps-1 and n+nsteps) to the other field pair.
-// Validity shrinks by 4 cells per sub-step from the edges of the loaded
-// region that are not edges of the padded grid, so after tb sub-steps the
-// output tile is exact.  Cells outside the padded grid are held at 0.  Under
-// a free top the top tile row loads k ghost rows above row 0 and keeps rows
-// -1..-4 equal to minus rows 1..4 after every sub-step.
+// Time-blocked step (overlapped tiling), forward (ADJ = false) or adjoint
+// (ADJ = true).  One workgroup advances one tile of one shot by t.nsteps
+// levels.  It loads the tile plus a halo of 4*tb cells (two levels) once,
+// runs the sub-steps out of LDS, and writes the output tile (the last two
+// levels) to the other field pair.  Validity shrinks by 4 cells per sub-step
+// from the edges of the loaded region that are not edges of the padded grid,
+// so after tb sub-steps the output tile is exact.  Cells outside the padded
+// grid are held at 0.  Under a free top the top tile row loads k ghost rows
+// above row 0 and keeps rows -1..-4 equal to minus rows 1..4.
 //
 // Threads: 64 lanes across x (one wave covers 64 adjacent columns), waves
 // stacked as NWX x NWZ; each thread owns one column and K consecutive rows,
 // whose values stay in registers (z neighbours inside the column come from
 // registers, only the 4 rows above and below and the x neighbours from LDS).
-template <int K, int NWX, int NWZ>
-__global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, TileArgs t)
+//
+// Forward: p^{n+1} = W L p^n + (2a (p^n - p^{n-1}) + p^{n-1}) + W S^n, with the
+// point sources S^n fused, receivers sampled from the tile's receiver list,
+// snapshots and (optionally) every new level stored to the ring.
+//
+// Adjoint: the transpose of that step map, in the variable mu = W lambda, is
+// the same stencil run backwards,
+//   mu^k = W L mu^{k+1} + (2a (mu^{k+1} - mu^{k+2}) + mu^{k+2}) + W R^T r^k,
+// with the residual r^k of recorded levels injected at the receiver nodes of
+// the new level.  Alongside, h += mu^{k+1} (p^{k+1} - 2 p^k + p^{k-1}) for
+// k <= nt-2: the velocity gradient is 2 / (dt^2 v^3) h (the damping terms of
+// the exact derivative cancel because eta does not depend on v).
+template <int K, int NWX, int NWZ, bool ADJ>
+__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs t)
 {
-    constexpr int EX = 64 * NWX, EZ = K * NWZ;
+    constexpr int EX = 64 * NWX, EZ = K * NWZ, NTHR = 64 * NWX * NWZ;
     constexpr int LW = EX + 2 * kHalo;           // LDS row: 4 pad cells each side
     constexpr int LH = EZ + 2 * kHalo;
     __shared__ float lds[2][LH * LW];
@@ -202,8 +214,9 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
     const int lz0 = (w / NWX) * K;               // first local row of this thread
     const int X = ex0 + lx, Z0 = ez0 + lz0;      // padded coordinates
     const bool xin = X >= 0 && X < s.Nx;
+    const bool xout = X >= ox && X < ox_end;     // column inside the output tile
 
-    const float *fbase = s.fields + (int64_t)shot * kFramesPerShot * s.frame;
+    const float *fbase = t.fields + (int64_t)shot * kFramesPerShot * s.frame;
     const float *in_prev = fbase + (int64_t)(2 * t.in_pair) * s.frame;
     const float *in_cur = in_prev + s.frame;
     float *out_prev = (float *)fbase + (int64_t)(2 * t.out_pair) * s.frame;
@@ -211,7 +224,7 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
 
     // ---- zero the LDS pad ring of both buffers (read only by cells whose
     // results are discarded; zero keeps every value finite)
-    for (int q = threadIdx.x; q < 2 * kHalo * (LW + EZ); q += 64 * NWX * NWZ) {
+    for (int q = threadIdx.x; q < 2 * kHalo * (LW + EZ); q += NTHR) {
         int r, c;
         if (q < 2 * kHalo * LW) {              // 4 rows on top, 4 at the bottom
             r = q / LW;
@@ -227,9 +240,10 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
         lds[1][r * LW + c] = 0.f;
     }
 
-    // ---- load levels n-1 (registers) and n (registers + LDS), coefficients.
-    // Cells the scheme does not update (outside the padded grid, the pinned
-    // free-surface row) get a2 = W = 0 and p = 0, so the update keeps them 0.
+    // ---- load the two input levels (registers; the newer one also to LDS)
+    // and the coefficients.  Cells the scheme does not update (outside the
+    // padded grid, the pinned free-surface row) get a2 = W = 0 and value 0,
+    // so the update keeps them 0.
     float cur[K], prev[K], a2[K], W[K];
     const float gxX = xin ? s.gx[X] : 0.f;
 #pragma unroll
@@ -255,42 +269,97 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
         lds[0][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
     }
 
-    // sources of this shot that fall inside the loaded region (uniform test)
+    // forward: sources of this shot inside the loaded region (uniform test);
+    // receivers whose base node is in the output tile
     bool has_src = false;
+    int32_t rbeg = 0, rend = 0;
+    const int32_t *rids = nullptr;
+    if (!ADJ) {
 #pragma unroll
-    for (int j = 0; j < kNodes; ++j) {
-        const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
-        has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
+        for (int j = 0; j < kNodes; ++j) {
+            const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
+            has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
+        }
+        rbeg = s.tile_rec[tile];
+        rend = s.tile_rec[tile + 1];
+        rids = s.tile_rec + (tiles + 1);
     }
-    const int32_t rbeg = s.tile_rec ? s.tile_rec[tile] : 0;
-    const int32_t rend = s.tile_rec ? s.tile_rec[tile + 1] : 0;
-    const int32_t *rids = s.tile_rec + (tiles + 1);
+    // adjoint: receiver nodes in the loaded region; forward levels of the
+    // imaging window (p^{k+1}, p^k), and the partial sums of h
+    int32_t ebeg = 0, eend = 0;
+    float pa[K], pb[K], hp[K];
+    const float *ringb = t.ring ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
+    if (ADJ) {
+        ebeg = t.inj.tile_start[tile];
+        eend = t.inj.tile_start[tile + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int Z = Z0 + k;
+            const bool own = xout && Z >= oz && Z < oz_end;
+            const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+            const int L1 = t.n + 1, L0 = t.n;
+            pa[k] = (own && L1 >= t.ring_lo && L1 <= t.ring_hi) ? ringb[(int64_t)(L1 - t.ring_lo) * s.frame + i] : 0.f;
+            pb[k] = (own && L0 >= t.ring_lo && L0 <= t.ring_hi) ? ringb[(int64_t)(L0 - t.ring_lo) * s.frame + i] : 0.f;
+            hp[k] = 0.f;
+        }
+    }
     __syncthreads();
 
     for (int st = 0; st < t.nsteps; ++st) {
-        const int n = t.n + st;                  // level held in `cur`
+        // forward: `cur` holds level n, the new level is n+1;
+        // adjoint: `cur` holds mu^{n+1}, the new level is mu^n
+        const int n = ADJ ? t.n - st : t.n + st;
         const float *Lc = lds[st & 1];
         float *Ln = lds[(st + 1) & 1];
 
-        // record level n: receivers whose base node is in this output tile
-        if (s.gathers && n % s.rec_every == 0) {
-            float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
-            for (int q = rbeg + (int)threadIdx.x; q < rend; q += 64 * NWX * NWZ) {
-                const int r = rids[q];
-                const int rz = s.rec_iz[r] - ez0 + kHalo, rx = s.rec_ix[r] - ex0 + kHalo;
-                const float *wr = s.rec_w + r * kNodes;
-                row[r] = wr[0] * Lc[rz * LW + rx] + wr[1] * Lc[rz * LW + rx + 1] +
-                         wr[2] * Lc[(rz + 1) * LW + rx] + wr[3] * Lc[(rz + 1) * LW + rx + 1];
+        if (!ADJ) {
+            // record level n: receivers whose base node is in this output tile
+            if (s.gathers && n % s.rec_every == 0) {
+                float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+                for (int q = rbeg + (int)threadIdx.x; q < rend; q += NTHR) {
+                    const int r = rids[q];
+                    const int rz = s.rec_iz[r] - ez0 + kHalo, rx = s.rec_ix[r] - ex0 + kHalo;
+                    const float *wr = s.rec_w + r * kNodes;
+                    row[r] = wr[0] * Lc[rz * LW + rx] + wr[1] * Lc[rz * LW + rx + 1] +
+                             wr[2] * Lc[(rz + 1) * LW + rx] + wr[3] * Lc[(rz + 1) * LW + rx + 1];
+                }
             }
-        }
-        if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count &&
-            X >= max(ox, s.xleft) && X < min(ox_end, s.xleft + s.nx)) {
-            float *fr = s.snaps + ((int64_t)shot * s.snap_count + n / s.snap_every) * s.nz * s.nx;
+            if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count &&
+                X >= max(ox, s.xleft) && X < min(ox_end, s.xleft + s.nx)) {
+                float *fr = s.snaps + ((int64_t)shot * s.snap_count + n / s.snap_every) * s.nz * s.nx;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int Z = Z0 + k;
+                    if (Z >= max(oz, s.ztop) && Z < min(oz_end, s.ztop + s.nz))
+                        fr[(int64_t)(Z - s.ztop) * s.nx + (X - s.xleft)] = cur[k];
+                }
+            }
+        } else if (n <= t.nt - 2) {
+            // imaging term n: h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1}) on the output tile
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int Z = Z0 + k;
-                if (Z >= max(oz, s.ztop) && Z < min(oz_end, s.ztop + s.nz))
-                    fr[(int64_t)(Z - s.ztop) * s.nx + (X - s.xleft)] = cur[k];
+                const bool own = xout && Z >= oz && Z < oz_end;
+                const int Lm = n - 1;
+                const float pc = (own && Lm >= t.ring_lo && Lm <= t.ring_hi)
+                                     ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + (int64_t)(Z + kGuard) * s.pitch + X + kGuard]
+                                     : 0.f;
+                hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
+                pa[k] = pb[k];
+                pb[k] = pc;
+            }
+        } else {
+            // mu^{nt} = 0: no imaging term; shift the window to p^{n}, p^{n-1}
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int Z = Z0 + k;
+                const bool own = xout && Z >= oz && Z < oz_end;
+                const int Lm = n - 1;
+                const float pc = (own && Lm >= t.ring_lo && Lm <= t.ring_hi)
+                                     ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + (int64_t)(Z + kGuard) * s.pitch + X + kGuard]
+                                     : 0.f;
+                pa[k] = pb[k];
+                pb[k] = pc;
             }
         }
 
@@ -301,11 +370,11 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
             up[j] = Lc[(lz0 + j) * LW + lx + kHalo];
             dn[j] = Lc[(lz0 + K + kHalo + j) * LW + lx + kHalo];
         }
-        const float wav = has_src ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
+        const float wav = (!ADJ && has_src) ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
 
-        // Row k needs rows k-4..k+4 of level n; once row k is done, row k-4
-        // of level n is dead and is replaced by its new value (the register
-        // window of new values stays 5 rows deep).
+        // Row k needs rows k-4..k+4 of the current level; once row k is done,
+        // row k-4 is dead and is replaced by its new value (the register window
+        // of new values stays 5 rows deep).
         float nw[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -319,7 +388,7 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
                 lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, rowp[m] + rowp[-m], c2);
             }
             float v = leapfrog(W[k], lap, a2[k], cur[k], prev[k]);
-            if (has_src) {
+            if (!ADJ && has_src) {
                 float amp = 0.f;
 #pragma unroll
                 for (int j = 0; j < kNodes; ++j)
@@ -342,11 +411,42 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
             prev[k] = cur[k];
             cur[k] = nw[k];
         }
+        if (!ADJ && ringb) {
+            // store the new level n+1 of the output tile
+            float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
+            if (xout) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int Z = Z0 + k;
+                    if (Z >= oz && Z < oz_end) rl[(int64_t)(Z + kGuard) * s.pitch + X + kGuard] = cur[k];
+                }
+            }
+        }
+        if (ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0) {
+            // inject W R^T r^n into the new level at the receiver nodes (one
+            // thread per node, so the sum per node is in a fixed order), then
+            // let every thread take its cells back from LDS
+            __syncthreads();
+            const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+            for (int e = ebeg + (int)threadIdx.x; e < eend; e += NTHR) {
+                float acc = 0.f;
+                for (int q = t.inj.pstart[e]; q < t.inj.pstart[e + 1]; ++q) acc += t.inj.w[q] * rrow[t.inj.rid[q]];
+                const int iz = t.inj.iz[e], ix = t.inj.ix[e];
+                const float v2 = s.V2[(int64_t)(iz + kGuard) * s.pitch + ix + kGuard];
+                const float Wc = v2 / (1.f + (s.gx[ix] + s.gz[iz]) * v2);
+                const float add = Wc * acc;
+                Ln[t.inj.lds[e]] += add;
+                if (top_tile && iz >= 1 && iz <= kHalo) Ln[(-iz - ez0 + kHalo) * LW + ix - ex0 + kHalo] -= add;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) cur[k] = Ln[(lz0 + k + kHalo) * LW + lx + kHalo];
+        }
         __syncthreads();
     }
 
-    // ---- write the output tile: levels n+nsteps-1 and n+nsteps
-    if (X >= ox && X < ox_end) {
+    // ---- write the output tile: the last two levels
+    if (xout) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int Z = Z0 + k;
@@ -354,9 +454,53 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_step_tiled(SliceDesc s, Tile
                 const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
                 out_cur[i] = cur[k];
                 out_prev[i] = prev[k];
+                if (ADJ) {
+                    // Kahan-compensated accumulation of this launch's partial sum
+                    float *hs = t.hsum + (int64_t)shot * s.frame;
+                    float *hc = t.hcomp + (int64_t)shot * s.frame;
+                    const float y = hp[k] - hc[i];
+                    const float tt = hs[i] + y;
+                    hc[i] = (tt - hs[i]) - y;
+                    hs[i] = tt;
+                }
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot,
+                                              int64_t n)
+{
+    const int shot = blockIdx.y;
+    float *d = dst + (int64_t)shot * dst_shot;
+    const float *sp = src + (int64_t)shot * src_shot;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = sp[i];
+}
+
+// Gradient on the physical grid: g(iz, ix) = 2 / (dt^2 v^3) * sum over shots
+// and over the padded cells whose velocity is the copy of v(iz, ix) (the
+// transpose of the edge replication into the sponge) of h = hsum - hcomp.
+__global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float *vp, const float *hsum,
+                                                       const float *hcomp, int64_t shot_stride, float dt,
+                                                       float *grad)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= s.nz * s.nx) return;
+    const int iz = q / s.nx, ix = q - iz * s.nx;
+    const int z_lo = iz == 0 ? 0 : iz + s.ztop, z_hi = iz == s.nz - 1 ? s.Nz - 1 : iz + s.ztop;
+    const int x_lo = ix == 0 ? 0 : ix + s.xleft, x_hi = ix == s.nx - 1 ? s.Nx - 1 : ix + s.xleft;
+    double acc = 0.0;
+    for (int sh = 0; sh < s.nshot; ++sh) {
+        const float *hs = hsum + (int64_t)sh * shot_stride, *hc = hcomp + (int64_t)sh * shot_stride;
+        for (int Z = z_lo; Z <= z_hi; ++Z)
+            for (int X = x_lo; X <= x_hi; ++X) {
+                const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+                acc += (double)hs[i] - (double)hc[i];
+            }
+    }
+    const double v = vp[q];
+    grad[q] = (float)(2.0 / ((double)dt * dt * v * v * v) * acc);
 }
 
 __global__ void __launch_bounds__(256) k_count_nonfinite(const float *x, size_t n, unsigned int *count)
@@ -417,6 +561,7 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
     T.ex = ex;
     T.ez = ez;
     T.k = k;
+    T.tb = tb;
     const int halo = kHalo * tb;
     T.tx = ex - 2 * halo;
     T.tz = ez - 2 * halo;
@@ -428,16 +573,45 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
     return T;
 }
 
-hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
+template <bool ADJ>
+static hipError_t launch_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
     const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
     switch (config) {
-    case 0: hipLaunchKernelGGL((k_step_tiled<8, 2, 8>), dim3(blocks), dim3(1024), 0, st, s, t); break;
-    case 1: hipLaunchKernelGGL((k_step_tiled<16, 1, 8>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 2: hipLaunchKernelGGL((k_step_tiled<8, 1, 8>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 3: hipLaunchKernelGGL((k_step_tiled<16, 2, 4>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 0: hipLaunchKernelGGL((k_tiled<8, 2, 8, ADJ>), dim3(blocks), dim3(1024), 0, st, s, t); break;
+    case 1: hipLaunchKernelGGL((k_tiled<16, 1, 8, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 2: hipLaunchKernelGGL((k_tiled<8, 1, 8, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 3: hipLaunchKernelGGL((k_tiled<16, 2, 4, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
+{
+    return launch_tiled<false>(s, t, config, st);
+}
+
+hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
+{
+    return launch_tiled<true>(s, t, config, st);
+}
+
+hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
+                       hipStream_t st)
+{
+    if (n <= 0 || nshot <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks, nshot), dim3(256), 0, st, dst, dst_shot, src, src_shot, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
+                                int64_t shot_stride, float dt, float *grad, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((s.nz * s.nx + 255) / 256);
+    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, hcomp, shot_stride, dt, grad);
     return hipGetLastError();
 }
 

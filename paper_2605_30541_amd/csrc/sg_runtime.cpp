@@ -90,24 +90,42 @@ struct sg_plan {
 namespace {
 
 // Workspace layout of one slice with nshot shots and nrec receivers
-// (byte offsets).  Everything from gx to tile_rec is uploaded from the
-// plan's pinned staging buffer in one copy.
+// (byte offsets).  Everything from gx to tables_end is uploaded from the
+// plan's pinned staging buffer in one copy.  With ckpt > 0 the layout also
+// holds the gradient state: checkpoints (levels jC-1, jC of every shot every
+// C = ckpt levels), the ring of recomputed forward levels of one segment
+// (C + 2 levels), the adjoint field pairs, the Kahan pair of the imaging sum,
+// and the residual-injection tables.
 struct Layout {
-    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec,
-        tables_end, fields, total;
+    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec;
+    size_t inj_tile, inj_lds, inj_iz, inj_ix, inj_pstart, inj_rid, inj_w;
+    size_t tables_end, fields;
+    size_t ckpt, ring, mu, hsum, hcomp, total;
+    int ckpt_every, nseg, ring_levels;
+    int64_t inj_cap;   // capacity (cells and pairs) of the injection tables
 };
 
 // Upper bound on the tiles of one shot over every tiling the plan may use
 // (the smallest output tile is 8 x 8 with a free top).
 int64_t max_tiles(const sg_plan *p) { return ((int64_t)p->Nz / 8 + 2) * ((int64_t)p->Nx / 8 + 2); }
 
-Layout layout_of(const sg_plan *p, int nshot, int nrec)
+// Upper bound on the loaded regions (tiles) one grid node can fall into, over
+// every built tiling: per dimension 1 + 2 ceil(halo / output tile) <= 9.
+constexpr int64_t kMaxTilesPerNode = 81;
+
+int ckpt_spacing(const sg_plan *p, int ckpt_every)
+{
+    return ckpt_every > 0 ? ckpt_every : (int)std::ceil(std::sqrt((double)p->g.nt));
+}
+
+Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
 {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
     const size_t ns = (size_t)nshot * sg::kNodes, nr = (size_t)std::max(nrec, 1);
-    L.v2 = take((size_t)p->frame * sizeof(float));
+    const size_t fr = (size_t)p->frame * sizeof(float);
+    L.v2 = take(fr);
     L.gx = take((size_t)p->Nx * sizeof(float));
     L.gz = take((size_t)p->Nz * sizeof(float));
     L.src_off = take(ns * sizeof(int32_t));
@@ -119,8 +137,29 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec)
     L.rec_ix = take(nr * sizeof(int32_t));
     L.rec_w = take(nr * sg::kNodes * sizeof(float));
     L.tile_rec = take(((size_t)max_tiles(p) + 1 + nr) * sizeof(int32_t));
+    if (ckpt > 0) {
+        L.inj_cap = kMaxTilesPerNode * sg::kNodes * (int64_t)nr;
+        const size_t cap = (size_t)L.inj_cap;
+        L.inj_tile = take(((size_t)max_tiles(p) + 1) * sizeof(int32_t));
+        L.inj_lds = take(cap * sizeof(int32_t));
+        L.inj_iz = take(cap * sizeof(int32_t));
+        L.inj_ix = take(cap * sizeof(int32_t));
+        L.inj_pstart = take((cap + 1) * sizeof(int32_t));
+        L.inj_rid = take(cap * sizeof(int32_t));
+        L.inj_w = take(cap * sizeof(float));
+    }
     L.tables_end = o;
-    L.fields = take((size_t)nshot * sg::kFramesPerShot * p->frame * sizeof(float));
+    L.fields = take((size_t)nshot * sg::kFramesPerShot * fr);
+    if (ckpt > 0) {
+        L.ckpt_every = ckpt;
+        L.nseg = (p->g.nt + ckpt - 1) / ckpt;
+        L.ring_levels = ckpt + 2;
+        L.ckpt = take((size_t)nshot * L.nseg * 2 * fr);
+        L.ring = take((size_t)nshot * L.ring_levels * fr);
+        L.mu = take((size_t)nshot * sg::kFramesPerShot * fr);
+        L.hsum = take((size_t)nshot * fr);
+        L.hcomp = take((size_t)nshot * fr);
+    }
     L.total = o;
     return L;
 }
@@ -340,6 +379,53 @@ sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *s
         int32_t *ids = csr + tiles + 1;
         for (int i = 0; i < sh->nrec; ++i) ids[count[rtile[i]]++] = i;
     }
+    if (T && L.inj_cap > 0) {
+        // adjoint residual injection: receiver nodes inside each tile's loaded
+        // region, grouped by cell in a fixed order
+        const int tiles = T->ntx * T->ntz, LW = T->ex + 2 * sg::kHalo, halo = sg::kHalo * T->tb;
+        const bool free_top = p->g.top == SG_TOP_FREE;
+        std::vector<Nodes> rn(std::max(sh->nrec, 0));
+        for (int i = 0; i < sh->nrec; ++i) bilinear(p, sh->rec_zx[2 * i], sh->rec_zx[2 * i + 1], 1.0, &rn[i]);
+        int32_t *tstart = (int32_t *)at(L.inj_tile), *clds = (int32_t *)at(L.inj_lds);
+        int32_t *ciz = (int32_t *)at(L.inj_iz), *cix = (int32_t *)at(L.inj_ix);
+        int32_t *cps = (int32_t *)at(L.inj_pstart), *prid = (int32_t *)at(L.inj_rid);
+        float *pw = (float *)at(L.inj_w);
+        int64_t ncell = 0, npair = 0;
+        std::vector<std::pair<int64_t, std::pair<int32_t, float>>> hits;
+        for (int tile = 0; tile < tiles; ++tile) {
+            const int tzi = tile / T->ntx, txi = tile % T->ntx;
+            const int ez0 = free_top ? (tzi == 0 ? -T->k : T->tz_top + (tzi - 1) * T->tz - halo) : tzi * T->tz - halo;
+            const int ex0 = txi * T->tx - halo;
+            hits.clear();
+            for (int r = 0; r < sh->nrec; ++r)
+                for (int q = 0; q < sg::kNodes; ++q) {
+                    if (rn[r].w[q] == 0.f) continue;
+                    const int iz = rn[r].iz[q], ix = rn[r].ix[q];
+                    if (iz >= ez0 && iz < ez0 + T->ez && ix >= ex0 && ix < ex0 + T->ex)
+                        hits.push_back({(int64_t)iz * p->Nx + ix, {r, rn[r].w[q]}});
+                }
+            std::stable_sort(hits.begin(), hits.end(),
+                             [](const auto &a, const auto &b) { return a.first < b.first; });
+            tstart[tile] = (int32_t)ncell;
+            for (size_t q = 0; q < hits.size(); ++q) {
+                if (q == 0 || hits[q].first != hits[q - 1].first) {
+                    if (ncell >= L.inj_cap) return fail(SG_EINVAL, "receiver injection tables overflow");
+                    const int iz = (int)(hits[q].first / p->Nx), ix = (int)(hits[q].first % p->Nx);
+                    ciz[ncell] = iz;
+                    cix[ncell] = ix;
+                    clds[ncell] = (iz - ez0 + sg::kHalo) * LW + (ix - ex0 + sg::kHalo);
+                    cps[ncell] = (int32_t)npair;
+                    ++ncell;
+                }
+                if (npair >= L.inj_cap) return fail(SG_EINVAL, "receiver injection tables overflow");
+                prid[npair] = hits[q].second.first;
+                pw[npair] = hits[q].second.second;
+                ++npair;
+            }
+        }
+        tstart[tiles] = (int32_t)ncell;
+        cps[ncell] = (int32_t)npair;
+    }
     SG_HIP(hipMemcpyAsync(ws + L.gx, h, bytes, hipMemcpyHostToDevice, st));
     SG_HIP(hipEventRecord(p->stage_done, st));
     return SG_OK;
@@ -358,40 +444,59 @@ sg_status prof_pair(sg_plan *p, int i, hipEvent_t *a, hipEvent_t *b)
     return SG_OK;
 }
 
-// Runs levels 0 .. nt-1 of every shot: records each level while stepping
-// from it, then records the last level.  With profiling on, one event pair
-// brackets the whole run of time-stepping launches.
-sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
-                      const sg::Tiling &T, hipStream_t st)
+sg::TileArgs tile_args(const sg::Tiling &T, float *fields, int n, int nsteps, int in_pair)
 {
-    const int nt = p->g.nt;
+    sg::TileArgs a{};
+    a.n = n;
+    a.nsteps = nsteps;
+    a.tb = T.tb;
+    a.tx = T.tx;
+    a.tz = T.tz;
+    a.tz_top = T.tz_top;
+    a.ntx = T.ntx;
+    a.ntz = T.ntz;
+    a.in_pair = in_pair;
+    a.out_pair = in_pair ^ 1;
+    a.fields = fields;
+    return a;
+}
+
+// Forward launches from level n0 to level n_end on the field pairs of `s`
+// (`*pair` holds levels n0-1, n0 on entry and n_end-1, n_end on return).
+// Launches end at every multiple of `cut` (if > 0) so the caller can act on
+// those levels through on_cut(level, pair).  With a ring, every new level is
+// also stored there.  With profiling on, one event pair brackets the run.
+template <class OnCut>
+sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config, const sg::Tiling &T,
+                      int n0, int n_end, int cut, int *pair, float *ring, int ring_lo, int64_t ring_shot,
+                      OnCut on_cut, hipStream_t st)
+{
     const int step = t.variant == 1 ? 1 : t.time_block;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    p->prof_used = 0;
     if (p->profiling) {
         sg_status rc = prof_pair(p, 0, &e0, &e1);
         if (rc != SG_OK) return rc;
         SG_HIP(hipEventRecord(e0, st));
     }
-    int pair = 0, launches = 0;
-    for (int n = 0; n < nt - 1; n += step, ++launches) {
-        const int k = std::min(step, nt - 1 - n);
+    int launches = 0;
+    for (int n = n0; n < n_end; ++launches) {
+        int k = std::min(step, n_end - n);
+        if (cut > 0) k = std::min(k, cut - n % cut);
         if (t.variant == 1) {
             SG_HIP(sg::launch_step_naive(s, n, st));
+            *pair = 0;
         } else {
-            sg::TileArgs a{};
-            a.n = n;
-            a.nsteps = k;
-            a.tb = t.time_block;
-            a.tx = T.tx;
-            a.tz = T.tz;
-            a.tz_top = T.tz_top;
-            a.ntx = T.ntx;
-            a.ntz = T.ntz;
-            a.in_pair = pair;
-            a.out_pair = pair ^ 1;
+            sg::TileArgs a = tile_args(T, s.fields, n, k, *pair);
+            a.ring = ring;
+            a.ring_lo = ring_lo;
+            a.ring_shot = ring_shot;
             SG_HIP(sg::launch_step_tiled(s, a, config, st));
-            pair ^= 1;
+            *pair ^= 1;
+        }
+        n += k;
+        if (cut > 0 && n % cut == 0) {
+            sg_status rc = on_cut(n, *pair);
+            if (rc != SG_OK) return rc;
         }
     }
     if (p->profiling) {
@@ -399,8 +504,58 @@ sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
         p->prof_used = 1;
         p->prof_launches = launches;
     }
-    const int last_slot = t.variant == 1 ? (nt - 1) & 1 : 2 * pair + 1;
-    SG_HIP(sg::launch_record_slot(s, nt - 1, last_slot, st));
+    return SG_OK;
+}
+
+// Frame holding level m after forward_run: the one-step kernel keeps level m
+// in frame m & 1; the tiled kernel keeps the newer level in frame 1 of the pair.
+int level_slot(const sg_tuning &t, int m, int pair) { return t.variant == 1 ? (m & 1) : 2 * pair + 1; }
+
+// Runs levels 0 .. nt-1 of every shot: records each level while stepping
+// from it, then records the last level.
+sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
+                      const sg::Tiling &T, hipStream_t st)
+{
+    const int nt = p->g.nt;
+    int pair = 0;
+    p->prof_used = 0;
+    sg_status rc = forward_run(p, s, t, config, T, 0, nt - 1, 0, &pair, nullptr, 0, 0,
+                               [](int, int) { return SG_OK; }, st);
+    if (rc != SG_OK) return rc;
+    SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(t, nt - 1, pair), st));
+    return SG_OK;
+}
+
+// Shared validation and set-up of the calls on one slice.
+struct CallSetup {
+    Layout L;
+    sg_tuning t;
+    int config = -1;
+    sg::Tiling T{};
+};
+
+sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *ws, size_t ws_bytes, int ckpt,
+                     bool need_tiled, CallSetup *c)
+{
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    if (!vp) return fail(SG_EINVAL, "vp is NULL");
+    if (!ws) return fail(SG_EINVAL, "workspace is NULL");
+    sg_status rc = check_shots(p, shots);
+    if (rc != SG_OK) return rc;
+    c->L = layout_of(p, shots->nshot, shots->nrec, ckpt);
+    if (ws_bytes < c->L.total)
+        return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, c->L.total);
+    c->t = resolve_tuning(p, shots->nshot);
+    if (need_tiled && c->t.variant == 1) {   // the gradient path runs on the tiled kernels
+        c->t.variant = 2;
+        c->t.tile_x = c->t.tile_z = c->t.rows_per_thread = 0;
+        c->t.time_block = 0;
+        sg_tuning keep = p->tuning;
+        p->tuning = sg_tuning{};
+        c->t = resolve_tuning(p, shots->nshot);
+        p->tuning = keep;
+    }
+    if (c->t.variant == 2 && (rc = tiling_for(p, c->t, &c->config, &c->T)) != SG_OK) return rc;
     return SG_OK;
 }
 
@@ -586,25 +741,16 @@ sg_status sg_forward_workspace_size(const sg_plan *p, int32_t nshot, int32_t nre
 sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers,
                      float *snaps, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!p) return fail(SG_EINVAL, "plan is NULL");
-    if (!vp) return fail(SG_EINVAL, "vp is NULL");
-    if (!ws) return fail(SG_EINVAL, "workspace is NULL");
-    sg_status rc = check_shots(p, shots);
+    CallSetup c;
+    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, 0, false, &c);
     if (rc != SG_OK) return rc;
-    const Layout L = layout_of(p, shots->nshot, shots->nrec);
-    if (ws_bytes < L.total)
-        return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
-    const sg_tuning t = resolve_tuning(p, shots->nshot);
-    int config = -1;
-    sg::Tiling T{};
-    if (t.variant == 2 && (rc = tiling_for(p, t, &config, &T)) != SG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
-    if ((rc = upload_tables(p, L, w, shots, t.variant == 2 ? &T : nullptr, st)) != SG_OK) return rc;
-    const sg::SliceDesc s = describe(p, L, w, shots, gathers, snaps);
+    if ((rc = upload_tables(p, c.L, w, shots, c.t.variant == 2 ? &c.T : nullptr, st)) != SG_OK) return rc;
+    const sg::SliceDesc s = describe(p, c.L, w, shots, gathers, snaps);
     SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
     SG_HIP(sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st));
-    return run_forward(p, s, t, config, T, st);
+    return run_forward(p, s, c.t, c.config, c.T, st);
 }
 
 sg_status sg_check_finite(const float *x, size_t n, void *ws, size_t ws_bytes, void *stream)
@@ -625,23 +771,114 @@ sg_status sg_check_finite(const float *x, size_t n, void *ws, size_t ws_bytes, v
 sg_status sg_grad_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec, int32_t ckpt_every,
                                  size_t *bytes)
 {
-    (void)p; (void)nshot; (void)nrec; (void)ckpt_every; (void)bytes;
-    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+    if (!p || !bytes) return fail(SG_EINVAL, "NULL argument");
+    if (nshot < 1 || nrec < 0) return fail(SG_EINVAL, "nshot must be >= 1 and nrec >= 0");
+    *bytes = layout_of(p, nshot, nrec, ckpt_spacing(p, ckpt_every)).total;
+    return SG_OK;
 }
 
 sg_status sg_forward_ckpt(sg_plan *p, const float *vp, const sg_shots *shots, int32_t ckpt_every,
                           float *gathers, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)p; (void)vp; (void)shots; (void)ckpt_every; (void)gathers; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    const int C = ckpt_spacing(p, ckpt_every);
+    CallSetup c;
+    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, C, true, &c);
+    if (rc != SG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    if ((rc = upload_tables(p, c.L, w, shots, &c.T, st)) != SG_OK) return rc;
+    sg::SliceDesc s = describe(p, c.L, w, shots, gathers, nullptr);
+    s.snaps = nullptr;
+    SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
+    const int nshot = shots->nshot, nt = p->g.nt;
+    SG_HIP(sg::launch_zero(s.fields, (size_t)nshot * sg::kFramesPerShot * p->frame, st));
+    float *ck = (float *)(w + c.L.ckpt);
+    const int64_t ck_shot = (int64_t)c.L.nseg * 2 * p->frame;
+    // checkpoint 0 holds levels -1 and 0, both zero
+    SG_HIP(sg::launch_copy(ck, ck_shot, s.fields, (int64_t)sg::kFramesPerShot * p->frame, 2 * p->frame, nshot, st));
+    int pair = 0;
+    p->prof_used = 0;
+    auto on_cut = [&](int level, int pr) -> sg_status {
+        const int j = level / C;
+        if (j >= c.L.nseg) return SG_OK;
+        // levels level-1, level are frames 2 pr, 2 pr + 1 of the pair
+        SG_HIP(sg::launch_copy(ck + (int64_t)j * 2 * p->frame, ck_shot, s.fields + (int64_t)(2 * pr) * p->frame,
+                               (int64_t)sg::kFramesPerShot * p->frame, 2 * p->frame, nshot, st));
+        return SG_OK;
+    };
+    rc = forward_run(p, s, c.t, c.config, c.T, 0, nt - 1, C, &pair, nullptr, 0, 0, on_cut, st);
+    if (rc != SG_OK) return rc;
+    SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(c.t, nt - 1, pair), st));
+    return SG_OK;
 }
 
 sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots, int32_t ckpt_every,
                               const float *resid, float *grad, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)p; (void)vp; (void)shots; (void)ckpt_every; (void)resid; (void)grad; (void)ws; (void)ws_bytes;
-    (void)stream;
-    return fail(SG_EUNSUPPORTED, "gradient path not built yet");
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    if (!resid || !grad) return fail(SG_EINVAL, "resid and grad must not be NULL");
+    const int C = ckpt_spacing(p, ckpt_every);
+    CallSetup c;
+    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, C, true, &c);
+    if (rc != SG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    if ((rc = upload_tables(p, c.L, w, shots, &c.T, st)) != SG_OK) return rc;
+    sg::SliceDesc s = describe(p, c.L, w, shots, nullptr, nullptr);
+    SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
+    const int nshot = shots->nshot, nt = p->g.nt;
+    const int64_t F = p->frame, fshot = (int64_t)sg::kFramesPerShot * F;
+    float *ck = (float *)(w + c.L.ckpt), *ring = (float *)(w + c.L.ring), *mu = (float *)(w + c.L.mu);
+    float *hsum = (float *)(w + c.L.hsum), *hcomp = (float *)(w + c.L.hcomp);
+    const int64_t ck_shot = (int64_t)c.L.nseg * 2 * F, ring_shot = (int64_t)c.L.ring_levels * F;
+    SG_HIP(sg::launch_zero(mu, (size_t)nshot * fshot, st));
+    SG_HIP(sg::launch_zero(hsum, (size_t)nshot * F, st));
+    SG_HIP(sg::launch_zero(hcomp, (size_t)nshot * F, st));
+
+    sg::InjTables inj{};
+    inj.tile_start = (const int32_t *)(w + c.L.inj_tile);
+    inj.lds = (const int32_t *)(w + c.L.inj_lds);
+    inj.iz = (const int32_t *)(w + c.L.inj_iz);
+    inj.ix = (const int32_t *)(w + c.L.inj_ix);
+    inj.pstart = (const int32_t *)(w + c.L.inj_pstart);
+    inj.rid = (const int32_t *)(w + c.L.inj_rid);
+    inj.w = (const float *)(w + c.L.inj_w);
+
+    int mpair = 0;   // adjoint pair: frame 0 = mu^{k+2}, frame 1 = mu^{k+1}
+    p->prof_used = 0;
+    for (int j = c.L.nseg - 1; j >= 0; --j) {
+        const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
+        // recompute levels lo-1 .. last into the ring from checkpoint j
+        const float *ckj = ck + (int64_t)j * 2 * F;
+        SG_HIP(sg::launch_copy(s.fields, fshot, ckj, ck_shot, 2 * F, nshot, st));
+        SG_HIP(sg::launch_copy(ring, ring_shot, ckj, ck_shot, 2 * F, nshot, st));
+        int pair = 0;
+        if (last > lo) {
+            rc = forward_run(p, s, c.t, c.config, c.T, lo, last, 0, &pair, ring, lo - 1, ring_shot,
+                             [](int, int) { return SG_OK; }, st);
+            if (rc != SG_OK) return rc;
+        }
+        // adjoint steps k = hi .. lo (mu^k from mu^{k+1}, mu^{k+2}) with imaging
+        for (int k0 = hi; k0 >= lo;) {
+            const int nsteps = std::min(c.t.time_block, k0 - lo + 1);
+            sg::TileArgs a = tile_args(c.T, mu, k0, nsteps, mpair);
+            a.ring = ring;
+            a.ring_lo = lo - 1;
+            a.ring_hi = last;
+            a.ring_shot = ring_shot;
+            a.resid = resid;
+            a.hsum = hsum;
+            a.hcomp = hcomp;
+            a.nt = nt;
+            a.inj = inj;
+            SG_HIP(sg::launch_adjoint_tiled(s, a, c.config, st));
+            mpair ^= 1;
+            k0 -= nsteps;
+        }
+    }
+    SG_HIP(sg::launch_fold_gradient(s, vp, hsum, hcomp, F, (float)p->g.dt, grad, st));
+    return SG_OK;
 }
 
 sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes)

@@ -288,6 +288,25 @@ def sg_forward(plan: Plan, vp, shots: Shots, gathers, snaps, ws, stream=None):
                             _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
 
+def sg_grad_workspace_size(plan: Plan, nshot: int, nrec: int, ckpt_every: int = 0) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sg_grad_workspace_size(plan.handle, nshot, nrec, ckpt_every, ctypes.byref(n)))
+    return n.value
+
+
+def sg_forward_ckpt(plan: Plan, vp, shots: Shots, ckpt_every: int, gathers, ws, stream=None):
+    sh = shots.c()
+    _check(lib().sg_forward_ckpt(plan.handle, _ptr(vp), ctypes.byref(sh), ckpt_every, _ptr(gathers),
+                                 _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def sg_adjoint_gradient(plan: Plan, vp, shots: Shots, ckpt_every: int, resid, grad, ws, stream=None):
+    sh = shots.c()
+    _check(lib().sg_adjoint_gradient(plan.handle, _ptr(vp), ctypes.byref(sh), ckpt_every, _ptr(resid),
+                                     _ptr(grad), _ptr(ws), ws.numel() * ws.element_size(),
+                                     _stream_ptr(stream)))
+
+
 def sg_check_finite(x, ws, stream=None):
     _check(lib().sg_check_finite(_ptr(x), x.numel(), _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))
@@ -318,3 +337,48 @@ def forward(plan: Plan, vp, shots: Shots, want_gathers=True, want_snaps=None, ws
                          device=dev)
     sg_forward(plan, vp, shots, gathers, snaps, ws, stream)
     return gathers, snaps
+
+
+def _autograd():
+    import torch
+
+    class Propagate(torch.autograd.Function):
+        """Shot gathers of every shot as a differentiable function of the
+        velocity: forward = sg_forward_ckpt (checkpoints kept in a workspace on
+        the autograd context), backward = sg_adjoint_gradient with the incoming
+        gradient of the gathers as the residual."""
+
+        @staticmethod
+        def forward(ctx, vp, plan, shots, ckpt_every):
+            g = plan.geom
+            ws = torch.empty(sg_grad_workspace_size(plan, shots.nshot, shots.nrec, ckpt_every),
+                             dtype=torch.uint8, device=vp.device)
+            gathers = torch.empty((shots.nshot, g.nrow, shots.nrec), dtype=torch.float32, device=vp.device)
+            sg_forward_ckpt(plan, vp, shots, ckpt_every, gathers, ws)
+            ctx.save_for_backward(vp)
+            ctx.plan, ctx.shots, ctx.ckpt_every, ctx.ws = plan, shots, ckpt_every, ws
+            return gathers
+
+        @staticmethod
+        def backward(ctx, dgathers):
+            (vp,) = ctx.saved_tensors
+            grad = torch.empty_like(vp)
+            sg_adjoint_gradient(ctx.plan, vp, ctx.shots, ctx.ckpt_every, dgathers.contiguous().float(),
+                                grad, ctx.ws)
+            ctx.ws = None
+            return grad, None, None, None
+
+    return Propagate
+
+
+_PROPAGATE = None
+
+
+def propagate(vp, plan: Plan, shots: Shots, ckpt_every: int = 0):
+    """Differentiable forward modelling: gathers [nshot, nrow, nrec] of the
+    float32 CUDA velocity `vp` [nz, nx]; vp.grad receives dJ/dv by the adjoint
+    state method when a loss of the gathers is back-propagated."""
+    global _PROPAGATE
+    if _PROPAGATE is None:
+        _PROPAGATE = _autograd()
+    return _PROPAGATE.apply(vp, plan, shots, ckpt_every)
