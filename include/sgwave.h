@@ -248,8 +248,22 @@ typedef struct {
 } sg_batch_item;
 
 sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes);
+
+/*
+ * Runs every item as sg_forward would (same outputs), on the tiled kernel
+ * with one tuning for the whole batch (NULL = the first item's plan tuning).
+ * Each time block of the whole batch is one launch over a flattened list of
+ * (item, shot, tile) work; the sequence of launches is captured once into a
+ * hipGraph per (workspace, batch shape) and replayed on later calls, unless
+ * the stream is already being captured by the caller (then the launches go
+ * into the caller's capture).  Items must share nt.
+ */
 sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* Turn the graph replay of sg_batch_forward on (default) or off (plain
+ * stream launches). */
+sg_status sg_set_graphs(int32_t on);
 
 /*
  * Scan `n` device floats for NaN/Inf.  Synchronises the stream; returns

@@ -101,6 +101,15 @@ struct TileArgs {
     InjTables inj;
 };
 
+// One slice of a batched launch: its descriptor, its tiling and field
+// pointers (launch-level fields of `t` are overwritten per launch), and the
+// first logical block it owns.
+struct BatchItem {
+    SliceDesc s;
+    TileArgs t;
+    int32_t block_start;
+};
+
 // Output tiling of the time-blocked kernel for an extended (LDS) tile of
 // ex x ez cells with time block tb and k rows per thread.
 struct Tiling {
@@ -122,6 +131,12 @@ hipError_t launch_zero(float *p, size_t n, hipStream_t st);
 hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);
 hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
 hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
+// Batched launches: items[0..nitems) in device memory, total_blocks = sum of
+// the items' blocks (items[i].block_start is the prefix sum).
+hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                   int in_pair, int config, hipStream_t st);
+hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                      int in_pair, int config, hipStream_t st);
 // dst[shot][0..n) = src[shot][0..n) for every shot (strides in floats)
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
                        hipStream_t st);

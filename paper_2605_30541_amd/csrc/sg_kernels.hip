@@ -181,15 +181,22 @@ __device__ inline int xcd_remap(int b, int nblocks)
 // the new level.  Alongside, h += mu^{k+1} (p^{k+1} - 2 p^k + p^{k-1}) for
 // k <= nt-2: the velocity gradient is 2 / (dt^2 v^3) h (the damping terms of
 // the exact derivative cancel because eta does not depend on v).
-template <int K, int NWX, int NWZ, bool ADJ>
-__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs t)
-{
-    constexpr int EX = 64 * NWX, EZ = K * NWZ, NTHR = 64 * NWX * NWZ;
-    constexpr int LW = EX + 2 * kHalo;           // LDS row: 4 pad cells each side
-    constexpr int LH = EZ + 2 * kHalo;
-    __shared__ float lds[2][LH * LW];
+template <int K, int NWX, int NWZ>
+struct TileShape {
+    static constexpr int EX = 64 * NWX, EZ = K * NWZ, NTHR = 64 * NWX * NWZ;
+    static constexpr int LW = EX + 2 * kHalo;    // LDS row: 4 pad cells each side
+    static constexpr int LH = EZ + 2 * kHalo;
+    static constexpr int LDS = LH * LW;          // floats per LDS buffer
+};
 
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+// Body of the tiled kernel for logical block b of the launch (b enumerates
+// shot-major, then tile rows, then tile columns).
+template <int K, int NWX, int NWZ, bool ADJ>
+__device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t, int b,
+                                           float (*lds)[TileShape<K, NWX, NWZ>::LDS])
+{
+    using TS = TileShape<K, NWX, NWZ>;
+    constexpr int EX = TS::EX, EZ = TS::EZ, NTHR = TS::NTHR, LW = TS::LW;
     const int tiles = t.ntx * t.ntz;
     const int shot = b / tiles;
     const int tile = b - shot * tiles;
@@ -468,6 +475,32 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs 
     }
 }
 
+template <int K, int NWX, int NWZ, bool ADJ>
+__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs t)
+{
+    __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
+    tiled_body<K, NWX, NWZ, ADJ>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// Batched form: one launch covers every (slice, shot, tile) of the batch.
+// Item i owns logical blocks [items[i].block_start, items[i+1].block_start);
+// launch-level fields (levels, pairs) come from the arguments.
+template <int K, int NWX, int NWZ, bool ADJ>
+__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled_batch(const BatchItem *items, int nitems, int n,
+                                                                 int nsteps, int in_pair)
+{
+    __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int it = 0;
+    while (it + 1 < nitems && items[it + 1].block_start <= b) ++it;
+    TileArgs t = items[it].t;
+    t.n = n;
+    t.nsteps = nsteps;
+    t.in_pair = in_pair;
+    t.out_pair = in_pair ^ 1;
+    tiled_body<K, NWX, NWZ, ADJ>(items[it].s, t, b - items[it].block_start, lds);
+}
+
 __global__ void __launch_bounds__(256) k_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot,
                                               int64_t n)
 {
@@ -571,6 +604,33 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
     T.ntx = (Nx + T.tx - 1) / T.tx;
     T.ntz = free_top ? 1 + (Nz > T.tz_top ? (Nz - T.tz_top + T.tz - 1) / T.tz : 0) : (Nz + T.tz - 1) / T.tz;
     return T;
+}
+
+template <bool ADJ>
+static hipError_t launch_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                     int in_pair, int config, hipStream_t st)
+{
+    const dim3 g((unsigned)total_blocks);
+    switch (config) {
+    case 0: hipLaunchKernelGGL((k_tiled_batch<8, 2, 8, ADJ>), g, dim3(1024), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 1: hipLaunchKernelGGL((k_tiled_batch<16, 1, 8, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 2: hipLaunchKernelGGL((k_tiled_batch<8, 1, 8, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 3: hipLaunchKernelGGL((k_tiled_batch<16, 2, 4, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                   int in_pair, int config, hipStream_t st)
+{
+    return launch_tiled_batch<false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
+}
+
+hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                      int in_pair, int config, hipStream_t st)
+{
+    return launch_tiled_batch<true>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
 }
 
 template <bool ADJ>

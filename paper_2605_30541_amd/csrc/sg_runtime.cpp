@@ -559,6 +559,107 @@ sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *w
     return SG_OK;
 }
 
+// Small pinned staging area for per-call device headers (batch item
+// tables); reused only after the previous copy out of it has completed.
+struct Stage {
+    std::mutex mu;
+    void *buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+Stage g_stage;
+
+sg_status stage_upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lock(g_stage.mu);
+    if (g_stage.done) SG_HIP(hipEventSynchronize(g_stage.done));
+    if (g_stage.bytes < bytes) {
+        if (g_stage.buf) SG_HIP(hipHostFree(g_stage.buf));
+        g_stage.buf = nullptr;
+        g_stage.bytes = 0;
+        SG_HIP(hipHostMalloc(&g_stage.buf, bytes, hipHostMallocDefault));
+        g_stage.bytes = bytes;
+    }
+    if (!g_stage.done) SG_HIP(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
+    std::memcpy(g_stage.buf, src, bytes);
+    SG_HIP(hipMemcpyAsync(dst, g_stage.buf, bytes, hipMemcpyHostToDevice, st));
+    SG_HIP(hipEventRecord(g_stage.done, st));
+    return SG_OK;
+}
+
+// Instantiated graphs of batched time stepping, keyed by everything their
+// kernel arguments depend on.
+bool g_batch_graphs = true;
+
+struct GraphKey {
+    uintptr_t ws;
+    int nitems, blocks, nt, tb, config;
+    uint64_t sig;
+    bool operator==(const GraphKey &o) const
+    {
+        return ws == o.ws && nitems == o.nitems && blocks == o.blocks && nt == o.nt && tb == o.tb &&
+               config == o.config && sig == o.sig;
+    }
+};
+
+// FNV-1a over the device pointers and sizes the record kernels receive by value.
+uint64_t items_signature(const std::vector<sg::BatchItem> &hb)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    for (const auto &b : hb) mix(&b.s, sizeof(b.s));
+    return h;
+}
+
+struct GraphCache {
+    std::mutex mu;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> entries;   // most recent last
+    hipStream_t capture = nullptr;   // private stream used only to record graphs
+};
+GraphCache g_graphs;
+constexpr size_t kGraphCacheSize = 8;
+
+template <class Enqueue>
+sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hipGraphExec_t *out)
+{
+    std::lock_guard<std::mutex> lock(g_graphs.mu);
+    for (size_t i = 0; i < g_graphs.entries.size(); ++i)
+        if (g_graphs.entries[i].first == key) {
+            auto e = g_graphs.entries[i];
+            g_graphs.entries.erase(g_graphs.entries.begin() + i);
+            g_graphs.entries.push_back(e);
+            *out = e.second;
+            return SG_OK;
+        }
+    // record on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is launched on `st`
+    (void)st;
+    if (!g_graphs.capture) SG_HIP(hipStreamCreateWithFlags(&g_graphs.capture, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    SG_HIP(hipStreamBeginCapture(g_graphs.capture, hipStreamCaptureModeThreadLocal));
+    sg_status rc = enqueue(g_graphs.capture);
+    hipError_t e2 = hipStreamEndCapture(g_graphs.capture, &graph);
+    if (rc != SG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e2 != hipSuccess) return fail(SG_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(SG_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+    if (g_graphs.entries.size() >= kGraphCacheSize) {
+        (void)hipGraphExecDestroy(g_graphs.entries.front().second);
+        g_graphs.entries.erase(g_graphs.entries.begin());
+    }
+    g_graphs.entries.push_back({key, exec});
+    *out = exec;
+    return SG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -883,15 +984,98 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
 
 sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes)
 {
-    (void)items; (void)nitems; (void)bytes;
-    return fail(SG_EUNSUPPORTED, "batched path not built yet");
+    if (!items || !bytes || nitems < 1) return fail(SG_EINVAL, "bad batch arguments");
+    size_t total = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (!items[i].plan || !items[i].shots) return fail(SG_EINVAL, "batch item %d has no plan or shots", i);
+        total += align_up(layout_of(items[i].plan, items[i].shots->nshot, items[i].shots->nrec).total, 256);
+    }
+    total += align_up((size_t)nitems * sizeof(sg::BatchItem), 256);
+    *bytes = total;
+    return SG_OK;
 }
 
 sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning, void *ws,
                            size_t ws_bytes, void *stream)
 {
-    (void)items; (void)nitems; (void)tuning; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(SG_EUNSUPPORTED, "batched path not built yet");
+    size_t need = 0;
+    sg_status rc = sg_batch_workspace_size(items, nitems, &need);
+    if (rc != SG_OK) return rc;
+    if (!ws) return fail(SG_EINVAL, "workspace is NULL");
+    if (ws_bytes < need) return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    const int nt = items[0].plan->g.nt;
+    for (int i = 1; i < nitems; ++i)
+        if (items[i].plan->g.nt != nt) return fail(SG_EINVAL, "batch items must share nt (%d vs %d)", items[i].plan->g.nt, nt);
+    sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot);
+    if (t.variant == 0) t = resolve_tuning(items[0].plan, items[0].shots->nshot);
+    if (t.variant != 2) return fail(SG_EUNSUPPORTED, "batched launches use the tiled kernel (variant 2)");
+    if (t.time_block <= 0) t.time_block = 4;
+    // validate everything before enqueueing anything
+    std::vector<CallSetup> cs(nitems);
+    std::vector<size_t> base(nitems);
+    size_t o = 0;
+    int64_t total_blocks = 0;
+    for (int i = 0; i < nitems; ++i) {
+        const sg_batch_item &it = items[i];
+        base[i] = o;
+        o += align_up(layout_of(it.plan, it.shots->nshot, it.shots->nrec).total, 256);
+        if (!it.vp) return fail(SG_EINVAL, "batch item %d: vp is NULL", i);
+        if ((rc = check_shots(it.plan, it.shots)) != SG_OK) return rc;
+        cs[i].L = layout_of(it.plan, it.shots->nshot, it.shots->nrec);
+        cs[i].t = t;
+        if ((rc = tiling_for(it.plan, t, &cs[i].config, &cs[i].T)) != SG_OK) return rc;
+        total_blocks += (int64_t)cs[i].T.ntx * cs[i].T.ntz * it.shots->nshot;
+    }
+    if (total_blocks >= ((int64_t)1 << 31)) return fail(SG_EINVAL, "batch too large");
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    std::vector<sg::BatchItem> hb(nitems);
+    int32_t start = 0;
+    for (int i = 0; i < nitems; ++i) {
+        const sg_batch_item &it = items[i];
+        char *wi = w + base[i];
+        if ((rc = upload_tables(it.plan, cs[i].L, wi, it.shots, &cs[i].T, st)) != SG_OK) return rc;
+        hb[i].s = describe(it.plan, cs[i].L, wi, it.shots, it.gathers, it.snaps);
+        SG_HIP(sg::launch_prepare(hb[i].s, it.vp, (float)(it.plan->g.dt * it.plan->g.dt), st));
+        SG_HIP(sg::launch_zero(hb[i].s.fields, (size_t)it.shots->nshot * sg::kFramesPerShot * it.plan->frame, st));
+        hb[i].t = tile_args(cs[i].T, hb[i].s.fields, 0, 0, 0);
+        hb[i].block_start = start;
+        start += cs[i].T.ntx * cs[i].T.ntz * it.shots->nshot;
+    }
+    sg::BatchItem *dev_items = (sg::BatchItem *)(w + o);
+    if ((rc = stage_upload(dev_items, hb.data(), hb.size() * sizeof(sg::BatchItem), st)) != SG_OK) return rc;
+
+    // the time-stepping launches (one per time block over the whole batch),
+    // replayed from a captured graph unless the caller is capturing already
+    const int config = cs[0].config, tb = t.time_block;
+    auto enqueue = [&](hipStream_t s2) -> sg_status {
+        int pair = 0;
+        for (int n = 0; n < nt - 1;) {
+            const int k = std::min(tb, nt - 1 - n);
+            SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, s2));
+            pair ^= 1;
+            n += k;
+        }
+        for (int i = 0; i < nitems; ++i)
+            SG_HIP(sg::launch_record_slot(hb[i].s, nt - 1, 2 * pair + 1, s2));
+        return SG_OK;
+    };
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SG_HIP(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
+    // per-item launch arguments never change for the same workspace and batch
+    // shape, so one instantiated graph per such key is replayed
+    GraphKey key{(uintptr_t)ws, nitems, (int)total_blocks, nt, tb, config, items_signature(hb)};
+    hipGraphExec_t exec = nullptr;
+    if ((rc = graph_lookup(key, st, enqueue, &exec)) != SG_OK) return rc;
+    SG_HIP(hipGraphLaunch(exec, st));
+    return SG_OK;
+}
+
+sg_status sg_set_graphs(int32_t on)
+{
+    g_batch_graphs = on != 0;
+    return SG_OK;
 }
 
 }  // extern "C"

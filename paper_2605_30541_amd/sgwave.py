@@ -104,6 +104,7 @@ _SIGS = {
                                           ctypes.c_void_p]),
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
 }
 
 
@@ -307,6 +308,40 @@ def sg_adjoint_gradient(plan: Plan, vp, shots: Shots, ckpt_every: int, resid, gr
                                      _stream_ptr(stream)))
 
 
+def _batch_items(items):
+    """items: list of (plan, vp, shots, gathers, snaps) -> ctypes array (and keep-alive list)."""
+    keep = []
+    arr = (sg_batch_item * len(items))()
+    for i, (plan, vp, shots, gathers, snaps) in enumerate(items):
+        sh = shots.c()
+        keep.append(sh)
+        arr[i] = sg_batch_item(plan.handle, vp.data_ptr(), ctypes.pointer(sh),
+                               gathers.data_ptr() if gathers is not None else None,
+                               snaps.data_ptr() if snaps is not None else None)
+    return arr, keep
+
+
+def sg_batch_workspace_size(items) -> int:
+    arr, keep = _batch_items(items)
+    n = ctypes.c_size_t()
+    _check(lib().sg_batch_workspace_size(arr, len(items), ctypes.byref(n)))
+    return n.value
+
+
+def sg_batch_forward(items, ws, tuning=None, stream=None):
+    arr, keep = _batch_items(items)
+    t = None
+    if tuning is not None:
+        t = ctypes.byref(sg_tuning(tuning.get("variant", 2), tuning.get("tile_x", 0), tuning.get("tile_z", 0),
+                                   tuning.get("time_block", 0), tuning.get("rows_per_thread", 0)))
+    _check(lib().sg_batch_forward(arr, len(items), t, _ptr(ws), ws.numel() * ws.element_size(),
+                                  _stream_ptr(stream)))
+
+
+def sg_set_graphs(on: bool):
+    _check(lib().sg_set_graphs(1 if on else 0))
+
+
 def sg_check_finite(x, ws, stream=None):
     _check(lib().sg_check_finite(_ptr(x), x.numel(), _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))
@@ -318,6 +353,24 @@ def ricker_tensor(f0: float, dt: float, nt: int, device="cuda"):
     """Ricker wavelet from sg_ricker as a [1, nt] float32 tensor."""
     import torch
     return torch.from_numpy(sg_ricker(f0, dt, nt)).reshape(1, nt).to(device)
+
+
+def batch_forward(items, tuning=None, ws=None, stream=None):
+    """items: list of (plan, vp, shots).  Allocates gathers (and snapshots
+    when the plan asks for them) per item and runs sg_batch_forward; returns
+    [(gathers, snaps), ...]."""
+    import torch
+    full = []
+    for plan, vp, shots in items:
+        g = plan.geom
+        gathers = torch.empty((shots.nshot, g.nrow, shots.nrec), dtype=torch.float32, device=vp.device)
+        snaps = torch.empty((shots.nshot, g.snap_count, g.nz, g.nx), dtype=torch.float32, device=vp.device) \
+            if g.snap_count > 0 else None
+        full.append((plan, vp, shots, gathers, snaps))
+    if ws is None:
+        ws = torch.empty(sg_batch_workspace_size(full), dtype=torch.uint8, device=full[0][1].device)
+    sg_batch_forward(full, ws, tuning, stream)
+    return [(f[3], f[4]) for f in full]
 
 
 def forward(plan: Plan, vp, shots: Shots, want_gathers=True, want_snaps=None, ws=None, stream=None):
