@@ -10,7 +10,9 @@ resident in HBM before the timed region.
 Prints one JSON line: grid-point updates per second over the padded grid
 (660 x 1081 points x 9999 updates per step), the HBM-roofline position of the
 time-stepping kernel, and the FP64 oracle timed on a bounded sample on the
-host cores.
+host cores.  Beside it, on the same GPU: the forward + adjoint-gradient rate
+(16 shots on the same slice, checkpoints every 100 levels) and the batched
+rate (8 slices of uneven size x 64 shots in one launch per time block).
 """
 import argparse
 import hashlib
@@ -38,6 +40,9 @@ def parse():
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-levels", type=int, default=10000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the gradient and batched comparisons")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -79,6 +84,82 @@ def cpu_baseline(v, geom, src, rec, f0, levels):
                       "%d of 10000 levels (%.1f s wall)" % (levels, sec)}
 
 
+def gradient_rate(v, fwd_rate):
+    """Forward with checkpoints + adjoint gradient: 16 shots on the field
+    slice (1D-smoothed start model), checkpoints every 100 levels."""
+    import numpy as np
+    import torch
+    from paper_2605_30541_amd import sgwave, synth
+    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
+    nz, nx, h, dt, nt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 10000, 16, 100
+    geom = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
+    plan = Plan(geom)
+    v0 = torch.from_numpy(synth.smoothed_1d(v, 500.0, h)).cuda()
+    shots = Shots(synth.shot_line(nshot, 1100.0, 8900.0), synth.surface_receivers(nx, h),
+                  sgwave.ricker_tensor(12.0, dt, nt))
+    ws = torch.empty(sgwave.sg_grad_workspace_size(plan, nshot, nx, ckpt), dtype=torch.uint8, device="cuda")
+    gathers = torch.empty((nshot, geom.nrow, nx), dtype=torch.float32, device="cuda")
+    resid = torch.randn((nshot, geom.nrow, nx), dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(v0)
+
+    def run():
+        sgwave.sg_forward_ckpt(plan, v0, shots, ckpt, gathers, ws)
+        sgwave.sg_adjoint_gradient(plan, v0, shots, ckpt, resid, grad, ws)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    Nz, Nx = plan.padded_shape
+    rate = Nz * Nx * (nt - 1) * nshot / (ms / 1e3) / 1e9
+    sgwave.sg_check_finite(grad, ws)
+    return {"workload": "forward with checkpoints + adjoint-state gradient, 16 shots on the 620x1001 "
+                        "slice, nt 10000, checkpoints every 100 levels (segment recompute)",
+            "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
+            "ratio_to_forward_value": rate / fwd_rate}
+
+
+def batched_rate(fwd_rate):
+    """8 field slices of uneven size (nz 400-620, nx 601-1001) x 64 shots,
+    nt 10000 at 0.8 ms, receivers on every column, one launch per time block."""
+    import numpy as np
+    import torch
+    from paper_2605_30541_amd import sgwave, synth
+    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
+    dt, nt = 8e-4, 10000
+    items, points = [], 0
+    for i, (nz, nx) in enumerate(synth.uneven_sizes(42, 8)):
+        geom = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
+        plan = Plan(geom)
+        W = (nx - 1) * 10.0
+        shots = Shots(synth.shot_line(64, 1100.0, W - 1100.0), synth.surface_receivers(nx, 10.0),
+                      sgwave.ricker_tensor(12.0, dt, nt))
+        items.append((plan, torch.from_numpy(synth.field_slice(42 + i, nz, nx)).cuda(), shots))
+        Nz, Nx = plan.padded_shape
+        points += Nz * Nx * 64
+    full = [(p_, v_, s_, torch.empty((64, p_.geom.nrow, s_.nrec), dtype=torch.float32, device="cuda"), None)
+            for p_, v_, s_ in items]
+    ws = torch.empty(sgwave.sg_batch_workspace_size(full), dtype=torch.uint8, device="cuda")
+    sgwave.sg_batch_forward(full, ws)          # warm-up: captures and instantiates the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sgwave.sg_batch_forward(full, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rate = points * (nt - 1) / (ms / 1e3) / 1e9
+    launches = -(-(nt - 1) // items[0][0].get_tuning(64)["time_block"])
+    achieved = BYTES_PER_UPDATE * points * (nt - 1) / (ms / 1e3) / 1e9
+    return {"workload": "8 uneven field slices (nz 400-620, nx 601-1001, 40-cell sponge) x 64 shots, "
+                        "nt 10000, 1 launch per time block, graph replay",
+            "ms": ms, "value": rate, "unit": "Gpt-updates/s", "ratio_to_forward_value": rate / fwd_rate,
+            "launches": launches, "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,16 +181,18 @@ def main():
     src = np.array([[10.0, 5000.0]])
     rec = synth.surface_receivers(nx, h)
     plan = Plan(geom)
-    if args.variant is not None:
-        plan.set_tuning(variant=args.variant, tile_x=args.tile_x, tile_z=args.tile_z,
-                        time_block=args.time_block, rows_per_thread=args.rows_per_thread)
-    tuning = plan.get_tuning(1)
     vp = torch.from_numpy(v).cuda()
     shots = Shots(src, rec, sgwave.ricker_tensor(f0, dt, nt))
     gathers = torch.empty((1, geom.nrow, nx), dtype=torch.float32, device="cuda")
     snaps = torch.empty((1, geom.snap_count, nz, nx), dtype=torch.float32, device="cuda")
     ws = torch.empty(sgwave.sg_forward_workspace_size(plan, 1, nx), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    if args.variant is not None:
+        plan.set_tuning(variant=args.variant, tile_x=args.tile_x, tile_z=args.tile_z,
+                        time_block=args.time_block, rows_per_thread=args.rows_per_thread)
+    elif not args.no_autotune:
+        sgwave.sg_autotune(plan, vp, shots, 64, ws, stream)     # untimed, part of warm-up
+    tuning = plan.get_tuning(1)
 
     def step():
         sgwave.sg_forward(plan, vp, shots, gathers, snaps, ws, stream)
@@ -166,6 +249,9 @@ def main():
                      "bytes_per_update": BYTES_PER_UPDATE},
         "cpu_baseline": None,
     }
+    if not args.no_extras:
+        out["gradient"] = gradient_rate(v, value)
+        out["batched"] = batched_rate(value)
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -176,6 +176,16 @@ sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t);
 sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t);
 
 /*
+ * Autotuner: times every built tile shape with every admissible time block
+ * (1..8) on this call's real shape -- trial_levels (>= 8) levels of the
+ * time-stepping launches for `shots` on `vp`, after one untimed pass -- and
+ * keeps the fastest as the plan's tuning (also returned in *best).  Uses the
+ * workspace of sg_forward (no outputs are written).  Synchronises the stream.
+ */
+sg_status sg_autotune(sg_plan *p, const float *vp, const sg_shots *shots, int32_t trial_levels, void *ws,
+                      size_t ws_bytes, void *stream, sg_tuning *best);
+
+/*
  * Kernel timing of the time-stepping launches.  With profiling on, later
  * calls on this plan bracket their back-to-back run of time-stepping
  * launches with a pair of HIP events on the call's stream; sg_plan_profile

@@ -50,11 +50,21 @@ struct SliceDesc {
     const int32_t *rec_iz;   // [nrec] padded row of the base node (weights in rec_w
     const int32_t *rec_ix;   // [nrec]   for (0,0), (0,1), (1,0), (1,1))
     const float *rec_w;      // [nrec][kNodes], 0 = unused
-    const int32_t *tile_rec; // tiled path: [tiles + 1] CSR start per tile, then receiver ids
+    const int32_t *tile_rec; // tiled path: [tiles + 1] start of each tile's entries in rec_list
+    const struct RecEntry *rec_list;   // tiled path: receivers grouped by tile
     const float *wavelet;    // [nshot or 1][nt]
     float *fields;           // [nshot][kFramesPerShot][frame]
     float *gathers;          // [nshot][nrow][nrec] or null
     float *snaps;            // [nshot][snap_count][nz][nx] or null
+};
+
+// A receiver as the tiled kernel reads it: LDS index of its base node within
+// the owning tile's buffer (nodes at +0, +1, +LW, +LW+1), its output column
+// and the bilinear weights of those nodes.
+struct RecEntry {
+    int32_t lds;
+    int32_t r;
+    float w[kNodes];
 };
 
 // Each shot owns two pairs of fields.  The one-step kernel keeps level m in
@@ -134,7 +144,7 @@ hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int confi
 // Batched launches: items[0..nitems) in device memory, total_blocks = sum of
 // the items' blocks (items[i].block_start is the prefix sum).
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                   int in_pair, int config, hipStream_t st);
+                                   int in_pair, int config, bool iso, hipStream_t st);
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                       int in_pair, int config, hipStream_t st);
 // dst[shot][0..n) = src[shot][0..n) for every shot (strides in floats)
@@ -144,7 +154,9 @@ hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t s
 // velocity is copied from (iz, ix) of (hsum - hcomp)
 hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
                                 int64_t shot_stride, float dt, float *grad, hipStream_t st);
-hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st);
+// Records level n held in frame `slot` of every shot: gather row (what & 1)
+// and snapshot (what & 2) when that level is due for them.
+hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st, int what = 3);
 hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st);
 
 }  // namespace sg

@@ -115,14 +115,17 @@ __global__ void __launch_bounds__(256) k_step_naive(SliceDesc s, int n)
     if (s.free_top && Iz == 0) return;             // p = 0 on the free surface
 
     const int64_t i = (int64_t)(Iz + kGuard) * s.pitch + Ix + kGuard;
-    const float c = cur[i], c2 = c + c;
+    const float c = cur[i], c2 = c + c, c4 = -4.f * c;
+    const bool iso = s.cz[1] == s.cx[1] && s.cz[2] == s.cx[2] && s.cz[3] == s.cx[3] && s.cz[4] == s.cx[4];
     float lap = 0.f;
 #pragma unroll
     for (int m = 1; m <= kHalo; ++m) {
         // above row 0 of a free top: odd mirror, p(Iz - m) = -p(m - Iz)
         const float up = (s.free_top && Iz - m < 0) ? -cur[i + (int64_t)(m - 2 * Iz) * s.pitch]
                                                     : cur[i - (int64_t)m * s.pitch];
-        lap = lap_pair(lap, s.cz[m], s.cx[m], cur[i + (int64_t)m * s.pitch] + up, cur[i + m] + cur[i - m], c2);
+        const float zs = cur[i + (int64_t)m * s.pitch] + up, xs = cur[i + m] + cur[i - m];
+        // same expression as the tiled kernel: one weight per m when dz == dx
+        lap = iso ? fmaf(s.cz[m], (zs + xs) + c4, lap) : lap_pair(lap, s.cz[m], s.cx[m], zs, xs, c2);
     }
     float amp = 0.f;
 #pragma unroll
@@ -138,10 +141,14 @@ __global__ void __launch_bounds__(256) k_step_naive(SliceDesc s, int n)
     nxt[i] = v;
 }
 
-__global__ void __launch_bounds__(256) k_record(SliceDesc s, int n, int slot)
+// Records level n held in frame `slot` of every shot: the gather row when
+// (what & 1), the snapshot when (what & 2), each only if that level is due.
+__global__ void __launch_bounds__(256) k_record(SliceDesc s, int n, int slot, int what)
 {
     const int shot = blockIdx.y;
     const float *cur = s.fields + ((int64_t)shot * kFramesPerShot + slot) * s.frame;
+    if (!(what & 1)) s.gathers = nullptr;
+    if (!(what & 2)) s.snaps = nullptr;
     record_level(s, cur, shot, n, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
 }
 
@@ -155,32 +162,6 @@ __device__ inline int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
-// Time-blocked step (overlapped tiling), forward (ADJ = false) or adjoint
-// (ADJ = true).  One workgroup advances one tile of one shot by t.nsteps
-// levels.  It loads the tile plus a halo of 4*tb cells (two levels) once,
-// runs the sub-steps out of LDS, and writes the output tile (the last two
-// levels) to the other field pair.  Validity shrinks by 4 cells per sub-step
-// from the edges of the loaded region that are not edges of the padded grid,
-// so after tb sub-steps the output tile is exact.  Cells outside the padded
-// grid are held at 0.  Under a free top the top tile row loads k ghost rows
-// above row 0 and keeps rows -1..-4 equal to minus rows 1..4.
-//
-// Threads: 64 lanes across x (one wave covers 64 adjacent columns), waves
-// stacked as NWX x NWZ; each thread owns one column and K consecutive rows,
-// whose values stay in registers (z neighbours inside the column come from
-// registers, only the 4 rows above and below and the x neighbours from LDS).
-//
-// Forward: p^{n+1} = W L p^n + (2a (p^n - p^{n-1}) + p^{n-1}) + W S^n, with the
-// point sources S^n fused, receivers sampled from the tile's receiver list,
-// snapshots and (optionally) every new level stored to the ring.
-//
-// Adjoint: the transpose of that step map, in the variable mu = W lambda, is
-// the same stencil run backwards,
-//   mu^k = W L mu^{k+1} + (2a (mu^{k+1} - mu^{k+2}) + mu^{k+2}) + W R^T r^k,
-// with the residual r^k of recorded levels injected at the receiver nodes of
-// the new level.  Alongside, h += mu^{k+1} (p^{k+1} - 2 p^k + p^{k-1}) for
-// k <= nt-2: the velocity gradient is 2 / (dt^2 v^3) h (the damping terms of
-// the exact derivative cancel because eta does not depend on v).
 template <int K, int NWX, int NWZ>
 struct TileShape {
     static constexpr int EX = 64 * NWX, EZ = K * NWZ, NTHR = 64 * NWX * NWZ;
@@ -189,14 +170,42 @@ struct TileShape {
     static constexpr int LDS = LH * LW;          // floats per LDS buffer
 };
 
-// Body of the tiled kernel for logical block b of the launch (b enumerates
-// shot-major, then tile rows, then tile columns).
-template <int K, int NWX, int NWZ, bool ADJ>
+// Time-blocked step (overlapped tiling).  One workgroup advances one tile of
+// one shot by t.nsteps levels.  It loads the tile plus a halo of 4*tb cells
+// (two levels) once, runs the sub-steps out of LDS, and writes the output tile
+// (the last two levels) to the other field pair.  The level computed by
+// sub-step s (1-based) is only needed on the loaded region shrunk by 4 s cells
+// at every edge that is not a grid edge, so after tb sub-steps the output tile
+// is exact; waves whose rows have all left that region stop computing.  Cells
+// outside the padded grid are held at 0.  Under a free top the top tile row
+// loads k ghost rows above row 0 and keeps rows -1..-4 equal to minus rows 1..4.
+//
+// Threads: 64 lanes across x (one wave covers 64 adjacent columns), waves
+// stacked as NWX x NWZ; each thread owns one column and K consecutive rows,
+// whose values stay in registers (z neighbours inside the column come from
+// registers, only the 4 rows above and below and the x neighbours from LDS).
+//
+// MODE kFwd:  p^{n+1} = W L p^n + (2a (p^n - p^{n-1}) + p^{n-1}) + W S^n, with the
+//             point sources S^n fused and the receivers of the tile sampled.
+// MODE kRing: the same, also storing every new level of the output tile in the
+//             ring (the forward recompute of the gradient; no receivers).
+// MODE kAdj:  the transpose of that step map in the variable mu = W lambda,
+//             the same stencil run backwards,
+//               mu^k = W L mu^{k+1} + (2a (mu^{k+1} - mu^{k+2}) + mu^{k+2}) + W R^T r^k,
+//             with the residual r^k of recorded levels injected at the receiver
+//             nodes of the new level; alongside h += mu^{k+1} (p^{k+1} - 2 p^k + p^{k-1})
+//             for k <= nt-2 (the velocity gradient is 2 / (dt^2 v^3) h: the
+//             damping terms of the exact derivative cancel because eta does not
+//             depend on v).
+enum { kFwd = 0, kRing = 1, kAdj = 2 };
+
+template <int K, int NWX, int NWZ, int MODE, bool ISO>
 __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t, int b,
                                            float (*lds)[TileShape<K, NWX, NWZ>::LDS])
 {
     using TS = TileShape<K, NWX, NWZ>;
     constexpr int EX = TS::EX, EZ = TS::EZ, NTHR = TS::NTHR, LW = TS::LW;
+    constexpr bool ADJ = MODE == kAdj;
     const int tiles = t.ntx * t.ntz;
     const int shot = b / tiles;
     const int tile = b - shot * tiles;
@@ -218,16 +227,25 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lx = (w % NWX) * 64 + lane;        // local column in [0, EX)
-    const int lz0 = (w / NWX) * K;               // first local row of this thread
+    const int lz0 = (w / NWX) * K;               // first local row of this thread (wave-uniform)
     const int X = ex0 + lx, Z0 = ez0 + lz0;      // padded coordinates
     const bool xin = X >= 0 && X < s.Nx;
     const bool xout = X >= ox && X < ox_end;     // column inside the output tile
+    // rows [k_lo, k_hi) of this thread's segment are output rows (wave-uniform)
+    const int k_lo = __builtin_amdgcn_readfirstlane(min(max(oz - Z0, 0), K));
+    const int k_hi = __builtin_amdgcn_readfirstlane(min(max(oz_end - Z0, 0), K));
+    // segment entirely outside the grid rows, or the ghost segment of a top tile
+    const int wave_x0 = ex0 + (w % NWX) * 64;
+    const bool seg_dead = Z0 >= s.Nz || Z0 + K <= 0 || wave_x0 >= s.Nx || wave_x0 + 64 <= 0;
+    const bool wr_ok = !(top_tile && Z0 < 0);    // ghost rows are written by the mirror only
+    const bool ghost_writer = top_tile && Z0 <= kHalo && Z0 + K > 1;
 
-    const float *fbase = t.fields + (int64_t)shot * kFramesPerShot * s.frame;
-    const float *in_prev = fbase + (int64_t)(2 * t.in_pair) * s.frame;
+    const int64_t fshot = (int64_t)shot * kFramesPerShot * s.frame;
+    const float *in_prev = t.fields + fshot + (int64_t)(2 * t.in_pair) * s.frame;
     const float *in_cur = in_prev + s.frame;
-    float *out_prev = (float *)fbase + (int64_t)(2 * t.out_pair) * s.frame;
+    float *out_prev = t.fields + fshot + (int64_t)(2 * t.out_pair) * s.frame;
     float *out_cur = out_prev + s.frame;
+    const int64_t col = (int64_t)(Z0 + kGuard) * s.pitch + X + kGuard;   // stored index of row k = 0
 
     // ---- zero the LDS pad ring of both buffers (read only by cells whose
     // results are discarded; zero keeps every value finite)
@@ -247,10 +265,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         lds[1][r * LW + c] = 0.f;
     }
 
-    // ---- load the two input levels (registers; the newer one also to LDS)
-    // and the coefficients.  Cells the scheme does not update (outside the
-    // padded grid, the pinned free-surface row) get a2 = W = 0 and value 0,
-    // so the update keeps them 0.
+    // ---- load the two input levels (registers; the newer one also to both
+    // LDS buffers, so cells that are never recomputed keep their value) and
+    // the coefficients.  Cells the scheme does not update (outside the padded
+    // grid, the pinned free-surface row) get a2 = W = 0 and value 0, so the
+    // update keeps them 0.
     float cur[K], prev[K], a2[K], W[K];
     const float gxX = xin ? s.gx[X] : 0.f;
 #pragma unroll
@@ -259,7 +278,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         const bool in = xin && Z >= 0 && Z < s.Nz;
         float c = 0.f, pv = 0.f, v2 = 0.f;
         if (in) {
-            const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+            const int64_t i = col + (int64_t)k * s.pitch;
             c = in_cur[i];
             pv = in_prev[i];
             v2 = s.V2[i];
@@ -274,39 +293,40 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         cur[k] = c;
         prev[k] = upd ? pv : 0.f;
         lds[0][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
+        lds[1][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
     }
 
     // forward: sources of this shot inside the loaded region (uniform test);
-    // receivers whose base node is in the output tile
+    // receiver entries of the tile
     bool has_src = false;
     int32_t rbeg = 0, rend = 0;
-    const int32_t *rids = nullptr;
     if (!ADJ) {
 #pragma unroll
         for (int j = 0; j < kNodes; ++j) {
             const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
             has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
         }
-        rbeg = s.tile_rec[tile];
-        rend = s.tile_rec[tile + 1];
-        rids = s.tile_rec + (tiles + 1);
+        if (MODE == kFwd && s.gathers) {
+            rbeg = s.tile_rec[tile];
+            rend = s.tile_rec[tile + 1];
+        }
     }
     // adjoint: receiver nodes in the loaded region; forward levels of the
     // imaging window (p^{k+1}, p^k), and the partial sums of h
     int32_t ebeg = 0, eend = 0;
-    float pa[K], pb[K], hp[K];
-    const float *ringb = t.ring ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
+    float pa[ADJ ? K : 1], pb[ADJ ? K : 1], hp[ADJ ? K : 1];
     if (ADJ) {
+        const float *ringb = t.ring + (int64_t)shot * t.ring_shot;
         ebeg = t.inj.tile_start[tile];
         eend = t.inj.tile_start[tile + 1];
+        const int L1 = t.n + 1, L0 = t.n;
+        const bool h1 = L1 >= t.ring_lo && L1 <= t.ring_hi, h0 = L0 >= t.ring_lo && L0 <= t.ring_hi;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int Z = Z0 + k;
-            const bool own = xout && Z >= oz && Z < oz_end;
-            const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
-            const int L1 = t.n + 1, L0 = t.n;
-            pa[k] = (own && L1 >= t.ring_lo && L1 <= t.ring_hi) ? ringb[(int64_t)(L1 - t.ring_lo) * s.frame + i] : 0.f;
-            pb[k] = (own && L0 >= t.ring_lo && L0 <= t.ring_hi) ? ringb[(int64_t)(L0 - t.ring_lo) * s.frame + i] : 0.f;
+            const bool own = xout && k >= k_lo && k < k_hi;
+            const int64_t i = col + (int64_t)k * s.pitch;
+            pa[k] = (own && h1) ? ringb[(int64_t)(L1 - t.ring_lo) * s.frame + i] : 0.f;
+            pb[k] = (own && h0) ? ringb[(int64_t)(L0 - t.ring_lo) * s.frame + i] : 0.f;
             hp[k] = 0.f;
         }
     }
@@ -319,114 +339,106 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         const float *Lc = lds[st & 1];
         float *Ln = lds[(st + 1) & 1];
 
-        if (!ADJ) {
+        if (MODE == kFwd && rend > rbeg && n % s.rec_every == 0) {
             // record level n: receivers whose base node is in this output tile
-            if (s.gathers && n % s.rec_every == 0) {
-                float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
-                for (int q = rbeg + (int)threadIdx.x; q < rend; q += NTHR) {
-                    const int r = rids[q];
-                    const int rz = s.rec_iz[r] - ez0 + kHalo, rx = s.rec_ix[r] - ex0 + kHalo;
-                    const float *wr = s.rec_w + r * kNodes;
-                    row[r] = wr[0] * Lc[rz * LW + rx] + wr[1] * Lc[rz * LW + rx + 1] +
-                             wr[2] * Lc[(rz + 1) * LW + rx] + wr[3] * Lc[(rz + 1) * LW + rx + 1];
-                }
+            float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+            for (int q = rbeg + (int)threadIdx.x; q < rend; q += NTHR) {
+                const RecEntry e = s.rec_list[q];
+                row[e.r] = e.w[0] * Lc[e.lds] + e.w[1] * Lc[e.lds + 1] + e.w[2] * Lc[e.lds + LW] +
+                           e.w[3] * Lc[e.lds + LW + 1];
             }
-            if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count &&
-                X >= max(ox, s.xleft) && X < min(ox_end, s.xleft + s.nx)) {
-                float *fr = s.snaps + ((int64_t)shot * s.snap_count + n / s.snap_every) * s.nz * s.nx;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int Z = Z0 + k;
-                    if (Z >= max(oz, s.ztop) && Z < min(oz_end, s.ztop + s.nz))
-                        fr[(int64_t)(Z - s.ztop) * s.nx + (X - s.xleft)] = cur[k];
-                }
-            }
-        } else if (n <= t.nt - 2) {
-            // imaging term n: h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1}) on the output tile
+        }
+        if (ADJ) {
+            // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1})
+            const float *ringb = t.ring + (int64_t)shot * t.ring_shot;
+            const int Lm = n - 1;
+            const bool hm = Lm >= t.ring_lo && Lm <= t.ring_hi;
+            const bool image = n <= t.nt - 2;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int Z = Z0 + k;
-                const bool own = xout && Z >= oz && Z < oz_end;
-                const int Lm = n - 1;
-                const float pc = (own && Lm >= t.ring_lo && Lm <= t.ring_hi)
-                                     ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + (int64_t)(Z + kGuard) * s.pitch + X + kGuard]
-                                     : 0.f;
-                hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
-                pa[k] = pb[k];
-                pb[k] = pc;
-            }
-        } else {
-            // mu^{nt} = 0: no imaging term; shift the window to p^{n}, p^{n-1}
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int Z = Z0 + k;
-                const bool own = xout && Z >= oz && Z < oz_end;
-                const int Lm = n - 1;
-                const float pc = (own && Lm >= t.ring_lo && Lm <= t.ring_hi)
-                                     ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + (int64_t)(Z + kGuard) * s.pitch + X + kGuard]
-                                     : 0.f;
-                pa[k] = pb[k];
-                pb[k] = pc;
+                if (k >= k_lo && k < k_hi) {
+                    const float pc = (xout && hm) ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + col + (int64_t)k * s.pitch] : 0.f;
+                    if (image) hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
+                    pa[k] = pb[k];
+                    pb[k] = pc;
+                }
             }
         }
 
-        // the 4 rows above and below this thread's column segment
-        float up[kHalo], dn[kHalo];
+        // rows still needed after this sub-step (local rows [need_lo, need_hi))
+        const int sdone = st + 1;
+        const int need_lo = top_tile ? K : kHalo * sdone, need_hi = EZ - kHalo * sdone;
+        const bool active = !seg_dead && lz0 + K > need_lo && lz0 < need_hi;
+        if (active) {
+            // the 4 rows above and below this thread's column segment
+            float up[kHalo], dn[kHalo];
 #pragma unroll
-        for (int j = 0; j < kHalo; ++j) {
-            up[j] = Lc[(lz0 + j) * LW + lx + kHalo];
-            dn[j] = Lc[(lz0 + K + kHalo + j) * LW + lx + kHalo];
-        }
-        const float wav = (!ADJ && has_src) ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
-
-        // Row k needs rows k-4..k+4 of the current level; once row k is done,
-        // row k-4 is dead and is replaced by its new value (the register window
-        // of new values stays 5 rows deep).
-        float nw[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float *rowp = Lc + (lz0 + k + kHalo) * LW + lx + kHalo;
-            const float c2 = cur[k] + cur[k];
-            float lap = 0.f;
-#pragma unroll
-            for (int m = 1; m <= kHalo; ++m) {
-                const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
-                const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
-                lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, rowp[m] + rowp[-m], c2);
+            for (int j = 0; j < kHalo; ++j) {
+                up[j] = Lc[(lz0 + j) * LW + lx + kHalo];
+                dn[j] = Lc[(lz0 + K + kHalo + j) * LW + lx + kHalo];
             }
-            float v = leapfrog(W[k], lap, a2[k], cur[k], prev[k]);
-            if (!ADJ && has_src) {
-                float amp = 0.f;
+            const float wav = (!ADJ && has_src) ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
+            // Row k needs rows k-4..k+4 of the current level; once row k is
+            // done, row k-4 is dead and is replaced by its new value (the
+            // register window of new values stays 5 rows deep).
+            float nw[K];
 #pragma unroll
-                for (int j = 0; j < kNodes; ++j)
-                    if (s.src_ix[shot * kNodes + j] == X && s.src_iz[shot * kNodes + j] == Z0 + k)
-                        amp += s.src_w[shot * kNodes + j];
-                if (amp != 0.f) v = fmaf(W[k], amp * wav, v);
-            }
-            nw[k] = v;
-            const int Z = Z0 + k;
-            if (!(top_tile && Z < 0)) Ln[(lz0 + k + kHalo) * LW + lx + kHalo] = v;
-            if (top_tile && Z >= 1 && Z <= kHalo)   // ghost row -Z of the new level
-                Ln[(-Z - ez0 + kHalo) * LW + lx + kHalo] = -v;
-            if (k >= kHalo) {
-                prev[k - kHalo] = cur[k - kHalo];
-                cur[k - kHalo] = nw[k - kHalo];
-            }
-        }
+            for (int k = 0; k < K; ++k) {
+                const float *rowp = Lc + (lz0 + k + kHalo) * LW + lx + kHalo;
+                float lap = 0.f;
+                if (ISO) {
+                    // dz == dx: one weight per m, sum_m c_m ((z+m)+(z-m)+(x+m)+(x-m) - 4p)
+                    const float c4 = -4.f * cur[k];
 #pragma unroll
-        for (int k = K - kHalo; k < K; ++k) {
-            prev[k] = cur[k];
-            cur[k] = nw[k];
-        }
-        if (!ADJ && ringb) {
-            // store the new level n+1 of the output tile
-            float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
-            if (xout) {
+                    for (int m = 1; m <= kHalo; ++m) {
+                        const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
+                        const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
+                        lap = fmaf(s.cz[m], ((zp + zm) + (rowp[m] + rowp[-m])) + c4, lap);
+                    }
+                } else {
+                    const float c2 = cur[k] + cur[k];
+#pragma unroll
+                    for (int m = 1; m <= kHalo; ++m) {
+                        const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
+                        const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
+                        lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, rowp[m] + rowp[-m], c2);
+                    }
+                }
+                float v = leapfrog(W[k], lap, a2[k], cur[k], prev[k]);
+                if (!ADJ && has_src) {
+                    float amp = 0.f;
+#pragma unroll
+                    for (int j = 0; j < kNodes; ++j)
+                        if (s.src_ix[shot * kNodes + j] == X && s.src_iz[shot * kNodes + j] == Z0 + k)
+                            amp += s.src_w[shot * kNodes + j];
+                    v = fmaf(W[k], amp * wav, v);
+                }
+                nw[k] = v;
+                if (wr_ok) Ln[(lz0 + k + kHalo) * LW + lx + kHalo] = v;
+                if (k >= kHalo) {
+                    prev[k - kHalo] = cur[k - kHalo];
+                    cur[k - kHalo] = nw[k - kHalo];
+                }
+            }
+#pragma unroll
+            for (int k = K - kHalo; k < K; ++k) {
+                prev[k] = cur[k];
+                cur[k] = nw[k];
+            }
+            if (ghost_writer) {
+                // ghost rows -1..-4 of the new level: minus rows 1..4
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int Z = Z0 + k;
-                    if (Z >= oz && Z < oz_end) rl[(int64_t)(Z + kGuard) * s.pitch + X + kGuard] = cur[k];
+                    if (Z >= 1 && Z <= kHalo) Ln[(-Z - ez0 + kHalo) * LW + lx + kHalo] = -cur[k];
                 }
+            }
+            if (MODE == kRing && xout) {
+                // store the new level n+1 of the output tile
+                float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k >= k_lo && k < k_hi) rl[col + (int64_t)k * s.pitch] = cur[k];
             }
         }
         if (ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0) {
@@ -446,8 +458,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 if (top_tile && iz >= 1 && iz <= kHalo) Ln[(-iz - ez0 + kHalo) * LW + ix - ex0 + kHalo] -= add;
             }
             __syncthreads();
+            if (active) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) cur[k] = Ln[(lz0 + k + kHalo) * LW + lx + kHalo];
+                for (int k = 0; k < K; ++k) cur[k] = Ln[(lz0 + k + kHalo) * LW + lx + kHalo];
+            }
         }
         __syncthreads();
     }
@@ -456,9 +470,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     if (xout) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int Z = Z0 + k;
-            if (Z >= oz && Z < oz_end) {
-                const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+            if (k >= k_lo && k < k_hi) {
+                const int64_t i = col + (int64_t)k * s.pitch;
                 out_cur[i] = cur[k];
                 out_prev[i] = prev[k];
                 if (ADJ) {
@@ -475,30 +488,31 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     }
 }
 
-template <int K, int NWX, int NWZ, bool ADJ>
+template <int K, int NWX, int NWZ, int MODE, bool ISO>
 __global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs t)
 {
     __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
-    tiled_body<K, NWX, NWZ, ADJ>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
+    tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Batched form: one launch covers every (slice, shot, tile) of the batch.
 // Item i owns logical blocks [items[i].block_start, items[i+1].block_start);
 // launch-level fields (levels, pairs) come from the arguments.
-template <int K, int NWX, int NWZ, bool ADJ>
-__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled_batch(const BatchItem *items, int nitems, int n,
-                                                                 int nsteps, int in_pair)
+template <int K, int NWX, int NWZ, int MODE, bool ISO>
+__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled_batch(const BatchItem *__restrict__ items, int nitems,
+                                                                 int n, int nsteps, int in_pair)
 {
     __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int it = 0;
     while (it + 1 < nitems && items[it + 1].block_start <= b) ++it;
+    const SliceDesc s = items[it].s;     // local copies: plain registers, no aliasing with LDS
     TileArgs t = items[it].t;
     t.n = n;
     t.nsteps = nsteps;
     t.in_pair = in_pair;
     t.out_pair = in_pair ^ 1;
-    tiled_body<K, NWX, NWZ, ADJ>(items[it].s, t, b - items[it].block_start, lds);
+    tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, b - items[it].block_start, lds);
 }
 
 __global__ void __launch_bounds__(256) k_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot,
@@ -570,13 +584,13 @@ hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st)
+hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st, int what)
 {
     int work = s.nrec;
     if (s.snaps && s.nz * s.nx > work) work = s.nz * s.nx;
     unsigned blocks = (unsigned)((work + 255) / 256);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_record, dim3(blocks, s.nshot), dim3(256), 0, st, s, n, slot);
+    hipLaunchKernelGGL(k_record, dim3(blocks, s.nshot), dim3(256), 0, st, s, n, slot, what);
     return hipGetLastError();
 }
 
@@ -606,55 +620,67 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
     return T;
 }
 
-template <bool ADJ>
-static hipError_t launch_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                     int in_pair, int config, hipStream_t st)
+// The isotropic forms (dz == dx: the z and x weights are equal) are built for
+// the forward modes; the adjoint uses the general form.
+template <int MODE, bool ISO>
+static hipError_t launch_tiled_batch_iso(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                         int in_pair, int config, hipStream_t st)
 {
     const dim3 g((unsigned)total_blocks);
     switch (config) {
-    case 0: hipLaunchKernelGGL((k_tiled_batch<8, 2, 8, ADJ>), g, dim3(1024), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 1: hipLaunchKernelGGL((k_tiled_batch<16, 1, 8, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 2: hipLaunchKernelGGL((k_tiled_batch<8, 1, 8, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 3: hipLaunchKernelGGL((k_tiled_batch<16, 2, 4, ADJ>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 0: hipLaunchKernelGGL((k_tiled_batch<8, 2, 8, MODE, ISO>), g, dim3(1024), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 1: hipLaunchKernelGGL((k_tiled_batch<16, 1, 8, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 2: hipLaunchKernelGGL((k_tiled_batch<8, 1, 8, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 3: hipLaunchKernelGGL((k_tiled_batch<16, 2, 4, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                   int in_pair, int config, hipStream_t st)
+                                   int in_pair, int config, bool iso, hipStream_t st)
 {
-    return launch_tiled_batch<false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
+    return iso ? launch_tiled_batch_iso<kFwd, true>(items, nitems, total_blocks, n, nsteps, in_pair, config, st)
+               : launch_tiled_batch_iso<kFwd, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
 }
 
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                       int in_pair, int config, hipStream_t st)
 {
-    return launch_tiled_batch<true>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
+    return launch_tiled_batch_iso<kAdj, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
 }
 
-template <bool ADJ>
+template <int MODE, bool ISO>
 static hipError_t launch_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
     const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
     switch (config) {
-    case 0: hipLaunchKernelGGL((k_tiled<8, 2, 8, ADJ>), dim3(blocks), dim3(1024), 0, st, s, t); break;
-    case 1: hipLaunchKernelGGL((k_tiled<16, 1, 8, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 2: hipLaunchKernelGGL((k_tiled<8, 1, 8, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 3: hipLaunchKernelGGL((k_tiled<16, 2, 4, ADJ>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 0: hipLaunchKernelGGL((k_tiled<8, 2, 8, MODE, ISO>), dim3(blocks), dim3(1024), 0, st, s, t); break;
+    case 1: hipLaunchKernelGGL((k_tiled<16, 1, 8, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 2: hipLaunchKernelGGL((k_tiled<8, 1, 8, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 3: hipLaunchKernelGGL((k_tiled<16, 2, 4, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+static bool isotropic(const SliceDesc &s)
+{
+    for (int m = 1; m <= kHalo; ++m)
+        if (s.cz[m] != s.cx[m]) return false;
+    return true;
+}
+
 hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
-    return launch_tiled<false>(s, t, config, st);
+    const bool iso = isotropic(s);
+    if (t.ring) return iso ? launch_tiled<kRing, true>(s, t, config, st) : launch_tiled<kRing, false>(s, t, config, st);
+    return iso ? launch_tiled<kFwd, true>(s, t, config, st) : launch_tiled<kFwd, false>(s, t, config, st);
 }
 
 hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
-    return launch_tiled<true>(s, t, config, st);
+    return launch_tiled<kAdj, false>(s, t, config, st);
 }
 
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,

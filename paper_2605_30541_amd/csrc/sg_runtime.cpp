@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -97,7 +98,7 @@ namespace {
 // (C + 2 levels), the adjoint field pairs, the Kahan pair of the imaging sum,
 // and the residual-injection tables.
 struct Layout {
-    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec;
+    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
     size_t inj_tile, inj_lds, inj_iz, inj_ix, inj_pstart, inj_rid, inj_w;
     size_t tables_end, fields;
     size_t ckpt, ring, mu, hsum, hcomp, total;
@@ -136,7 +137,8 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
     L.rec_iz = take(nr * sizeof(int32_t));
     L.rec_ix = take(nr * sizeof(int32_t));
     L.rec_w = take(nr * sg::kNodes * sizeof(float));
-    L.tile_rec = take(((size_t)max_tiles(p) + 1 + nr) * sizeof(int32_t));
+    L.tile_rec = take(((size_t)max_tiles(p) + 1) * sizeof(int32_t));
+    L.rec_list = take(nr * sizeof(sg::RecEntry));
     if (ckpt > 0) {
         L.inj_cap = kMaxTilesPerNode * sg::kNodes * (int64_t)nr;
         const size_t cap = (size_t)L.inj_cap;
@@ -265,6 +267,7 @@ sg::SliceDesc describe(const sg_plan *p, const Layout &L, char *ws, const sg_sho
     s.rec_ix = (const int32_t *)(ws + L.rec_ix);
     s.rec_w = (const float *)(ws + L.rec_w);
     s.tile_rec = (const int32_t *)(ws + L.tile_rec);
+    s.rec_list = (const sg::RecEntry *)(ws + L.rec_list);
     s.wavelet = sh->wavelet;
     s.fields = (float *)(ws + L.fields);
     s.gathers = sh->nrec > 0 ? gathers : nullptr;
@@ -369,15 +372,25 @@ sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *s
             rtile[i] = tz * T->ntx + nd.base_ix / T->tx;
         }
     }
-    if (T) {   // CSR: start offsets per tile, then receiver ids grouped by tile
-        const int tiles = T->ntx * T->ntz;
-        int32_t *csr = (int32_t *)at(L.tile_rec);
+    if (T) {   // receivers grouped by the tile holding their base node, with LDS indices
+        const int tiles = T->ntx * T->ntz, LW = T->ex + 2 * sg::kHalo, halo = sg::kHalo * T->tb;
+        const bool free_top = p->g.top == SG_TOP_FREE;
+        int32_t *start = (int32_t *)at(L.tile_rec);
+        sg::RecEntry *list = (sg::RecEntry *)at(L.rec_list);
         std::vector<int32_t> count(tiles + 1, 0);
         for (int i = 0; i < sh->nrec; ++i) ++count[rtile[i] + 1];
         for (int q = 0; q < tiles; ++q) count[q + 1] += count[q];
-        for (int q = 0; q <= tiles; ++q) csr[q] = count[q];
-        int32_t *ids = csr + tiles + 1;
-        for (int i = 0; i < sh->nrec; ++i) ids[count[rtile[i]]++] = i;
+        for (int q = 0; q <= tiles; ++q) start[q] = count[q];
+        for (int i = 0; i < sh->nrec; ++i) {
+            const int tile = rtile[i], tzi = tile / T->ntx, txi = tile % T->ntx;
+            const int ez0 = free_top ? (tzi == 0 ? -T->k : T->tz_top + (tzi - 1) * T->tz - halo) : tzi * T->tz - halo;
+            const int ex0 = txi * T->tx - halo;
+            sg::RecEntry &e = list[count[tile]++];
+            const int32_t biz = ((const int32_t *)at(L.rec_iz))[i], bix = ((const int32_t *)at(L.rec_ix))[i];
+            e.lds = (biz - ez0 + sg::kHalo) * LW + (bix - ex0 + sg::kHalo);
+            e.r = i;
+            for (int k = 0; k < sg::kNodes; ++k) e.w[k] = ((const float *)at(L.rec_w))[i * sg::kNodes + k];
+        }
     }
     if (T && L.inj_cap > 0) {
         // adjoint residual injection: receiver nodes inside each tile's loaded
@@ -472,16 +485,22 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
                       OnCut on_cut, hipStream_t st)
 {
     const int step = t.variant == 1 ? 1 : t.time_block;
+    // the tiled kernel leaves snapshots to launch boundaries at snapshot levels
+    const bool snap_cuts = t.variant == 2 && s.snaps != nullptr;
+    const int se = s.snap_every, slast = (s.snap_count - 1) * s.snap_every;
+    auto snap_due = [&](int level) { return snap_cuts && level % se == 0 && level <= slast; };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p->profiling) {
         sg_status rc = prof_pair(p, 0, &e0, &e1);
         if (rc != SG_OK) return rc;
         SG_HIP(hipEventRecord(e0, st));
     }
+    if (snap_due(n0) && n0 < n_end) SG_HIP(sg::launch_record_slot(s, n0, 2 * (*pair) + 1, st, 2));
     int launches = 0;
     for (int n = n0; n < n_end; ++launches) {
         int k = std::min(step, n_end - n);
         if (cut > 0) k = std::min(k, cut - n % cut);
+        if (snap_cuts && n < slast) k = std::min(k, se - n % se);
         if (t.variant == 1) {
             SG_HIP(sg::launch_step_naive(s, n, st));
             *pair = 0;
@@ -494,6 +513,7 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
             *pair ^= 1;
         }
         n += k;
+        if (n < n_end && snap_due(n)) SG_HIP(sg::launch_record_slot(s, n, 2 * (*pair) + 1, st, 2));
         if (cut > 0 && n % cut == 0) {
             sg_status rc = on_cut(n, *pair);
             if (rc != SG_OK) return rc;
@@ -658,6 +678,29 @@ sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hip
     g_graphs.entries.push_back({key, exec});
     *out = exec;
     return SG_OK;
+}
+
+// Candidate tunings of the autotuner: every built shape with every time block
+// that leaves an output tile.
+std::vector<sg_tuning> tuning_candidates(const sg_plan *p)
+{
+    static const int tbs[] = {1, 2, 3, 4, 5, 6, 8};
+    std::vector<sg_tuning> out;
+    for (int c = 0; c < sg::kTiledShapes; ++c) {
+        const sg::TiledShape sh = sg::tiled_shape(c);
+        for (int tb : tbs) {
+            const sg::Tiling T = sg::make_tiling(p->Nz, p->Nx, p->g.top == SG_TOP_FREE, sh.ex, sh.ez, sh.k, tb);
+            if (!T.ok || (int64_t)T.ntx * T.ntz > max_tiles(p)) continue;
+            sg_tuning t{};
+            t.variant = 2;
+            t.tile_x = sh.ex;
+            t.tile_z = sh.ez;
+            t.time_block = tb;
+            t.rows_per_thread = sh.k;
+            out.push_back(t);
+        }
+    }
+    return out;
 }
 
 }  // namespace
@@ -1048,13 +1091,38 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
     // the time-stepping launches (one per time block over the whole batch),
     // replayed from a captured graph unless the caller is capturing already
     const int config = cs[0].config, tb = t.time_block;
+    // the isotropic kernel form needs dz == dx on every item
+    bool iso = true;
+    for (int i = 0; i < nitems; ++i)
+        for (int m = 1; m <= sg::kHalo; ++m) iso = iso && hb[i].s.cz[m] == hb[i].s.cx[m];
+    // snapshots are copied at launch boundaries: launches are cut at every
+    // snapshot level of any item
+    auto snap_due = [&](int i, int level) {
+        const sg::SliceDesc &d = hb[i].s;
+        return d.snaps && level % d.snap_every == 0 && level / d.snap_every < d.snap_count;
+    };
+    auto next_cut = [&](int n) {   // smallest snapshot level > n of any item, or INT_MAX
+        int best = INT32_MAX;
+        for (int i = 0; i < nitems; ++i) {
+            const sg::SliceDesc &d = hb[i].s;
+            if (!d.snaps) continue;
+            const int L = (n / d.snap_every + 1) * d.snap_every;
+            if (L / d.snap_every < d.snap_count) best = std::min(best, L);
+        }
+        return best;
+    };
     auto enqueue = [&](hipStream_t s2) -> sg_status {
         int pair = 0;
+        for (int i = 0; i < nitems; ++i)
+            if (snap_due(i, 0)) SG_HIP(sg::launch_record_slot(hb[i].s, 0, 1, s2, 2));
         for (int n = 0; n < nt - 1;) {
-            const int k = std::min(tb, nt - 1 - n);
-            SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, s2));
+            const int k = std::min(std::min(tb, nt - 1 - n), next_cut(n) - n);
+            SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, iso, s2));
             pair ^= 1;
             n += k;
+            if (n < nt - 1)
+                for (int i = 0; i < nitems; ++i)
+                    if (snap_due(i, n)) SG_HIP(sg::launch_record_slot(hb[i].s, n, 2 * pair + 1, s2, 2));
         }
         for (int i = 0; i < nitems; ++i)
             SG_HIP(sg::launch_record_slot(hb[i].s, nt - 1, 2 * pair + 1, s2));
@@ -1069,6 +1137,71 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
     hipGraphExec_t exec = nullptr;
     if ((rc = graph_lookup(key, st, enqueue, &exec)) != SG_OK) return rc;
     SG_HIP(hipGraphLaunch(exec, st));
+    return SG_OK;
+}
+
+sg_status sg_autotune(sg_plan *p, const float *vp, const sg_shots *shots, int32_t trial_levels, void *ws,
+                      size_t ws_bytes, void *stream, sg_tuning *best)
+{
+    if (!p || !best) return fail(SG_EINVAL, "NULL argument");
+    if (trial_levels < 8) return fail(SG_EINVAL, "trial_levels must be >= 8");
+    const sg_tuning keep = p->tuning;
+    sg_tuning probe{};
+    probe.variant = 2;
+    p->tuning = probe;
+    CallSetup c;
+    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, 0, true, &c);
+    p->tuning = keep;
+    if (rc != SG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    hipEvent_t e0, e1;
+    SG_HIP(hipEventCreate(&e0));
+    SG_HIP(hipEventCreate(&e1));
+    const int levels = std::min(trial_levels, p->g.nt - 1);
+    double best_ms = 1e300;
+    sg_tuning chosen{};
+    for (const sg_tuning &t : tuning_candidates(p)) {
+        int config = -1;
+        sg::Tiling T{};
+        if (tiling_for(p, t, &config, &T) != SG_OK) continue;
+        if ((rc = upload_tables(p, c.L, w, shots, &T, st)) != SG_OK) break;
+        // a trial: no outputs recorded, fields zeroed, the same levels for every candidate
+        sg::SliceDesc s = describe(p, c.L, w, shots, nullptr, nullptr);
+        if (hipSuccess != sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st) ||
+            hipSuccess != sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st)) {
+            rc = fail(SG_EHIP, "autotune set-up launch failed");
+            break;
+        }
+        int pair = 0;
+        const bool prof = p->profiling;
+        p->profiling = false;
+        // one untimed pass to warm caches and code, then the timed pass
+        for (int rep = 0; rep < 2 && rc == SG_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(SG_EHIP, "event record failed");
+            if (rc == SG_OK)
+                rc = forward_run(p, s, t, config, T, 0, levels, 0, &pair, nullptr, 0, 0,
+                                 [](int, int) { return SG_OK; }, st);
+            if (rep == 1 && rc == SG_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(SG_EHIP, "event record failed");
+        }
+        p->profiling = prof;
+        if (rc != SG_OK) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(SG_EHIP, "event timing failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            chosen = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SG_OK) return rc;
+    if (best_ms == 1e300) return fail(SG_EUNSUPPORTED, "no tiling fits this grid");
+    p->tuning = chosen;
+    *best = chosen;
     return SG_OK;
 }
 

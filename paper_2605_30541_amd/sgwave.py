@@ -105,6 +105,9 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots), ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.POINTER(sg_tuning)]),
 }
 
 
@@ -336,6 +339,15 @@ def sg_batch_forward(items, ws, tuning=None, stream=None):
                                    tuning.get("time_block", 0), tuning.get("rows_per_thread", 0)))
     _check(lib().sg_batch_forward(arr, len(items), t, _ptr(ws), ws.numel() * ws.element_size(),
                                   _stream_ptr(stream)))
+
+
+def sg_autotune(plan: Plan, vp, shots: Shots, trial_levels: int, ws, stream=None) -> dict:
+    sh = shots.c()
+    t = sg_tuning()
+    _check(lib().sg_autotune(plan.handle, _ptr(vp), ctypes.byref(sh), trial_levels, _ptr(ws),
+                             ws.numel() * ws.element_size(), _stream_ptr(stream), ctypes.byref(t)))
+    return dict(variant=t.variant, tile_x=t.tile_x, tile_z=t.tile_z, time_block=t.time_block,
+                rows_per_thread=t.rows_per_thread)
 
 
 def sg_set_graphs(on: bool):
