@@ -271,6 +271,31 @@ sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, si
 sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning,
                            void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Batched velocity gradients over several slices of uneven size (items share
+ * dt and nt).  Shots run in waves of at most shots_per_wave shots per item
+ * (<= 0: all at once), so the checkpoint and recompute store fits the
+ * workspace; within a wave every time block of every shot of every item is
+ * one launch.  Each wave runs the forward with checkpoints every ckpt_every
+ * levels (<= 0: ceil(sqrt(nt))), then the segments backwards (recompute +
+ * adjoint), and adds its shots' contribution to the item's gradient.
+ *   resid  device [nshot][ceil(nt/rec_every)][nrec] float, dJ/dd of the item
+ *   grad   device [nz][nx] float, overwritten with dJ/dv summed over the item's shots
+ */
+typedef struct {
+    sg_plan *plan;
+    const float *vp;
+    const sg_shots *shots;
+    const float *resid;
+    float *grad;
+} sg_batch_grad_item;
+
+sg_status sg_batch_grad_workspace_size(const sg_batch_grad_item *items, int32_t nitems, int32_t ckpt_every,
+                                       int32_t shots_per_wave, size_t *bytes);
+sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nitems, int32_t ckpt_every,
+                                    int32_t shots_per_wave, const sg_tuning *tuning, void *ws, size_t ws_bytes,
+                                    void *stream);
+
 /* Turn the graph replay of sg_batch_forward on (default) or off (plain
  * stream launches). */
 sg_status sg_set_graphs(int32_t on);

@@ -40,8 +40,13 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
+    # export only the C ABI (sg_*)
+    vscript = os.path.join(OUT_DIR, "exports.map")
+    with open(vscript, "w") as f:
+        f.write("{ global: sg_*; local: *; };\n")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined",
+           "-Wl,--version-script=" + vscript, *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

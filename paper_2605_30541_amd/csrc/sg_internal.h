@@ -145,15 +145,17 @@ hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int confi
 // the items' blocks (items[i].block_start is the prefix sum).
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                    int in_pair, int config, bool iso, hipStream_t st);
+hipError_t launch_ring_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                   int in_pair, int config, bool iso, int ring_lo, hipStream_t st);
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                      int in_pair, int config, hipStream_t st);
+                                      int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st);
 // dst[shot][0..n) = src[shot][0..n) for every shot (strides in floats)
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
                        hipStream_t st);
-// grad[iz][ix] = 2 / (dt^2 v^3) * sum over shots and over the padded cells whose
-// velocity is copied from (iz, ix) of (hsum - hcomp)
+// grad[iz][ix] (+)= 2 / (dt^2 v^3) * sum over shots and over the padded cells
+// whose velocity is copied from (iz, ix) of (hsum - hcomp)
 hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
-                                int64_t shot_stride, float dt, float *grad, hipStream_t st);
+                                int64_t shot_stride, float dt, float *grad, hipStream_t st, bool accumulate = false);
 // Records level n held in frame `slot` of every shot: gather row (what & 1)
 // and snapshot (what & 2) when that level is due for them.
 hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st, int what = 3);

@@ -488,8 +488,12 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     }
 }
 
+// Forward kernels ask for 4 waves per SIMD: two 512-thread workgroups share a
+// CU, so one's loads and stores overlap the other's sub-steps.
+#define SG_TILED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MODE == kAdj ? 1 : 4)))
+
 template <int K, int NWX, int NWZ, int MODE, bool ISO>
-__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs t)
+__global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled(SliceDesc s, TileArgs t)
 {
     __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
     tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
@@ -499,8 +503,8 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled(SliceDesc s, TileArgs 
 // Item i owns logical blocks [items[i].block_start, items[i+1].block_start);
 // launch-level fields (levels, pairs) come from the arguments.
 template <int K, int NWX, int NWZ, int MODE, bool ISO>
-__global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled_batch(const BatchItem *__restrict__ items, int nitems,
-                                                                 int n, int nsteps, int in_pair)
+__global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled_batch(const BatchItem *__restrict__ items, int nitems,
+                                                                 int n, int nsteps, int in_pair, int ring_lo, int ring_hi)
 {
     __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -512,6 +516,8 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) k_tiled_batch(const BatchItem 
     t.nsteps = nsteps;
     t.in_pair = in_pair;
     t.out_pair = in_pair ^ 1;
+    t.ring_lo = ring_lo;
+    t.ring_hi = ring_hi;
     tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, b - items[it].block_start, lds);
 }
 
@@ -530,7 +536,7 @@ __global__ void __launch_bounds__(256) k_copy(float *dst, int64_t dst_shot, cons
 // transpose of the edge replication into the sponge) of h = hsum - hcomp.
 __global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float *vp, const float *hsum,
                                                        const float *hcomp, int64_t shot_stride, float dt,
-                                                       float *grad)
+                                                       float *grad, int accumulate)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= s.nz * s.nx) return;
@@ -547,7 +553,8 @@ __global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float 
             }
     }
     const double v = vp[q];
-    grad[q] = (float)(2.0 / ((double)dt * dt * v * v * v) * acc);
+    const float g = (float)(2.0 / ((double)dt * dt * v * v * v) * acc);
+    grad[q] = accumulate ? grad[q] + g : g;
 }
 
 __global__ void __launch_bounds__(256) k_count_nonfinite(const float *x, size_t n, unsigned int *count)
@@ -624,30 +631,42 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
 // the forward modes; the adjoint uses the general form.
 template <int MODE, bool ISO>
 static hipError_t launch_tiled_batch_iso(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                         int in_pair, int config, hipStream_t st)
+                                         int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st)
 {
     const dim3 g((unsigned)total_blocks);
+#define SG_BATCH_LAUNCH(KK, NX, NZ, THR)                                                                    \
+    hipLaunchKernelGGL((k_tiled_batch<KK, NX, NZ, MODE, ISO>), g, dim3(THR), 0, st, items, nitems, n, nsteps, \
+                       in_pair, ring_lo, ring_hi)
     switch (config) {
-    case 0: hipLaunchKernelGGL((k_tiled_batch<8, 2, 8, MODE, ISO>), g, dim3(1024), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 1: hipLaunchKernelGGL((k_tiled_batch<16, 1, 8, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 2: hipLaunchKernelGGL((k_tiled_batch<8, 1, 8, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
-    case 3: hipLaunchKernelGGL((k_tiled_batch<16, 2, 4, MODE, ISO>), g, dim3(512), 0, st, items, nitems, n, nsteps, in_pair); break;
+    case 0: SG_BATCH_LAUNCH(8, 2, 8, 1024); break;
+    case 1: SG_BATCH_LAUNCH(16, 1, 8, 512); break;
+    case 2: SG_BATCH_LAUNCH(8, 1, 8, 512); break;
+    case 3: SG_BATCH_LAUNCH(16, 2, 4, 512); break;
     default: return hipErrorInvalidValue;
     }
+#undef SG_BATCH_LAUNCH
     return hipGetLastError();
 }
 
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                    int in_pair, int config, bool iso, hipStream_t st)
 {
-    return iso ? launch_tiled_batch_iso<kFwd, true>(items, nitems, total_blocks, n, nsteps, in_pair, config, st)
-               : launch_tiled_batch_iso<kFwd, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
+    return iso ? launch_tiled_batch_iso<kFwd, true>(items, nitems, total_blocks, n, nsteps, in_pair, config, 0, 0, st)
+               : launch_tiled_batch_iso<kFwd, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, 0, 0, st);
+}
+
+hipError_t launch_ring_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
+                                   int in_pair, int config, bool iso, int ring_lo, hipStream_t st)
+{
+    return iso ? launch_tiled_batch_iso<kRing, true>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo, 0, st)
+               : launch_tiled_batch_iso<kRing, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo, 0, st);
 }
 
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                      int in_pair, int config, hipStream_t st)
+                                      int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st)
 {
-    return launch_tiled_batch_iso<kAdj, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, st);
+    return launch_tiled_batch_iso<kAdj, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo,
+                                               ring_hi, st);
 }
 
 template <int MODE, bool ISO>
@@ -694,10 +713,11 @@ hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t s
 }
 
 hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
-                                int64_t shot_stride, float dt, float *grad, hipStream_t st)
+                                int64_t shot_stride, float dt, float *grad, hipStream_t st, bool accumulate)
 {
     const unsigned blocks = (unsigned)((s.nz * s.nx + 255) / 256);
-    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, hcomp, shot_stride, dt, grad);
+    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, hcomp, shot_stride, dt, grad,
+                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

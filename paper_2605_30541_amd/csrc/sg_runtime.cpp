@@ -703,6 +703,18 @@ std::vector<sg_tuning> tuning_candidates(const sg_plan *p)
     return out;
 }
 
+// Shots [s0, s0 + cnt) of an item as their own sg_shots.
+sg_shots shots_view(const sg_shots *sh, int s0, int cnt, int nt)
+{
+    sg_shots v = *sh;
+    v.nshot = cnt;
+    v.src_zx = sh->src_zx + 2 * (size_t)s0;
+    if (sh->wavelet_per_shot) v.wavelet = sh->wavelet + (size_t)s0 * nt;
+    return v;
+}
+
+int wave_shots(int nshot, int per_wave) { return per_wave > 0 ? std::min(nshot, per_wave) : nshot; }
+
 }  // namespace
 
 extern "C" {
@@ -1202,6 +1214,212 @@ sg_status sg_autotune(sg_plan *p, const float *vp, const sg_shots *shots, int32_
     if (best_ms == 1e300) return fail(SG_EUNSUPPORTED, "no tiling fits this grid");
     p->tuning = chosen;
     *best = chosen;
+    return SG_OK;
+}
+
+
+sg_status sg_batch_grad_workspace_size(const sg_batch_grad_item *items, int32_t nitems, int32_t ckpt_every,
+                                       int32_t shots_per_wave, size_t *bytes)
+{
+    if (!items || !bytes || nitems < 1) return fail(SG_EINVAL, "bad batch arguments");
+    size_t total = 0;
+    for (int i = 0; i < nitems; ++i) {
+        if (!items[i].plan || !items[i].shots) return fail(SG_EINVAL, "batch item %d has no plan or shots", i);
+        const int S = wave_shots(items[i].shots->nshot, shots_per_wave);
+        if (S < 1) return fail(SG_EINVAL, "batch item %d has no shots", i);
+        total += align_up(layout_of(items[i].plan, S, items[i].shots->nrec,
+                                    ckpt_spacing(items[i].plan, ckpt_every)).total, 256);
+    }
+    total += 2 * align_up((size_t)nitems * sizeof(sg::BatchItem), 256);
+    *bytes = total;
+    return SG_OK;
+}
+
+sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nitems, int32_t ckpt_every,
+                                    int32_t shots_per_wave, const sg_tuning *tuning, void *ws, size_t ws_bytes,
+                                    void *stream)
+{
+    size_t need = 0;
+    sg_status rc = sg_batch_grad_workspace_size(items, nitems, ckpt_every, shots_per_wave, &need);
+    if (rc != SG_OK) return rc;
+    if (!ws) return fail(SG_EINVAL, "workspace is NULL");
+    if (ws_bytes < need) return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    const int nt = items[0].plan->g.nt;
+    const int C = ckpt_spacing(items[0].plan, ckpt_every);
+    for (int i = 0; i < nitems; ++i) {
+        if (items[i].plan->g.nt != nt) return fail(SG_EINVAL, "batch items must share nt");
+        if (!items[i].vp || !items[i].resid || !items[i].grad) return fail(SG_EINVAL, "batch item %d: NULL pointer", i);
+        if ((rc = check_shots(items[i].plan, items[i].shots)) != SG_OK) return rc;
+    }
+    sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot);
+    if (t.variant != 2) {
+        sg_plan *p0 = items[0].plan;
+        sg_tuning keep = p0->tuning;
+        p0->tuning = sg_tuning{};
+        t = resolve_tuning(p0, items[0].shots->nshot);
+        p0->tuning = keep;
+    }
+    std::vector<sg::Tiling> T(nitems);
+    int config = -1;
+    for (int i = 0; i < nitems; ++i)
+        if ((rc = tiling_for(items[i].plan, t, &config, &T[i])) != SG_OK) return rc;
+    bool iso = true;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int nwave = 0;
+    for (int i = 0; i < nitems; ++i) {
+        const int S = wave_shots(items[i].shots->nshot, shots_per_wave);
+        nwave = std::max(nwave, (items[i].shots->nshot + S - 1) / S);
+    }
+    for (int wv = 0; wv < nwave; ++wv) {
+        // the items that still have shots in this wave, and their set-up
+        std::vector<int> act;
+        std::vector<sg_shots> views;
+        std::vector<Layout> Ls;
+        std::vector<sg::BatchItem> hb;
+        size_t o = 0;
+        int32_t start = 0;
+        views.reserve(nitems);
+        for (int i = 0; i < nitems; ++i) {
+            const sg_batch_grad_item &it = items[i];
+            const int S = wave_shots(it.shots->nshot, shots_per_wave);
+            const int s0 = wv * S, cnt = std::min(S, it.shots->nshot - s0);
+            const size_t region = align_up(layout_of(it.plan, S, it.shots->nrec, C).total, 256);
+            if (cnt <= 0) {
+                o += region;
+                continue;
+            }
+            act.push_back(i);
+            views.push_back(shots_view(it.shots, s0, cnt, nt));
+            const sg_shots *sv = &views.back();
+            const Layout L = layout_of(it.plan, cnt, it.shots->nrec, C);
+            Ls.push_back(L);
+            char *wi = w + o;
+            o += region;
+            if ((rc = upload_tables(it.plan, L, wi, sv, &T[i], st)) != SG_OK) return rc;
+            sg::BatchItem b{};
+            b.s = describe(it.plan, L, wi, sv, nullptr, nullptr);
+            for (int m = 1; m <= sg::kHalo; ++m) iso = iso && b.s.cz[m] == b.s.cx[m];
+            SG_HIP(sg::launch_prepare(b.s, it.vp, (float)(it.plan->g.dt * it.plan->g.dt), st));
+            const int64_t F = it.plan->frame;
+            SG_HIP(sg::launch_zero(b.s.fields, (size_t)cnt * sg::kFramesPerShot * F, st));
+            SG_HIP(sg::launch_zero((float *)(wi + L.mu), (size_t)cnt * sg::kFramesPerShot * F, st));
+            SG_HIP(sg::launch_zero((float *)(wi + L.hsum), (size_t)cnt * F, st));
+            SG_HIP(sg::launch_zero((float *)(wi + L.hcomp), (size_t)cnt * F, st));
+            b.t = tile_args(T[i], b.s.fields, 0, 0, 0);
+            b.t.ring = (float *)(wi + L.ring);
+            b.t.ring_shot = (int64_t)L.ring_levels * F;
+            b.t.resid = it.resid + (size_t)s0 * it.plan->nrow * it.shots->nrec;
+            b.t.hsum = (float *)(wi + L.hsum);
+            b.t.hcomp = (float *)(wi + L.hcomp);
+            b.t.nt = nt;
+            b.t.inj.tile_start = (const int32_t *)(wi + L.inj_tile);
+            b.t.inj.lds = (const int32_t *)(wi + L.inj_lds);
+            b.t.inj.iz = (const int32_t *)(wi + L.inj_iz);
+            b.t.inj.ix = (const int32_t *)(wi + L.inj_ix);
+            b.t.inj.pstart = (const int32_t *)(wi + L.inj_pstart);
+            b.t.inj.rid = (const int32_t *)(wi + L.inj_rid);
+            b.t.inj.w = (const float *)(wi + L.inj_w);
+            b.block_start = start;
+            start += T[i].ntx * T[i].ntz * cnt;
+            hb.push_back(b);
+            // checkpoint 0: levels -1 and 0, both zero
+            SG_HIP(sg::launch_copy((float *)(wi + L.ckpt), (int64_t)L.nseg * 2 * F, b.s.fields,
+                                   (int64_t)sg::kFramesPerShot * F, 2 * F, cnt, st));
+        }
+        const int na = (int)act.size();
+        // two device copies of the item table (forward fields, adjoint fields),
+        // both uploaded once per wave in one copy
+        const size_t tbl = align_up((size_t)nitems * sizeof(sg::BatchItem), 256);
+        sg::BatchItem *dev_fwd = (sg::BatchItem *)(w + need - 2 * tbl);
+        sg::BatchItem *dev_adj = (sg::BatchItem *)(w + need - tbl);
+        {
+            std::vector<char> both(2 * tbl, 0);
+            std::memcpy(both.data(), hb.data(), hb.size() * sizeof(sg::BatchItem));
+            std::vector<sg::BatchItem> hb_adj = hb;
+            for (int q = 0; q < na; ++q)
+                hb_adj[q].t.fields = (float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].mu);
+            std::memcpy(both.data() + tbl, hb_adj.data(), hb_adj.size() * sizeof(sg::BatchItem));
+            if ((rc = stage_upload(dev_fwd, both.data(), 2 * tbl, st)) != SG_OK) return rc;
+        }
+        auto copy_items = [&](auto dst_of, auto src_of, int64_t n) -> sg_status {
+            for (int q = 0; q < na; ++q) {
+                const int64_t F = items[act[q]].plan->frame;
+                float *dst;
+                int64_t dshot;
+                const float *src;
+                int64_t sshot;
+                dst_of(q, F, &dst, &dshot);
+                src_of(q, F, &src, &sshot);
+                SG_HIP(sg::launch_copy(dst, dshot, src, sshot, n * F, views[q].nshot, st));
+            }
+            return SG_OK;
+        };
+        // forward with checkpoints (no outputs)
+        int pair = 0;
+        for (int n = 0; n < nt - 1;) {
+            const int k = std::min(std::min(t.time_block, nt - 1 - n), C - n % C);
+            SG_HIP(sg::launch_step_tiled_batch(dev_fwd, na, start, n, k, pair, config, iso, st));
+            pair ^= 1;
+            n += k;
+            if (n % C == 0 && n / C < Ls[0].nseg) {
+                const int j = n / C, pr = pair;
+                rc = copy_items(
+                    [&](int q, int64_t F, float **d, int64_t *ds) {
+                        *d = (float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].ckpt) + (int64_t)j * 2 * F;
+                        *ds = (int64_t)Ls[q].nseg * 2 * F;
+                    },
+                    [&](int q, int64_t F, const float **sp, int64_t *ss) {
+                        *sp = hb[q].s.fields + (int64_t)(2 * pr) * F;
+                        *ss = (int64_t)sg::kFramesPerShot * F;
+                    },
+                    2);
+                if (rc != SG_OK) return rc;
+            }
+        }
+        // segments backwards: recompute into the ring, then the adjoint
+        int mpair = 0;
+        const int nseg = Ls[0].nseg;
+        for (int j = nseg - 1; j >= 0; --j) {
+            const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
+            for (int target = 0; target < 2; ++target) {
+                rc = copy_items(
+                    [&](int q, int64_t F, float **d, int64_t *ds) {
+                        if (target == 0) {
+                            *d = hb[q].s.fields;
+                            *ds = (int64_t)sg::kFramesPerShot * F;
+                        } else {
+                            *d = hb[q].t.ring;
+                            *ds = hb[q].t.ring_shot;
+                        }
+                    },
+                    [&](int q, int64_t F, const float **sp, int64_t *ss) {
+                        *sp = (const float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].ckpt) + (int64_t)j * 2 * F;
+                        *ss = (int64_t)Ls[q].nseg * 2 * F;
+                    },
+                    2);
+                if (rc != SG_OK) return rc;
+            }
+            int fp = 0;
+            for (int n = lo; n < last;) {
+                const int k = std::min(t.time_block, last - n);
+                SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo - 1, st));
+                fp ^= 1;
+                n += k;
+            }
+            for (int k0 = hi; k0 >= lo;) {
+                const int ns = std::min(t.time_block, k0 - lo + 1);
+                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, lo - 1, last, st));
+                mpair ^= 1;
+                k0 -= ns;
+            }
+        }
+        for (int q = 0; q < na; ++q) {
+            const sg_batch_grad_item &it = items[act[q]];
+            SG_HIP(sg::launch_fold_gradient(hb[q].s, it.vp, hb[q].t.hsum, hb[q].t.hcomp, it.plan->frame,
+                                            (float)it.plan->g.dt, it.grad, st, wv > 0));
+        }
+    }
     return SG_OK;
 }
 

@@ -65,6 +65,12 @@ class sg_batch_item(ctypes.Structure):
                 ("snaps", ctypes.c_void_p)]
 
 
+class sg_batch_grad_item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("vp", ctypes.c_void_p),
+                ("shots", ctypes.POINTER(sg_shots)), ("resid", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p)]
+
+
 _lib = None
 _SIGS = {
     "sg_abi_version": (ctypes.c_int32, []),
@@ -105,6 +111,12 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_batch_grad_workspace_size": (ctypes.c_int32, [ctypes.POINTER(sg_batch_grad_item), ctypes.c_int32,
+                                                      ctypes.c_int32, ctypes.c_int32,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_batch_adjoint_gradient": (ctypes.c_int32, [ctypes.POINTER(sg_batch_grad_item), ctypes.c_int32,
+                                                   ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(sg_tuning),
+                                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "sg_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots), ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                      ctypes.POINTER(sg_tuning)]),
@@ -348,6 +360,35 @@ def sg_autotune(plan: Plan, vp, shots: Shots, trial_levels: int, ws, stream=None
                              ws.numel() * ws.element_size(), _stream_ptr(stream), ctypes.byref(t)))
     return dict(variant=t.variant, tile_x=t.tile_x, tile_z=t.tile_z, time_block=t.time_block,
                 rows_per_thread=t.rows_per_thread)
+
+
+def _grad_items(items):
+    """items: list of (plan, vp, shots, resid, grad) -> ctypes array (and keep-alive list)."""
+    keep = []
+    arr = (sg_batch_grad_item * len(items))()
+    for i, (plan, vp, shots, resid, grad) in enumerate(items):
+        sh = shots.c()
+        keep.append(sh)
+        arr[i] = sg_batch_grad_item(plan.handle, vp.data_ptr(), ctypes.pointer(sh), resid.data_ptr(),
+                                    grad.data_ptr())
+    return arr, keep
+
+
+def sg_batch_grad_workspace_size(items, ckpt_every=0, shots_per_wave=0) -> int:
+    arr, keep = _grad_items(items)
+    n = ctypes.c_size_t()
+    _check(lib().sg_batch_grad_workspace_size(arr, len(items), ckpt_every, shots_per_wave, ctypes.byref(n)))
+    return n.value
+
+
+def sg_batch_adjoint_gradient(items, ws, ckpt_every=0, shots_per_wave=0, tuning=None, stream=None):
+    arr, keep = _grad_items(items)
+    t = None
+    if tuning is not None:
+        t = ctypes.byref(sg_tuning(tuning.get("variant", 2), tuning.get("tile_x", 0), tuning.get("tile_z", 0),
+                                   tuning.get("time_block", 0), tuning.get("rows_per_thread", 0)))
+    _check(lib().sg_batch_adjoint_gradient(arr, len(items), ckpt_every, shots_per_wave, t, _ptr(ws),
+                                           ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
 
 def sg_set_graphs(on: bool):

@@ -133,3 +133,48 @@ def test_uneven_field_slices_sampled_against_oracle():
         e = rel_l2(batch[i][0][k], od[0])
         print("slice %d shot %d rel-L2 %.3e" % (i, k, e), flush=True)
         assert e <= TOL
+
+
+@pytest.mark.parametrize("shots_per_wave", [0, 1, 2])
+def test_batched_gradient_equals_single_slice_gradients_and_oracle(shots_per_wave):
+    """Three uneven slices with 3, 1, 2 shots in one batched gradient (in shot
+    waves of 1 or 2 shots, or all at once): each item's gradient equals the
+    single-slice adjoint gradient, and the oracle's to 1e-4."""
+    import torch
+    sizes, nshots = [(44, 61), (37, 83), (52, 49)], [3, 1, 2]
+    items = make_items(sizes, nshots, nt=330, snaps=False, seed=30)
+    ckpt = 37
+    full, refs = [], []
+    for it in items:
+        g = it["geom"]
+        og = oracle.Geometry(nz=g.nz, nx=g.nx, dz=g.dz, dx=g.dx, dt=g.dt, nt=g.nt, nbl=g.nbl)
+        v_true = it["v"].copy()
+        v_true[g.nz // 3: g.nz // 2, g.nx // 3: g.nx // 2] *= 1.06
+        d, _ = oracle.forward(og, it["v"].astype(np.float64), it["src"], it["wl"], it["rec"])
+        d_obs, _ = oracle.forward(og, v_true.astype(np.float64), it["src"], it["wl"], it["rec"])
+        resid = (d - d_obs).astype(np.float32)
+        refs.append(oracle.gradient(og, it["v"].astype(np.float64), it["src"], it["wl"], it["rec"],
+                                    resid.astype(np.float64)))
+        r = torch.from_numpy(resid).cuda()
+        full.append((it["plan"], it["vp"], it["shots"], r, torch.empty_like(it["vp"])))
+    ws = torch.empty(sgwave.sg_batch_grad_workspace_size(full, ckpt, shots_per_wave), dtype=torch.uint8,
+                     device="cuda")
+    sgwave.sg_batch_adjoint_gradient(full, ws, ckpt, shots_per_wave)
+    torch.cuda.synchronize()
+    for (plan, vp, shots, r, grad), ref in zip(full, refs):
+        # single-slice path on the same residual
+        ws1 = torch.empty(sgwave.sg_grad_workspace_size(plan, shots.nshot, shots.nrec, ckpt), dtype=torch.uint8,
+                          device="cuda")
+        gathers = torch.empty((shots.nshot, plan.geom.nrow, shots.nrec), dtype=torch.float32, device="cuda")
+        sgwave.sg_forward_ckpt(plan, vp, shots, ckpt, gathers, ws1)
+        g1 = torch.empty_like(vp)
+        sgwave.sg_adjoint_gradient(plan, vp, shots, ckpt, r, g1, ws1)
+        torch.cuda.synchronize()
+        a, b = grad.cpu().numpy(), g1.cpu().numpy()
+        if shots_per_wave == 0:
+            assert np.array_equal(a, b)
+        else:
+            assert rel_l2(a, b) <= 1e-6
+        e = rel_l2(a, ref)
+        print("batched gradient rel-L2 %.3e" % e, flush=True)
+        assert e <= TOL
