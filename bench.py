@@ -43,10 +43,17 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the gradient and batched comparisons")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batched-gradient", action="store_true",
+                    help="also run the 4 slices x 100 shots batched gradient (about a minute)")
+    ap.add_argument("--shots-per-wave", type=int, default=25)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
     return ap.parse_args()
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_sha():
@@ -160,6 +167,48 @@ def batched_rate(fwd_rate):
             "launches": launches, "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}
 
 
+def batched_gradient_rate(fwd_rate, shots_per_wave):
+    """4 field slices of uneven size (nz 500-620, nx 801-1001) x 100 shots
+    spread evenly over the full width, nt 10000 at 0.8 ms, receivers on every
+    column: forward with checkpoints every 100 levels, segment recompute and
+    adjoint for all slices in one launch per time block, in waves of
+    `shots_per_wave` shots per slice; random residuals stand in for dJ/dd."""
+    import torch
+    from paper_2605_30541_amd import sgwave, synth
+    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
+    dt, nt, nshot, ckpt = 8e-4, 10000, 100, 100
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    items, pts = [], 0
+    for i, (nz, nx) in enumerate(synth.uneven_sizes(42, 4, nz_range=(500, 620), nx_range=(801, 1001))):
+        geom = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
+        plan = Plan(geom)
+        W = (nx - 1) * 10.0
+        shots = Shots(synth.shot_line(nshot, 0.0, W), synth.surface_receivers(nx, 10.0),
+                      sgwave.ricker_tensor(12.0, dt, nt))
+        v0 = torch.from_numpy(synth.smoothed_1d(synth.field_slice(42 + i, nz, nx), 500.0, 10.0)).cuda()
+        resid = torch.randn((nshot, geom.nrow, nx), dtype=torch.float32, device="cuda", generator=gen)
+        items.append((plan, v0, shots, resid, torch.empty_like(v0)))
+        Nz, Nx = plan.padded_shape
+        pts += Nz * Nx * nshot
+    ws = torch.empty(sgwave.sg_batch_grad_workspace_size(items, ckpt, shots_per_wave), dtype=torch.uint8,
+                     device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sgwave.sg_batch_adjoint_gradient(items, ws, ckpt, shots_per_wave)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    for it in items:
+        sgwave.sg_check_finite(it[4], ws)
+    rate = pts * (nt - 1) / (ms / 1e3) / 1e9
+    return {"workload": "4 uneven field slices (nz 500-620, nx 801-1001, 40-cell sponge) x 100 shots, nt 10000, "
+                        "forward with checkpoints every 100 levels + segment recompute + adjoint, "
+                        "%d shots per slice per wave" % shots_per_wave,
+            "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
+            "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -249,9 +298,15 @@ def main():
                      "bytes_per_update": BYTES_PER_UPDATE},
         "cpu_baseline": None,
     }
+    log("field shot: %.1f Gpt-updates/s" % value)
     if not args.no_extras:
         out["gradient"] = gradient_rate(v, value)
+        log("gradient: %.1f Gpt-steps/s" % out["gradient"]["value"])
         out["batched"] = batched_rate(value)
+        log("batched: %.1f Gpt-updates/s" % out["batched"]["value"])
+    if args.batched_gradient:
+        out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
+        log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -259,6 +314,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
+        log("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(v, geom, src, rec, f0, args.cpu_sample_levels)
     print(json.dumps(out), flush=True)
 
