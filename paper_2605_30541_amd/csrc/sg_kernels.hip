@@ -15,6 +15,8 @@
 // overwrites level n-1 with level n+1 in place.
 #include "sg_internal.h"
 
+#include <type_traits>
+
 namespace sg {
 
 namespace {
@@ -200,11 +202,10 @@ struct TileShape {
 enum { kFwd = 0, kRing = 1, kAdj = 2 };
 
 template <int K, int NWX, int NWZ, int MODE, bool ISO>
-__device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t, int b,
-                                           float (*lds)[TileShape<K, NWX, NWZ>::LDS])
+__device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t, int b, float *lds)
 {
     using TS = TileShape<K, NWX, NWZ>;
-    constexpr int EX = TS::EX, EZ = TS::EZ, NTHR = TS::NTHR, LW = TS::LW;
+    constexpr int EX = TS::EX, EZ = TS::EZ, NTHR = TS::NTHR, LW = TS::LW, NB = TS::LDS;
     constexpr bool ADJ = MODE == kAdj;
     const int tiles = t.ntx * t.ntz;
     const int shot = b / tiles;
@@ -234,10 +235,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // rows [k_lo, k_hi) of this thread's segment are output rows (wave-uniform)
     const int k_lo = __builtin_amdgcn_readfirstlane(min(max(oz - Z0, 0), K));
     const int k_hi = __builtin_amdgcn_readfirstlane(min(max(oz_end - Z0, 0), K));
-    // segment entirely outside the grid rows, or the ghost segment of a top tile
+    // segment entirely outside the grid rows, or the ghost segment of a top
+    // tile (whose rows only the mirror writes)
     const int wave_x0 = ex0 + (w % NWX) * 64;
     const bool seg_dead = Z0 >= s.Nz || Z0 + K <= 0 || wave_x0 >= s.Nx || wave_x0 + 64 <= 0;
-    const bool wr_ok = !(top_tile && Z0 < 0);    // ghost rows are written by the mirror only
     const bool ghost_writer = top_tile && Z0 <= kHalo && Z0 + K > 1;
 
     const int64_t fshot = (int64_t)shot * kFramesPerShot * s.frame;
@@ -246,6 +247,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     float *out_prev = t.fields + fshot + (int64_t)(2 * t.out_pair) * s.frame;
     float *out_cur = out_prev + s.frame;
     const int64_t col = (int64_t)(Z0 + kGuard) * s.pitch + X + kGuard;   // stored index of row k = 0
+    // LDS index of this thread's row k = 0 (buffer 0); buffer 1 starts NB floats later
+    const int lbase = (lz0 + kHalo) * LW + lx + kHalo;
 
     // ---- zero the LDS pad ring of both buffers (read only by cells whose
     // results are discarded; zero keeps every value finite)
@@ -261,16 +264,17 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             c = q2 % (2 * kHalo);
             if (c >= kHalo) c += EX;
         }
-        lds[0][r * LW + c] = 0.f;
-        lds[1][r * LW + c] = 0.f;
+        lds[r * LW + c] = 0.f;
+        lds[NB + r * LW + c] = 0.f;
     }
 
     // ---- load the two input levels (registers; the newer one also to both
     // LDS buffers, so cells that are never recomputed keep their value) and
     // the coefficients.  Cells the scheme does not update (outside the padded
     // grid, the pinned free-surface row) get a2 = W = 0 and value 0, so the
-    // update keeps them 0.
-    float cur[K], prev[K], a2[K], W[K];
+    // update keeps them 0.  A and B hold the two live levels; their roles
+    // alternate every sub-step (the new level overwrites the older one).
+    float A[K], B[K], a2[K], W[K];
     const float gxX = xin ? s.gx[X] : 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -290,10 +294,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         const float a = 1.f / (1.f + gam);
         a2[k] = upd ? 2.f * a : 0.f;
         W[k] = upd ? a * v2 : 0.f;
-        cur[k] = c;
-        prev[k] = upd ? pv : 0.f;
-        lds[0][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
-        lds[1][(lz0 + k + kHalo) * LW + lx + kHalo] = c;
+        A[k] = c;
+        B[k] = upd ? pv : 0.f;
+        lds[lbase + k * LW] = c;
+        lds[NB + lbase + k * LW] = c;
     }
 
     // forward: sources of this shot inside the loaded region (uniform test);
@@ -332,16 +336,20 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     }
     __syncthreads();
 
-    for (int st = 0; st < t.nsteps; ++st) {
-        // forward: `cur` holds level n, the new level is n+1;
-        // adjoint: `cur` holds mu^{n+1}, the new level is mu^n
+    // One sub-step.  PAR selects the roles: cur (level n forward, mu^{n+1}
+    // adjoint) and old (the level before it, overwritten by the new level),
+    // and the LDS buffer read (cur) and written (new).
+    auto substep = [&](auto par, const int st) {
+        constexpr bool PAR = decltype(par)::value;
+        float(&cur)[K] = PAR ? B : A;
+        float(&old)[K] = PAR ? A : B;
+        const int lc = PAR ? NB : 0, ln = PAR ? 0 : NB;
         const int n = ADJ ? t.n - st : t.n + st;
-        const float *Lc = lds[st & 1];
-        float *Ln = lds[(st + 1) & 1];
 
         if (MODE == kFwd && rend > rbeg && n % s.rec_every == 0) {
             // record level n: receivers whose base node is in this output tile
             float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+            const float *Lc = lds + lc;
             for (int q = rbeg + (int)threadIdx.x; q < rend; q += NTHR) {
                 const RecEntry e = s.rec_list[q];
                 row[e.r] = e.w[0] * Lc[e.lds] + e.w[1] * Lc[e.lds + 1] + e.w[2] * Lc[e.lds + LW] +
@@ -374,17 +382,36 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             float up[kHalo], dn[kHalo];
 #pragma unroll
             for (int j = 0; j < kHalo; ++j) {
-                up[j] = Lc[(lz0 + j) * LW + lx + kHalo];
-                dn[j] = Lc[(lz0 + K + kHalo + j) * LW + lx + kHalo];
+                up[j] = lds[lc + lbase + (j - kHalo) * LW];
+                dn[j] = lds[lc + lbase + (K + j) * LW];
             }
-            const float wav = (!ADJ && has_src) ? s.wavelet[(int64_t)shot * s.wavelet_stride + n] : 0.f;
-            // Row k needs rows k-4..k+4 of the current level; once row k is
-            // done, row k-4 is dead and is replaced by its new value (the
-            // register window of new values stays 5 rows deep).
-            float nw[K];
+            // x neighbours of row k: xv[m-1] = p(x+m), xv[kHalo+m-1] = p(x-m),
+            // read one row ahead of the arithmetic.  The LDS byte address of
+            // (row, x - 4) steps down one row per call in one register (the
+            // empty asm keeps the optimiser from folding each row's offset
+            // into the reads, which would cost an address add per read pair,
+            // or from keeping every row's address live), so the eight reads
+            // use small immediate offsets.
+            int roff = (lc + lbase - kHalo) * 4;
+            auto xrow = [&](float(&xv)[2 * kHalo]) {
+                asm volatile("" : "+v"(roff));
+                const float *rp = (const float *)((const char *)lds + roff);
+#pragma unroll
+                for (int m = 1; m <= kHalo; ++m) {
+                    xv[m - 1] = rp[kHalo + m];
+                    xv[kHalo + m - 1] = rp[kHalo - m];
+                }
+                roff += LW * 4;
+            };
+            // (the adjoint, short of registers, reads each row where it is used)
+            constexpr bool kAhead = !ADJ;
+            float xa[2 * kHalo], xb[2 * kHalo];
+            if (kAhead) xrow(xa);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float *rowp = Lc + (lz0 + k + kHalo) * LW + lx + kHalo;
+                if (!kAhead) xrow(xa);
+                else if (k + 1 < K) xrow((k & 1) ? xa : xb);
+                const float(&xv)[2 * kHalo] = (kAhead && (k & 1)) ? xb : xa;
                 float lap = 0.f;
                 if (ISO) {
                     // dz == dx: one weight per m, sum_m c_m ((z+m)+(z-m)+(x+m)+(x-m) - 4p)
@@ -393,7 +420,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                     for (int m = 1; m <= kHalo; ++m) {
                         const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
                         const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
-                        lap = fmaf(s.cz[m], ((zp + zm) + (rowp[m] + rowp[-m])) + c4, lap);
+                        lap = fmaf(s.cz[m], ((zp + zm) + (xv[m - 1] + xv[kHalo + m - 1])) + c4, lap);
                     }
                 } else {
                     const float c2 = cur[k] + cur[k];
@@ -401,36 +428,63 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                     for (int m = 1; m <= kHalo; ++m) {
                         const float zp = k + m < K ? cur[k + m] : dn[k + m - K];
                         const float zm = k - m >= 0 ? cur[k - m] : up[k - m + kHalo];
-                        lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, rowp[m] + rowp[-m], c2);
+                        lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, xv[m - 1] + xv[kHalo + m - 1], c2);
                     }
                 }
-                float v = leapfrog(W[k], lap, a2[k], cur[k], prev[k]);
-                if (!ADJ && has_src) {
-                    float amp = 0.f;
-#pragma unroll
-                    for (int j = 0; j < kNodes; ++j)
-                        if (s.src_ix[shot * kNodes + j] == X && s.src_iz[shot * kNodes + j] == Z0 + k)
-                            amp += s.src_w[shot * kNodes + j];
-                    v = fmaf(W[k], amp * wav, v);
+                old[k] = leapfrog(W[k], lap, a2[k], cur[k], old[k]);
+                lds[ln + lbase + k * LW] = old[k];
+            }
+        }
+
+        // point sources (forward) or the residual (adjoint) enter the new
+        // level in LDS, one thread per node, after which the owners of those
+        // cells take their values back from LDS
+        const bool inj_src = !ADJ && has_src;
+        const bool inj_res = ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0;
+        if (inj_src || inj_res) {
+            __syncthreads();
+            float *Ln = lds + ln;
+            if (inj_src) {
+                // p^{n+1} += W S^n at the bilinear nodes of this shot's source
+                const int j = threadIdx.x;
+                if (j < kNodes) {
+                    const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
+                    const float sw = s.src_w[shot * kNodes + j];
+                    const bool inside = sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
+                    if (inside && sw != 0.f && sz >= 0 && sz < s.Nz && sx >= 0 && sx < s.Nx &&
+                        !(s.free_top && sz == 0)) {
+                        const float v2 = s.V2[(int64_t)(sz + kGuard) * s.pitch + sx + kGuard];
+                        const float a = 1.f / (1.f + (s.gx[sx] + s.gz[sz]) * v2);
+                        const float wav = s.wavelet[(int64_t)shot * s.wavelet_stride + n];
+                        const int li = (sz - ez0 + kHalo) * LW + sx - ex0 + kHalo;
+                        Ln[li] = fmaf(a * v2, sw * wav, Ln[li]);
+                    }
                 }
-                nw[k] = v;
-                if (wr_ok) Ln[(lz0 + k + kHalo) * LW + lx + kHalo] = v;
-                if (k >= kHalo) {
-                    prev[k - kHalo] = cur[k - kHalo];
-                    cur[k - kHalo] = nw[k - kHalo];
+            } else {
+                // mu^n += W R^T r^n at the receiver nodes (the sum per node in a fixed order)
+                const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+                for (int e = ebeg + (int)threadIdx.x; e < eend; e += NTHR) {
+                    float acc = 0.f;
+                    for (int q = t.inj.pstart[e]; q < t.inj.pstart[e + 1]; ++q) acc += t.inj.w[q] * rrow[t.inj.rid[q]];
+                    const int iz = t.inj.iz[e], ix = t.inj.ix[e];
+                    const float v2 = s.V2[(int64_t)(iz + kGuard) * s.pitch + ix + kGuard];
+                    const float Wc = v2 / (1.f + (s.gx[ix] + s.gz[iz]) * v2);
+                    Ln[t.inj.lds[e]] += Wc * acc;
                 }
             }
+            __syncthreads();
+            if (active) {
 #pragma unroll
-            for (int k = K - kHalo; k < K; ++k) {
-                prev[k] = cur[k];
-                cur[k] = nw[k];
+                for (int k = 0; k < K; ++k) old[k] = Ln[lbase + k * LW];
             }
+        }
+        if (active) {
             if (ghost_writer) {
                 // ghost rows -1..-4 of the new level: minus rows 1..4
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int Z = Z0 + k;
-                    if (Z >= 1 && Z <= kHalo) Ln[(-Z - ez0 + kHalo) * LW + lx + kHalo] = -cur[k];
+                    if (Z >= 1 && Z <= kHalo) lds[ln + (-Z - ez0 + kHalo) * LW + lx + kHalo] = -old[k];
                 }
             }
             if (MODE == kRing && xout) {
@@ -438,33 +492,20 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (k >= k_lo && k < k_hi) rl[col + (int64_t)k * s.pitch] = cur[k];
-            }
-        }
-        if (ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0) {
-            // inject W R^T r^n into the new level at the receiver nodes (one
-            // thread per node, so the sum per node is in a fixed order), then
-            // let every thread take its cells back from LDS
-            __syncthreads();
-            const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
-            for (int e = ebeg + (int)threadIdx.x; e < eend; e += NTHR) {
-                float acc = 0.f;
-                for (int q = t.inj.pstart[e]; q < t.inj.pstart[e + 1]; ++q) acc += t.inj.w[q] * rrow[t.inj.rid[q]];
-                const int iz = t.inj.iz[e], ix = t.inj.ix[e];
-                const float v2 = s.V2[(int64_t)(iz + kGuard) * s.pitch + ix + kGuard];
-                const float Wc = v2 / (1.f + (s.gx[ix] + s.gz[iz]) * v2);
-                const float add = Wc * acc;
-                Ln[t.inj.lds[e]] += add;
-                if (top_tile && iz >= 1 && iz <= kHalo) Ln[(-iz - ez0 + kHalo) * LW + ix - ex0 + kHalo] -= add;
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) cur[k] = Ln[(lz0 + k + kHalo) * LW + lx + kHalo];
+                    if (k >= k_lo && k < k_hi) rl[col + (int64_t)k * s.pitch] = old[k];
             }
         }
         __syncthreads();
+    };
+
+    int st = 0;
+    for (; st + 2 <= t.nsteps; st += 2) {
+        substep(std::false_type{}, st);
+        substep(std::true_type{}, st + 1);
     }
+    if (st < t.nsteps) substep(std::false_type{}, st);
+    // the newest level is in A after an even number of sub-steps, else in B
+    const bool odd = t.nsteps & 1;
 
     // ---- write the output tile: the last two levels
     if (xout) {
@@ -472,8 +513,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         for (int k = 0; k < K; ++k) {
             if (k >= k_lo && k < k_hi) {
                 const int64_t i = col + (int64_t)k * s.pitch;
-                out_cur[i] = cur[k];
-                out_prev[i] = prev[k];
+                out_cur[i] = odd ? B[k] : A[k];
+                out_prev[i] = odd ? A[k] : B[k];
                 if (ADJ) {
                     // Kahan-compensated accumulation of this launch's partial sum
                     float *hs = t.hsum + (int64_t)shot * s.frame;
@@ -495,7 +536,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
 template <int K, int NWX, int NWZ, int MODE, bool ISO>
 __global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled(SliceDesc s, TileArgs t)
 {
-    __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
+    __shared__ float lds[2 * TileShape<K, NWX, NWZ>::LDS];
     tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
@@ -506,7 +547,7 @@ template <int K, int NWX, int NWZ, int MODE, bool ISO>
 __global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled_batch(const BatchItem *__restrict__ items, int nitems,
                                                                  int n, int nsteps, int in_pair, int ring_lo, int ring_hi)
 {
-    __shared__ float lds[2][TileShape<K, NWX, NWZ>::LDS];
+    __shared__ float lds[2 * TileShape<K, NWX, NWZ>::LDS];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int it = 0;
     while (it + 1 < nitems && items[it + 1].block_start <= b) ++it;
