@@ -21,6 +21,9 @@ constexpr int kGuard = 4;
 // Up to four bilinear nodes per source or receiver.
 constexpr int kNodes = 4;
 
+// Largest time block (sub-steps per launch) of the time-blocked kernel.
+constexpr int kMaxTimeBlock = 8;
+
 // Device-side description of one padded slice and its fields.  All offsets
 // are in floats relative to a field's base; node (Iz, Ix) of the padded grid
 // lives at (Iz + kGuard) * pitch + (Ix + kGuard).

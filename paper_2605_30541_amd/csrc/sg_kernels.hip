@@ -274,64 +274,133 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // grid, the pinned free-surface row) get a2 = W = 0 and value 0, so the
     // update keeps them 0.  A and B hold the two live levels; their roles
     // alternate every sub-step (the new level overwrites the older one).
+    // Every load is issued unconditionally from a clamped, in-bounds cell
+    // (ghost rows above a free top read their mirror row) and the values are
+    // selected afterwards, so the loads of all rows are in flight together
+    // instead of one row after another.
+    const int Xc = min(max(X, 0), s.Nx - 1);
     float A[K], B[K], a2[K], W[K];
-    const float gxX = xin ? s.gx[X] : 0.f;
+    {
+        float rc[K], rp[K], rv[K], rg[K];
+        const float gxX = s.gx[Xc];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int Z = Z0 + k;
-        const bool in = xin && Z >= 0 && Z < s.Nz;
-        float c = 0.f, pv = 0.f, v2 = 0.f;
-        if (in) {
-            const int64_t i = col + (int64_t)k * s.pitch;
-            c = in_cur[i];
-            pv = in_prev[i];
-            v2 = s.V2[i];
-        } else if (top_tile && xin && Z < 0 && Z >= -kHalo) {
-            c = -in_cur[(int64_t)(-Z + kGuard) * s.pitch + X + kGuard];   // odd mirror
+        for (int k = 0; k < K; ++k) {
+            const int Z = Z0 + k;
+            const int Zr = min(Z < 0 ? -Z : Z, s.Nz - 1);
+            const int64_t i = (int64_t)(Zr + kGuard) * s.pitch + Xc + kGuard;
+            rc[k] = in_cur[i];
+            rp[k] = in_prev[i];
+            rv[k] = s.V2[i];
+            rg[k] = s.gz[min(max(Z, 0), s.Nz - 1)];
         }
-        const bool upd = in && !(s.free_top && Z == 0);
-        const float gam = upd ? (gxX + s.gz[Z]) * v2 : 0.f;
-        const float a = 1.f / (1.f + gam);
-        a2[k] = upd ? 2.f * a : 0.f;
-        W[k] = upd ? a * v2 : 0.f;
-        A[k] = c;
-        B[k] = upd ? pv : 0.f;
-        lds[lbase + k * LW] = c;
-        lds[NB + lbase + k * LW] = c;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int Z = Z0 + k;
+            const bool in = xin && Z >= 0 && Z < s.Nz;
+            const bool ghost = top_tile && xin && Z < 0 && Z >= -kHalo;   // odd mirror of row -Z
+            const float c = in ? rc[k] : (ghost ? -rc[k] : 0.f);
+            const bool upd = in && !(s.free_top && Z == 0);
+            const float v2 = upd ? rv[k] : 0.f;
+            const float gam = (gxX + rg[k]) * v2;
+            const float a = 1.f / (1.f + gam);
+            a2[k] = upd ? 2.f * a : 0.f;
+            W[k] = upd ? a * v2 : 0.f;
+            A[k] = c;
+            B[k] = upd ? rp[k] : 0.f;
+            lds[lbase + k * LW] = c;
+            lds[NB + lbase + k * LW] = c;
+        }
     }
+    // stored index of this thread's row k = 0 at the clamped column (in bounds
+    // for the output rows of any lane)
+    const int64_t colc = (int64_t)(Z0 + kGuard) * s.pitch + Xc + kGuard;
 
-    // forward: sources of this shot inside the loaded region (uniform test);
-    // receiver entries of the tile
+    // forward: the source nodes of this shot inside the loaded region.  Each
+    // thread keeps the (at most two) nodes in its own column segment: row and
+    // weight; the wavelet samples of this launch go to LDS.  The receiver
+    // entries of the tile: the first NTHR are copied to LDS.
+    __shared__ float wav_s[kMaxTimeBlock];
+    __shared__ RecEntry rec_s[MODE == kFwd ? NTHR : 1];
     bool has_src = false;
+    int sk0 = -1, sk1 = -1;
+    float sw0 = 0.f, sw1 = 0.f;
     int32_t rbeg = 0, rend = 0;
     if (!ADJ) {
 #pragma unroll
         for (int j = 0; j < kNodes; ++j) {
             const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
+            const float sw = s.src_w[shot * kNodes + j];
             has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
+            if (sx == X && sz >= Z0 && sz < Z0 + K && sw != 0.f) {
+                if (sk0 < 0) {
+                    sk0 = sz - Z0;
+                    sw0 = sw;
+                } else {
+                    sk1 = sz - Z0;
+                    sw1 = sw;
+                }
+            }
         }
+        if (has_src && (int)threadIdx.x < t.nsteps)
+            wav_s[threadIdx.x] = s.wavelet[(int64_t)shot * s.wavelet_stride + t.n + threadIdx.x];
         if (MODE == kFwd && s.gathers) {
             rbeg = s.tile_rec[tile];
             rend = s.tile_rec[tile + 1];
+            if (rbeg + (int)threadIdx.x < rend) rec_s[threadIdx.x] = s.rec_list[rbeg + threadIdx.x];
         }
     }
-    // adjoint: receiver nodes in the loaded region; forward levels of the
-    // imaging window (p^{k+1}, p^k), and the partial sums of h
+    // adjoint: the residual injections W R^T r^n of this launch's levels at
+    // the receiver nodes of the loaded region, summed (in a fixed order per
+    // node) before the first sub-step when the tile has at most kInjE nodes
+    constexpr int kInjE = ADJ ? 256 : 1;
+    __shared__ float inj_a[kMaxTimeBlock * kInjE];
+    __shared__ int inj_l[kInjE];
     int32_t ebeg = 0, eend = 0;
+    if (ADJ) {
+        ebeg = t.inj.tile_start[tile];
+        eend = t.inj.tile_start[tile + 1];
+    }
+    const int E = eend - ebeg;
+    const bool inj_pre = ADJ && E > 0 && E <= kInjE;
+    if (inj_pre) {
+        for (int q = threadIdx.x; q < (t.nsteps + 1) * E; q += NTHR) {
+            const int st = q / E, e = q - st * E, eg = ebeg + e;
+            if (st == t.nsteps) {
+                inj_l[e] = t.inj.lds[eg];
+                continue;
+            }
+            const int n = t.n - st;
+            float add = 0.f;
+            if (n >= 1 && n % s.rec_every == 0) {
+                const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
+                float acc = 0.f;
+                for (int j = t.inj.pstart[eg]; j < t.inj.pstart[eg + 1]; ++j) acc += t.inj.w[j] * rrow[t.inj.rid[j]];
+                const int iz = t.inj.iz[eg], ix = t.inj.ix[eg];
+                const float v2 = s.V2[(int64_t)(iz + kGuard) * s.pitch + ix + kGuard];
+                const float Wc = v2 / (1.f + (s.gx[ix] + s.gz[iz]) * v2);
+                add = Wc * acc;
+            }
+            inj_a[st * kInjE + e] = add;
+        }
+    }
+    // adjoint: forward levels of the imaging window (p^{k+1}, p^k), and the
+    // partial sums of h
     float pa[ADJ ? K : 1], pb[ADJ ? K : 1], hp[ADJ ? K : 1];
     if (ADJ) {
         const float *ringb = t.ring + (int64_t)shot * t.ring_shot;
-        ebeg = t.inj.tile_start[tile];
-        eend = t.inj.tile_start[tile + 1];
         const int L1 = t.n + 1, L0 = t.n;
         const bool h1 = L1 >= t.ring_lo && L1 <= t.ring_hi, h0 = L0 >= t.ring_lo && L0 <= t.ring_hi;
+        const float *r1 = ringb + (int64_t)(h1 ? L1 - t.ring_lo : 0) * s.frame;
+        const float *r0 = ringb + (int64_t)(h0 ? L0 - t.ring_lo : 0) * s.frame;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const bool own = xout && k >= k_lo && k < k_hi;
-            const int64_t i = col + (int64_t)k * s.pitch;
-            pa[k] = (own && h1) ? ringb[(int64_t)(L1 - t.ring_lo) * s.frame + i] : 0.f;
-            pb[k] = (own && h0) ? ringb[(int64_t)(L0 - t.ring_lo) * s.frame + i] : 0.f;
-            hp[k] = 0.f;
+            pa[k] = pb[k] = hp[k] = 0.f;
+            if (k >= k_lo && k < k_hi) {           // output rows: in bounds at the clamped column
+                const int64_t i = colc + (int64_t)k * s.pitch;
+                const float v1 = h1 ? r1[i] : 0.f, v0 = h0 ? r0[i] : 0.f;
+                pa[k] = xout ? v1 : 0.f;
+                pb[k] = xout ? v0 : 0.f;
+            }
         }
     }
     __syncthreads();
@@ -339,8 +408,9 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // One sub-step.  PAR selects the roles: cur (level n forward, mu^{n+1}
     // adjoint) and old (the level before it, overwritten by the new level),
     // and the LDS buffer read (cur) and written (new).
-    auto substep = [&](auto par, const int st) {
+    auto substep = [&](auto par, auto src, const int st) {
         constexpr bool PAR = decltype(par)::value;
+        constexpr bool SRC = !ADJ && decltype(src)::value;   // this tile holds a source node
         float(&cur)[K] = PAR ? B : A;
         float(&old)[K] = PAR ? A : B;
         const int lc = PAR ? NB : 0, ln = PAR ? 0 : NB;
@@ -350,11 +420,12 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             // record level n: receivers whose base node is in this output tile
             float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
             const float *Lc = lds + lc;
-            for (int q = rbeg + (int)threadIdx.x; q < rend; q += NTHR) {
-                const RecEntry e = s.rec_list[q];
+            auto sample = [&](const RecEntry &e) {
                 row[e.r] = e.w[0] * Lc[e.lds] + e.w[1] * Lc[e.lds + 1] + e.w[2] * Lc[e.lds + LW] +
                            e.w[3] * Lc[e.lds + LW + 1];
-            }
+            };
+            if (rbeg + (int)threadIdx.x < rend) sample(rec_s[threadIdx.x]);
+            for (int q = rbeg + NTHR + (int)threadIdx.x; q < rend; q += NTHR) sample(s.rec_list[q]);
         }
         if (ADJ) {
             // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1})
@@ -362,10 +433,15 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             const int Lm = n - 1;
             const bool hm = Lm >= t.ring_lo && Lm <= t.ring_hi;
             const bool image = n <= t.nt - 2;
+            const float *rm = ringb + (int64_t)(hm ? Lm - t.ring_lo : 0) * s.frame;
+            float rv[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                rv[k] = (hm && k >= k_lo && k < k_hi) ? rm[colc + (int64_t)k * s.pitch] : 0.f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (k >= k_lo && k < k_hi) {
-                    const float pc = (xout && hm) ? ringb[(int64_t)(Lm - t.ring_lo) * s.frame + col + (int64_t)k * s.pitch] : 0.f;
+                    const float pc = xout ? rv[k] : 0.f;
                     if (image) hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
                     pa[k] = pb[k];
                     pb[k] = pc;
@@ -405,6 +481,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             };
             // (the adjoint, short of registers, reads each row where it is used)
             constexpr bool kAhead = !ADJ;
+            const float wav = SRC ? wav_s[st] : 0.f;
             float xa[2 * kHalo], xb[2 * kHalo];
             if (kAhead) xrow(xa);
 #pragma unroll
@@ -431,37 +508,25 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                         lap = lap_pair(lap, s.cz[m], s.cx[m], zp + zm, xv[m - 1] + xv[kHalo + m - 1], c2);
                     }
                 }
-                old[k] = leapfrog(W[k], lap, a2[k], cur[k], old[k]);
-                lds[ln + lbase + k * LW] = old[k];
+                float v = leapfrog(W[k], lap, a2[k], cur[k], old[k]);
+                if (SRC) {
+                    // p^{n+1} += W S^n at this thread's source nodes
+                    if (k == sk0) v = fmaf(W[k], sw0 * wav, v);
+                    if (k == sk1) v = fmaf(W[k], sw1 * wav, v);
+                }
+                old[k] = v;
+                lds[ln + lbase + k * LW] = v;
             }
         }
 
-        // point sources (forward) or the residual (adjoint) enter the new
-        // level in LDS, one thread per node, after which the owners of those
-        // cells take their values back from LDS
-        const bool inj_src = !ADJ && has_src;
-        const bool inj_res = ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0;
-        if (inj_src || inj_res) {
+        // adjoint: the residual enters the new level in LDS, one thread per
+        // node, after which the owners of those cells take their values back
+        if (ADJ && eend > ebeg && n >= 1 && n % s.rec_every == 0) {
             __syncthreads();
             float *Ln = lds + ln;
-            if (inj_src) {
-                // p^{n+1} += W S^n at the bilinear nodes of this shot's source
-                const int j = threadIdx.x;
-                if (j < kNodes) {
-                    const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
-                    const float sw = s.src_w[shot * kNodes + j];
-                    const bool inside = sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
-                    if (inside && sw != 0.f && sz >= 0 && sz < s.Nz && sx >= 0 && sx < s.Nx &&
-                        !(s.free_top && sz == 0)) {
-                        const float v2 = s.V2[(int64_t)(sz + kGuard) * s.pitch + sx + kGuard];
-                        const float a = 1.f / (1.f + (s.gx[sx] + s.gz[sz]) * v2);
-                        const float wav = s.wavelet[(int64_t)shot * s.wavelet_stride + n];
-                        const int li = (sz - ez0 + kHalo) * LW + sx - ex0 + kHalo;
-                        Ln[li] = fmaf(a * v2, sw * wav, Ln[li]);
-                    }
-                }
+            if (inj_pre) {
+                for (int e = threadIdx.x; e < E; e += NTHR) Ln[inj_l[e]] += inj_a[st * kInjE + e];
             } else {
-                // mu^n += W R^T r^n at the receiver nodes (the sum per node in a fixed order)
                 const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
                 for (int e = ebeg + (int)threadIdx.x; e < eend; e += NTHR) {
                     float acc = 0.f;
@@ -498,16 +563,36 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         __syncthreads();
     };
 
-    int st = 0;
-    for (; st + 2 <= t.nsteps; st += 2) {
-        substep(std::false_type{}, st);
-        substep(std::true_type{}, st + 1);
-    }
-    if (st < t.nsteps) substep(std::false_type{}, st);
+    auto run = [&](auto src) {
+        int st = 0;
+        for (; st + 2 <= t.nsteps; st += 2) {
+            substep(std::false_type{}, src, st);
+            substep(std::true_type{}, src, st + 1);
+        }
+        if (st < t.nsteps) substep(std::false_type{}, src, st);
+    };
+    if (!ADJ && has_src)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
     // the newest level is in A after an even number of sub-steps, else in B
     const bool odd = t.nsteps & 1;
 
     // ---- write the output tile: the last two levels
+    float hsv[ADJ ? K : 1], hcv[ADJ ? K : 1];
+    float *hs = ADJ ? t.hsum + (int64_t)shot * s.frame : nullptr;
+    float *hc = ADJ ? t.hcomp + (int64_t)shot * s.frame : nullptr;
+    if (ADJ) {
+        // Kahan pair of the output rows, all loads in flight together
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            hsv[k] = hcv[k] = 0.f;
+            if (k >= k_lo && k < k_hi) {
+                hsv[k] = hs[colc + (int64_t)k * s.pitch];
+                hcv[k] = hc[colc + (int64_t)k * s.pitch];
+            }
+        }
+    }
     if (xout) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -517,11 +602,9 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 out_prev[i] = odd ? A[k] : B[k];
                 if (ADJ) {
                     // Kahan-compensated accumulation of this launch's partial sum
-                    float *hs = t.hsum + (int64_t)shot * s.frame;
-                    float *hc = t.hcomp + (int64_t)shot * s.frame;
-                    const float y = hp[k] - hc[i];
-                    const float tt = hs[i] + y;
-                    hc[i] = (tt - hs[i]) - y;
+                    const float y = hp[k] - hcv[k];
+                    const float tt = hsv[k] + y;
+                    hc[i] = (tt - hsv[k]) - y;
                     hs[i] = tt;
                 }
             }

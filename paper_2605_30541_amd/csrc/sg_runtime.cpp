@@ -311,6 +311,8 @@ sg_status tiling_for(const sg_plan *p, const sg_tuning &t, int *config, sg::Tili
 {
     *config = shape_of(t);
     if (*config < 0) return fail(SG_EUNSUPPORTED, "no kernel built for a %d x %d tile", t.tile_x, t.tile_z);
+    if (t.time_block < 1 || t.time_block > sg::kMaxTimeBlock)
+        return fail(SG_EINVAL, "time_block must be in 1..%d", sg::kMaxTimeBlock);
     const sg::TiledShape sh = sg::tiled_shape(*config);
     *T = sg::make_tiling(p->Nz, p->Nx, p->g.top == SG_TOP_FREE, sh.ex, sh.ez, sh.k, t.time_block);
     if (!T->ok) return fail(SG_EUNSUPPORTED, "time block %d leaves no output tile in %d x %d", t.time_block,
@@ -857,7 +859,8 @@ sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t)
         return SG_OK;
     }
     if (t->variant < 0 || t->variant > 2) return fail(SG_EINVAL, "variant must be 0, 1 or 2");
-    if (t->time_block < 0 || t->time_block > 8) return fail(SG_EINVAL, "time_block must be in 0..8");
+    if (t->time_block < 0 || t->time_block > sg::kMaxTimeBlock)
+        return fail(SG_EINVAL, "time_block must be in 0..%d", sg::kMaxTimeBlock);
     if (t->tile_x < 0 || t->tile_z < 0) return fail(SG_EINVAL, "tile sizes must be >= 0");
     if (t->rows_per_thread < 0) return fail(SG_EINVAL, "rows_per_thread must be >= 0");
     if (t->variant != 1 && (t->tile_x || t->tile_z) && shape_of(*t) < 0)
