@@ -151,7 +151,7 @@ hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total
 hipError_t launch_ring_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                    int in_pair, int config, bool iso, int ring_lo, hipStream_t st);
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                      int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st);
+                                      int in_pair, int config, bool iso, int ring_lo, int ring_hi, hipStream_t st);
 // dst[shot][0..n) = src[shot][0..n) for every shot (strides in floats)
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
                        hipStream_t st);

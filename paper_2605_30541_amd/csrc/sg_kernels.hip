@@ -383,24 +383,26 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             inj_a[st * kInjE + e] = add;
         }
     }
-    // adjoint: forward levels of the imaging window (p^{k+1}, p^k), and the
-    // partial sums of h
-    float pa[ADJ ? K : 1], pb[ADJ ? K : 1], hp[ADJ ? K : 1];
+    // adjoint: forward levels of the imaging window (p^{k+1}, p^k, and p^{k-1}
+    // read one sub-step ahead), and the partial sums of h.  Only the output
+    // rows are read (in bounds at the clamped column); other lanes keep 0.
+    float pa[ADJ ? K : 1], pb[ADJ ? K : 1], pn[ADJ ? K : 1], hp[ADJ ? K : 1];
+    const float *ringb = ADJ ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
+    auto ring_level = [&](int L, float(&dst)[ADJ ? K : 1]) {
+        const bool h = L >= t.ring_lo && L <= t.ring_hi;
+        const float *rl = ringb + (int64_t)(h ? L - t.ring_lo : 0) * s.frame;
+#pragma unroll
+        for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? rl[colc + (int64_t)k * s.pitch] : 0.f;
+    };
     if (ADJ) {
-        const float *ringb = t.ring + (int64_t)shot * t.ring_shot;
-        const int L1 = t.n + 1, L0 = t.n;
-        const bool h1 = L1 >= t.ring_lo && L1 <= t.ring_hi, h0 = L0 >= t.ring_lo && L0 <= t.ring_hi;
-        const float *r1 = ringb + (int64_t)(h1 ? L1 - t.ring_lo : 0) * s.frame;
-        const float *r0 = ringb + (int64_t)(h0 ? L0 - t.ring_lo : 0) * s.frame;
+        ring_level(t.n + 1, pa);
+        ring_level(t.n, pb);
+        ring_level(t.n - 1, pn);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            pa[k] = pb[k] = hp[k] = 0.f;
-            if (k >= k_lo && k < k_hi) {           // output rows: in bounds at the clamped column
-                const int64_t i = colc + (int64_t)k * s.pitch;
-                const float v1 = h1 ? r1[i] : 0.f, v0 = h0 ? r0[i] : 0.f;
-                pa[k] = xout ? v1 : 0.f;
-                pb[k] = xout ? v0 : 0.f;
-            }
+            pa[k] = xout ? pa[k] : 0.f;
+            pb[k] = xout ? pb[k] : 0.f;
+            hp[k] = 0.f;
         }
     }
     __syncthreads();
@@ -428,25 +430,20 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             for (int q = rbeg + NTHR + (int)threadIdx.x; q < rend; q += NTHR) sample(s.rec_list[q]);
         }
         if (ADJ) {
-            // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1})
-            const float *ringb = t.ring + (int64_t)shot * t.ring_shot;
-            const int Lm = n - 1;
-            const bool hm = Lm >= t.ring_lo && Lm <= t.ring_hi;
+            // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1}),
+            // then the loads of p^{n-2} for the next sub-step go out, to land
+            // while this sub-step computes
             const bool image = n <= t.nt - 2;
-            const float *rm = ringb + (int64_t)(hm ? Lm - t.ring_lo : 0) * s.frame;
-            float rv[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                rv[k] = (hm && k >= k_lo && k < k_hi) ? rm[colc + (int64_t)k * s.pitch] : 0.f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (k >= k_lo && k < k_hi) {
-                    const float pc = xout ? rv[k] : 0.f;
+                    const float pc = xout ? pn[k] : 0.f;
                     if (image) hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
                     pa[k] = pb[k];
                     pb[k] = pc;
                 }
             }
+            if (st + 1 < t.nsteps) ring_level(n - 2, pn);
         }
 
         // rows still needed after this sub-step (local rows [need_lo, need_hi))
@@ -751,8 +748,8 @@ Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb)
     return T;
 }
 
-// The isotropic forms (dz == dx: the z and x weights are equal) are built for
-// the forward modes; the adjoint uses the general form.
+// Every mode is built in the isotropic form (dz == dx: the z and x weights
+// are equal, one weight per m) and the general form.
 template <int MODE, bool ISO>
 static hipError_t launch_tiled_batch_iso(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
                                          int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st)
@@ -787,10 +784,12 @@ hipError_t launch_ring_tiled_batch(const BatchItem *items, int nitems, int total
 }
 
 hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,
-                                      int in_pair, int config, int ring_lo, int ring_hi, hipStream_t st)
+                                      int in_pair, int config, bool iso, int ring_lo, int ring_hi, hipStream_t st)
 {
-    return launch_tiled_batch_iso<kAdj, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo,
-                                               ring_hi, st);
+    return iso ? launch_tiled_batch_iso<kAdj, true>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo,
+                                                    ring_hi, st)
+               : launch_tiled_batch_iso<kAdj, false>(items, nitems, total_blocks, n, nsteps, in_pair, config, ring_lo,
+                                                     ring_hi, st);
 }
 
 template <int MODE, bool ISO>
@@ -823,7 +822,7 @@ hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, 
 
 hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
-    return launch_tiled<kAdj, false>(s, t, config, st);
+    return isotropic(s) ? launch_tiled<kAdj, true>(s, t, config, st) : launch_tiled<kAdj, false>(s, t, config, st);
 }
 
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,

@@ -1412,7 +1412,7 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             }
             for (int k0 = hi; k0 >= lo;) {
                 const int ns = std::min(t.time_block, k0 - lo + 1);
-                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, lo - 1, last, st));
+                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, iso, lo - 1, last, st));
                 mpair ^= 1;
                 k0 -= ns;
             }

@@ -136,3 +136,40 @@ def test_autograd_function_backward_equals_direct_call():
     assert np.allclose(vp.grad.cpu().numpy(), direct, rtol=0, atol=1e-6 * np.abs(direct).max())
     ref = oracle.gradient(_og(g), v.astype(np.float64), src, wl, rec, resid.astype(np.float64))
     assert rel_l2(vp.grad.cpu().numpy(), ref) <= TOL
+
+
+GOLDEN_FIELD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "field_gradient_16shots.npz")
+
+
+def test_field_scale_gradient_sixteen_shots_full_length():
+    """The differentiable workload at full size: the 620 x 1001 field slice
+    (seed 42, 40-cell sponge, free surface), 16 shots at 10 m evenly spaced on
+    [1.1, 8.9] km, 1001 receivers, 10000 levels of 0.8 ms, a 12 Hz Ricker,
+    start model = lateral mean smoothed in depth (500 m), checkpoints every
+    100 levels.  The GPU forms its residual from its own FP32 gathers on the
+    true and start models; the reference is the FP64 oracle's gradient and
+    misfit stored by golden/make_field_gradient.py (oracle calls only)."""
+    import torch
+    ref = np.load(GOLDEN_FIELD)
+    nz, nx, h, dt, nt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 10000, 16, 100
+    g = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
+    v_true = synth.field_slice(42, nz, nx)
+    v0 = synth.smoothed_1d(v_true, 500.0, h)
+    w = torch.from_numpy(oracle.ricker(12.0, dt, nt).astype(np.float32)).reshape(1, -1).cuda()
+    shots = Shots(synth.shot_line(nshot, 1100.0, 8900.0), synth.surface_receivers(nx, h), w)
+    plan = Plan(g)
+    ws = torch.empty(sgwave.sg_grad_workspace_size(plan, nshot, nx, ckpt), dtype=torch.uint8, device="cuda")
+    d_obs = torch.empty((nshot, g.nrow, nx), dtype=torch.float32, device="cuda")
+    sgwave.sg_forward(plan, torch.from_numpy(v_true).cuda(), shots, d_obs, None, ws)
+    vp = torch.from_numpy(v0).cuda()
+    d = torch.empty_like(d_obs)
+    sgwave.sg_forward_ckpt(plan, vp, shots, ckpt, d, ws)
+    resid = d - d_obs
+    grad = torch.empty_like(vp)
+    sgwave.sg_adjoint_gradient(plan, vp, shots, ckpt, resid, grad, ws)
+    misfit = 0.5 * float((resid.double() ** 2).sum())
+    e_m = abs(misfit - float(ref["misfit"])) / float(ref["misfit"])
+    e = rel_l2(grad.cpu().numpy(), ref["grad"].astype(np.float64))
+    print("16-shot misfit rel err %.3e, gradient rel-L2 %.3e" % (e_m, e), flush=True)
+    assert e_m <= TOL
+    assert e <= TOL
