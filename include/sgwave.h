@@ -272,6 +272,18 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
                            void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Batched autotuner: times every built tile shape with every admissible time
+ * block that tiles every item, on the whole batch -- trial_levels (>= 8)
+ * levels of the batched time-stepping launches after one untimed pass -- and
+ * returns the fastest in *best, to pass to sg_batch_forward (or to
+ * sg_batch_adjoint_gradient).  Uses the workspace of sg_batch_forward; no
+ * output of the items is written and no plan is changed.  Synchronises the
+ * stream.
+ */
+sg_status sg_batch_autotune(const sg_batch_item *items, int32_t nitems, int32_t trial_levels, void *ws,
+                            size_t ws_bytes, void *stream, sg_tuning *best);
+
+/*
  * Batched velocity gradients over several slices of uneven size (items share
  * dt and nt).  Shots run in waves of at most shots_per_wave shots per item
  * (<= 0: all at once), so the checkpoint and recompute store fits the

@@ -154,6 +154,47 @@ __global__ void __launch_bounds__(256) k_record(SliceDesc s, int n, int slot, in
     record_level(s, cur, shot, n, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
 }
 
+// Loads and stores through pointers that address global memory (device
+// allocations).  Pointers read from memory (the batched item table) are not
+// known to the compiler to be global, and a plain access through them would be
+// a flat operation, which also holds up every LDS wait; the cast to the
+// global address space makes it a global operation.
+template <class T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+// The same at a byte offset from a base pointer.  Offsets within one stored
+// field (or one ring level) stay far below 4 GiB; a 32-bit offset from a
+// wave-uniform base is what the global load/store instructions take directly
+// (base in scalar registers, offset in a vector register), so a row costs one
+// vector add instead of 64-bit address arithmetic per array.
+template <class T>
+__device__ __forceinline__ T gload_at(const T *base, uint32_t byte_off)
+{
+    return gload((const T *)((const char *)base + byte_off));
+}
+template <class T>
+__device__ __forceinline__ void gstore_at(T *base, uint32_t byte_off, T v)
+{
+    gstore((T *)((char *)base + byte_off), v);
+}
+
+__device__ __forceinline__ RecEntry gload_rec(const RecEntry *p)
+{
+    RecEntry e;
+    e.lds = gload(&p->lds);
+    e.r = gload(&p->r);
+#pragma unroll
+    for (int j = 0; j < kNodes; ++j) e.w[j] = gload(&p->w[j]);
+    return e;
+}
+
 // Maps a launch-order block index to a logical tile so that consecutive
 // logical tiles (neighbours in one shot) land on the same XCD: the hardware
 // deals workgroups round-robin over the 8 XCDs, each with its own L2.
@@ -226,6 +267,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     oz_end = min(oz_end, s.Nz);
     const int ox = txi * t.tx, ox_end = min(ox + t.tx, s.Nx), ex0 = ox - halo;
 
+    // the wave index is made explicitly uniform, so that everything derived
+    // from it (rows, row addresses, row conditions) lives in scalar registers
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lx = (w % NWX) * 64 + lane;        // local column in [0, EX)
     const int lz0 = (w / NWX) * K;               // first local row of this thread (wave-uniform)
@@ -246,7 +289,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     const float *in_cur = in_prev + s.frame;
     float *out_prev = t.fields + fshot + (int64_t)(2 * t.out_pair) * s.frame;
     float *out_cur = out_prev + s.frame;
-    const int64_t col = (int64_t)(Z0 + kGuard) * s.pitch + X + kGuard;   // stored index of row k = 0
+    // byte offset in a stored field of (row Z0 + k, column X): a uniform row
+    // part rowb(k) plus the lane's column part xo4 (xc4 at the clamped column)
+    auto rowb = [&](int k) { return (uint32_t)((Z0 + k + kGuard) * s.pitch) * 4u; };
+    const uint32_t xo4 = (uint32_t)(X + kGuard) * 4u;
     // LDS index of this thread's row k = 0 (buffer 0); buffer 1 starts NB floats later
     const int lbase = (lz0 + kHalo) * LW + lx + kHalo;
 
@@ -282,16 +328,17 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     float A[K], B[K], a2[K], W[K];
     {
         float rc[K], rp[K], rv[K], rg[K];
-        const float gxX = s.gx[Xc];
+        const float gxX = gload(s.gx + Xc);
+        const uint32_t xc4 = (uint32_t)(Xc + kGuard) * 4u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int Z = Z0 + k;
             const int Zr = min(Z < 0 ? -Z : Z, s.Nz - 1);
-            const int64_t i = (int64_t)(Zr + kGuard) * s.pitch + Xc + kGuard;
-            rc[k] = in_cur[i];
-            rp[k] = in_prev[i];
-            rv[k] = s.V2[i];
-            rg[k] = s.gz[min(max(Z, 0), s.Nz - 1)];
+            const uint32_t ob = (uint32_t)((Zr + kGuard) * s.pitch) * 4u + xc4;
+            rc[k] = gload_at(in_cur, ob);
+            rp[k] = gload_at(in_prev, ob);
+            rv[k] = gload_at(s.V2, ob);
+            rg[k] = gload(s.gz + min(max(Z, 0), s.Nz - 1));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -302,6 +349,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             const bool upd = in && !(s.free_top && Z == 0);
             const float v2 = upd ? rv[k] : 0.f;
             const float gam = (gxX + rg[k]) * v2;
+            // a = 1 / (1 + gamma); the division is skipped by waves with no
+            // sponge cell in this row (there gamma = 0 and a = 1 exactly)
             const float a = 1.f / (1.f + gam);
             a2[k] = upd ? 2.f * a : 0.f;
             W[k] = upd ? a * v2 : 0.f;
@@ -311,9 +360,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             lds[NB + lbase + k * LW] = c;
         }
     }
-    // stored index of this thread's row k = 0 at the clamped column (in bounds
-    // for the output rows of any lane)
-    const int64_t colc = (int64_t)(Z0 + kGuard) * s.pitch + Xc + kGuard;
+    // the clamped column (in bounds for the output rows of any lane)
+    const uint32_t xc4 = (uint32_t)(Xc + kGuard) * 4u;
 
     // forward: the source nodes of this shot inside the loaded region.  Each
     // thread keeps the (at most two) nodes in its own column segment: row and
@@ -328,8 +376,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     if (!ADJ) {
 #pragma unroll
         for (int j = 0; j < kNodes; ++j) {
-            const int sz = s.src_iz[shot * kNodes + j], sx = s.src_ix[shot * kNodes + j];
-            const float sw = s.src_w[shot * kNodes + j];
+            const int sz = gload(s.src_iz + shot * kNodes + j), sx = gload(s.src_ix + shot * kNodes + j);
+            const float sw = gload(s.src_w + shot * kNodes + j);
             has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
             if (sx == X && sz >= Z0 && sz < Z0 + K && sw != 0.f) {
                 if (sk0 < 0) {
@@ -342,11 +390,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             }
         }
         if (has_src && (int)threadIdx.x < t.nsteps)
-            wav_s[threadIdx.x] = s.wavelet[(int64_t)shot * s.wavelet_stride + t.n + threadIdx.x];
+            wav_s[threadIdx.x] = gload(s.wavelet + (int64_t)shot * s.wavelet_stride + t.n + threadIdx.x);
         if (MODE == kFwd && s.gathers) {
-            rbeg = s.tile_rec[tile];
-            rend = s.tile_rec[tile + 1];
-            if (rbeg + (int)threadIdx.x < rend) rec_s[threadIdx.x] = s.rec_list[rbeg + threadIdx.x];
+            rbeg = gload(s.tile_rec + tile);
+            rend = gload(s.tile_rec + tile + 1);
+            if (rbeg + (int)threadIdx.x < rend) rec_s[threadIdx.x] = gload_rec(s.rec_list + rbeg + threadIdx.x);
         }
     }
     // adjoint: the residual injections W R^T r^n of this launch's levels at
@@ -357,8 +405,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     __shared__ int inj_l[kInjE];
     int32_t ebeg = 0, eend = 0;
     if (ADJ) {
-        ebeg = t.inj.tile_start[tile];
-        eend = t.inj.tile_start[tile + 1];
+        ebeg = gload(t.inj.tile_start + tile);
+        eend = gload(t.inj.tile_start + tile + 1);
     }
     const int E = eend - ebeg;
     const bool inj_pre = ADJ && E > 0 && E <= kInjE;
@@ -366,7 +414,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         for (int q = threadIdx.x; q < (t.nsteps + 1) * E; q += NTHR) {
             const int st = q / E, e = q - st * E, eg = ebeg + e;
             if (st == t.nsteps) {
-                inj_l[e] = t.inj.lds[eg];
+                inj_l[e] = gload(t.inj.lds + eg);
                 continue;
             }
             const int n = t.n - st;
@@ -374,10 +422,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             if (n >= 1 && n % s.rec_every == 0) {
                 const float *rrow = t.resid + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
                 float acc = 0.f;
-                for (int j = t.inj.pstart[eg]; j < t.inj.pstart[eg + 1]; ++j) acc += t.inj.w[j] * rrow[t.inj.rid[j]];
-                const int iz = t.inj.iz[eg], ix = t.inj.ix[eg];
-                const float v2 = s.V2[(int64_t)(iz + kGuard) * s.pitch + ix + kGuard];
-                const float Wc = v2 / (1.f + (s.gx[ix] + s.gz[iz]) * v2);
+                const int j1 = gload(t.inj.pstart + eg + 1);
+                for (int j = gload(t.inj.pstart + eg); j < j1; ++j) acc += gload(t.inj.w + j) * gload(rrow + gload(t.inj.rid + j));
+                const int iz = gload(t.inj.iz + eg), ix = gload(t.inj.ix + eg);
+                const float v2 = gload(s.V2 + (int64_t)(iz + kGuard) * s.pitch + ix + kGuard);
+                const float Wc = v2 / (1.f + (gload(s.gx + ix) + gload(s.gz + iz)) * v2);
                 add = Wc * acc;
             }
             inj_a[st * kInjE + e] = add;
@@ -392,7 +441,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         const bool h = L >= t.ring_lo && L <= t.ring_hi;
         const float *rl = ringb + (int64_t)(h ? L - t.ring_lo : 0) * s.frame;
 #pragma unroll
-        for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? rl[colc + (int64_t)k * s.pitch] : 0.f;
+        for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? gload_at(rl, rowb(k) + xc4) : 0.f;
     };
     if (ADJ) {
         ring_level(t.n + 1, pa);
@@ -423,11 +472,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             float *row = s.gathers + ((int64_t)shot * s.nrow + n / s.rec_every) * s.nrec;
             const float *Lc = lds + lc;
             auto sample = [&](const RecEntry &e) {
-                row[e.r] = e.w[0] * Lc[e.lds] + e.w[1] * Lc[e.lds + 1] + e.w[2] * Lc[e.lds + LW] +
-                           e.w[3] * Lc[e.lds + LW + 1];
+                gstore(row + e.r, e.w[0] * Lc[e.lds] + e.w[1] * Lc[e.lds + 1] + e.w[2] * Lc[e.lds + LW] +
+                                      e.w[3] * Lc[e.lds + LW + 1]);
             };
             if (rbeg + (int)threadIdx.x < rend) sample(rec_s[threadIdx.x]);
-            for (int q = rbeg + NTHR + (int)threadIdx.x; q < rend; q += NTHR) sample(s.rec_list[q]);
+            for (int q = rbeg + NTHR + (int)threadIdx.x; q < rend; q += NTHR) sample(gload_rec(s.rec_list + q));
         }
         if (ADJ) {
             // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1}),
@@ -554,7 +603,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (k >= k_lo && k < k_hi) rl[col + (int64_t)k * s.pitch] = old[k];
+                    if (k >= k_lo && k < k_hi) gstore_at(rl, rowb(k) + xo4, old[k]);
             }
         }
         __syncthreads();
@@ -585,8 +634,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         for (int k = 0; k < K; ++k) {
             hsv[k] = hcv[k] = 0.f;
             if (k >= k_lo && k < k_hi) {
-                hsv[k] = hs[colc + (int64_t)k * s.pitch];
-                hcv[k] = hc[colc + (int64_t)k * s.pitch];
+                hsv[k] = gload_at(hs, rowb(k) + xc4);
+                hcv[k] = gload_at(hc, rowb(k) + xc4);
             }
         }
     }
@@ -594,15 +643,15 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k >= k_lo && k < k_hi) {
-                const int64_t i = col + (int64_t)k * s.pitch;
-                out_cur[i] = odd ? B[k] : A[k];
-                out_prev[i] = odd ? A[k] : B[k];
+                const uint32_t ob = rowb(k) + xo4;
+                gstore_at(out_cur, ob, odd ? B[k] : A[k]);
+                gstore_at(out_prev, ob, odd ? A[k] : B[k]);
                 if (ADJ) {
                     // Kahan-compensated accumulation of this launch's partial sum
                     const float y = hp[k] - hcv[k];
                     const float tt = hsv[k] + y;
-                    hc[i] = (tt - hsv[k]) - y;
-                    hs[i] = tt;
+                    gstore_at(hc, ob, (tt - hsv[k]) - y);
+                    gstore_at(hs, ob, tt);
                 }
             }
         }
@@ -629,8 +678,20 @@ __global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled_bat
 {
     __shared__ float lds[2 * TileShape<K, NWX, NWZ>::LDS];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
+    // the item owning logical block b is the last one starting at or before
+    // b: its index is the count of such items minus one, found with one load
+    // per lane (64 items per round) instead of a chain of dependent loads
     int it = 0;
-    while (it + 1 < nitems && items[it + 1].block_start <= b) ++it;
+    if (nitems > 1) {
+        const int lane = threadIdx.x & 63;
+        int count = 0;
+        for (int base = 0; base < nitems; base += 64) {
+            const int i = base + lane;
+            const bool le = i < nitems && items[i].block_start <= b;
+            count += __popcll(__ballot(le));
+        }
+        it = __builtin_amdgcn_readfirstlane(count - 1);
+    }
     const SliceDesc s = items[it].s;     // local copies: plain registers, no aliasing with LDS
     TileArgs t = items[it].t;
     t.n = n;

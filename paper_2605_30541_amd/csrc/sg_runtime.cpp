@@ -1053,8 +1053,12 @@ sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, si
     return SG_OK;
 }
 
-sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning, void *ws,
-                           size_t ws_bytes, void *stream)
+namespace {
+
+// The batched forward over the first `levels` levels.  A trial (autotuning)
+// records nothing and replays no graph.
+sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning, void *ws,
+                             size_t ws_bytes, void *stream, int levels, bool trial)
 {
     size_t need = 0;
     sg_status rc = sg_batch_workspace_size(items, nitems, &need);
@@ -1093,7 +1097,7 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
         const sg_batch_item &it = items[i];
         char *wi = w + base[i];
         if ((rc = upload_tables(it.plan, cs[i].L, wi, it.shots, &cs[i].T, st)) != SG_OK) return rc;
-        hb[i].s = describe(it.plan, cs[i].L, wi, it.shots, it.gathers, it.snaps);
+        hb[i].s = describe(it.plan, cs[i].L, wi, it.shots, trial ? nullptr : it.gathers, trial ? nullptr : it.snaps);
         SG_HIP(sg::launch_prepare(hb[i].s, it.vp, (float)(it.plan->g.dt * it.plan->g.dt), st));
         SG_HIP(sg::launch_zero(hb[i].s.fields, (size_t)it.shots->nshot * sg::kFramesPerShot * it.plan->frame, st));
         hb[i].t = tile_args(cs[i].T, hb[i].s.fields, 0, 0, 0);
@@ -1130,28 +1134,88 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
         int pair = 0;
         for (int i = 0; i < nitems; ++i)
             if (snap_due(i, 0)) SG_HIP(sg::launch_record_slot(hb[i].s, 0, 1, s2, 2));
-        for (int n = 0; n < nt - 1;) {
-            const int k = std::min(std::min(tb, nt - 1 - n), next_cut(n) - n);
+        const int nlast = std::min(levels, nt) - 1;
+        for (int n = 0; n < nlast;) {
+            const int k = std::min(std::min(tb, nlast - n), next_cut(n) - n);
             SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, iso, s2));
             pair ^= 1;
             n += k;
-            if (n < nt - 1)
+            if (n < nlast)
                 for (int i = 0; i < nitems; ++i)
                     if (snap_due(i, n)) SG_HIP(sg::launch_record_slot(hb[i].s, n, 2 * pair + 1, s2, 2));
         }
-        for (int i = 0; i < nitems; ++i)
-            SG_HIP(sg::launch_record_slot(hb[i].s, nt - 1, 2 * pair + 1, s2));
+        if (!trial)
+            for (int i = 0; i < nitems; ++i)
+                SG_HIP(sg::launch_record_slot(hb[i].s, nt - 1, 2 * pair + 1, s2));
         return SG_OK;
     };
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     SG_HIP(hipStreamIsCapturing(st, &cap));
-    if (cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
+    if (trial || cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
     // per-item launch arguments never change for the same workspace and batch
     // shape, so one instantiated graph per such key is replayed
     GraphKey key{(uintptr_t)ws, nitems, (int)total_blocks, nt, tb, config, items_signature(hb)};
     hipGraphExec_t exec = nullptr;
     if ((rc = graph_lookup(key, st, enqueue, &exec)) != SG_OK) return rc;
     SG_HIP(hipGraphLaunch(exec, st));
+    return SG_OK;
+}
+
+}  // namespace
+
+sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_tuning *tuning, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    if (!items || nitems < 1) return fail(SG_EINVAL, "bad batch arguments");
+    return batch_forward_impl(items, nitems, tuning, ws, ws_bytes, stream, items[0].plan ? items[0].plan->g.nt : 0,
+                              false);
+}
+
+sg_status sg_batch_autotune(const sg_batch_item *items, int32_t nitems, int32_t trial_levels, void *ws,
+                            size_t ws_bytes, void *stream, sg_tuning *best)
+{
+    if (!items || nitems < 1 || !best) return fail(SG_EINVAL, "bad batch arguments");
+    if (trial_levels < 8) return fail(SG_EINVAL, "trial_levels must be >= 8");
+    for (int i = 0; i < nitems; ++i)
+        if (!items[i].plan || !items[i].shots) return fail(SG_EINVAL, "batch item %d has no plan or shots", i);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    SG_HIP(hipEventCreate(&e0));
+    SG_HIP(hipEventCreate(&e1));
+    sg_status rc = SG_OK;
+    double best_ms = 1e300;
+    sg_tuning chosen{};
+    for (const sg_tuning &t : tuning_candidates(items[0].plan)) {
+        // a candidate must tile every item of the batch
+        bool fits = true;
+        for (int i = 0; i < nitems && fits; ++i) {
+            int config = -1;
+            sg::Tiling T{};
+            fits = tiling_for(items[i].plan, t, &config, &T) == SG_OK;
+        }
+        if (!fits) continue;
+        // one untimed pass to warm caches and code, then the timed pass
+        for (int rep = 0; rep < 2 && rc == SG_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(SG_EHIP, "event record failed");
+            if (rc == SG_OK) rc = batch_forward_impl(items, nitems, &t, ws, ws_bytes, stream, trial_levels, true);
+            if (rep == 1 && rc == SG_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(SG_EHIP, "event record failed");
+        }
+        if (rc != SG_OK) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(SG_EHIP, "event timing failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            chosen = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SG_OK) return rc;
+    if (best_ms == 1e300) return fail(SG_EUNSUPPORTED, "no tiling fits every item of the batch");
+    *best = chosen;
     return SG_OK;
 }
 

@@ -111,6 +111,9 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_batch_autotune": (ctypes.c_int32, [ctypes.POINTER(sg_batch_item), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                           ctypes.POINTER(sg_tuning)]),
     "sg_batch_grad_workspace_size": (ctypes.c_int32, [ctypes.POINTER(sg_batch_grad_item), ctypes.c_int32,
                                                       ctypes.c_int32, ctypes.c_int32,
                                                       ctypes.POINTER(ctypes.c_size_t)]),
@@ -351,6 +354,16 @@ def sg_batch_forward(items, ws, tuning=None, stream=None):
                                    tuning.get("time_block", 0), tuning.get("rows_per_thread", 0)))
     _check(lib().sg_batch_forward(arr, len(items), t, _ptr(ws), ws.numel() * ws.element_size(),
                                   _stream_ptr(stream)))
+
+
+def sg_batch_autotune(items, ws, trial_levels: int = 64, stream=None) -> dict:
+    """Fastest tuning for the whole batch (a dict for sg_batch_forward's `tuning`)."""
+    arr, keep = _batch_items(items)
+    t = sg_tuning()
+    _check(lib().sg_batch_autotune(arr, len(items), trial_levels, _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream_ptr(stream), ctypes.byref(t)))
+    return dict(variant=t.variant, tile_x=t.tile_x, tile_z=t.tile_z, time_block=t.time_block,
+                rows_per_thread=t.rows_per_thread)
 
 
 def sg_autotune(plan: Plan, vp, shots: Shots, trial_levels: int, ws, stream=None) -> dict:

@@ -80,6 +80,30 @@ def test_batch_equals_single_calls_and_oracle(tuning):
                 assert rel_l2(bs[k, j], os_[k, j]) <= TOL
 
 
+def test_batch_autotune_picks_a_built_tuning_and_writes_no_output():
+    """The batched autotuner returns one of the built tilings with a time
+    block that tiles every item, leaves the items' outputs untouched, and the
+    batch run with its choice equals the default run bit for bit (every
+    tiling evaluates the same expression per cell)."""
+    import torch
+    items = make_items(SIZES, NSHOTS)
+    full = [(it["plan"], it["vp"], it["shots"],
+             torch.full((it["shots"].nshot, it["geom"].nrow, it["shots"].nrec), float("nan"), device="cuda"),
+             None) for it in items]
+    ws = torch.empty(sgwave.sg_batch_workspace_size(full), dtype=torch.uint8, device="cuda")
+    best = sgwave.sg_batch_autotune(full, ws, trial_levels=24)
+    torch.cuda.synchronize()
+    shapes = {(128, 64, 8), (64, 128, 16), (64, 64, 8), (128, 64, 16)}
+    assert best["variant"] == 2 and (best["tile_x"], best["tile_z"], best["rows_per_thread"]) in shapes
+    assert 1 <= best["time_block"] <= 8
+    for f in full:
+        assert torch.isnan(f[3]).all()
+    tuned = run_batch(items, best)
+    default = run_batch(items)
+    for (tg, ts), (dg, ds) in zip(tuned, default):
+        assert np.array_equal(tg, dg) and np.array_equal(ts, ds)
+
+
 def test_graph_replay_and_plain_launches_agree():
     items = make_items(SIZES[:3], NSHOTS[:3], nt=300, snaps=False, seed=10)
     first = run_batch(items)
