@@ -270,7 +270,7 @@ def main():
     avg_ms = kms / launches
     bytes_per_launch = BYTES_PER_UPDATE * updates / launches
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    kernel = "k_step_naive" if tuning["variant"] == 1 else "k_step_tiled"
+    kernel = "k_step_naive" if tuning["variant"] == 1 else "k_tiled"
     traffic = traffic_record(kernel, "field_shot")
     sgwave.sg_check_finite(gathers, ws)
 
