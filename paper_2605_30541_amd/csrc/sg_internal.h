@@ -43,6 +43,8 @@ struct SliceDesc {
     float cz[kHalo + 1];     // c_m / dz^2
     float cx[kHalo + 1];     // c_m / dx^2
     const float *V2;         // (v dt)^2 on the padded grid, stored-field layout
+    const float *W;          // W = a (v dt)^2 on updated cells, else 0 (stored-field layout)
+    const float *A2;         // 2a on updated cells, else 0 (stored-field layout)
     const float *gx;         // [Nx] eta_x / (2 dt); gamma = (gx + gz) * V2
     const float *gz;         // [Nz]
     const int32_t *src_off;  // [nshot][kNodes] stored-field offsets, -1 = unused
@@ -139,6 +141,7 @@ constexpr int kTiledShapes = 4;
 TiledShape tiled_shape(int config);
 
 // Kernel launchers (sg_kernels.hip).  All return hipSuccess or the launch error.
+// launch_prepare fills V2, W and A2 (needs gx and gz in place).
 hipError_t launch_prepare(const SliceDesc &s, const float *vp, float dt2, hipStream_t st);
 hipError_t launch_zero(float *p, size_t n, hipStream_t st);
 hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);

@@ -74,21 +74,33 @@ __device__ inline void record_level(const SliceDesc &s, const float *cur, int sh
 }
 
 // Velocity -> (v dt)^2 on the padded grid (edge replication into the sponge),
-// zero on the guard cells.
+// and the update coefficients of every cell: W = a (v dt)^2 and 2a with
+// a = 1 / (1 + gamma), gamma = (eta_x + eta_z) / (2 dt) (v dt)^2; both 0 on
+// cells the scheme does not update (the guard cells, the pinned free-surface
+// row).  The tiled kernel reads W and 2a; the one-step kernel forms them from
+// (v dt)^2 with the same operations.
 __global__ void __launch_bounds__(256) k_prepare(SliceDesc s, const float *vp, float dt2)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= s.frame) return;
     const int r = (int)(q / s.pitch), c = (int)(q - (int64_t)r * s.pitch);
     const int Iz = r - kGuard, Ix = c - kGuard;
-    float out = 0.f;
+    float out = 0.f, w = 0.f, a2 = 0.f;
     if (Iz >= 0 && Iz < s.Nz && Ix >= 0 && Ix < s.Nx) {
         int iz = min(max(Iz - s.ztop, 0), s.nz - 1);
         int ix = min(max(Ix - s.xleft, 0), s.nx - 1);
         float v = vp[(int64_t)iz * s.nx + ix];
         out = v * v * dt2;
+        if (!(s.free_top && Iz == 0)) {
+            const float gam = (s.gx[Ix] + s.gz[Iz]) * out;
+            const float a = 1.f / (1.f + gam);
+            w = a * out;
+            a2 = 2.f * a;
+        }
     }
     ((float *)s.V2)[q] = out;
+    ((float *)s.W)[q] = w;
+    ((float *)s.A2)[q] = a2;
 }
 
 __global__ void __launch_bounds__(256) k_zero(float *p, size_t n)
@@ -267,9 +279,12 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     oz_end = min(oz_end, s.Nz);
     const int ox = txi * t.tx, ox_end = min(ox + t.tx, s.Nx), ex0 = ox - halo;
 
-    // the wave index is made explicitly uniform, so that everything derived
-    // from it (rows, row addresses, row conditions) lives in scalar registers
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // In the adjoint the wave index is made explicitly uniform, so that what
+    // derives from it (rows, row addresses, row conditions) lives in scalar
+    // registers: that mode is short of vector registers.  The forward modes
+    // keep it per lane, which costs fewer scalar instructions.
+    const int lane = threadIdx.x & 63;
+    const int w = ADJ ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
     const int lx = (w % NWX) * 64 + lane;        // local column in [0, EX)
     const int lz0 = (w / NWX) * K;               // first local row of this thread (wave-uniform)
     const int X = ex0 + lx, Z0 = ez0 + lz0;      // padded coordinates
@@ -316,19 +331,18 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
 
     // ---- load the two input levels (registers; the newer one also to both
     // LDS buffers, so cells that are never recomputed keep their value) and
-    // the coefficients.  Cells the scheme does not update (outside the padded
-    // grid, the pinned free-surface row) get a2 = W = 0 and value 0, so the
-    // update keeps them 0.  A and B hold the two live levels; their roles
-    // alternate every sub-step (the new level overwrites the older one).
-    // Every load is issued unconditionally from a clamped, in-bounds cell
-    // (ghost rows above a free top read their mirror row) and the values are
-    // selected afterwards, so the loads of all rows are in flight together
-    // instead of one row after another.
+    // the coefficients W and 2a of every cell.  Cells the scheme does not
+    // update (outside the padded grid, the pinned free-surface row) get
+    // a2 = W = 0 and value 0, so the update keeps them 0.  A and B hold the two
+    // live levels; their roles alternate every sub-step (the new level
+    // overwrites the older one).  Every load is issued unconditionally from a
+    // clamped, in-bounds cell (ghost rows above a free top read their mirror
+    // row) and the values are selected afterwards, so the loads of all rows
+    // are in flight together instead of one row after another.
     const int Xc = min(max(X, 0), s.Nx - 1);
     float A[K], B[K], a2[K], W[K];
     {
-        float rc[K], rp[K], rv[K], rg[K];
-        const float gxX = gload(s.gx + Xc);
+        float rc[K], rp[K], rw[K], ra[K];
         const uint32_t xc4 = (uint32_t)(Xc + kGuard) * 4u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -337,8 +351,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             const uint32_t ob = (uint32_t)((Zr + kGuard) * s.pitch) * 4u + xc4;
             rc[k] = gload_at(in_cur, ob);
             rp[k] = gload_at(in_prev, ob);
-            rv[k] = gload_at(s.V2, ob);
-            rg[k] = gload(s.gz + min(max(Z, 0), s.Nz - 1));
+            rw[k] = gload_at(s.W, ob);
+            ra[k] = gload_at(s.A2, ob);
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -346,16 +360,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             const bool in = xin && Z >= 0 && Z < s.Nz;
             const bool ghost = top_tile && xin && Z < 0 && Z >= -kHalo;   // odd mirror of row -Z
             const float c = in ? rc[k] : (ghost ? -rc[k] : 0.f);
-            const bool upd = in && !(s.free_top && Z == 0);
-            const float v2 = upd ? rv[k] : 0.f;
-            const float gam = (gxX + rg[k]) * v2;
-            // a = 1 / (1 + gamma); the division is skipped by waves with no
-            // sponge cell in this row (there gamma = 0 and a = 1 exactly)
-            const float a = 1.f / (1.f + gam);
-            a2[k] = upd ? 2.f * a : 0.f;
-            W[k] = upd ? a * v2 : 0.f;
+            a2[k] = in ? ra[k] : 0.f;
+            W[k] = in ? rw[k] : 0.f;
             A[k] = c;
-            B[k] = upd ? rp[k] : 0.f;
+            B[k] = in ? rp[k] : 0.f;
             lds[lbase + k * LW] = c;
             lds[NB + lbase + k * LW] = c;
         }

@@ -98,7 +98,7 @@ namespace {
 // (C + 2 levels), the adjoint field pairs, the Kahan pair of the imaging sum,
 // and the residual-injection tables.
 struct Layout {
-    size_t v2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
+    size_t v2, w, a2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
     size_t inj_tile, inj_lds, inj_iz, inj_ix, inj_pstart, inj_rid, inj_w;
     size_t tables_end, fields;
     size_t ckpt, ring, mu, hsum, hcomp, total;
@@ -127,6 +127,8 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
     const size_t ns = (size_t)nshot * sg::kNodes, nr = (size_t)std::max(nrec, 1);
     const size_t fr = (size_t)p->frame * sizeof(float);
     L.v2 = take(fr);
+    L.w = take(fr);
+    L.a2 = take(fr);
     L.gx = take((size_t)p->Nx * sizeof(float));
     L.gz = take((size_t)p->Nz * sizeof(float));
     L.src_off = take(ns * sizeof(int32_t));
@@ -256,6 +258,8 @@ sg::SliceDesc describe(const sg_plan *p, const Layout &L, char *ws, const sg_sho
         s.cx[m] = (float)(kC8[m] / (g.dx * g.dx));
     }
     s.V2 = (const float *)(ws + L.v2);
+    s.W = (const float *)(ws + L.w);
+    s.A2 = (const float *)(ws + L.a2);
     s.gx = (const float *)(ws + L.gx);
     s.gz = (const float *)(ws + L.gz);
     s.src_off = (const int32_t *)(ws + L.src_off);
