@@ -218,7 +218,13 @@ sg_status sg_forward_workspace_size(const sg_plan *p, int32_t nshot, int32_t nre
  *   gathers   device [nshot][ceil(nt/rec_every)][nrec] float, or NULL
  *   snaps     device [nshot][snap_count][nz][nx] float, or NULL
  *   ws        device workspace of ws_bytes >= sg_forward_workspace_size
- * Every element of the non-NULL outputs is written.
+ * Every element of the non-NULL outputs is written.  The time-stepping
+ * launches of a call are recorded once into a hipGraph per (plan shape,
+ * tuning, workspace, output and wavelet pointers) and replayed on later calls
+ * with the same ones (positions, velocities and wavelet values may change
+ * between calls: they are read from the workspace and the caller's buffers at
+ * run time), unless graphs are turned off (sg_set_graphs) or the caller is
+ * already capturing the stream.
  */
 sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots,
                      float *gathers, float *snaps, void *ws, size_t ws_bytes,
@@ -308,8 +314,8 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
                                     int32_t shots_per_wave, const sg_tuning *tuning, void *ws, size_t ws_bytes,
                                     void *stream);
 
-/* Turn the graph replay of sg_batch_forward on (default) or off (plain
- * stream launches). */
+/* Turn the graph replay of sg_forward and sg_batch_forward on (default) or
+ * off (plain stream launches); process-wide. */
 sg_status sg_set_graphs(int32_t on);
 
 /*

@@ -488,7 +488,7 @@ sg::TileArgs tile_args(const sg::Tiling &T, float *fields, int n, int nsteps, in
 template <class OnCut>
 sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config, const sg::Tiling &T,
                       int n0, int n_end, int cut, int *pair, float *ring, int ring_lo, int64_t ring_shot,
-                      OnCut on_cut, hipStream_t st)
+                      OnCut on_cut, hipStream_t st, int *count = nullptr)
 {
     const int step = t.variant == 1 ? 1 : t.time_block;
     // the tiled kernel leaves snapshots to launch boundaries at snapshot levels
@@ -530,6 +530,7 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
         p->prof_used = 1;
         p->prof_launches = launches;
     }
+    if (count) *count = launches;
     return SG_OK;
 }
 
@@ -539,18 +540,6 @@ int level_slot(const sg_tuning &t, int m, int pair) { return t.variant == 1 ? (m
 
 // Runs levels 0 .. nt-1 of every shot: records each level while stepping
 // from it, then records the last level.
-sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
-                      const sg::Tiling &T, hipStream_t st)
-{
-    const int nt = p->g.nt;
-    int pair = 0;
-    p->prof_used = 0;
-    sg_status rc = forward_run(p, s, t, config, T, 0, nt - 1, 0, &pair, nullptr, 0, 0,
-                               [](int, int) { return SG_OK; }, st);
-    if (rc != SG_OK) return rc;
-    SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(t, nt - 1, pair), st));
-    return SG_OK;
-}
 
 // Shared validation and set-up of the calls on one slice.
 struct CallSetup {
@@ -642,22 +631,30 @@ uint64_t items_signature(const std::vector<sg::BatchItem> &hb)
 
 struct GraphCache {
     std::mutex mu;
-    std::vector<std::pair<GraphKey, hipGraphExec_t>> entries;   // most recent last
+    struct Entry {
+        GraphKey key;
+        hipGraphExec_t exec;
+        int aux;                     // a count the caller keeps with the graph
+    };
+    std::vector<Entry> entries;      // most recent last
     hipStream_t capture = nullptr;   // private stream used only to record graphs
 };
 GraphCache g_graphs;
 constexpr size_t kGraphCacheSize = 8;
 
+// The instantiated graph for `key`, recorded with `enqueue` on first use.
+// *aux (optional) is stored with a new graph and returned with a cached one.
 template <class Enqueue>
-sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hipGraphExec_t *out)
+sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hipGraphExec_t *out, int *aux = nullptr)
 {
     std::lock_guard<std::mutex> lock(g_graphs.mu);
     for (size_t i = 0; i < g_graphs.entries.size(); ++i)
-        if (g_graphs.entries[i].first == key) {
+        if (g_graphs.entries[i].key == key) {
             auto e = g_graphs.entries[i];
             g_graphs.entries.erase(g_graphs.entries.begin() + i);
             g_graphs.entries.push_back(e);
-            *out = e.second;
+            *out = e.exec;
+            if (aux) *aux = e.aux;
             return SG_OK;
         }
     // record on a private stream (the caller's may be the legacy default
@@ -678,11 +675,67 @@ sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hip
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return fail(SG_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
     if (g_graphs.entries.size() >= kGraphCacheSize) {
-        (void)hipGraphExecDestroy(g_graphs.entries.front().second);
+        (void)hipGraphExecDestroy(g_graphs.entries.front().exec);
         g_graphs.entries.erase(g_graphs.entries.begin());
     }
-    g_graphs.entries.push_back({key, exec});
+    g_graphs.entries.push_back({key, exec, aux ? *aux : 0});
     *out = exec;
+    return SG_OK;
+}
+
+// FNV-1a over a slice descriptor (every pointer and size its launches take by value).
+uint64_t desc_signature(const sg::SliceDesc &d)
+{
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char *c = (const unsigned char *)&d;
+    for (size_t i = 0; i < sizeof(d); ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
+// The whole time stepping of one call (every level, then the last level's
+// records).  The sequence of launches is recorded once into a hipGraph per
+// (descriptor, tiling, nt) and replayed, unless graphs are off or the caller
+// is capturing the stream already; plan profiling brackets the replay.
+sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
+                      const sg::Tiling &T, hipStream_t st)
+{
+    const int nt = p->g.nt;
+    p->prof_used = 0;
+    int launches = 0;
+    auto enqueue = [&](hipStream_t s2) -> sg_status {
+        int pair = 0;
+        sg_status rc = forward_run(p, s, t, config, T, 0, nt - 1, 0, &pair, nullptr, 0, 0,
+                                   [](int, int) { return SG_OK; }, s2, &launches);
+        if (rc != SG_OK) return rc;
+        SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(t, nt - 1, pair), s2));
+        return SG_OK;
+    };
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SG_HIP(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
+    const bool prof = p->profiling;
+    GraphKey key{(uintptr_t)s.fields, -1, t.variant == 2 ? T.ntx * T.ntz * s.nshot : 0, nt,
+                 t.variant == 2 ? t.time_block : 0, t.variant == 2 ? config : -1, desc_signature(s)};
+    hipGraphExec_t exec = nullptr;
+    auto record = [&](hipStream_t s2) -> sg_status {
+        p->profiling = false;          // the replay is bracketed instead
+        sg_status rc = enqueue(s2);
+        p->profiling = prof;
+        return rc;
+    };
+    sg_status rc = graph_lookup(key, st, record, &exec, &launches);
+    if (rc != SG_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+        if ((rc = prof_pair(p, 0, &e0, &e1)) != SG_OK) return rc;
+        SG_HIP(hipEventRecord(e0, st));
+    }
+    SG_HIP(hipGraphLaunch(exec, st));
+    if (prof) {
+        SG_HIP(hipEventRecord(e1, st));
+        p->prof_used = 1;
+        p->prof_launches = launches;
+    }
     return SG_OK;
 }
 
