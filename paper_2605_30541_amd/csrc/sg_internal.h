@@ -111,7 +111,7 @@ struct TileArgs {
     int64_t ring_shot;  // floats per shot in the ring
     // adjoint only
     const float *resid; // [nshot][nrow][nrec], dJ/dd at the recorded levels
-    float *hsum, *hcomp;// [nshot][frame] Kahan pair of sum_n mu^{n+1} (p^{n+1} - 2p^n + p^{n-1})
+    double *hsum;       // [nshot][frame] sum_n mu^{n+1} (p^{n+1} - 2p^n + p^{n-1}), accumulated in FP64
     int32_t nt;
     InjTables inj;
 };
@@ -159,8 +159,8 @@ hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int to
 hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t src_shot, int64_t n, int nshot,
                        hipStream_t st);
 // grad[iz][ix] (+)= 2 / (dt^2 v^3) * sum over shots and over the padded cells
-// whose velocity is copied from (iz, ix) of (hsum - hcomp)
-hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
+// whose velocity is copied from (iz, ix) of hsum
+hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const double *hsum,
                                 int64_t shot_stride, float dt, float *grad, hipStream_t st, bool accumulate = false);
 // Records level n held in frame `slot` of every shot: gather row (what & 1)
 // and snapshot (what & 2) when that level is due for them.

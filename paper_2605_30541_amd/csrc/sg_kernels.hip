@@ -632,20 +632,16 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // the newest level is in A after an even number of sub-steps, else in B
     const bool odd = t.nsteps & 1;
 
-    // ---- write the output tile: the last two levels
-    float hsv[ADJ ? K : 1], hcv[ADJ ? K : 1];
-    float *hs = ADJ ? t.hsum + (int64_t)shot * s.frame : nullptr;
-    float *hc = ADJ ? t.hcomp + (int64_t)shot * s.frame : nullptr;
+    // ---- write the output tile: the last two levels; the adjoint adds this
+    // launch's partial imaging sums to the FP64 accumulator h of its cells
+    // (loads first, all in flight together)
+    double hsv[ADJ ? K : 1];
+    double *hs = ADJ ? t.hsum + (int64_t)shot * s.frame : nullptr;
+    // byte offset of a double in the accumulator: twice the float offset
     if (ADJ) {
-        // Kahan pair of the output rows, all loads in flight together
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            hsv[k] = hcv[k] = 0.f;
-            if (k >= k_lo && k < k_hi) {
-                hsv[k] = gload_at(hs, rowb(k) + xc4);
-                hcv[k] = gload_at(hc, rowb(k) + xc4);
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            hsv[k] = (k >= k_lo && k < k_hi) ? gload_at(hs, 2u * (rowb(k) + xc4)) : 0.0;
     }
     if (xout) {
 #pragma unroll
@@ -654,13 +650,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 const uint32_t ob = rowb(k) + xo4;
                 gstore_at(out_cur, ob, odd ? B[k] : A[k]);
                 gstore_at(out_prev, ob, odd ? A[k] : B[k]);
-                if (ADJ) {
-                    // Kahan-compensated accumulation of this launch's partial sum
-                    const float y = hp[k] - hcv[k];
-                    const float tt = hsv[k] + y;
-                    gstore_at(hc, ob, (tt - hsv[k]) - y);
-                    gstore_at(hs, ob, tt);
-                }
+                if (ADJ) gstore_at(hs, 2u * ob, hsv[k] + (double)hp[k]);
             }
         }
     }
@@ -723,9 +713,9 @@ __global__ void __launch_bounds__(256) k_copy(float *dst, int64_t dst_shot, cons
 
 // Gradient on the physical grid: g(iz, ix) = 2 / (dt^2 v^3) * sum over shots
 // and over the padded cells whose velocity is the copy of v(iz, ix) (the
-// transpose of the edge replication into the sponge) of h = hsum - hcomp.
-__global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float *vp, const float *hsum,
-                                                       const float *hcomp, int64_t shot_stride, float dt,
+// transpose of the edge replication into the sponge) of h = hsum.
+__global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float *vp, const double *hsum,
+                                                       int64_t shot_stride, float dt,
                                                        float *grad, int accumulate)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -735,11 +725,11 @@ __global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float 
     const int x_lo = ix == 0 ? 0 : ix + s.xleft, x_hi = ix == s.nx - 1 ? s.Nx - 1 : ix + s.xleft;
     double acc = 0.0;
     for (int sh = 0; sh < s.nshot; ++sh) {
-        const float *hs = hsum + (int64_t)sh * shot_stride, *hc = hcomp + (int64_t)sh * shot_stride;
+        const double *hs = hsum + (int64_t)sh * shot_stride;
         for (int Z = z_lo; Z <= z_hi; ++Z)
             for (int X = x_lo; X <= x_hi; ++X) {
                 const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
-                acc += (double)hs[i] - (double)hc[i];
+                acc += hs[i];
             }
     }
     const double v = vp[q];
@@ -904,11 +894,11 @@ hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t s
     return hipGetLastError();
 }
 
-hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const float *hsum, const float *hcomp,
+hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const double *hsum,
                                 int64_t shot_stride, float dt, float *grad, hipStream_t st, bool accumulate)
 {
     const unsigned blocks = (unsigned)((s.nz * s.nx + 255) / 256);
-    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, hcomp, shot_stride, dt, grad,
+    hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, shot_stride, dt, grad,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }

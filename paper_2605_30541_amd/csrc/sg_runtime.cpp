@@ -95,13 +95,13 @@ namespace {
 // plan's pinned staging buffer in one copy.  With ckpt > 0 the layout also
 // holds the gradient state: checkpoints (levels jC-1, jC of every shot every
 // C = ckpt levels), the ring of recomputed forward levels of one segment
-// (C + 2 levels), the adjoint field pairs, the Kahan pair of the imaging sum,
+// (C + 2 levels), the adjoint field pairs, the FP64 accumulator of the imaging sum,
 // and the residual-injection tables.
 struct Layout {
     size_t v2, w, a2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
     size_t inj_tile, inj_lds, inj_iz, inj_ix, inj_pstart, inj_rid, inj_w;
     size_t tables_end, fields;
-    size_t ckpt, ring, mu, hsum, hcomp, total;
+    size_t ckpt, ring, mu, hsum, total;
     int ckpt_every, nseg, ring_levels;
     int64_t inj_cap;   // capacity (cells and pairs) of the injection tables
 };
@@ -161,8 +161,7 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
         L.ckpt = take((size_t)nshot * L.nseg * 2 * fr);
         L.ring = take((size_t)nshot * L.ring_levels * fr);
         L.mu = take((size_t)nshot * sg::kFramesPerShot * fr);
-        L.hsum = take((size_t)nshot * fr);
-        L.hcomp = take((size_t)nshot * fr);
+        L.hsum = take((size_t)nshot * 2 * fr);     // doubles
     }
     L.total = o;
     return L;
@@ -1046,11 +1045,10 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
     const int nshot = shots->nshot, nt = p->g.nt;
     const int64_t F = p->frame, fshot = (int64_t)sg::kFramesPerShot * F;
     float *ck = (float *)(w + c.L.ckpt), *ring = (float *)(w + c.L.ring), *mu = (float *)(w + c.L.mu);
-    float *hsum = (float *)(w + c.L.hsum), *hcomp = (float *)(w + c.L.hcomp);
+    double *hsum = (double *)(w + c.L.hsum);
     const int64_t ck_shot = (int64_t)c.L.nseg * 2 * F, ring_shot = (int64_t)c.L.ring_levels * F;
     SG_HIP(sg::launch_zero(mu, (size_t)nshot * fshot, st));
-    SG_HIP(sg::launch_zero(hsum, (size_t)nshot * F, st));
-    SG_HIP(sg::launch_zero(hcomp, (size_t)nshot * F, st));
+    SG_HIP(sg::launch_zero((float *)hsum, (size_t)nshot * 2 * F, st));
 
     sg::InjTables inj{};
     inj.tile_start = (const int32_t *)(w + c.L.inj_tile);
@@ -1085,7 +1083,6 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
             a.ring_shot = ring_shot;
             a.resid = resid;
             a.hsum = hsum;
-            a.hcomp = hcomp;
             a.nt = nt;
             a.inj = inj;
             SG_HIP(sg::launch_adjoint_tiled(s, a, c.config, st));
@@ -1093,7 +1090,7 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
             k0 -= nsteps;
         }
     }
-    SG_HIP(sg::launch_fold_gradient(s, vp, hsum, hcomp, F, (float)p->g.dt, grad, st));
+    SG_HIP(sg::launch_fold_gradient(s, vp, hsum, F, (float)p->g.dt, grad, st));
     return SG_OK;
 }
 
@@ -1428,14 +1425,12 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             const int64_t F = it.plan->frame;
             SG_HIP(sg::launch_zero(b.s.fields, (size_t)cnt * sg::kFramesPerShot * F, st));
             SG_HIP(sg::launch_zero((float *)(wi + L.mu), (size_t)cnt * sg::kFramesPerShot * F, st));
-            SG_HIP(sg::launch_zero((float *)(wi + L.hsum), (size_t)cnt * F, st));
-            SG_HIP(sg::launch_zero((float *)(wi + L.hcomp), (size_t)cnt * F, st));
+            SG_HIP(sg::launch_zero((float *)(wi + L.hsum), (size_t)cnt * 2 * F, st));
             b.t = tile_args(T[i], b.s.fields, 0, 0, 0);
             b.t.ring = (float *)(wi + L.ring);
             b.t.ring_shot = (int64_t)L.ring_levels * F;
             b.t.resid = it.resid + (size_t)s0 * it.plan->nrow * it.shots->nrec;
-            b.t.hsum = (float *)(wi + L.hsum);
-            b.t.hcomp = (float *)(wi + L.hcomp);
+            b.t.hsum = (double *)(wi + L.hsum);
             b.t.nt = nt;
             b.t.inj.tile_start = (const int32_t *)(wi + L.inj_tile);
             b.t.inj.lds = (const int32_t *)(wi + L.inj_lds);
@@ -1540,7 +1535,7 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         }
         for (int q = 0; q < na; ++q) {
             const sg_batch_grad_item &it = items[act[q]];
-            SG_HIP(sg::launch_fold_gradient(hb[q].s, it.vp, hb[q].t.hsum, hb[q].t.hcomp, it.plan->frame,
+            SG_HIP(sg::launch_fold_gradient(hb[q].s, it.vp, hb[q].t.hsum, it.plan->frame,
                                             (float)it.plan->g.dt, it.grad, st, wv > 0));
         }
     }
