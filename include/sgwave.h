@@ -126,7 +126,9 @@ typedef struct {
  *                (variant 2), one of the built shapes 128x64, 64x128, 64x64;
  *                the output tile is that minus a halo of 4*time_block per side
  *                (under a free top the top tile row trades halo for ghost rows)
- *   time_block   time steps per launch (variant 2), 1..8
+ *   time_block   time steps per launch (variant 2), 1..8; 0 = 4 for forward
+ *                calls, 3 for the gradient calls (sg_forward_ckpt,
+ *                sg_adjoint_gradient, sg_batch_adjoint_gradient)
  *   rows_per_thread   rows of the tile column each thread keeps in registers
  *                (variant 2): 8 or 16 for 128x64, 16 for 64x128, 8 for 64x64;
  *                0 = the first built one

@@ -289,8 +289,10 @@ int shape_of(const sg_tuning &t)
     return -1;
 }
 
-// Tuning of a call: the plan's setting with zeros replaced by defaults.
-sg_tuning resolve_tuning(const sg_plan *p, int nshot)
+// Tuning of a call: the plan's setting with zeros replaced by defaults (time
+// block 4 for forward calls, 3 for the gradient calls, the fastest in
+// measurements of each on the field-scale workloads).
+sg_tuning resolve_tuning(const sg_plan *p, int nshot, bool gradient = false)
 {
     (void)nshot;
     sg_tuning t = p->tuning;
@@ -304,7 +306,7 @@ sg_tuning resolve_tuning(const sg_plan *p, int nshot)
         t.tile_x = 128;
         t.tile_z = 64;
     }
-    if (t.time_block <= 0) t.time_block = 4;
+    if (t.time_block <= 0) t.time_block = gradient ? 3 : 4;
     const int c = shape_of(t);
     if (c >= 0) t.rows_per_thread = sg::tiled_shape(c).k;
     return t;
@@ -559,14 +561,12 @@ sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *w
     c->L = layout_of(p, shots->nshot, shots->nrec, ckpt);
     if (ws_bytes < c->L.total)
         return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, c->L.total);
-    c->t = resolve_tuning(p, shots->nshot);
+    const bool gradient = need_tiled && ckpt > 0;
+    c->t = resolve_tuning(p, shots->nshot, gradient);
     if (need_tiled && c->t.variant == 1) {   // the gradient path runs on the tiled kernels
-        c->t.variant = 2;
-        c->t.tile_x = c->t.tile_z = c->t.rows_per_thread = 0;
-        c->t.time_block = 0;
         sg_tuning keep = p->tuning;
         p->tuning = sg_tuning{};
-        c->t = resolve_tuning(p, shots->nshot);
+        c->t = resolve_tuning(p, shots->nshot, gradient);
         p->tuning = keep;
     }
     if (c->t.variant == 2 && (rc = tiling_for(p, c->t, &c->config, &c->T)) != SG_OK) return rc;
@@ -1372,12 +1372,12 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         if (!items[i].vp || !items[i].resid || !items[i].grad) return fail(SG_EINVAL, "batch item %d: NULL pointer", i);
         if ((rc = check_shots(items[i].plan, items[i].shots)) != SG_OK) return rc;
     }
-    sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot);
+    sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot, true);
     if (t.variant != 2) {
         sg_plan *p0 = items[0].plan;
         sg_tuning keep = p0->tuning;
         p0->tuning = sg_tuning{};
-        t = resolve_tuning(p0, items[0].shots->nshot);
+        t = resolve_tuning(p0, items[0].shots->nshot, true);
         p0->tuning = keep;
     }
     std::vector<sg::Tiling> T(nitems);
