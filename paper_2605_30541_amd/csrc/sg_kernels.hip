@@ -60,7 +60,7 @@ __device__ inline void record_level(const SliceDesc &s, const float *cur, int sh
                 int off = s.rec_off[r * kNodes + k];
                 if (off >= 0) d += s.rec_w[r * kNodes + k] * cur[off];
             }
-            row[r] = d;
+            __builtin_nontemporal_store(d, row + r);      // written once
         }
     }
     if (s.snaps && n % s.snap_every == 0 && n / s.snap_every < s.snap_count) {
@@ -68,7 +68,7 @@ __device__ inline void record_level(const SliceDesc &s, const float *cur, int sh
         const int npts = s.nz * s.nx;
         for (int q = tid; q < npts; q += nthr) {
             int iz = q / s.nx, ix = q - iz * s.nx;
-            fr[q] = cur[(int64_t)(iz + s.ztop + kGuard) * s.pitch + ix + s.xleft + kGuard];
+            __builtin_nontemporal_store(cur[(int64_t)(iz + s.ztop + kGuard) * s.pitch + ix + s.xleft + kGuard], fr + q);
         }
     }
 }
@@ -195,6 +195,12 @@ template <class T>
 __device__ __forceinline__ void gstore_at(T *base, uint32_t byte_off, T v)
 {
     gstore((T *)((char *)base + byte_off), v);
+}
+
+// Streaming store (no reuse expected before the data leaves the caches).
+__device__ __forceinline__ void gstore_nt_at(float *base, uint32_t byte_off, float v)
+{
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) float *)((char *)base + byte_off));
 }
 
 __device__ __forceinline__ RecEntry gload_rec(const RecEntry *p)
@@ -607,11 +613,12 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 }
             }
             if (MODE == kRing && xout) {
-                // store the new level n+1 of the output tile
+                // store the new level n+1 of the output tile (read back by the
+                // adjoint only after the whole segment: streaming stores)
                 float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (k >= k_lo && k < k_hi) gstore_at(rl, rowb(k) + xo4, old[k]);
+                    if (k >= k_lo && k < k_hi) gstore_nt_at(rl, rowb(k) + xo4, old[k]);
             }
         }
         __syncthreads();
