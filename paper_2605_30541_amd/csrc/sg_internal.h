@@ -103,9 +103,9 @@ struct TileArgs {
     int32_t ntx, ntz;   // tiles per row / column
     int32_t in_pair, out_pair;
     float *fields;      // [nshot][kFramesPerShot][frame]
-    // forward: each new level of the output tile is also stored in ring slot
-    // (level - ring_lo) when ring != null; adjoint: the ring holds the forward
-    // levels ring_lo .. ring_hi read by the imaging term
+    // forward with ring != null: the second time difference D^n of the output
+    // tile is stored in ring slot n - ring_lo for every level n advanced;
+    // adjoint: the ring holds D^ring_lo .. D^ring_hi read by the imaging term
     float *ring;
     int32_t ring_lo, ring_hi;
     int64_t ring_shot;  // floats per shot in the ring

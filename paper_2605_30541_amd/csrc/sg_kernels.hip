@@ -248,16 +248,17 @@ struct TileShape {
 //
 // MODE kFwd:  p^{n+1} = W L p^n + (2a (p^n - p^{n-1}) + p^{n-1}) + W S^n, with the
 //             point sources S^n fused and the receivers of the tile sampled.
-// MODE kRing: the same, also storing every new level of the output tile in the
-//             ring (the forward recompute of the gradient; no receivers).
+// MODE kRing: the same, also storing the second time difference
+//             D^n = (p^{n+1} - p^n) - (p^n - p^{n-1}) of the output tile in ring
+//             slot n - ring_lo (the forward recompute of the gradient; no receivers).
 // MODE kAdj:  the transpose of that step map in the variable mu = W lambda,
 //             the same stencil run backwards,
 //               mu^k = W L mu^{k+1} + (2a (mu^{k+1} - mu^{k+2}) + mu^{k+2}) + W R^T r^k,
 //             with the residual r^k of recorded levels injected at the receiver
-//             nodes of the new level; alongside h += mu^{k+1} (p^{k+1} - 2 p^k + p^{k-1})
-//             for k <= nt-2 (the velocity gradient is 2 / (dt^2 v^3) h: the
-//             damping terms of the exact derivative cancel because eta does not
-//             depend on v).
+//             nodes of the new level; alongside h += mu^{k+1} D^k for k <= nt-2,
+//             D^k read from the ring (the velocity gradient is 2 / (dt^2 v^3) h:
+//             the damping terms of the exact derivative cancel because eta does
+//             not depend on v).
 enum { kFwd = 0, kRing = 1, kAdj = 2 };
 
 template <int K, int NWX, int NWZ, int MODE, bool ISO>
@@ -446,10 +447,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             inj_a[st * kInjE + e] = add;
         }
     }
-    // adjoint: forward levels of the imaging window (p^{k+1}, p^k, and p^{k-1}
-    // read one sub-step ahead), and the partial sums of h.  Only the output
-    // rows are read (in bounds at the clamped column); other lanes keep 0.
-    float pa[ADJ ? K : 1], pb[ADJ ? K : 1], pn[ADJ ? K : 1], hp[ADJ ? K : 1];
+    // adjoint: the second time difference D^k of the forward field for the
+    // imaging term (read one sub-step ahead), and the partial sums of h.  Only
+    // the output rows are read (in bounds at the clamped column); only the
+    // output columns' sums are stored.
+    float pn[ADJ ? K : 1], hp[ADJ ? K : 1];
     const float *ringb = ADJ ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
     auto ring_level = [&](int L, float(&dst)[ADJ ? K : 1]) {
         const bool h = L >= t.ring_lo && L <= t.ring_hi;
@@ -458,15 +460,9 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? gload_at(rl, rowb(k) + xc4) : 0.f;
     };
     if (ADJ) {
-        ring_level(t.n + 1, pa);
-        ring_level(t.n, pb);
-        ring_level(t.n - 1, pn);
+        ring_level(t.n, pn);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            pa[k] = xout ? pa[k] : 0.f;
-            pb[k] = xout ? pb[k] : 0.f;
-            hp[k] = 0.f;
-        }
+        for (int k = 0; k < K; ++k) hp[k] = 0.f;
     }
     __syncthreads();
 
@@ -493,20 +489,15 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             for (int q = rbeg + NTHR + (int)threadIdx.x; q < rend; q += NTHR) sample(gload_rec(s.rec_list + q));
         }
         if (ADJ) {
-            // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} (p^{n+1} - 2 p^n + p^{n-1}),
-            // then the loads of p^{n-2} for the next sub-step go out, to land
-            // while this sub-step computes
-            const bool image = n <= t.nt - 2;
+            // imaging term n (needs mu^{n+1} = cur): h += mu^{n+1} D^n, then the
+            // loads of D^{n-1} for the next sub-step go out, to land while this
+            // sub-step computes
+            if (n <= t.nt - 2) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k >= k_lo && k < k_hi) {
-                    const float pc = xout ? pn[k] : 0.f;
-                    if (image) hp[k] = fmaf(cur[k], (pa[k] - pb[k]) - (pb[k] - pc), hp[k]);
-                    pa[k] = pb[k];
-                    pb[k] = pc;
-                }
+                for (int k = 0; k < K; ++k)
+                    if (k >= k_lo && k < k_hi) hp[k] = fmaf(cur[k], pn[k], hp[k]);
             }
-            if (st + 1 < t.nsteps) ring_level(n - 2, pn);
+            if (st + 1 < t.nsteps) ring_level(n - 1, pn);
         }
 
         // rows still needed after this sub-step (local rows [need_lo, need_hi))
@@ -542,6 +533,10 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
             // (the adjoint, short of registers, reads each row where it is used)
             constexpr bool kAhead = !ADJ;
             const float wav = SRC ? wav_s[st] : 0.f;
+            // kRing: the ring slot of D^n (read back by the adjoint only after
+            // the whole segment: streaming stores)
+            float *rl_new = MODE == kRing ? t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n - t.ring_lo) * s.frame
+                                          : nullptr;
             float xa[2 * kHalo], xb[2 * kHalo];
             if (kAhead) xrow(xa);
 #pragma unroll
@@ -574,6 +569,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                     if (k == sk0) v = fmaf(W[k], sw0 * wav, v);
                     if (k == sk1) v = fmaf(W[k], sw1 * wav, v);
                 }
+                if (MODE == kRing && k >= k_lo && k < k_hi && xout)
+                    gstore_nt_at(rl_new, rowb(k) + xo4, (v - cur[k]) - (cur[k] - old[k]));   // D^n
                 old[k] = v;
                 lds[ln + lbase + k * LW] = v;
             }
@@ -611,14 +608,6 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                     const int Z = Z0 + k;
                     if (Z >= 1 && Z <= kHalo) lds[ln + (-Z - ez0 + kHalo) * LW + lx + kHalo] = -old[k];
                 }
-            }
-            if (MODE == kRing && xout) {
-                // store the new level n+1 of the output tile (read back by the
-                // adjoint only after the whole segment: streaming stores)
-                float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(n + 1 - t.ring_lo) * s.frame;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k >= k_lo && k < k_hi) gstore_nt_at(rl, rowb(k) + xo4, old[k]);
             }
         }
         __syncthreads();

@@ -94,8 +94,9 @@ namespace {
 // (byte offsets).  Everything from gx to tables_end is uploaded from the
 // plan's pinned staging buffer in one copy.  With ckpt > 0 the layout also
 // holds the gradient state: checkpoints (levels jC-1, jC of every shot every
-// C = ckpt levels), the ring of recomputed forward levels of one segment
-// (C + 2 levels), the adjoint field pairs, the FP64 accumulator of the imaging sum,
+// C = ckpt levels), the ring of one segment's recomputed second time
+// differences D^n (C levels), the adjoint field pairs, the FP64 accumulator
+// of the imaging sum,
 // and the residual-injection tables.
 struct Layout {
     size_t v2, w, a2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
@@ -157,7 +158,7 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
     if (ckpt > 0) {
         L.ckpt_every = ckpt;
         L.nseg = (p->g.nt + ckpt - 1) / ckpt;
-        L.ring_levels = ckpt + 2;
+        L.ring_levels = ckpt;                     // D^n of one segment
         L.ckpt = take((size_t)nshot * L.nseg * 2 * fr);
         L.ring = take((size_t)nshot * L.ring_levels * fr);
         L.mu = take((size_t)nshot * sg::kFramesPerShot * fr);
@@ -1063,13 +1064,13 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
     p->prof_used = 0;
     for (int j = c.L.nseg - 1; j >= 0; --j) {
         const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
-        // recompute levels lo-1 .. last into the ring from checkpoint j
+        // recompute levels lo+1 .. last from checkpoint j (levels lo-1, lo),
+        // storing D^lo .. D^{last-1} in the ring
         const float *ckj = ck + (int64_t)j * 2 * F;
         SG_HIP(sg::launch_copy(s.fields, fshot, ckj, ck_shot, 2 * F, nshot, st));
-        SG_HIP(sg::launch_copy(ring, ring_shot, ckj, ck_shot, 2 * F, nshot, st));
         int pair = 0;
         if (last > lo) {
-            rc = forward_run(p, s, c.t, c.config, c.T, lo, last, 0, &pair, ring, lo - 1, ring_shot,
+            rc = forward_run(p, s, c.t, c.config, c.T, lo, last, 0, &pair, ring, lo, ring_shot,
                              [](int, int) { return SG_OK; }, st);
             if (rc != SG_OK) return rc;
         }
@@ -1078,8 +1079,8 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
             const int nsteps = std::min(c.t.time_block, k0 - lo + 1);
             sg::TileArgs a = tile_args(c.T, mu, k0, nsteps, mpair);
             a.ring = ring;
-            a.ring_lo = lo - 1;
-            a.ring_hi = last;
+            a.ring_lo = lo;
+            a.ring_hi = last - 1;
             a.ring_shot = ring_shot;
             a.resid = resid;
             a.hsum = hsum;
@@ -1501,34 +1502,27 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         const int nseg = Ls[0].nseg;
         for (int j = nseg - 1; j >= 0; --j) {
             const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
-            for (int target = 0; target < 2; ++target) {
-                rc = copy_items(
-                    [&](int q, int64_t F, float **d, int64_t *ds) {
-                        if (target == 0) {
-                            *d = hb[q].s.fields;
-                            *ds = (int64_t)sg::kFramesPerShot * F;
-                        } else {
-                            *d = hb[q].t.ring;
-                            *ds = hb[q].t.ring_shot;
-                        }
-                    },
-                    [&](int q, int64_t F, const float **sp, int64_t *ss) {
-                        *sp = (const float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].ckpt) + (int64_t)j * 2 * F;
-                        *ss = (int64_t)Ls[q].nseg * 2 * F;
-                    },
-                    2);
-                if (rc != SG_OK) return rc;
-            }
+            rc = copy_items(
+                [&](int q, int64_t F, float **d, int64_t *ds) {
+                    *d = hb[q].s.fields;
+                    *ds = (int64_t)sg::kFramesPerShot * F;
+                },
+                [&](int q, int64_t F, const float **sp, int64_t *ss) {
+                    *sp = (const float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].ckpt) + (int64_t)j * 2 * F;
+                    *ss = (int64_t)Ls[q].nseg * 2 * F;
+                },
+                2);
+            if (rc != SG_OK) return rc;
             int fp = 0;
             for (int n = lo; n < last;) {
                 const int k = std::min(t.time_block, last - n);
-                SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo - 1, st));
+                SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo, st));
                 fp ^= 1;
                 n += k;
             }
             for (int k0 = hi; k0 >= lo;) {
                 const int ns = std::min(t.time_block, k0 - lo + 1);
-                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, iso, lo - 1, last, st));
+                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, iso, lo, last - 1, st));
                 mpair ^= 1;
                 k0 -= ns;
             }
