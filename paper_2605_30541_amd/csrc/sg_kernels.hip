@@ -286,12 +286,9 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     oz_end = min(oz_end, s.Nz);
     const int ox = txi * t.tx, ox_end = min(ox + t.tx, s.Nx), ex0 = ox - halo;
 
-    // In the adjoint the wave index is made explicitly uniform, so that what
-    // derives from it (rows, row addresses, row conditions) lives in scalar
-    // registers: that mode is short of vector registers.  The forward modes
-    // keep it per lane, which costs fewer scalar instructions.
-    const int lane = threadIdx.x & 63;
-    const int w = ADJ ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
+    // (the wave index stays a per-lane value: making it explicitly uniform
+    // moves the row arithmetic to the scalar unit, which measured slower)
+    const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
     const int lx = (w % NWX) * 64 + lane;        // local column in [0, EX)
     const int lz0 = (w / NWX) * K;               // first local row of this thread (wave-uniform)
     const int X = ex0 + lx, Z0 = ez0 + lz0;      // padded coordinates
