@@ -192,3 +192,20 @@ def test_graph_replay_follows_new_inputs_and_matches_plain_launches():
         assert rel_l2(gd[0], od[0]) <= TOL
         for j in range(1, 3):
             assert rel_l2(gs[0, j], os_[0, j]) <= TOL
+
+
+def test_paper_production_shape_with_decimation():
+    """The paper's production shape: a 619 x 1000 slice at 10 m with a 60-cell
+    sponge, dt 1 ms, 8001 levels; gathers decimated by k = 14 (572 samples per
+    trace, 1000 receivers at 10 m) and wavefield snapshots every 14 levels over
+    the first 5 s (358 frames of 619 x 1000), every one compared."""
+    nz, nx, h = 619, 1000, 10.0
+    g = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=1e-3, nt=8001, nbl=60, vmax_hint=4500.0, rec_every=14,
+                 snap_every=14, snap_count=358)
+    assert g.nrow == 572
+    v = synth.field_slice(7, nz, nx)
+    src = np.array([[10.0, 4990.0]])
+    rec = synth.surface_receivers(nx, h)
+    gd, gs = run_gpu(g, v, src, rec, 10.25)
+    assert gd.shape == (1, 572, 1000) and gs.shape == (1, 358, 619, 1000)
+    compare((gd, gs), run_oracle(g, v, src, rec, 10.25))
