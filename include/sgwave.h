@@ -205,6 +205,20 @@ sg_status sg_plan_profile(sg_plan *p, double *kernel_ms, int32_t *launches);
  */
 sg_status sg_ricker(double f0, double dt, int32_t nt, double t0, float *out);
 
+/*
+ * Band-limited source of App. E.4 (Table "bands"): the Ricker pulse of peak
+ * frequency f0 centred at 1/f0, filtered forward and backward (zero phase) by
+ * a 4th-order Butterworth band-pass with corners fmin < fmax [Hz] (bilinear
+ * design with pre-warped corners; each pass starts from the filter's rest
+ * state at the first sample of an odd extension of 27 samples at both ends),
+ * divided by its l2 norm and scaled by sqrt((fmax - fmin) / bandwidth_ref)
+ * (the paper uses 24 Hz).  Computed in double precision on the host, rounded
+ * to float into `out` (host memory of nt floats).  SG_EINVAL for nt <= 27,
+ * corners outside (0, Nyquist) or fmin >= fmax.
+ */
+sg_status sg_bandpass_ricker(double f0, double fmin, double fmax, double dt, int32_t nt, double bandwidth_ref,
+                             float *out);
+
 /* CFL time-step limit s_max h / vmax of App. E.3.2 for this stencil, with
  * h = min(dz, dx). */
 double sg_cfl_dt_max(double dz, double dx, double vmax);

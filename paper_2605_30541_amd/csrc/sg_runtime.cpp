@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -943,6 +944,127 @@ sg_status sg_ricker(double f0, double dt, int32_t nt, double t0, float *out)
         const double q = kPi * kPi * f0 * f0 * tau * tau;
         out[n] = (float)((1.0 - 2.0 * q) * std::exp(-q));
     }
+    return SG_OK;
+}
+
+namespace {
+
+// One second-order section y = (b0 + b1 z^-1 + b2 z^-2) / (1 + a1 z^-1 + a2 z^-2) x
+// in transposed direct form II with state (s0, s1).
+struct Biquad {
+    double b0, b1, b2, a1, a2;
+};
+
+// State of a section at rest under a constant unit input: the fixed point
+// s = A s + B of the transposed direct form, i.e. (I - A) s = B with
+// A = [[-a1, 1], [-a2, 0]] and B = (b1 - a1 b0, b2 - a2 b0).
+void biquad_rest_state(const Biquad &q, double s[2])
+{
+    const double r0 = q.b1 - q.a1 * q.b0, r1 = q.b2 - q.a2 * q.b0;
+    // [[1 + a1, -1], [a2, 1]] s = r
+    const double det = (1.0 + q.a1) + q.a2;
+    s[0] = (r0 + r1) / det;
+    s[1] = r1 - q.a2 * s[0];
+}
+
+// Runs the cascade over x[0..n) in place, starting every section from the
+// state it holds at rest under the constant input `level` (zero-phase
+// filtering starts both passes this way, so the edges see no step).
+void run_cascade(const std::vector<Biquad> &secs, double level, std::vector<double> &x)
+{
+    std::vector<double> st(2 * secs.size());
+    double scale = level;
+    for (size_t i = 0; i < secs.size(); ++i) {
+        biquad_rest_state(secs[i], &st[2 * i]);
+        st[2 * i] *= scale;
+        st[2 * i + 1] *= scale;
+        const Biquad &q = secs[i];
+        scale *= (q.b0 + q.b1 + q.b2) / (1.0 + q.a1 + q.a2);   // DC gain of the section
+    }
+    for (double &v : x) {
+        double u = v;
+        for (size_t i = 0; i < secs.size(); ++i) {
+            const Biquad &q = secs[i];
+            double &s0 = st[2 * i], &s1 = st[2 * i + 1];
+            const double y = q.b0 * u + s0;
+            s0 = q.b1 * u - q.a1 * y + s1;
+            s1 = q.b2 * u - q.a2 * y;
+            u = y;
+        }
+        v = u;
+    }
+}
+
+}  // namespace
+
+sg_status sg_bandpass_ricker(double f0, double fmin, double fmax, double dt, int32_t nt, double bandwidth_ref,
+                             float *out)
+{
+    if (!out || nt < 2 || !(f0 > 0) || !(dt > 0) || !(fmin > 0) || !(fmax > fmin) || !(fmax < 0.5 / dt) ||
+        !(bandwidth_ref > 0))
+        return fail(SG_EINVAL, "bad band-pass wavelet arguments");
+    // 4th-order Butterworth band-pass by the bilinear transform with
+    // pre-warped corners (normalised to the Nyquist frequency, design rate 2)
+    constexpr int N = 4;
+    const double w1 = 4.0 * std::tan(kPi * (2.0 * fmin * dt) / 2.0);
+    const double w2 = 4.0 * std::tan(kPi * (2.0 * fmax * dt) / 2.0);
+    const double bw = w2 - w1, wo2 = w1 * w2;
+    using cd = std::complex<double>;
+    std::vector<cd> poles;
+    for (int m = -N + 1; m < N; m += 2) {
+        const cd p = -std::exp(cd(0.0, kPi * m / (2.0 * N)));   // analog low-pass prototype
+        const cd pl = p * (bw / 2.0);
+        const cd r = std::sqrt(pl * pl - wo2);
+        poles.push_back(pl + r);                                 // low-pass -> band-pass
+        poles.push_back(pl - r);
+    }
+    // bilinear map s -> z = (4 + s) / (4 - s); the N analog zeros at 0 map to
+    // z = 1, the N at infinity to z = -1; gain k = bw^N prod(4 - 0) / prod(4 - p)
+    cd gain = std::pow(bw, N) * std::pow(4.0, N);
+    std::vector<cd> zp;
+    for (const cd &p : poles) {
+        gain /= (4.0 - p);
+        zp.push_back((4.0 + p) / (4.0 - p));
+    }
+    // sections: one conjugate pole pair each (upper half plane members) with
+    // one zero at +1 and one at -1; the gain goes to the first section
+    std::vector<Biquad> secs;
+    for (const cd &p : zp) {
+        if (p.imag() <= 0.0) continue;
+        Biquad q{1.0, 0.0, -1.0, -2.0 * p.real(), std::norm(p)};
+        secs.push_back(q);
+    }
+    if ((int)secs.size() != N) return fail(SG_EINVAL, "band too narrow or too wide for the filter design");
+    secs[0].b0 *= gain.real();
+    secs[0].b2 *= gain.real();
+    // zero-phase filtering of the Ricker pulse: odd extension of 3 (2 sections + 1)
+    // samples at each end, forward pass from rest at the first sample, backward
+    // pass from rest at the last output, extension removed
+    const int pad = 3 * (2 * N + 1);
+    if (nt <= pad) return fail(SG_EINVAL, "nt must exceed %d samples for the band-pass filter", pad);
+    std::vector<double> w(nt);
+    const double t0 = 1.0 / f0;
+    for (int n = 0; n < nt; ++n) {
+        const double tau = n * dt - t0;
+        const double q = kPi * kPi * f0 * f0 * tau * tau;
+        w[n] = (1.0 - 2.0 * q) * std::exp(-q);
+    }
+    std::vector<double> x(nt + 2 * pad);
+    for (int i = 0; i < pad; ++i) {
+        x[i] = 2.0 * w[0] - w[pad - i];
+        x[pad + nt + i] = 2.0 * w[nt - 1] - w[nt - 2 - i];
+    }
+    for (int n = 0; n < nt; ++n) x[pad + n] = w[n];
+    run_cascade(secs, x.front(), x);
+    std::reverse(x.begin(), x.end());
+    run_cascade(secs, x.front(), x);
+    std::reverse(x.begin(), x.end());
+    double norm = 0.0;
+    for (int n = 0; n < nt; ++n) norm += x[pad + n] * x[pad + n];
+    norm = std::sqrt(norm);
+    if (!(norm > 0)) return fail(SG_EINVAL, "the band-passed pulse is zero");
+    const double scale = std::sqrt((fmax - fmin) / bandwidth_ref) / norm;
+    for (int n = 0; n < nt; ++n) out[n] = (float)(x[pad + n] * scale);
     return SG_OK;
 }
 

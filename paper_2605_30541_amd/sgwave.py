@@ -111,6 +111,8 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_bandpass_ricker": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_float)]),
     "sg_batch_autotune": (ctypes.c_int32, [ctypes.POINTER(sg_batch_item), ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                            ctypes.POINTER(sg_tuning)]),
@@ -133,6 +135,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libsgwave.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # torch (which owns device memory and streams here) is loaded first:
+        # loading this library before torch's HIP runtime has left the
+        # library's later HIP calls without a device
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -414,6 +420,14 @@ def sg_check_finite(x, ws, stream=None):
 
 
 # ------------------------------------------------------------------ helpers
+
+def sg_bandpass_ricker(f0: float, fmin: float, fmax: float, dt: float, nt: int,
+                       bandwidth_ref: float = 24.0) -> np.ndarray:
+    out = np.empty(nt, np.float32)
+    _check(lib().sg_bandpass_ricker(f0, fmin, fmax, dt, nt, bandwidth_ref,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
 
 def ricker_tensor(f0: float, dt: float, nt: int, device="cuda"):
     """Ricker wavelet from sg_ricker as a [1, nt] float32 tensor."""

@@ -35,6 +35,26 @@ def test_ricker_matches_oracle():
         assert np.abs(a - b).max() <= 6e-8 * np.abs(b).max()
 
 
+def test_bandpass_ricker_matches_oracle():
+    """The band-limited sources of App. E.4 for the paper's five bands (Table
+    "bands", peak frequencies of App. E.4) at the paper's and the field
+    workload's sampling: equal to the oracle's (SciPy zero-phase
+    second-order-section filtering) to float rounding."""
+    import json
+    import os
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_params.json")))
+    for f0, b in zip(golden["peak_frequencies_hz"]["value"], golden["bands"]):
+        for dt, nt in ((1e-3, 8001), (8e-4, 10000)):
+            a = sgwave.sg_bandpass_ricker(f0, b["fmin"], b["fmax"], dt, nt)
+            r = oracle.bandpass_ricker(f0, (b["fmin"], b["fmax"]), dt, nt)
+            assert np.abs(a - r).max() <= 2e-7 * np.abs(r).max(), (f0, dt)
+    for bad in ((10.0, 5.0, 5.0, 1e-3, 500), (10.0, 0.0, 5.0, 1e-3, 500), (10.0, 3.0, 600.0, 1e-3, 500),
+                (10.0, 3.0, 25.0, 1e-3, 27)):
+        with pytest.raises(SGError) as e:
+            sgwave.sg_bandpass_ricker(*bad)
+        assert e.value.status == sgwave.SG_EINVAL
+
+
 def test_cfl_limit_matches_paper_constant():
     assert sgwave.sg_cfl_dt_max(10.0, 10.0, 5000.0) == pytest.approx(oracle.cfl_dt_max(10.0, 5000.0), rel=1e-14)
 
