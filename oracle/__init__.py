@@ -13,7 +13,8 @@ Contents
     sources, receivers, snapshots, and the exact adjoint and velocity gradient.
   * ``wave.py``: ctypes marshalling for ``fdo.c`` and the host-side formulas
     of the paper (Ricker pulse, CFL and dispersion limits, temporal
-    subsampling, band-passed wavelets).
+    subsampling, band-passed wavelets) and the residual of the discretised
+    wave operator on a stack of frames.
 """
 from .wave import (  # noqa: F401
     Geometry,
@@ -35,4 +36,5 @@ from .wave import (  # noqa: F401
     c_damp,
     bandpass_ricker,
     misfit,
+    wave_residual,
 )

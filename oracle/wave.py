@@ -236,6 +236,50 @@ def fd_coefficients(M: int = 4):
     return c
 
 
+def wave_residual(frames, v, dz: float, dx: float, dt: float, top_free: bool = True):
+    """Residual of the discretised acoustic operator on a stack of wavefield
+    frames (App. F.5, the physics-residual ratio of the predicted wavefields):
+
+        R_t = (u_{t+1} - 2 u_t + u_{t-1}) / dt^2 - v^2 L u_t,
+
+    L the 8th-order Laplacian of App. E.3, dt the spacing of the frames.
+    Evaluated where the frames alone define it: frames t = 1..T-2; columns
+    4..nx-5; rows 4..nz-5, or rows 1..nz-5 under a free top (odd mirror
+    u(-m) = -u(m) above the pinned row 0).
+
+    Returns (res2, dtt2): per-frame sums over those cells of R_t^2 and of
+    ((u_{t+1} - 2 u_t + u_{t-1}) / dt^2)^2 (zero for the first and last
+    frames).  The ratio sqrt(sum res2 / sum dtt2) measures how far the
+    frames are from satisfying the discrete wave equation.
+    """
+    u = np.asarray(frames, np.float64)
+    v2 = np.asarray(v, np.float64) ** 2
+    T, nz, nx = u.shape
+    c = [float(x) for x in fd_coefficients()]
+    z0 = 1 if top_free else 4
+    res2, dtt2 = np.zeros(T), np.zeros(T)
+    if T < 3 or nz - 4 <= z0 or nx <= 8:
+        return res2, dtt2
+    for t in range(1, T - 1):
+        ut = u[t]
+        if top_free:   # rows -4..-1 are the odd mirror of rows 4..1
+            ut = np.concatenate([-ut[4:0:-1], ut], axis=0)
+            off = 4
+        else:
+            off = 0
+        zs = slice(z0 + off, nz - 4 + off)
+        xs = slice(4, nx - 4)
+        lap = (c[0] / dz ** 2 + c[0] / dx ** 2) * ut[zs, xs]
+        for m in range(1, 5):
+            lap = lap + c[m] / dz ** 2 * (ut[z0 + off + m:nz - 4 + off + m, xs] + ut[z0 + off - m:nz - 4 + off - m, xs])
+            lap = lap + c[m] / dx ** 2 * (ut[zs, 4 + m:nx - 4 + m] + ut[zs, 4 - m:nx - 4 - m])
+        dtt = (u[t + 1, z0:nz - 4, 4:nx - 4] - 2.0 * u[t, z0:nz - 4, 4:nx - 4] + u[t - 1, z0:nz - 4, 4:nx - 4]) / dt ** 2
+        r = dtt - v2[z0:nz - 4, 4:nx - 4] * lap
+        res2[t] = float(np.sum(r * r))
+        dtt2[t] = float(np.sum(dtt * dtt))
+    return res2, dtt2
+
+
 def cfl_smax(M: int = 4, d: int = 2) -> float:
     """Paper's stability constant s_max = (sqrt(d sum_{m=1}^M |a_m|))^{-1}
     (App. E.3.2, "CFL Stability Condition")."""

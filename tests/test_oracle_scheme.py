@@ -346,3 +346,49 @@ def test_bruteforce_space_time_system():
     ref = _bruteforce_gathers(nz, nx, h, h, dt, nt, nbl, v, src, w, rec)
     assert np.abs(ref).max() > 0
     assert np.abs(d[0] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("top_free", [True, False])
+def test_wave_residual_closed_form_on_a_separable_mode(top_free):
+    """u = cos(w t) sin(kz z) cos(kx x) (odd about z = 0, so the free-surface
+    mirror holds exactly): the discrete second difference in time and the
+    8th-order Laplacian act as multiplications by closed-form symbols, so
+    R = u [(2 cos(w dt) - 2) / dt^2 - v^2 (sum_m c_m 2 (cos(m kz dz) - 1) / dz^2
+    + sum_m c_m 2 (cos(m kx dx) - 1) / dx^2)] at every evaluated cell."""
+    nz, nx, T, dz, dx, dt, vel = 30, 41, 7, 8.0, 11.0, 1.3e-3, 2300.0
+    w, kz, kx = 2 * np.pi * 17.0, 2 * np.pi / 97.0, 2 * np.pi / 131.0
+    t = np.arange(T)[:, None, None] * dt
+    z = np.arange(nz)[None, :, None] * dz
+    x = np.arange(nx)[None, None, :] * dx
+    u = np.cos(w * t) * np.sin(kz * z) * np.cos(kx * x)
+    c = [float(q) for q in oracle.fd_coefficients()]
+    sym_t = (2 * np.cos(w * dt) - 2) / dt ** 2
+    sym_l = sum(c[m] * 2 * (np.cos(m * kz * dz) - 1) for m in range(1, 5)) / dz ** 2 + \
+        sum(c[m] * 2 * (np.cos(m * kx * dx) - 1) for m in range(1, 5)) / dx ** 2
+    res2, dtt2 = oracle.wave_residual(u, np.full((nz, nx), vel), dz, dx, dt, top_free=top_free)
+    z0 = 1 if top_free else 4
+    for k in range(1, T - 1):
+        cells = u[k, z0:nz - 4, 4:nx - 4]
+        assert res2[k] == pytest.approx(np.sum((cells * (sym_t - vel ** 2 * sym_l)) ** 2), rel=1e-9)
+        assert dtt2[k] == pytest.approx(np.sum((cells * sym_t) ** 2), rel=1e-9)
+    assert res2[0] == res2[-1] == 0.0 and dtt2[0] == dtt2[-1] == 0.0
+
+
+def test_wave_residual_vanishes_on_the_schemes_own_frames():
+    """Frames of the scheme itself (rigid boundary, no sponge: a = 1,
+    W = (v dt)^2) at the time step of the scheme satisfy the discrete wave
+    equation exactly once the source has stopped: the residual is round-off."""
+    nz, nx, dt, nt = 40, 50, 1e-3, 90
+    g = oracle.Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=dt, nt=nt, nbl=0, top_free=True)
+    rng = np.random.default_rng(3)
+    v = rng.uniform(2000.0, 3000.0, (nz, nx))
+    wl = np.zeros(nt)
+    wl[:25] = oracle.ricker(60.0, dt, 25)
+    _, snaps = oracle.forward(g, v, np.array([[200.0, 250.0]]), wl[None], np.zeros((0, 2)),
+                              snap_every=1, snap_count=nt)
+    res2, dtt2 = oracle.wave_residual(snaps[0], v, 10.0, 10.0, dt, top_free=True)
+    late = slice(30, nt - 1)
+    assert np.sum(dtt2[late]) > 0
+    assert np.sqrt(np.sum(res2[late]) / np.sum(dtt2[late])) < 1e-9
+    # while the source acts the residual is the source term, not round-off
+    assert np.sqrt(res2[10] / dtt2[10]) > 1e-3
