@@ -208,6 +208,36 @@ def paper_workload_rate(fwd_rate):
             "ratio_to_forward_value": rate / fwd_rate}
 
 
+def residual_rate(passes=10):
+    """Physics-residual pass (App. F.5) over the paper's saved wavefield stack
+    of one shot: 572 frames (8001 levels decimated by 14) of 619 x 1000, free
+    top, frame spacing 14 ms.  Seeded random frames: the pass does the same
+    work for any values.  Algorithmic traffic: every frame and the velocity
+    read once (4 B per cell), the sums written (16 B per frame)."""
+    import torch
+    from paper_2605_30541_amd import sgwave
+    T, nz, nx = 572, 619, 1000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    frames = torch.randn((T, nz, nx), dtype=torch.float32, device="cuda", generator=gen)
+    vp = torch.empty((nz, nx), dtype=torch.float32, device="cuda").uniform_(1500.0, 4500.0, generator=gen)
+    sgwave.wave_residual(frames, vp, 10.0, 10.0, 14e-3)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(passes):
+        res2, dtt2 = sgwave.wave_residual(frames, vp, 10.0, 10.0, 14e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / passes
+    ratio = float(torch.sqrt(res2.sum() / dtt2.sum()))
+    algo = 4.0 * (T + 1) * nz * nx + 16.0 * T
+    del frames
+    return {"workload": "572 frames of 619x1000 (one shot's wavefields, 8001 levels decimated by 14), free top",
+            "ms": ms, "frames_per_s": T / (ms / 1e3), "hbm_algorithmic_GBs": algo / (ms / 1e3) / 1e9,
+            "frac_of_hbm_peak": algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "residual_ratio": ratio}
+
+
 def batched_gradient_rate(fwd_rate, shots_per_wave):
     """4 field slices of uneven size (nz 500-620, nx 801-1001) x 100 shots
     spread evenly over the full width, nt 10000 at 0.8 ms, receivers on every
@@ -347,6 +377,8 @@ def main():
         log("batched: %.1f Gpt-updates/s" % out["batched"]["value"])
         out["paper_workload"] = paper_workload_rate(value)
         log("paper-shaped batch: %.1f Gpt-updates/s" % out["paper_workload"]["value"])
+        out["physics_residual"] = residual_rate()
+        log("physics residual: %.3f ms per 572-frame stack" % out["physics_residual"]["ms"])
     if args.batched_gradient:
         out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])

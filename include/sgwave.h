@@ -330,6 +330,32 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
                                     int32_t shots_per_wave, const sg_tuning *tuning, void *ws, size_t ws_bytes,
                                     void *stream);
 
+/*
+ * Physics residual of a stack of wavefield frames (App. F.5: the residual of
+ * the discretised acoustic wave operator, used there to judge predicted
+ * wavefields without the ground truth):
+ *     R_t = (u_{t+1} - 2 u_t + u_{t-1}) / dt^2 - v^2 L u_t
+ * with L the 8th-order Laplacian of App. E.3 and dt the spacing of the frames,
+ * evaluated where the frames alone define it: frames 1..nframes-2, columns
+ * 4..nx-5, rows 1..nz-5 under SG_TOP_FREE (odd mirror above the pinned row 0)
+ * or rows 4..nz-5 under SG_TOP_ABSORBING.
+ *   frames  device [nframes][nz][nx] float (physical grid, x fastest)
+ *   vp      device [nz][nx] float velocity [m/s]
+ *   res2    device [nframes] double, written: sum over the cells of R_t^2
+ *   dtt2    device [nframes] double, written: sum of ((u_{t+1} - 2u_t + u_{t-1}) / dt^2)^2
+ * (0 for the first and last frame).  sqrt(sum res2 / sum dtt2) is the
+ * residual ratio.  FP32 stencil arithmetic (difference form); FP32 sums over
+ * 8 rows, FP64 beyond, in a fixed order (deterministic).
+ * ws: sg_wave_residual_workspace_size bytes (caller-owned device scratch).  SG_EINVAL for NULL pointers, non-positive
+ * sizes or spacings, more than 65537 frames or frames of 2^30 cells or more;
+ * SG_ENOSPACE for a short workspace.  Fewer than 3 frames, or a grid with no
+ * evaluated cell, gives all-zero sums.
+ */
+sg_status sg_wave_residual_workspace_size(int32_t nframes, int32_t nz, int32_t nx, int32_t top, size_t *bytes);
+sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int32_t nx, const float *vp, double dz,
+                           double dx, double dt, int32_t top, double *res2, double *dtt2, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* Turn the graph replay of sg_forward and sg_batch_forward on (default) or
  * off (plain stream launches); process-wide. */
 sg_status sg_set_graphs(int32_t on);

@@ -167,4 +167,18 @@ hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const doubl
 hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st, int what = 3);
 hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st);
 
+// Wave-equation residual of a frame stack: c_m / dz^2 and c_m / dx^2, m = 0..4.
+struct ResidualCoef {
+    float cz[kHalo + 1];
+    float cx[kHalo + 1];
+};
+// Partial sums per frame of the residual kernel (one per wave of each tile)
+// for rows z0..nz-5, columns 4..nx-5.
+int wave_residual_slots(int nz, int nx, int z0);
+// res2/dtt2 [nframes] (device) from frames [nframes][nz][nx] and vp [nz][nx];
+// partials: 2 * (nframes - 2) * wave_residual_slots doubles of scratch.
+hipError_t launch_wave_residual(const float *frames, int nframes, int nz, int nx, const float *vp, double dt,
+                                const ResidualCoef &cf, int z0, double *partials, double *res2, double *dtt2,
+                                hipStream_t st);
+
 }  // namespace sg

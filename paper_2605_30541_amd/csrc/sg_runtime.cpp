@@ -1658,6 +1658,50 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
     return SG_OK;
 }
 
+namespace {
+sg_status residual_args(int32_t nframes, int32_t nz, int32_t nx, int32_t top, int *z0, size_t *bytes)
+{
+    if (nframes < 1 || nz < 1 || nx < 1) return fail(SG_EINVAL, "nframes, nz and nx must be >= 1");
+    if (nframes > 65537) return fail(SG_EINVAL, "at most 65537 frames per call");
+    if ((int64_t)nz * nx >= ((int64_t)1 << 30)) return fail(SG_EINVAL, "frame of %d x %d cells is too large", nz, nx);
+    if (top != SG_TOP_FREE && top != SG_TOP_ABSORBING) return fail(SG_EINVAL, "top must be SG_TOP_FREE or SG_TOP_ABSORBING");
+    *z0 = top == SG_TOP_FREE ? 1 : 4;
+    const int nb = sg::wave_residual_slots(nz, nx, *z0);
+    *bytes = align_up((size_t)std::max(nframes - 2, 0) * nb * 2 * sizeof(double), 256);
+    if (*bytes == 0) *bytes = 256;
+    return SG_OK;
+}
+}  // namespace
+
+sg_status sg_wave_residual_workspace_size(int32_t nframes, int32_t nz, int32_t nx, int32_t top, size_t *bytes)
+{
+    if (!bytes) return fail(SG_EINVAL, "NULL argument");
+    int z0 = 0;
+    return residual_args(nframes, nz, nx, top, &z0, bytes);
+}
+
+sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int32_t nx, const float *vp, double dz,
+                           double dx, double dt, int32_t top, double *res2, double *dtt2, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    if (!frames || !vp || !res2 || !dtt2 || !ws) return fail(SG_EINVAL, "NULL argument");
+    if (!(dz > 0) || !(dx > 0) || !(dt > 0) || !std::isfinite(dz) || !std::isfinite(dx) || !std::isfinite(dt))
+        return fail(SG_EINVAL, "dz, dx and dt must be finite and > 0");
+    int z0 = 0;
+    size_t need = 0;
+    sg_status rc = residual_args(nframes, nz, nx, top, &z0, &need);
+    if (rc != SG_OK) return rc;
+    if (ws_bytes < need) return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    sg::ResidualCoef cf{};
+    for (int m = 0; m <= sg::kHalo; ++m) {
+        cf.cz[m] = (float)(kC8[m] / (dz * dz));
+        cf.cx[m] = (float)(kC8[m] / (dx * dx));
+    }
+    SG_HIP(sg::launch_wave_residual(frames, nframes, nz, nx, vp, dt, cf, z0, (double *)ws, res2, dtt2,
+                                    (hipStream_t)stream));
+    return SG_OK;
+}
+
 sg_status sg_set_graphs(int32_t on)
 {
     g_batch_graphs = on != 0;

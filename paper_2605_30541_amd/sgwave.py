@@ -111,6 +111,12 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_wave_residual_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_wave_residual": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_bandpass_ricker": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_float)]),
     "sg_batch_autotune": (ctypes.c_int32, [ctypes.POINTER(sg_batch_item), ctypes.c_int32, ctypes.c_int32,
@@ -408,6 +414,26 @@ def sg_batch_adjoint_gradient(items, ws, ckpt_every=0, shots_per_wave=0, tuning=
                                    tuning.get("time_block", 0), tuning.get("rows_per_thread", 0)))
     _check(lib().sg_batch_adjoint_gradient(arr, len(items), ckpt_every, shots_per_wave, t, _ptr(ws),
                                            ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def sg_wave_residual_workspace_size(nframes: int, nz: int, nx: int, top: int = SG_TOP_FREE) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().sg_wave_residual_workspace_size(nframes, nz, nx, top, ctypes.byref(n)))
+    return n.value
+
+
+def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP_FREE, stream=None):
+    """Per-frame sums (res2, dtt2) of the wave-equation residual of a device
+    frame stack [T][nz][nx] (float32) on velocity vp [nz][nx]; returns two
+    float64 device tensors of T entries."""
+    import torch
+    T, nz, nx = frames.shape
+    res2 = torch.empty(T, dtype=torch.float64, device=frames.device)
+    dtt2 = torch.empty_like(res2)
+    ws = torch.empty(sg_wave_residual_workspace_size(T, nz, nx, top), dtype=torch.uint8, device=frames.device)
+    _check(lib().sg_wave_residual(_ptr(frames), T, nz, nx, _ptr(vp), dz, dx, dt, top, _ptr(res2), _ptr(dtt2),
+                                  _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return res2, dtt2
 
 
 def sg_set_graphs(on: bool):

@@ -157,3 +157,33 @@ def test_forward_argument_errors_touch_nothing():
 
 def test_destroy_null_is_ok():
     assert sgwave.lib().sg_plan_destroy(None) == 0
+
+
+def test_wave_residual_workspace_and_argument_errors():
+    """Workspace of the residual pass (FP64 partial sums per workgroup and
+    frame) and its argument checks, which return before any device work."""
+    def blocks(nz, nx, z0):   # 4 partial sums per tile of 64 columns x 32 rows
+        if nx <= 8 or nz - 4 - z0 <= 0:
+            return 0
+        return 4 * (-(-(nx - 8) // 64)) * (-(-(nz - 4 - z0) // 32))
+    for T, nz, nx, top, z0 in ((10, 619, 1000, sgwave.SG_TOP_FREE, 1), (10, 619, 1000, sgwave.SG_TOP_ABSORBING, 4),
+                               (3, 9, 9, sgwave.SG_TOP_FREE, 1)):
+        need = (T - 2) * blocks(nz, nx, z0) * 16
+        assert sgwave.sg_wave_residual_workspace_size(T, nz, nx, top) == max(-(-need // 256) * 256, 256)
+    assert sgwave.sg_wave_residual_workspace_size(2, 50, 50) == 256
+    assert sgwave.sg_wave_residual_workspace_size(10, 5, 5) == 256
+    for bad in ((0, 10, 10, 0), (5, 0, 10, 0), (5, 10, 10, 2), (70000, 10, 10, 0)):
+        with pytest.raises(SGError) as e:
+            sgwave.sg_wave_residual_workspace_size(*bad)
+        assert e.value.status == sgwave.SG_EINVAL
+    L = sgwave.lib()
+    fake = ctypes.c_void_p(4096)
+    ws = sgwave.sg_wave_residual_workspace_size(10, 40, 50)
+    # (pointers, sizes, spacings, top, workspace bytes) -> expected status
+    cases = [((None, 10, 40, 50, fake, 10.0, 10.0, 1e-3, 0, fake, fake, fake, ws), sgwave.SG_EINVAL),
+             ((fake, 10, 40, 50, fake, 0.0, 10.0, 1e-3, 0, fake, fake, fake, ws), sgwave.SG_EINVAL),
+             ((fake, 10, 40, 50, fake, 10.0, 10.0, float("nan"), 0, fake, fake, fake, ws), sgwave.SG_EINVAL),
+             ((fake, 10, 40, 50, fake, 10.0, 10.0, 1e-3, 3, fake, fake, fake, ws), sgwave.SG_EINVAL),
+             ((fake, 10, 40, 50, fake, 10.0, 10.0, 1e-3, 0, fake, fake, fake, ws - 1), sgwave.SG_ENOSPACE)]
+    for args, status in cases:
+        assert L.sg_wave_residual(*args, None) == status
