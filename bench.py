@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--batched-gradient", action="store_true",
                     help="also run the 4 slices x 100 shots batched gradient (about a minute)")
     ap.add_argument("--shots-per-wave", type=int, default=25)
+    ap.add_argument("--residual-only", action="store_true",
+                    help="time only the physics-residual pass over the 572-frame stack and print its record")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -208,6 +210,19 @@ def paper_workload_rate(fwd_rate):
             "ratio_to_forward_value": rate / fwd_rate}
 
 
+def copy_reference(mib):
+    """A device-to-device copy of `mib` MiB: a kernel of known traffic that
+    calibrates the hardware byte counters."""
+    if mib <= 0:
+        return
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def residual_rate(passes=10):
     """Physics-residual pass (App. F.5) over the paper's saved wavefield stack
     of one shot: 572 frames (8001 levels decimated by 14) of 619 x 1000, free
@@ -287,6 +302,11 @@ def main():
               "(shots shard across GPUs with no communication, see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.residual_only:
+        out = {"physics_residual": residual_rate()}
+        copy_reference(args.copy_mib)
+        print(json.dumps(out), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -382,12 +402,7 @@ def main():
     if args.batched_gradient:
         out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
-    if args.copy_mib > 0:
-        n = args.copy_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
+    copy_reference(args.copy_mib)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(v, geom, src, rec, f0, args.cpu_sample_levels)
