@@ -156,8 +156,11 @@ const char *sg_last_error(void);
 
 /*
  * Validate a geometry and create a plan (host only, no device work).
- * Returns SG_EINVAL for bad sizes, SG_ECFL when dt > s_max h / vmax_hint
- * unless flags has SG_ALLOW_UNSTABLE.  *out is NULL on error.
+ * Returns SG_EINVAL for bad sizes (among them a stored padded field, guard
+ * ring included, of more than 2^29 cells: the kernels address a field with
+ * 32-bit byte offsets, the FP64 gradient accumulator included), SG_ECFL when
+ * dt > s_max h / vmax_hint unless flags has SG_ALLOW_UNSTABLE.  *out is NULL
+ * on error.
  */
 sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out);
 
@@ -344,10 +347,11 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
  *   res2    device [nframes] double, written: sum over the cells of R_t^2
  *   dtt2    device [nframes] double, written: sum of ((u_{t+1} - 2u_t + u_{t-1}) / dt^2)^2
  * (0 for the first and last frame).  sqrt(sum res2 / sum dtt2) is the
- * residual ratio.  FP32 stencil arithmetic (difference form); FP32 sums over
- * 8 rows, FP64 beyond, in a fixed order (deterministic).
- * ws: sg_wave_residual_workspace_size bytes (caller-owned device scratch).  SG_EINVAL for NULL pointers, non-positive
- * sizes or spacings, more than 65537 frames or frames of 2^30 cells or more;
+ * residual ratio.  FP32 stencil arithmetic; FP32 sums over the 8 rows of a
+ * lane and the 16 lanes of a row, FP64 beyond, in a fixed order
+ * (deterministic).  ws: sg_wave_residual_workspace_size bytes (caller-owned
+ * device scratch).  SG_EINVAL for NULL pointers, non-positive sizes or
+ * spacings, more than 65537 frames or frames of 2^30 cells or more;
  * SG_ENOSPACE for a short workspace.  Fewer than 3 frames, or a grid with no
  * evaluated cell, gives all-zero sums.
  */

@@ -831,8 +831,11 @@ sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out)
     const int64_t Nz = (int64_t)g->nz + ztop + g->nbl, Nx = (int64_t)g->nx + 2 * g->nbl;
     const int64_t pitch = (int64_t)align_up((size_t)(Nx + 2 * sg::kGuard), 32);
     const int64_t frame = (Nz + 2 * sg::kGuard) * pitch;
-    if (frame >= ((int64_t)1 << 31)) return fail(SG_EINVAL, "grid too large (%lld x %lld)", (long long)Nz,
-                                                 (long long)Nx);
+    // in-field addressing uses 32-bit byte offsets, 8 bytes per cell in the
+    // FP64 imaging accumulator
+    if (frame > ((int64_t)1 << 29))
+        return fail(SG_EINVAL, "grid too large (%lld x %lld padded; a stored field holds at most 2^29 cells)",
+                    (long long)Nz, (long long)Nx);
     sg_plan *p = new (std::nothrow) sg_plan();
     if (!p) return fail(SG_EINVAL, "out of host memory");
     p->g = *g;

@@ -80,6 +80,21 @@ def test_plan_validation_errors():
         Plan(_geom(snap_count=5, snap_every=100, nt=400))
 
 
+def test_largest_grid():
+    """A stored field (padded grid + 4-cell guard ring, rows padded to 32
+    floats) may hold 2^29 cells, no more: 32-bit byte offsets reach every cell
+    of the FP64 imaging accumulator."""
+    # free top, no sponge: stored field (nz + 8) x pitch, pitch = nx + 8 rounded up to 32
+    nx = 16384 - 8                                   # pitch 16384
+    nz_max = (1 << 29) // 16384 - 8                  # 32760 rows: exactly 2^29 cells
+    g = _geom(nz=nz_max, nx=nx, nbl=0, nt=10)
+    p = Plan(g)
+    assert p.padded_shape == (nz_max, nx)
+    with pytest.raises(SGError) as e:
+        Plan(_geom(nz=nz_max + 1, nx=nx, nbl=0, nt=10))
+    assert e.value.status == sgwave.SG_EINVAL and "2^29" in e.value.message
+
+
 def test_plan_cfl_rejection_and_override():
     dtmax = oracle.cfl_dt_max(10.0, 5000.0)
     Plan(_geom(dt=dtmax * 0.999, vmax_hint=5000.0))
