@@ -33,6 +33,7 @@ struct SliceDesc {
     int32_t nz, nx;          // physical grid
     int32_t ztop, xleft;     // padded index of physical (0, 0)
     int32_t free_top;        // 1: row 0 pinned to 0, odd mirror above
+    int32_t unit_z0, unit_z1, unit_x0, unit_x1;   // padded box [z0, z1) x [x0, x1) of updated cells with a = 1
     int32_t nshot;
     int32_t nrec;
     int32_t nrow;            // gather rows = ceil(nt / rec_every)

@@ -343,33 +343,77 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // clamped, in-bounds cell (ghost rows above a free top read their mirror
     // row) and the values are selected afterwards, so the loads of all rows
     // are in flight together instead of one row after another.
+    //
+    // The newer level is loaded first and goes to LDS as soon as it arrives;
+    // the older level and the coefficients are still in flight meanwhile.
+    // Where every loaded cell has a = 1 (no sponge, no pinned row, inside the
+    // grid; a box computed on the host) 2a is exactly 2 and is not loaded.
+    //
+    // The small tables (source nodes, this launch's wavelet samples, the
+    // tile's receiver range and entries) are requested around the field loads
+    // so that all of them travel together: used after the field loads, one
+    // after another, they cost several dependent round trips.
+    int psz[kNodes], psx[kNodes];
+    float psw[kNodes];
+    float pwav = 0.f;
+    int32_t rbeg = 0, rend = 0;
+    RecEntry prec{};
+    if (!ADJ) {
+#pragma unroll
+        for (int j = 0; j < kNodes; ++j) {
+            psz[j] = gload(s.src_iz + shot * kNodes + j);
+            psx[j] = gload(s.src_ix + shot * kNodes + j);
+            psw[j] = gload(s.src_w + shot * kNodes + j);
+        }
+        if ((int)threadIdx.x < t.nsteps) pwav = gload(s.wavelet + (int64_t)shot * s.wavelet_stride + t.n + threadIdx.x);
+        if (MODE == kFwd && s.gathers) {
+            rbeg = gload(s.tile_rec + tile);
+            rend = gload(s.tile_rec + tile + 1);
+        }
+    }
     const int Xc = min(max(X, 0), s.Nx - 1);
+    const bool unit_a = ez0 >= s.unit_z0 && ez0 + EZ <= s.unit_z1 && ex0 >= s.unit_x0 && ex0 + EX <= s.unit_x1;
     float A[K], B[K], a2[K], W[K];
     {
         float rc[K], rp[K], rw[K], ra[K];
+        uint32_t ob[K];
         const uint32_t xc4 = (uint32_t)(Xc + kGuard) * 4u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int Z = Z0 + k;
             const int Zr = min(Z < 0 ? -Z : Z, s.Nz - 1);
-            const uint32_t ob = (uint32_t)((Zr + kGuard) * s.pitch) * 4u + xc4;
-            rc[k] = gload_at(in_cur, ob);
-            rp[k] = gload_at(in_prev, ob);
-            rw[k] = gload_at(s.W, ob);
-            ra[k] = gload_at(s.A2, ob);
+            ob[k] = (uint32_t)((Zr + kGuard) * s.pitch) * 4u + xc4;
+            rc[k] = gload_at(in_cur, ob[k]);
         }
+#pragma unroll
+        for (int k = 0; k < K; ++k) rp[k] = gload_at(in_prev, ob[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) rw[k] = gload_at(s.W, ob[k]);
+        if (unit_a) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) ra[k] = 2.f;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) ra[k] = gload_at(s.A2, ob[k]);
+        }
+        if (MODE == kFwd && rbeg + (int)threadIdx.x < rend) prec = gload_rec(s.rec_list + rbeg + threadIdx.x);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int Z = Z0 + k;
             const bool in = xin && Z >= 0 && Z < s.Nz;
             const bool ghost = top_tile && xin && Z < 0 && Z >= -kHalo;   // odd mirror of row -Z
             const float c = in ? rc[k] : (ghost ? -rc[k] : 0.f);
-            a2[k] = in ? ra[k] : 0.f;
-            W[k] = in ? rw[k] : 0.f;
             A[k] = c;
-            B[k] = in ? rp[k] : 0.f;
             lds[lbase + k * LW] = c;
             lds[NB + lbase + k * LW] = c;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int Z = Z0 + k;
+            const bool in = xin && Z >= 0 && Z < s.Nz;
+            a2[k] = in ? ra[k] : 0.f;
+            W[k] = in ? rw[k] : 0.f;
+            B[k] = in ? rp[k] : 0.f;
         }
     }
     // the clamped column (in bounds for the output rows of any lane)
@@ -384,12 +428,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     bool has_src = false;
     int sk0 = -1, sk1 = -1;
     float sw0 = 0.f, sw1 = 0.f;
-    int32_t rbeg = 0, rend = 0;
     if (!ADJ) {
 #pragma unroll
         for (int j = 0; j < kNodes; ++j) {
-            const int sz = gload(s.src_iz + shot * kNodes + j), sx = gload(s.src_ix + shot * kNodes + j);
-            const float sw = gload(s.src_w + shot * kNodes + j);
+            const int sz = psz[j], sx = psx[j];
+            const float sw = psw[j];
             has_src |= sz >= ez0 && sz < ez0 + EZ && sx >= ex0 && sx < ex0 + EX;
             if (sx == X && sz >= Z0 && sz < Z0 + K && sw != 0.f) {
                 if (sk0 < 0) {
@@ -401,13 +444,8 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                 }
             }
         }
-        if (has_src && (int)threadIdx.x < t.nsteps)
-            wav_s[threadIdx.x] = gload(s.wavelet + (int64_t)shot * s.wavelet_stride + t.n + threadIdx.x);
-        if (MODE == kFwd && s.gathers) {
-            rbeg = gload(s.tile_rec + tile);
-            rend = gload(s.tile_rec + tile + 1);
-            if (rbeg + (int)threadIdx.x < rend) rec_s[threadIdx.x] = gload_rec(s.rec_list + rbeg + threadIdx.x);
-        }
+        if (has_src && (int)threadIdx.x < t.nsteps) wav_s[threadIdx.x] = pwav;
+        if (MODE == kFwd && rbeg + (int)threadIdx.x < rend) rec_s[threadIdx.x] = prec;
     }
     // adjoint: the residual injections W R^T r^n of this launch's levels at
     // the receiver nodes of the loaded region, summed (in a fixed order per

@@ -246,6 +246,12 @@ sg::SliceDesc describe(const sg_plan *p, const Layout &L, char *ws, const sg_sho
     s.ztop = p->ztop;
     s.xleft = p->xleft;
     s.free_top = g.top == SG_TOP_FREE;
+    // cells outside every sponge side have eta = 0 exactly, so a = 1 and 2a = 2;
+    // the pinned free-surface row is not updated (2a = 0)
+    s.unit_z0 = std::max(p->ztop, s.free_top ? 1 : 0);
+    s.unit_z1 = p->ztop + g.nz;
+    s.unit_x0 = p->xleft;
+    s.unit_x1 = p->xleft + g.nx;
     s.nshot = sh->nshot;
     s.nrec = sh->nrec;
     s.nrow = p->nrow;
