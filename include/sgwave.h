@@ -335,7 +335,7 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
 
 /*
  * Physics residual of a stack of wavefield frames (App. F.5: the residual of
- * the discretised acoustic wave operator, used there to judge predicted
+ * the discretised acoustic wave operator, used there to assess predicted
  * wavefields without the ground truth):
  *     R_t = (u_{t+1} - 2 u_t + u_{t-1}) / dt^2 - v^2 L u_t
  * with L the 8th-order Laplacian of App. E.3 and dt the spacing of the frames,

@@ -15,6 +15,7 @@
 // overwrites level n-1 with level n+1 in place.
 #include "sg_internal.h"
 
+#include <atomic>
 #include <type_traits>
 
 namespace sg {
@@ -261,7 +262,7 @@ struct TileShape {
 //             not depend on v).
 enum { kFwd = 0, kRing = 1, kAdj = 2 };
 
-template <int K, int NWX, int NWZ, int MODE, bool ISO>
+template <int K, int NWX, int NWZ, int MODE, bool ISO, bool STREAM = false>
 __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t, int b, float *lds)
 {
     using TS = TileShape<K, NWX, NWZ>;
@@ -674,13 +675,23 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         for (int k = 0; k < K; ++k)
             hsv[k] = (k >= k_lo && k < k_hi) ? gload_at(hs, 2u * (rowb(k) + xc4)) : 0.0;
     }
+    // STREAM (a launch whose workgroups all run at once): the levels go out
+    // with streaming (non-temporal) stores.  The next launch starts with cold
+    // caches anyway, and the end of this one then has little dirty data left
+    // to write back.
     if (xout) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k >= k_lo && k < k_hi) {
                 const uint32_t ob = rowb(k) + xo4;
-                gstore_at(out_cur, ob, odd ? B[k] : A[k]);
-                gstore_at(out_prev, ob, odd ? A[k] : B[k]);
+                const float vc = odd ? B[k] : A[k], vp = odd ? A[k] : B[k];
+                if constexpr (STREAM) {
+                    gstore_nt_at(out_cur, ob, vc);
+                    gstore_nt_at(out_prev, ob, vp);
+                } else {
+                    gstore_at(out_cur, ob, vc);
+                    gstore_at(out_prev, ob, vp);
+                }
                 if (ADJ) gstore_at(hs, 2u * ob, hsv[k] + (double)hp[k]);
             }
         }
@@ -691,11 +702,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
 // CU, so one's loads and stores overlap the other's sub-steps.
 #define SG_TILED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MODE == kAdj ? 1 : 4)))
 
-template <int K, int NWX, int NWZ, int MODE, bool ISO>
+template <int K, int NWX, int NWZ, int MODE, bool ISO, bool STREAM>
 __global__ void __launch_bounds__(64 * NWX * NWZ) SG_TILED_OCCUPANCY k_tiled(SliceDesc s, TileArgs t)
 {
     __shared__ float lds[2 * TileShape<K, NWX, NWZ>::LDS];
-    tiled_body<K, NWX, NWZ, MODE, ISO>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
+    tiled_body<K, NWX, NWZ, MODE, ISO, STREAM>(s, t, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Batched form: one launch covers every (slice, shot, tile) of the batch.
@@ -882,18 +893,42 @@ hipError_t launch_adjoint_tiled_batch(const BatchItem *items, int nitems, int to
                                                      ring_hi, st);
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
+template <int MODE, bool ISO, bool STREAM>
+static hipError_t launch_tiled_as(const SliceDesc &s, const TileArgs &t, int config, unsigned blocks, hipStream_t st)
+{
+    switch (config) {
+    case 0: hipLaunchKernelGGL((k_tiled<8, 2, 8, MODE, ISO, STREAM>), dim3(blocks), dim3(1024), 0, st, s, t); break;
+    case 1: hipLaunchKernelGGL((k_tiled<16, 1, 8, MODE, ISO, STREAM>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 2: hipLaunchKernelGGL((k_tiled<8, 1, 8, MODE, ISO, STREAM>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    case 3: hipLaunchKernelGGL((k_tiled<16, 2, 4, MODE, ISO, STREAM>), dim3(blocks), dim3(512), 0, st, s, t); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int MODE, bool ISO>
 static hipError_t launch_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st)
 {
     const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
-    switch (config) {
-    case 0: hipLaunchKernelGGL((k_tiled<8, 2, 8, MODE, ISO>), dim3(blocks), dim3(1024), 0, st, s, t); break;
-    case 1: hipLaunchKernelGGL((k_tiled<16, 1, 8, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 2: hipLaunchKernelGGL((k_tiled<8, 1, 8, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    case 3: hipLaunchKernelGGL((k_tiled<16, 2, 4, MODE, ISO>), dim3(blocks), dim3(512), 0, st, s, t); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    // all workgroups resident at once (one 1024-thread or two 512-thread
+    // workgroups per compute unit): streaming stores for the output levels
+    const bool one_round = blocks <= (unsigned)device_cus() * (config == 0 ? 1u : 2u);
+    return one_round ? launch_tiled_as<MODE, ISO, true>(s, t, config, blocks, st)
+                     : launch_tiled_as<MODE, ISO, false>(s, t, config, blocks, st);
 }
 
 static bool isotropic(const SliceDesc &s)
