@@ -15,6 +15,8 @@ Contents
     of the paper (Ricker pulse, CFL and dispersion limits, temporal
     subsampling, band-passed wavelets) and the residual of the discretised
     wave operator on a stack of frames.
+  * ``builder.py``: two velocity-model builder modules (Squish, Fault) with
+    their windowed-sinc pull sampling, in NumPy FP64.
 """
 from .wave import (  # noqa: F401
     Geometry,
@@ -38,3 +40,4 @@ from .wave import (  # noqa: F401
     misfit,
     wave_residual,
 )
+from . import builder  # noqa: F401,E402

@@ -1,0 +1,167 @@
+"""FP64 reference of two velocity-model builder modules of SubsurfaceGen
+(arXiv 2605.30541, App. B): Squish (Alg. 2, vertical warping by a fractal-noise
+displacement) and Fault (Alg. 3, one listric normal fault as a tapered
+rotation about a horizontal cylinder), both pull-sampling the model with a
+windowed sinc.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use it; it shares no code with the HIP library.
+
+Volumes are [nz][ny][nx] (x fastest), z is depth (down), positions in metres
+are (z*dz, y*dy, x*dx).  Readings where the paper leaves the details open:
+
+* sinc: 8-point Kaiser-windowed sinc, w(t) = sinc(t) I0(6 sqrt(1 - (t/4)^2)) /
+  I0(6) on the taps floor(s)-3 .. floor(s)+4, weights divided by their sum;
+  tap indices outside the axis are clamped to it (edge replication).  At
+  integer s the weights are a unit impulse, so the sample is exact.  A 3D
+  sample is the separable product of the three axes' weights.  (Among the
+  usual 8-point windows this one keeps the error on band-limited signals
+  below 1e-3 from 4 to 64 samples per period.)
+* fractal noise (Alg. 2): smooth value noise on a periodic lattice per octave
+  (values given, e.g. uniform in [-1, 1]), quintic fade between lattice
+  nodes; horizontal coordinates rotated by the azimuth and scaled by the
+  wavelengths; octave o has frequency 2^o and weight 2^-o; the sum is divided
+  by sum_o 2^-o and scaled by the maximum shift, so |dz| <= dz_max.
+* fault frame (Alg. 3): the horizontal unit vector n = (sin a, cos a) in
+  (y, x) is the offset direction of the cylinder axis from the centre (the
+  dip direction), s = (cos a, -sin a) the strike along the axis; in the plane
+  across strike h = (p - c~).n and v = depth - c~_z give r = |(h, v)| and
+  theta = atan2(v, h); the along-strike offset is (p - c~).s.  Angles in
+  radians internally; the die-off angle is given in degrees.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+HALF = 4          # taps on each side of the sample position
+BETA = 6.0        # Kaiser window shape
+
+
+def _sinc(u):
+    u = np.asarray(u, np.float64)
+    out = np.ones_like(u)
+    nz = u != 0.0
+    out[nz] = np.sin(np.pi * u[nz]) / (np.pi * u[nz])
+    return out
+
+
+def sinc_taps(s, n: int):
+    """Tap indices [..., 8] (clamped to 0..n-1) and normalised Kaiser-sinc
+    weights [..., 8] for sample positions s (in cells) on an axis of n."""
+    s = np.asarray(s, np.float64)
+    base = np.floor(s)
+    j = base[..., None] + np.arange(-HALF + 1, HALF + 1)
+    t = s[..., None] - j
+    w = _sinc(t) * np.i0(BETA * np.sqrt(np.clip(1.0 - (t / HALF) ** 2, 0.0, 1.0))) / np.i0(BETA)
+    w = w / w.sum(axis=-1, keepdims=True)
+    return np.clip(j, 0, n - 1).astype(np.int64), w
+
+
+def sinc_sample_3d(V, sz, sy, sx):
+    """V sampled at the positions (sz, sy, sx) (cells, arrays of one shape)."""
+    V = np.asarray(V, np.float64)
+    nz, ny, nx = V.shape
+    jz, wz = sinc_taps(sz, nz)
+    jy, wy = sinc_taps(sy, ny)
+    jx, wx = sinc_taps(sx, nx)
+    out = np.zeros(np.shape(sz))
+    for a in range(2 * HALF):
+        for b in range(2 * HALF):
+            wab = wz[..., a] * wy[..., b]
+            for c in range(2 * HALF):
+                out += wab * wx[..., c] * V[jz[..., a], jy[..., b], jx[..., c]]
+    return out
+
+
+def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: float, lam_x: float,
+                    azimuth_deg: float, amplitude: float):
+    """Alg. 2, first step: the displacement field dz(y, x) [ny, nx] in metres
+    from per-octave lattices [noct, gy, gx] (periodic)."""
+    lattice = np.asarray(lattice, np.float64)
+    noct, gy, gx = lattice.shape
+    a = math.radians(azimuth_deg)
+    Y = np.arange(ny)[:, None] * dy
+    X = np.arange(nx)[None, :] * dx
+    u = (X * math.cos(a) + Y * math.sin(a)) / lam_x      # along the azimuth
+    w = (-X * math.sin(a) + Y * math.cos(a)) / lam_y     # across it
+    fade = lambda t: t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+    total = np.zeros((ny, nx))
+    norm = 0.0
+    for o in range(noct):
+        f = 2.0 ** o
+        pu, pw = u * f, w * f
+        iu, iw = np.floor(pu), np.floor(pw)
+        tu, tw = fade(pu - iu), fade(pw - iw)
+        iu, iw = iu.astype(np.int64), iw.astype(np.int64)
+        L = lattice[o]
+        v00 = L[iw % gy, iu % gx]
+        v01 = L[iw % gy, (iu + 1) % gx]
+        v10 = L[(iw + 1) % gy, iu % gx]
+        v11 = L[(iw + 1) % gy, (iu + 1) % gx]
+        n = (v00 * (1 - tu) + v01 * tu) * (1 - tw) + (v10 * (1 - tu) + v11 * tu) * tw
+        total += n / f
+        norm += 1.0 / f
+    return amplitude * total / norm
+
+
+def squish(V, dz: float, shift):
+    """Alg. 2, second step: V pulled from (z + shift(y, x), y, x); shift in
+    metres, [ny, nx]."""
+    V = np.asarray(V, np.float64)
+    nz, ny, nx = V.shape
+    sz = np.arange(nz)[:, None, None] + np.asarray(shift, np.float64)[None] / dz
+    sy = np.broadcast_to(np.arange(ny)[None, :, None], sz.shape).astype(np.float64)
+    sx = np.broadcast_to(np.arange(nx)[None, None, :], sz.shape).astype(np.float64)
+    return sinc_sample_3d(V, sz, sy, sx)
+
+
+def fault_source(shape, dz: float, dy: float, dx: float, p: dict):
+    """Alg. 3: for every voxel, the pull source (metres, three arrays z, y, x)
+    and the taper w.  p holds cz, cy, cx [m], azimuth_deg, dip_deg, radius,
+    slip, direction (+1/-1), die_r, die_strike [m], die_theta_deg."""
+    nz, ny, nx = shape
+    a, th, R = math.radians(p["azimuth_deg"]), math.radians(p["dip_deg"]), p["radius"]
+    ny_, nx_ = math.sin(a), math.cos(a)            # n: offset direction of the axis
+    sy_, sx_ = math.cos(a), -math.sin(a)           # s: strike
+    dlt_z, dlt_az = R * math.sin(th), R * math.cos(th)
+    cz = p["cz"] - dlt_z
+    cy = p["cy"] - dlt_az * ny_
+    cx = p["cx"] - dlt_az * nx_
+    theta0 = math.atan2(dlt_z, dlt_az)
+    shift = p["slip"] / (2.0 * math.pi * R) * 2.0 * math.pi  # 360 deg per circumference, in radians
+    Z = np.arange(nz)[:, None, None] * dz
+    Y = np.arange(ny)[None, :, None] * dy
+    X = np.arange(nx)[None, None, :] * dx
+    Z, Y, X = np.broadcast_arrays(Z, Y, X)
+    qy, qx, v = Y - cy, X - cx, Z - cz
+    h = qy * ny_ + qx * nx_
+    az = qy * sy_ + qx * sx_
+    r = np.hypot(h, v)
+    t_old = np.arctan2(v, h)
+    rho_r = np.abs(r - R) / p["die_r"]
+    rho_t = np.abs(t_old - theta0) / math.radians(p["die_theta_deg"])
+    rho_s = np.abs(az) / p["die_strike"]
+    inside = (rho_r < 1) & (rho_t < 1) & (rho_s < 1)
+    wt = np.where(inside, np.cos(0.5 * np.pi * rho_r) * np.cos(0.5 * np.pi * rho_t) * np.cos(0.5 * np.pi * rho_s), 0.0)
+    chi = np.where(r >= R, 1.0, -1.0)
+    dth = -chi * p["direction"] * wt * shift       # theta_new - theta_old
+    # p_fwd - p = r (cos t_new - cos t_old, sin t_new - sin t_old) in the (h, v)
+    # plane, the along-strike offset unchanged; written with half-angle
+    # products it is exactly 0 where the rotation is 0 (src = 2p - p_fwd = p)
+    mid, half = t_old + 0.5 * dth, np.sin(0.5 * dth)
+    dh = -2.0 * r * np.sin(mid) * half
+    dv = 2.0 * r * np.cos(mid) * half
+    return (Z - dv, Y - dh * ny_, X - dh * nx_), wt
+
+
+def fault(V, dz: float, dy: float, dx: float, p: dict, fill: float):
+    """Alg. 3: V pulled from the sources of fault_source; voxels whose source
+    depth falls outside [0, nz) cells get `fill`."""
+    V = np.asarray(V, np.float64)
+    (sz, sy, sx), _ = fault_source(V.shape, dz, dy, dx, p)
+    sz, sy, sx = sz / dz, sy / dy, sx / dx
+    out = sinc_sample_3d(V, sz, sy, sx)
+    out[(sz < 0) | (sz >= V.shape[0])] = fill
+    return out

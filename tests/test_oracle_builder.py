@@ -1,0 +1,171 @@
+"""Pins of the builder oracle (Squish, Alg. 2; Fault, Alg. 3; the windowed-sinc
+pull sampling) against what holds independently of its code: exact samples at
+integer positions, analytic band-limited functions, exact shifts, rotation
+invariants of the fault map, first-order symmetry of the fault slip, the
+amplitude bound and lattice values of the fractal noise."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import builder as B
+
+
+def test_sinc_is_exact_at_integer_positions_and_on_constants():
+    rng = np.random.default_rng(1)
+    V = rng.standard_normal((17, 3, 11))
+    z, y, x = np.meshgrid(np.arange(17.0), np.arange(3.0), np.arange(11.0), indexing="ij")
+    assert np.abs(B.sinc_sample_3d(V, z, y, x) - V).max() < 1e-14
+    C = np.full((9, 4, 6), 2.5)
+    s = rng.uniform(-3, 12, (50,))
+    assert np.abs(B.sinc_sample_3d(C, s, s * 0.3, s * 0.5) - 2.5).max() < 1e-14
+
+
+@pytest.mark.parametrize("period", [4.0, 8.0, 16.0, 64.0])
+def test_sinc_reproduces_a_band_limited_cosine(period):
+    """Interior samples of cos(2 pi z / P) at fractional positions against the
+    function itself.  The window's error stays below 1e-3 of the amplitude
+    from 4 to 64 samples per period; a plain truncated sinc (no window) is off
+    by 7e-3 to 2e-1 and a window misplaced by one tap by ~1e-2."""
+    n = 256
+    z = np.arange(n, dtype=np.float64)
+    V = np.cos(2 * np.pi * z / period)[:, None, None]
+    s = np.linspace(60.3, 180.7, 301)
+    got = B.sinc_sample_3d(V, s, np.zeros_like(s), np.zeros_like(s))
+    err = np.abs(got - np.cos(2 * np.pi * s / period)).max()
+    assert err < 1.2e-3, err
+
+
+def test_sinc_weights_are_symmetric_about_the_sample_position():
+    """Mirroring the axis mirrors the sample: the taps are centred."""
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(40)
+    V, W = v[:, None, None], v[::-1].copy()[:, None, None]
+    s = rng.uniform(5, 34, 50)
+    a = B.sinc_sample_3d(V, s, 0 * s, 0 * s)
+    b = B.sinc_sample_3d(W, 39 - s, 0 * s, 0 * s)
+    assert np.abs(a - b).max() < 1e-13
+
+
+def test_squish_shifts_columns_exactly_by_whole_cells_and_keeps_zero_shift():
+    rng = np.random.default_rng(2)
+    V = rng.standard_normal((40, 2, 5))
+    dz = 12.5
+    assert np.abs(B.squish(V, dz, np.zeros((2, 5))) - V).max() < 1e-14
+    shift = np.array([[3, -2, 0, 5, 1], [-4, 2, 7, 0, -1]], np.float64) * dz
+    out = B.squish(V, dz, shift)
+    for iy in range(2):
+        for ix in range(5):
+            k = int(shift[iy, ix] / dz)
+            zs = np.arange(40) + k
+            ok = (zs >= 0) & (zs < 40)
+            # (sin(pi k) is zero only to rounding: exact to 1e-13)
+            assert np.abs(out[ok, iy, ix] - V[zs[ok], iy, ix]).max() < 1e-13
+            # past the ends the edge value is replicated
+            assert np.abs(out[~ok, iy, ix] - V[np.clip(zs[~ok], 0, 39), iy, ix]).max(initial=0.0) < 1e-13
+
+
+def test_squish_of_a_smooth_profile_samples_it_at_the_shifted_depth():
+    dz = 10.0
+    z = np.arange(200) * dz
+    prof = 2000.0 + 1.5 * z + 80.0 * np.sin(2 * np.pi * z / 600.0)
+    V = np.broadcast_to(prof[:, None, None], (200, 3, 4)).copy()
+    shift = np.array([[13.7, -42.2, 0.0, 77.1], [5.5, -5.5, 120.3, -0.4], [33.3, 1.0, -90.9, 64.0]])
+    out = B.squish(V, dz, shift)
+    zz = z[30:170, None, None] + shift[None]
+    ref = 2000.0 + 1.5 * zz + 80.0 * np.sin(2 * np.pi * zz / 600.0)
+    # (a 15 m/s-per-cell trend: the window's first-moment bias, ~5e-3 cells, leaves < 0.1 m/s;
+    # a wrong sign or unit of the shift would be off by hundreds)
+    assert np.abs(out[30:170] - ref).max() < 0.1         # of values ~2000-4600
+
+
+def test_fractal_noise_hits_lattice_values_and_stays_in_bounds():
+    rng = np.random.default_rng(3)
+    lat = rng.uniform(-1, 1, (1, 5, 7))
+    # one octave, azimuth 0, grid spacing = wavelength: every node is a lattice node
+    dzf = B.fractal_noise2d(lat, 5, 7, 100.0, 100.0, 100.0, 100.0, 0.0, 30.0)
+    assert np.abs(dzf - 30.0 * lat[0]).max() < 1e-12
+    lat4 = rng.uniform(-1, 1, (4, 6, 6))
+    f = B.fractal_noise2d(lat4, 50, 60, 10.0, 10.0, 170.0, 230.0, 37.0, 25.0)
+    assert np.abs(f).max() <= 25.0 + 1e-12
+    assert f.std() > 1.0
+    # the lattice is periodic: a whole lattice period further gives the same field
+    per_x = 6 * 230.0
+    g = B.fractal_noise2d(lat4, 1, 60, 10.0, 10.0, 170.0, 230.0, 0.0, 25.0)
+    lat_shift = B.fractal_noise2d(lat4, 1, 60 + int(per_x / 10.0), 10.0, 10.0, 170.0, 230.0, 0.0, 25.0)
+    assert np.abs(lat_shift[0, int(per_x / 10.0):] - g[0]).max() < 1e-9
+
+
+FAULT = dict(cz=300.0, cy=200.0, cx=400.0, azimuth_deg=25.0, dip_deg=55.0, radius=900.0, slip=60.0,
+             direction=1, die_r=250.0, die_strike=300.0, die_theta_deg=25.0)
+
+
+def _frame(p):
+    a, th, R = math.radians(p["azimuth_deg"]), math.radians(p["dip_deg"]), p["radius"]
+    n = np.array([math.sin(a), math.cos(a)])
+    s = np.array([math.cos(a), -math.sin(a)])
+    ct = np.array([p["cz"] - R * math.sin(th), p["cy"] - R * math.cos(th) * n[0], p["cx"] - R * math.cos(th) * n[1]])
+    return n, s, ct
+
+
+def test_fault_with_zero_slip_or_outside_the_taper_is_the_identity():
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((40, 30, 50))
+    p = dict(FAULT, slip=0.0)
+    assert np.abs(B.fault(V, 10.0, 10.0, 10.0, p, 1500.0) - V).max() < 1e-14
+    (sz, sy, sx), w = B.fault_source(V.shape, 10.0, 10.0, 10.0, FAULT)
+    out = B.fault(V, 10.0, 10.0, 10.0, FAULT, 1500.0)
+    assert 0 < np.count_nonzero(w) < w.size
+    assert np.abs(out[w == 0] - V[w == 0]).max() < 1e-13
+    assert w.max() <= 1.0 and w.min() >= 0.0
+
+
+def test_fault_map_is_a_rotation_about_the_cylinder_axis():
+    """p_fwd = 2p - src keeps each voxel's distance to the axis and its
+    along-strike offset, and turns it by -chi d w s / R."""
+    shape, h = (40, 30, 50), 10.0
+    (sz, sy, sx), w = B.fault_source(shape, h, h, h, FAULT)
+    Z, Y, X = np.meshgrid(np.arange(40) * h, np.arange(30) * h, np.arange(50) * h, indexing="ij")
+    fz, fy, fx = 2 * Z - sz, 2 * Y - sy, 2 * X - sx
+    n, s, ct = _frame(FAULT)
+
+    def cyl(z, y, x):
+        hh = (y - ct[1]) * n[0] + (x - ct[2]) * n[1]
+        vv = z - ct[0]
+        return np.hypot(hh, vv), np.arctan2(vv, hh), (y - ct[1]) * s[0] + (x - ct[2]) * s[1]
+
+    r0, t0, a0 = cyl(Z, Y, X)
+    r1, t1, a1 = cyl(fz, fy, fx)
+    assert np.abs(r1 - r0).max() < 1e-9
+    assert np.abs(a1 - a0).max() < 1e-9
+    chi = np.where(r0 >= FAULT["radius"], 1.0, -1.0)
+    expect = -chi * FAULT["direction"] * w * FAULT["slip"] / FAULT["radius"]
+    assert np.abs((t1 - t0) - expect).max() < 1e-12
+    # the two walls move in opposite senses; the largest displacement is about the slip
+    disp = np.sqrt((fz - Z) ** 2 + (fy - Y) ** 2 + (fx - X) ** 2)
+    assert 0.7 * FAULT["slip"] < disp.max() <= 1.5 * FAULT["slip"]
+
+
+def test_fault_direction_reverses_the_slip_to_first_order():
+    shape, h = (30, 20, 40), 10.0
+    Z, Y, X = np.meshgrid(np.arange(30) * h, np.arange(20) * h, np.arange(40) * h, indexing="ij")
+    (az, ay, ax), _ = B.fault_source(shape, h, h, h, FAULT)
+    (bz, by, bx), _ = B.fault_source(shape, h, h, h, dict(FAULT, direction=-1))
+    # (src+ - p) + (src- - p) = O(theta_shift^2 r)
+    th = FAULT["slip"] / FAULT["radius"]
+    resid = np.abs(az + bz - 2 * Z) + np.abs(ay + by - 2 * Y) + np.abs(ax + bx - 2 * X)
+    assert resid.max() < 4 * th * th * 2000.0
+    assert np.abs(az - Z).max() > 10.0
+
+
+def test_fault_fills_voxels_pulled_from_outside_the_model_depth():
+    """A fault through a thin model: where the pull source depth falls outside
+    [0, nz) cells the fill value appears, and only there."""
+    rng = np.random.default_rng(5)
+    V = 2000.0 + rng.uniform(0, 100, (20, 4, 40))
+    p = dict(FAULT, cz=10.0, cy=20.0, cx=200.0, slip=150.0, die_r=400.0, die_strike=1000.0, die_theta_deg=60.0)
+    (sz, _, _), _ = B.fault_source(V.shape, 10.0, 10.0, 10.0, p)
+    out = B.fault(V, 10.0, 10.0, 10.0, p, -1.0)
+    outside = (sz / 10.0 < 0) | (sz / 10.0 >= 20)
+    assert (sz / 10.0 < 0).any()
+    assert np.all(out[outside] == -1.0) and np.all(out[~outside] > 1000.0)
