@@ -360,6 +360,60 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
                            double dx, double dt, int32_t top, double *res2, double *dtt2, void *ws, size_t ws_bytes,
                            void *stream);
 
+/*
+ * Velocity-model builder modules (App. B): the vertical warp of Squish
+ * (Alg. 2) and the listric normal fault of Fault (Alg. 3), on a device volume
+ * [nz][ny][nx] of floats (x fastest; a 2D slice is ny = 1), z = depth.  Both
+ * pull-sample the input through an 8-point Kaiser-windowed sinc (beta 6,
+ * weights normalised to sum 1, tap indices clamped to the axis), exact at
+ * integer positions.  out must not alias the input.  Stream-ordered, no
+ * allocation.  SG_EINVAL for NULL pointers, non-positive sizes or spacings,
+ * aliasing, or parameters outside the ranges below.
+ */
+
+/* Alg. 2, first step: the displacement field out [ny][nx] (metres, device)
+ * as fractal value noise: per octave o = 0..noct-1 a periodic lattice
+ * lattice[o] [gy][gx] (device floats, e.g. uniform in [-1, 1]), sampled with
+ * a quintic fade at the horizontal coordinates rotated by azimuth_deg and
+ * divided by the wavelengths lam_y, lam_x [m], times 2^o; octave weights
+ * 2^-o; the sum divided by sum_o 2^-o and multiplied by amplitude [m], so
+ * |out| <= amplitude.  noct in 1..24. */
+sg_status sg_fractal_noise2d(const float *lattice, int32_t noct, int32_t gy, int32_t gx, int32_t ny, int32_t nx,
+                             double dy, double dx, double lam_y, double lam_x, double azimuth_deg, double amplitude,
+                             float *out, void *stream);
+
+/* Alg. 2, second step: out(z, y, x) = v sampled at depth z + shift(y, x) / dz
+ * cells (shift [ny][nx] in metres, device; rows past either end repeat the
+ * edge row). */
+sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, const float *shift, float *out,
+                    void *stream);
+
+/* Alg. 3 (one fault; no rough surface or subsidiary faults).  Positions in
+ * metres are (z dz, y dy, x dx).  The cylinder axis runs along the strike
+ * s = (cos a, -sin a) in (y, x); it sits at c~ = c - (R sin(dip), R cos(dip) n)
+ * with n = (sin a, cos a), a = azimuth.  Each voxel, in the plane across the
+ * axis (radius r, angle theta = atan2(depth offset, offset along n)), turns by
+ * -chi direction w slip / R (chi = +1 where r >= R, else -1) with the taper
+ * w = cos(pi/2 |r - R| / die_r) cos(pi/2 |theta - theta0| / die_theta)
+ *     cos(pi/2 |along-strike offset| / die_strike)
+ * inside all three extents and 0 outside; theta0 = atan2(R sin(dip),
+ * R cos(dip)).  The output pulls v from src = 2p - p_forward; where src lies
+ * above depth 0 or at/below nz cells it is `fill`.  radius, die_* > 0,
+ * direction +1 or -1. */
+typedef struct sg_fault_params {
+    double cz, cy, cx;      /* fault centre [m] */
+    double azimuth_deg;     /* a */
+    double dip_deg;         /* dip */
+    double radius;          /* R [m] */
+    double slip;            /* arc length [m] */
+    int32_t direction;      /* +1 or -1 */
+    double die_r;           /* die-off across the fault [m] */
+    double die_strike;      /* die-off along strike [m] */
+    double die_theta_deg;   /* die-off in angle about the axis [deg] */
+} sg_fault_params;
+sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                   const sg_fault_params *p, float fill, float *out, void *stream);
+
 /* Turn the graph replay of sg_forward and sg_batch_forward on (default) or
  * off (plain stream launches); process-wide. */
 sg_status sg_set_graphs(int32_t on);

@@ -1,0 +1,215 @@
+// Velocity-model builder modules of SubsurfaceGen (arXiv 2605.30541, App. B):
+// the fractal-noise displacement and vertical warp of Squish (Alg. 2) and the
+// listric normal fault of Fault (Alg. 3), both pulling the model through an
+// 8-point Kaiser-windowed sinc (beta 6, weights normalised to sum 1, taps
+// clamped to the axis).  Volumes are [nz][ny][nx], x fastest.
+//
+// Squish: one thread per (y, x) column.  The shift is constant down a column,
+// so the 8 weights are computed once and the column streams through an
+// 8-value register window: one load and 8 FMAs per voxel (HBM-bound, 8 B per
+// voxel read + written).
+// Fault: one thread per voxel.  The pull source is computed in FP64 (the
+// frame and the angles of Alg. 3); voxels outside the taper are copied, the
+// others take 8 x 8 x 8 taps (8 x 8 when ny = 1) with FP32 weights and sums.
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+constexpr int kTaps = 8;
+constexpr float kBeta = 6.f;
+
+// I0 by its power series sum_k ((x/2)^2)^k / (k!)^2; for x <= 6 the terms
+// after k = 16 are below 1e-10 of the sum.
+__device__ inline float bessel_i0(float x)
+{
+    const float q = 0.25f * x * x;
+    float term = 1.f, sum = 1.f;
+#pragma unroll
+    for (int k = 1; k <= 16; ++k) {
+        term *= q / (float)(k * k);
+        sum += term;
+    }
+    return sum;
+}
+
+// Normalised weights of the taps floor(s)-3 .. floor(s)+4 for the fractional
+// part f = s - floor(s): tap j sits at t = f + 3 - j from the sample.
+__device__ inline void sinc_weights(float f, float (&w)[kTaps])
+{
+    const float inv_i0b = 1.f / bessel_i0(kBeta);
+    float sum = 0.f;
+#pragma unroll
+    for (int j = 0; j < kTaps; ++j) {
+        const float t = f + 3.f - (float)j;
+        const float sc = t == 0.f ? 1.f : sinpif(t) / (3.14159265358979f * t);
+        const float u = 1.f - 0.0625f * t * t;
+        const float win = bessel_i0(kBeta * sqrtf(fmaxf(u, 0.f))) * inv_i0b;
+        w[j] = sc * win;
+        sum += w[j];
+    }
+    const float inv = 1.f / sum;
+#pragma unroll
+    for (int j = 0; j < kTaps; ++j) w[j] *= inv;
+}
+
+__global__ void __launch_bounds__(256) k_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny,
+                                                          int nx, double dy, double dx, double inv_lam_y,
+                                                          double inv_lam_x, double ca, double sa, double scale,
+                                                          float *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)ny * nx) return;
+    const int iy = (int)(q / nx), ix = (int)(q - (int64_t)iy * nx);
+    const double Y = iy * dy, X = ix * dx;
+    const double u = (X * ca + Y * sa) * inv_lam_x;
+    const double w = (-X * sa + Y * ca) * inv_lam_y;
+    double total = 0.0, f = 1.0;
+    for (int o = 0; o < noct; ++o, f *= 2.0) {
+        const double pu = u * f, pw = w * f;
+        const double fu = floor(pu), fw = floor(pw);
+        double tu = pu - fu, tw = pw - fw;
+        tu = tu * tu * tu * (tu * (tu * 6.0 - 15.0) + 10.0);
+        tw = tw * tw * tw * (tw * (tw * 6.0 - 15.0) + 10.0);
+        const int64_t iu = (int64_t)fu, iw = (int64_t)fw;
+        const int u0 = (int)(((iu % gx) + gx) % gx), u1 = (u0 + 1) % gx;
+        const int w0 = (int)(((iw % gy) + gy) % gy), w1 = (w0 + 1) % gy;
+        const float *L = lattice + (int64_t)o * gy * gx;
+        const double v00 = L[w0 * gx + u0], v01 = L[w0 * gx + u1], v10 = L[w1 * gx + u0], v11 = L[w1 * gx + u1];
+        total += ((v00 * (1 - tu) + v01 * tu) * (1 - tw) + (v10 * (1 - tu) + v11 * tu) * tw) / f;
+    }
+    out[q] = (float)(total * scale);
+}
+
+__global__ void __launch_bounds__(256) k_squish(const float *__restrict__ v, int nz, int ny, int nx, double inv_dz,
+                                                const float *__restrict__ shift, float *__restrict__ out)
+{
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= (int64_t)ny * nx) return;
+    const int64_t plane = (int64_t)ny * nx;
+    // sample position z + c, c = shift / dz: whole part c0, fraction f (c is
+    // bounded before the integer cast; every tap index is clamped anyway)
+    const double c = fmin(fmax((double)shift[col] * inv_dz, -1e9), 1e9);
+    const double cf = floor(c);
+    const int c0 = (int)cf;
+    float w[kTaps];
+    sinc_weights((float)(c - cf), w);
+    const float *vc = v + col;
+    // window of the taps c0 - 3 .. c0 + 4 below z = 0 (clamped rows)
+    float win[kTaps];
+#pragma unroll
+    for (int j = 0; j < kTaps; ++j) win[j] = vc[(int64_t)min(max(c0 - 3 + j, 0), nz - 1) * plane];
+    for (int z = 0; z < nz; ++z) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < kTaps; ++j) acc = fmaf(w[j], win[j], acc);
+        out[col + (int64_t)z * plane] = acc;
+#pragma unroll
+        for (int j = 0; j < kTaps - 1; ++j) win[j] = win[j + 1];
+        win[kTaps - 1] = vc[(int64_t)min(max(z + 1 + c0 + 4, 0), nz - 1) * plane];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, FaultFrame F,
+                                               float fill, float *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t plane = (int64_t)ny * nx;
+    if (q >= plane * nz) return;
+    const int iz = (int)(q / plane);
+    const int64_t r2 = q - (int64_t)iz * plane;
+    const int iy = (int)(r2 / nx), ix = (int)(r2 - (int64_t)iy * nx);
+    const double Z = iz * F.dz, Y = iy * F.dy, X = ix * F.dx;
+    const double qy = Y - F.cy, qx = X - F.cx, vv = Z - F.cz;
+    const double h = qy * F.n_y + qx * F.n_x;
+    const double az = qy * F.s_y + qx * F.s_x;
+    const double r = sqrt(h * h + vv * vv);
+    const double t_old = atan2(vv, h);
+    const double rho_r = fabs(r - F.radius) * F.inv_die_r;
+    const double rho_t = fabs(t_old - F.theta0) * F.inv_die_t;
+    const double rho_s = fabs(az) * F.inv_die_s;
+    if (!(rho_r < 1.0 && rho_t < 1.0 && rho_s < 1.0)) {   // w = 0: the source is the voxel itself
+        out[q] = v[q];
+        return;
+    }
+    const double half_pi = 1.5707963267948966;
+    const double wt = cos(half_pi * rho_r) * cos(half_pi * rho_t) * cos(half_pi * rho_s);
+    const double chi = r >= F.radius ? 1.0 : -1.0;
+    const double dth = -chi * F.direction * wt * F.shift;
+    // p_fwd - p in the (h, v) plane, exactly 0 where the rotation is 0
+    const double mid = t_old + 0.5 * dth, hs = sin(0.5 * dth);
+    const double dh = -2.0 * r * sin(mid) * hs, dv = 2.0 * r * cos(mid) * hs;
+    const double sz = (Z - dv) * F.inv_dz, sy = (Y - dh * F.n_y) * F.inv_dy, sx = (X - dh * F.n_x) * F.inv_dx;
+    if (!(sz >= 0.0 && sz < (double)nz)) {
+        out[q] = fill;
+        return;
+    }
+    // (bounded before the integer casts; every tap index is clamped anyway)
+    const double fz = floor(sz), fy = floor(fmin(fmax(sy, -1e9), 1e9)), fx = floor(fmin(fmax(sx, -1e9), 1e9));
+    float wz[kTaps], wy[kTaps], wx[kTaps];
+    sinc_weights((float)(sz - fz), wz);
+    sinc_weights((float)(fmin(fmax(sy, -1e9), 1e9) - fy), wy);
+    sinc_weights((float)(fmin(fmax(sx, -1e9), 1e9) - fx), wx);
+    const int z0 = (int)fz - 3, y0 = (int)fy - 3, x0 = (int)fx - 3;
+    int jx[kTaps];
+#pragma unroll
+    for (int c = 0; c < kTaps; ++c) jx[c] = min(max(x0 + c, 0), nx - 1);
+    float acc = 0.f;
+    for (int a = 0; a < kTaps; ++a) {
+        const int jz = min(max(z0 + a, 0), nz - 1);
+        float accy = 0.f;
+        if (ny == 1) {
+            const float *row = v + (int64_t)jz * plane;
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < kTaps; ++c) s = fmaf(wx[c], row[jx[c]], s);
+            accy = s;   // the y weights sum to 1 on a one-row axis
+        } else {
+            for (int b = 0; b < kTaps; ++b) {
+                const int jy = min(max(y0 + b, 0), ny - 1);
+                const float *row = v + (int64_t)jz * plane + (int64_t)jy * nx;
+                float s = 0.f;
+#pragma unroll
+                for (int c = 0; c < kTaps; ++c) s = fmaf(wx[c], row[jx[c]], s);
+                accy = fmaf(wy[b], s, accy);
+            }
+        }
+        acc = fmaf(wz[a], accy, acc);
+    }
+    out[q] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny, int nx, double dy,
+                                  double dx, double lam_y, double lam_x, double azimuth_rad, double amplitude,
+                                  float *out, hipStream_t st)
+{
+    double norm = 0.0, f = 1.0;
+    for (int o = 0; o < noct; ++o, f *= 2.0) norm += 1.0 / f;
+    const int64_t n = (int64_t)ny * nx;
+    hipLaunchKernelGGL(k_fractal_noise2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lattice, noct, gy,
+                       gx, ny, nx, dy, dx, 1.0 / lam_y, 1.0 / lam_x, cos(azimuth_rad), sin(azimuth_rad),
+                       amplitude / norm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, const float *shift, float *out,
+                         hipStream_t st)
+{
+    const int64_t n = (int64_t)ny * nx;
+    hipLaunchKernelGGL(k_squish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, nz, ny, nx, 1.0 / dz,
+                       shift, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
+                        hipStream_t st)
+{
+    const int64_t n = (int64_t)nz * ny * nx;
+    hipLaunchKernelGGL(k_fault, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, nz, ny, nx, F, fill, out);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -168,6 +168,25 @@ hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const doubl
 hipError_t launch_record_slot(const SliceDesc &s, int n, int slot, hipStream_t st, int what = 3);
 hipError_t launch_count_nonfinite(const float *x, size_t n, unsigned int *count, hipStream_t st);
 
+// Fault (Alg. 3) in the form the kernel uses: grid spacings, the cylinder axis
+// point c~ (metres), the unit vectors n (axis offset, across strike) and s
+// (strike) in (y, x), the reference angle, the rotation for w = 1 and the
+// reciprocal die-off extents.
+struct FaultFrame {
+    double dz, dy, dx, inv_dz, inv_dy, inv_dx;
+    double cz, cy, cx;
+    double n_y, n_x, s_y, s_x;
+    double radius, theta0, shift, direction;
+    double inv_die_r, inv_die_t, inv_die_s;
+};
+hipError_t launch_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny, int nx, double dy,
+                                  double dx, double lam_y, double lam_x, double azimuth_rad, double amplitude,
+                                  float *out, hipStream_t st);
+hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, const float *shift, float *out,
+                         hipStream_t st);
+hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
+                        hipStream_t st);
+
 // Wave-equation residual of a frame stack: c_m / dz^2 and c_m / dx^2, m = 0..4.
 struct ResidualCoef {
     float cz[kHalo + 1];

@@ -1711,6 +1711,88 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
     return SG_OK;
 }
 
+namespace {
+bool positive_finite(double x) { return std::isfinite(x) && x > 0; }
+sg_status volume_args(const void *v, int32_t nz, int32_t ny, int32_t nx, const void *out)
+{
+    if (!v || !out) return fail(SG_EINVAL, "NULL argument");
+    if (nz < 1 || ny < 1 || nx < 1) return fail(SG_EINVAL, "nz, ny and nx must be >= 1");
+    if ((int64_t)nz * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "volume too large");
+    if (v == out) return fail(SG_EINVAL, "out must not alias the input volume (pull sampling reads neighbours)");
+    return SG_OK;
+}
+}  // namespace
+
+sg_status sg_fractal_noise2d(const float *lattice, int32_t noct, int32_t gy, int32_t gx, int32_t ny, int32_t nx,
+                             double dy, double dx, double lam_y, double lam_x, double azimuth_deg, double amplitude,
+                             float *out, void *stream)
+{
+    if (!lattice || !out) return fail(SG_EINVAL, "NULL argument");
+    if (noct < 1 || noct > 24) return fail(SG_EINVAL, "noct must be in 1..24");
+    if (gy < 1 || gx < 1 || ny < 1 || nx < 1) return fail(SG_EINVAL, "lattice and grid sizes must be >= 1");
+    if ((int64_t)ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "grid too large");
+    if (!positive_finite(dy) || !positive_finite(dx) || !positive_finite(lam_y) || !positive_finite(lam_x))
+        return fail(SG_EINVAL, "spacings and wavelengths must be finite and > 0");
+    if (!std::isfinite(azimuth_deg) || !std::isfinite(amplitude))
+        return fail(SG_EINVAL, "azimuth and amplitude must be finite");
+    SG_HIP(sg::launch_fractal_noise2d(lattice, noct, gy, gx, ny, nx, dy, dx, lam_y, lam_x, azimuth_deg * kPi / 180.0,
+                                      amplitude, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, const float *shift, float *out,
+                    void *stream)
+{
+    sg_status rc = volume_args(v, nz, ny, nx, out);
+    if (rc != SG_OK) return rc;
+    if (!shift) return fail(SG_EINVAL, "NULL argument");
+    if (!positive_finite(dz)) return fail(SG_EINVAL, "dz must be finite and > 0");
+    SG_HIP(sg::launch_squish(v, nz, ny, nx, dz, shift, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                   const sg_fault_params *p, float fill, float *out, void *stream)
+{
+    sg_status rc = volume_args(v, nz, ny, nx, out);
+    if (rc != SG_OK) return rc;
+    if (!p) return fail(SG_EINVAL, "NULL argument");
+    if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx))
+        return fail(SG_EINVAL, "dz, dy and dx must be finite and > 0");
+    if (!std::isfinite(p->cz) || !std::isfinite(p->cy) || !std::isfinite(p->cx) || !std::isfinite(p->azimuth_deg) ||
+        !std::isfinite(p->dip_deg) || !std::isfinite(p->slip))
+        return fail(SG_EINVAL, "fault centre, azimuth, dip and slip must be finite");
+    if (!positive_finite(p->radius) || !positive_finite(p->die_r) || !positive_finite(p->die_strike) ||
+        !positive_finite(p->die_theta_deg))
+        return fail(SG_EINVAL, "radius and die-off extents must be finite and > 0");
+    if (p->direction != 1 && p->direction != -1) return fail(SG_EINVAL, "direction must be +1 or -1");
+    const double a = p->azimuth_deg * kPi / 180.0, th = p->dip_deg * kPi / 180.0, R = p->radius;
+    sg::FaultFrame F{};
+    F.dz = dz;
+    F.dy = dy;
+    F.dx = dx;
+    F.inv_dz = 1.0 / dz;
+    F.inv_dy = 1.0 / dy;
+    F.inv_dx = 1.0 / dx;
+    F.n_y = std::sin(a);    // horizontal offset of the axis from the centre
+    F.n_x = std::cos(a);
+    F.s_y = std::cos(a);    // strike, along the axis
+    F.s_x = -std::sin(a);
+    const double dlt_z = R * std::sin(th), dlt_az = R * std::cos(th);
+    F.cz = p->cz - dlt_z;
+    F.cy = p->cy - dlt_az * F.n_y;
+    F.cx = p->cx - dlt_az * F.n_x;
+    F.radius = R;
+    F.theta0 = std::atan2(dlt_z, dlt_az);
+    F.shift = p->slip / R;  // s / (2 pi R) of a full turn, in radians
+    F.direction = p->direction;
+    F.inv_die_r = 1.0 / p->die_r;
+    F.inv_die_t = 1.0 / (p->die_theta_deg * kPi / 180.0);
+    F.inv_die_s = 1.0 / p->die_strike;
+    SG_HIP(sg::launch_fault(v, nz, ny, nx, F, fill, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
 sg_status sg_set_graphs(int32_t on)
 {
     g_batch_graphs = on != 0;

@@ -72,6 +72,13 @@ class sg_batch_grad_item(ctypes.Structure):
 
 
 _lib = None
+class sg_fault_params(ctypes.Structure):
+    _fields_ = [("cz", ctypes.c_double), ("cy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("azimuth_deg", ctypes.c_double), ("dip_deg", ctypes.c_double), ("radius", ctypes.c_double),
+                ("slip", ctypes.c_double), ("direction", ctypes.c_int32), ("die_r", ctypes.c_double),
+                ("die_strike", ctypes.c_double), ("die_theta_deg", ctypes.c_double)]
+
+
 _SIGS = {
     "sg_abi_version": (ctypes.c_int32, []),
     "sg_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -111,6 +118,15 @@ _SIGS = {
     "sg_check_finite": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p]),
     "sg_set_graphs": (ctypes.c_int32, [ctypes.c_int32]),
+    "sg_fractal_noise2d": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_squish": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_fault": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.POINTER(sg_fault_params), ctypes.c_float,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
     "sg_wave_residual_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "sg_wave_residual": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -158,7 +174,7 @@ def header_functions() -> list[str]:
     """Names of the functions include/sgwave.h declares."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", text)) - {"sg_shots"})
+    return sorted(set(re.findall(r"\b(sg_[a-z0-9_]+)\s*\(", text)) - {"sg_shots"})
 
 
 def _check(status: int):
@@ -420,6 +436,40 @@ def sg_wave_residual_workspace_size(nframes: int, nz: int, nx: int, top: int = S
     n = ctypes.c_size_t()
     _check(lib().sg_wave_residual_workspace_size(nframes, nz, nx, top, ctypes.byref(n)))
     return n.value
+
+
+def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: float, lam_x: float,
+                    azimuth_deg: float, amplitude: float, stream=None):
+    """Displacement field [ny, nx] (float32 device tensor, metres) from the
+    per-octave lattices [noct, gy, gx] (float32 device)."""
+    import torch
+    noct, gy, gx = lattice.shape
+    out = torch.empty((ny, nx), dtype=torch.float32, device=lattice.device)
+    _check(lib().sg_fractal_noise2d(_ptr(lattice), noct, gy, gx, ny, nx, dy, dx, lam_y, lam_x, azimuth_deg,
+                                    amplitude, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def squish(v, dz: float, shift, stream=None):
+    """v [nz, ny, nx] pulled from depth z + shift(y, x) (shift [ny, nx] in
+    metres); float32 device tensors in, a new one out."""
+    import torch
+    nz, ny, nx = v.shape
+    out = torch.empty_like(v)
+    _check(lib().sg_squish(_ptr(v), nz, ny, nx, dz, _ptr(shift), _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def fault(v, dz: float, dy: float, dx: float, params: dict, fill: float, stream=None):
+    """v [nz, ny, nx] through one listric normal fault; params holds the
+    fields of sg_fault_params."""
+    import torch
+    nz, ny, nx = v.shape
+    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
+                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    out = torch.empty_like(v)
+    _check(lib().sg_fault(_ptr(v), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out), _stream_ptr(stream)))
+    return out
 
 
 def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP_FREE, stream=None):

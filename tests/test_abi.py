@@ -202,3 +202,26 @@ def test_wave_residual_workspace_and_argument_errors():
              ((fake, 10, 40, 50, fake, 10.0, 10.0, 1e-3, 0, fake, fake, fake, ws - 1), sgwave.SG_ENOSPACE)]
     for args, status in cases:
         assert L.sg_wave_residual(*args, None) == status
+
+
+def test_builder_argument_errors_touch_nothing():
+    """The builder calls validate before any device work (fake pointers)."""
+    L = sgwave.lib()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    E = sgwave.SG_EINVAL
+    assert L.sg_squish(a, 10, 2, 3, 10.0, b, a, None) == E                # output aliases the input
+    assert L.sg_squish(a, 0, 2, 3, 10.0, b, b, None) == E
+    assert L.sg_squish(a, 10, 2, 3, 0.0, a, b, None) == E
+    assert L.sg_squish(a, 10, 2, 3, 10.0, None, b, None) == E
+    good = dict(cz=1.0, cy=1.0, cx=1.0, azimuth_deg=0.0, dip_deg=60.0, radius=100.0, slip=5.0, direction=1,
+                die_r=10.0, die_strike=10.0, die_theta_deg=10.0)
+    for bad in (dict(direction=0), dict(radius=0.0), dict(die_r=-1.0), dict(slip=float("inf")),
+                dict(die_theta_deg=float("nan"))):
+        p = sgwave.sg_fault_params(**dict(good, **bad))
+        assert L.sg_fault(a, 10, 2, 3, 10.0, 10.0, 10.0, ctypes.byref(p), 0.0, b, None) == E, bad
+    p = sgwave.sg_fault_params(**good)
+    assert L.sg_fault(a, 10, 2, 3, 10.0, -1.0, 10.0, ctypes.byref(p), 0.0, b, None) == E
+    assert L.sg_fault(a, 10, 2, 3, 10.0, 10.0, 10.0, None, 0.0, b, None) == E
+    assert L.sg_fractal_noise2d(a, 0, 4, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E
+    assert L.sg_fractal_noise2d(a, 2, 4, 4, 10, 10, 10.0, 10.0, 0.0, 100.0, 0.0, 5.0, b, None) == E
+    assert L.sg_fractal_noise2d(a, 2, 0, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E

@@ -1,0 +1,102 @@
+"""GPU parity of the builder modules (Squish, Alg. 2; Fault, Alg. 3) against
+the FP64 oracle on the same float32 inputs: the fractal-noise displacement,
+the vertical warp and the fault on 3D volumes and 2D slices, both slip
+directions, a fault through the top (fill values), zero slip (identity)."""
+import numpy as np
+import pytest
+
+from oracle import builder as OB
+from paper_2605_30541_amd import sgwave
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _layered(nz, ny, nx, seed):
+    """A layered model with a smooth lateral trend and mild noise."""
+    rng = np.random.default_rng(seed)
+    z = np.arange(nz)[:, None, None]
+    y = np.arange(ny)[None, :, None]
+    x = np.arange(nx)[None, None, :]
+    base = 1600.0 + 25.0 * z + 60.0 * np.sin(x / 9.0 + y / 7.0)
+    layers = 150.0 * (np.floor((z + 2.0 * np.sin(x / 13.0)) / 6.0) % 3)
+    return (base + layers + rng.normal(0, 5.0, (nz, ny, nx))).astype(np.float32)
+
+
+@pytest.mark.parametrize("noct,gy,gx,ny,nx,az", [(1, 5, 7, 30, 40, 0.0), (4, 6, 6, 64, 90, 37.0),
+                                                 (6, 9, 4, 17, 201, -120.0)])
+def test_fractal_noise_matches_the_oracle(noct, gy, gx, ny, nx, az):
+    rng = np.random.default_rng(noct * 100 + nx)
+    lat = rng.uniform(-1, 1, (noct, gy, gx)).astype(np.float32)
+    got = _host(sgwave.fractal_noise2d(_dev(lat), ny, nx, 10.0, 12.5, 170.0, 230.0, az, 35.0))
+    ref = OB.fractal_noise2d(lat.astype(np.float64), ny, nx, 10.0, 12.5, 170.0, 230.0, az, 35.0)
+    e = np.abs(got - ref).max() / 35.0
+    print("noise max error / amplitude %.2e" % e, flush=True)
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("nz,ny,nx", [(37, 5, 41), (80, 1, 300), (9, 3, 8)])
+def test_squish_matches_the_oracle(nz, ny, nx):
+    V = _layered(nz, ny, nx, nz)
+    rng = np.random.default_rng(nx)
+    lat = rng.uniform(-1, 1, (3, 5, 5))
+    shift = OB.fractal_noise2d(lat, ny, nx, 10.0, 10.0, 150.0, 120.0, 20.0, 60.0).astype(np.float32)
+    got = _host(sgwave.squish(_dev(V), 10.0, _dev(shift)))
+    ref = OB.squish(V.astype(np.float64), 10.0, shift.astype(np.float64))
+    e = rel_l2(got, ref)
+    print("squish rel-L2 %.2e" % e, flush=True)
+    assert e <= TOL
+    # zero shift: the input itself
+    same = _host(sgwave.squish(_dev(V), 10.0, _dev(np.zeros((ny, nx)))))
+    assert np.abs(same - V).max() <= 1e-6 * np.abs(V).max()
+
+
+FAULT = dict(cz=250.0, cy=110.0, cx=280.0, azimuth_deg=25.0, dip_deg=55.0, radius=900.0, slip=45.0,
+             direction=1, die_r=180.0, die_strike=200.0, die_theta_deg=25.0)
+
+
+@pytest.mark.parametrize("case", ["3d", "3d-reverse", "2d-slice", "through-top", "steep-oblique"])
+def test_fault_matches_the_oracle(case):
+    nz, ny, nx, p, fill = 48, 24, 56, dict(FAULT), 1480.0
+    if case == "3d-reverse":
+        p["direction"] = -1
+    elif case == "2d-slice":
+        ny, p["cy"], p["azimuth_deg"] = 1, 0.0, 0.0
+    elif case == "through-top":
+        p.update(cz=20.0, slip=140.0, die_r=400.0, die_strike=600.0, die_theta_deg=60.0)
+    elif case == "steep-oblique":
+        p.update(azimuth_deg=-70.0, dip_deg=80.0, radius=3000.0, slip=70.0, die_theta_deg=10.0)
+    V = _layered(nz, ny, nx, 7)
+    got = _host(sgwave.fault(_dev(V), 10.0, 10.0, 10.0, p, fill))
+    ref = OB.fault(V.astype(np.float64), 10.0, 10.0, 10.0, p, fill)
+    (_, _, _), w = OB.fault_source(V.shape, 10.0, 10.0, 10.0, p)
+    assert np.count_nonzero(w) > 100
+    e = rel_l2(got, ref)
+    print("%s: fault rel-L2 %.2e, moved voxels %d" % (case, e, np.count_nonzero(w)), flush=True)
+    assert e <= TOL
+    # outside the taper the GPU copies the input exactly
+    assert np.array_equal(got[w == 0], V.astype(np.float64)[w == 0])
+    if case == "through-top":
+        assert np.count_nonzero(ref == fill) > 0
+        assert np.array_equal(got == fill, ref == fill)
+
+
+def test_fault_with_zero_slip_is_the_identity():
+    V = _layered(30, 10, 40, 3)
+    got = _host(sgwave.fault(_dev(V), 10.0, 10.0, 10.0, dict(FAULT, slip=0.0), 0.0))
+    assert np.abs(got - V).max() <= 1e-6 * np.abs(V).max()
