@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--shots-per-wave", type=int, default=25)
     ap.add_argument("--residual-only", action="store_true",
                     help="time only the physics-residual pass over the 572-frame stack and print its record")
+    ap.add_argument("--builder-only", action="store_true",
+                    help="time only the builder modules on a 619x1000x1000 volume and print their record")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -253,6 +255,53 @@ def residual_rate(passes=10):
             "frac_of_hbm_peak": algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "residual_ratio": ratio}
 
 
+def builder_rate(passes=3):
+    """Builder modules at the paper's model shape, 619 x 1000 x 1000 voxels at
+    10 m (App. C): a 4-octave fractal-noise displacement (max 90 m) and the
+    Squish warp it drives, then one listric normal fault across the model.
+    The input is a seeded layered volume built on the device.  Algorithmic
+    traffic: each voxel read and written once (8 B)."""
+    import torch
+    from paper_2605_30541_amd import sgwave
+    nz, ny, nx, h = 619, 1000, 1000, 10.0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13)
+    z = torch.arange(nz, device="cuda", dtype=torch.float32)[:, None, None]
+    x = torch.arange(nx, device="cuda", dtype=torch.float32)[None, None, :]
+    y = torch.arange(ny, device="cuda", dtype=torch.float32)[None, :, None]
+    v = (1600.0 + 4.0 * z + 150.0 * torch.remainder(torch.floor((z + 3.0 * torch.sin(x / 40.0 + y / 55.0)) / 12.0), 3.0)
+         ).contiguous()
+    lattice = torch.rand((4, 8, 8), device="cuda", generator=gen) * 2.0 - 1.0
+    fault = dict(cz=3000.0, cy=5000.0, cx=5000.0, azimuth_deg=30.0, dip_deg=60.0, radius=6000.0, slip=120.0,
+                 direction=1, die_r=1500.0, die_strike=4500.0, die_theta_deg=35.0)
+    shift = sgwave.fractal_noise2d(lattice, ny, nx, h, h, 2500.0, 4000.0, 20.0, 90.0)
+    out = sgwave.squish(v, h, shift)
+    out2 = sgwave.fault(out, h, h, h, fault, 1500.0)     # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(passes):
+        shift = sgwave.fractal_noise2d(lattice, ny, nx, h, h, 2500.0, 4000.0, 20.0, 90.0)
+        out = sgwave.squish(v, h, shift, stream=None)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(passes):
+        out2 = sgwave.fault(out, h, h, h, fault, 1500.0)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms_sq = ev[0].elapsed_time(ev[1]) / passes
+    ms_f = ev[2].elapsed_time(ev[3]) / passes
+    nvox = nz * ny * nx
+    moved = float((out2 != out).float().mean())
+    del v, out, out2
+    return {"workload": "619x1000x1000 voxels @10 m; squish 90 m max shift, 4 octaves; one fault "
+                        "(R 6 km, slip 120 m, die-off 1.5 km / 4.5 km / 35 deg)",
+            "squish_ms": ms_sq, "squish_Gvoxel_per_s": nvox / (ms_sq / 1e3) / 1e9,
+            "squish_frac_of_hbm_peak": 8.0 * nvox / (ms_sq / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "fault_ms": ms_f, "fault_Gvoxel_per_s": nvox / (ms_f / 1e3) / 1e9,
+            "fault_moved_fraction": moved}
+
+
 def batched_gradient_rate(fwd_rate, shots_per_wave):
     """4 field slices of uneven size (nz 500-620, nx 801-1001) x 100 shots
     spread evenly over the full width, nt 10000 at 0.8 ms, receivers on every
@@ -302,8 +351,8 @@ def main():
               "(shots shard across GPUs with no communication, see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.residual_only:
-        out = {"physics_residual": residual_rate()}
+    if args.residual_only or args.builder_only:
+        out = {"physics_residual": residual_rate()} if args.residual_only else {"builder": builder_rate()}
         copy_reference(args.copy_mib)
         print(json.dumps(out), flush=True)
         return
@@ -399,6 +448,9 @@ def main():
         log("paper-shaped batch: %.1f Gpt-updates/s" % out["paper_workload"]["value"])
         out["physics_residual"] = residual_rate()
         log("physics residual: %.3f ms per 572-frame stack" % out["physics_residual"]["ms"])
+        out["builder"] = builder_rate()
+        log("builder: squish %.2f ms, fault %.1f ms per 619x1000x1000 volume" % (
+            out["builder"]["squish_ms"], out["builder"]["fault_ms"]))
     if args.batched_gradient:
         out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])

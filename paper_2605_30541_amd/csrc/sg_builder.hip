@@ -5,9 +5,9 @@
 // clamped to the axis).  Volumes are [nz][ny][nx], x fastest.
 //
 // Squish: one thread per (y, x) column.  The shift is constant down a column,
-// so the 8 weights are computed once and the column streams through an
-// 8-value register window: one load and 8 FMAs per voxel (HBM-bound, 8 B per
-// voxel read + written).
+// so the 8 weights are computed once and the column streams through registers
+// in blocks of 8 rows: one load and 8 FMAs per voxel (HBM-bound, 8 B per voxel
+// read + written).
 // Fault: one thread per voxel.  The pull source is computed in FP64 (the
 // frame and the angles of Alg. 3); voxels outside the taper are copied, the
 // others take 8 x 8 x 8 taps (8 x 8 when ny = 1) with FP32 weights and sums.
@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kTaps = 8;
 constexpr float kBeta = 6.f;
+constexpr int kBrickZ = 16, kBrickY = 16, kBrickRows = kBrickZ * kBrickY;   // fault kernel
 
 // I0 by its power series sum_k ((x/2)^2)^k / (k!)^2; for x <= 6 the terms
 // after k = 16 are below 1e-10 of the sum.
@@ -28,7 +29,7 @@ __device__ inline float bessel_i0(float x)
     float term = 1.f, sum = 1.f;
 #pragma unroll
     for (int k = 1; k <= 16; ++k) {
-        term *= q / (float)(k * k);
+        term *= q * (1.f / (float)(k * k));   // constant reciprocal: no division
         sum += term;
     }
     return sum;
@@ -96,30 +97,50 @@ __global__ void __launch_bounds__(256) k_squish(const float *__restrict__ v, int
     float w[kTaps];
     sinc_weights((float)(c - cf), w);
     const float *vc = v + col;
-    // window of the taps c0 - 3 .. c0 + 4 below z = 0 (clamped rows)
-    float win[kTaps];
+    // rows c0 - 3 + z .. c0 + 4 + z feed output row z; they come in blocks of
+    // kChunk rows, so kChunk loads are in flight at a time, and the last 7
+    // rows of a block carry over to the next (rows past either end clamped)
+    constexpr int kChunk = 8;
+    float buf[kChunk + kTaps - 1];
 #pragma unroll
-    for (int j = 0; j < kTaps; ++j) win[j] = vc[(int64_t)min(max(c0 - 3 + j, 0), nz - 1) * plane];
-    for (int z = 0; z < nz; ++z) {
-        float acc = 0.f;
+    for (int k = 0; k < kTaps - 1; ++k) buf[k] = vc[(int64_t)min(max(c0 - 3 + k, 0), nz - 1) * plane];
+    for (int z0 = 0; z0 < nz; z0 += kChunk) {
 #pragma unroll
-        for (int j = 0; j < kTaps; ++j) acc = fmaf(w[j], win[j], acc);
-        out[col + (int64_t)z * plane] = acc;
+        for (int k = 0; k < kChunk; ++k)
+            buf[kTaps - 1 + k] = vc[(int64_t)min(max(z0 + c0 + 4 + k, 0), nz - 1) * plane];
 #pragma unroll
-        for (int j = 0; j < kTaps - 1; ++j) win[j] = win[j + 1];
-        win[kTaps - 1] = vc[(int64_t)min(max(z + 1 + c0 + 4, 0), nz - 1) * plane];
+        for (int u = 0; u < kChunk; ++u) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) acc = fmaf(w[j], buf[u + j], acc);
+            if (z0 + u < nz) out[col + (int64_t)(z0 + u) * plane] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < kTaps - 1; ++k) buf[k] = buf[kChunk + k];
     }
 }
 
 __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, FaultFrame F,
                                                float fill, float *__restrict__ out)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // The volume is cut in bricks of kBrickZ x kBrickY rows of 256 columns,
+    // one workgroup per row.  Workgroups go to the 8 XCDs in turn; here all
+    // rows of a brick go to one XCD (the rows its voxels sample are then
+    // fetched into one L2) and the bricks are dealt round-robin (the moved
+    // region of a fault stays spread over the XCDs).
+    const int bx_n = (nx + 255) / 256, by_n = (ny + kBrickY - 1) / kBrickY;
+    const int64_t nbrick = (int64_t)bx_n * by_n * ((nz + kBrickZ - 1) / kBrickZ);
+    const int64_t t = blockIdx.x / 8;
+    const int64_t brick = (t / kBrickRows) * 8 + blockIdx.x % 8;
+    if (brick >= nbrick) return;
+    const int row = (int)(t % kBrickRows);
+    const int bx = (int)(brick % bx_n);
+    const int64_t rest = brick / bx_n;
+    const int by = (int)(rest % by_n), bz = (int)(rest / by_n);
+    const int iz = bz * kBrickZ + row / kBrickY, iy = by * kBrickY + row % kBrickY, ix = bx * 256 + threadIdx.x;
+    if (iz >= nz || iy >= ny || ix >= nx) return;
     const int64_t plane = (int64_t)ny * nx;
-    if (q >= plane * nz) return;
-    const int iz = (int)(q / plane);
-    const int64_t r2 = q - (int64_t)iz * plane;
-    const int iy = (int)(r2 / nx), ix = (int)(r2 - (int64_t)iy * nx);
+    const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
     const double Z = iz * F.dz, Y = iy * F.dy, X = ix * F.dx;
     const double qy = Y - F.cy, qx = X - F.cx, vv = Z - F.cz;
     const double h = qy * F.n_y + qx * F.n_x;
@@ -207,8 +228,10 @@ hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, cons
 hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
                         hipStream_t st)
 {
-    const int64_t n = (int64_t)nz * ny * nx;
-    hipLaunchKernelGGL(k_fault, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, nz, ny, nx, F, fill, out);
+    const int64_t nbrick = (int64_t)((nx + 255) / 256) * ((ny + kBrickY - 1) / kBrickY) * ((nz + kBrickZ - 1) / kBrickZ);
+    const int64_t blocks = (nbrick + 7) / 8 * 8 * kBrickRows;
+    if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, F, fill, out);
     return hipGetLastError();
 }
 
