@@ -165,3 +165,62 @@ def fault(V, dz: float, dy: float, dx: float, p: dict, fill: float):
     out = sinc_sample_3d(V, sz, sy, sx)
     out[(sz < 0) | (sz >= V.shape[0])] = fill
     return out
+
+
+def value_noise3d(lattice, z, y, x, lam_z: float, lam_y: float, lam_x: float):
+    """Smooth value noise in [-1, 1] (lattice values in [-1, 1]) at points
+    (z, y, x) in metres: periodic lattice [gz, gy, gx], node spacing
+    (lam_z, lam_y, lam_x), quintic fade between nodes (the texture field of
+    Alg. 1; one octave)."""
+    lattice = np.asarray(lattice, np.float64)
+    gz, gy, gx = lattice.shape
+    fade = lambda t: t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+    pz, py, px = np.asarray(z) / lam_z, np.asarray(y) / lam_y, np.asarray(x) / lam_x
+    iz, iy, ix = np.floor(pz), np.floor(py), np.floor(px)
+    tz, ty, tx = fade(pz - iz), fade(py - iy), fade(px - ix)
+    iz, iy, ix = iz.astype(np.int64), iy.astype(np.int64), ix.astype(np.int64)
+    out = 0.0
+    for a in (0, 1):
+        wz = tz if a else 1 - tz
+        for b in (0, 1):
+            wy = ty if b else 1 - ty
+            for c in (0, 1):
+                wx = tx if c else 1 - tx
+                out = out + wz * wy * wx * lattice[(iz + a) % gz, (iy + b) % gy, (ix + c) % gx]
+    return out
+
+
+def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vbed, beta: float,
+            eta_b, a_B: float, tex_lattice, lam, tex_off, a_eta: float, f_top: float, f_base: float):
+    """Alg. 1 (interbedded package, boundary path) on a band of t cells:
+    thick [n] bed thicknesses in cells (the drawn, clamped values), vbed [n]
+    bed velocities, beta the velocity gradient [m/s per m], eta_b [n-1, ny, nx]
+    boundary noise, a_B its amplitude [cells], tex_lattice / lam / tex_off [n]
+    (metres) the texture noise and per-bed depth offsets, a_eta its amplitude
+    [m/s], f_top / f_base the taper fractions.  Returns V [t, ny, nx].
+
+    Readings: the internal boundaries are the cumulative thicknesses
+    H_i = sum_{k < i} thick_k, i = 1..n-1; a voxel at depth z (cells) belongs
+    to bed l = #{i : H_i(y, x) <= z}, whose start S_l is the largest perturbed
+    boundary <= z (0 for bed 0); the texture is sampled at depth
+    (z - S_l) dz + tex_off_l."""
+    thick = np.asarray(thick, np.float64)
+    vbed = np.asarray(vbed, np.float64)
+    n = thick.size
+    H = np.cumsum(thick)[:-1]                          # n - 1 internal boundaries
+    vbar = vbed.mean()
+
+    def tau(z):
+        z = np.asarray(z, np.float64)
+        return np.minimum(z / (f_top * t), 1.0) * np.minimum((t - z) / (f_base * t), 1.0)
+
+    Hyx = np.clip(H[:, None, None] + tau(H)[:, None, None] * a_B * np.asarray(eta_b, np.float64), 0.0, t - 1.0)
+    z = np.arange(t, dtype=np.float64)[:, None, None]
+    le = Hyx[None, :, :, :] <= z[:, None, :, :]         # [t, n-1, ny, nx]
+    bed = le.sum(axis=1)                               # [t, ny, nx]
+    start = np.where(le, Hyx[None], 0.0).max(axis=1)   # largest boundary <= z (0 if none)
+    Y = (np.arange(ny) * dy)[None, :, None]
+    X = (np.arange(nx) * dx)[None, None, :]
+    zt = (z - start) * dz + np.asarray(tex_off, np.float64)[bed]
+    eta = value_noise3d(tex_lattice, zt, np.broadcast_to(Y, zt.shape), np.broadcast_to(X, zt.shape), *lam)
+    return (vbar + beta * z * dz) + tau(z) * ((vbed[bed] - vbar) + a_eta * eta)

@@ -169,3 +169,63 @@ def test_fault_fills_voxels_pulled_from_outside_the_model_depth():
     outside = (sz / 10.0 < 0) | (sz / 10.0 >= 20)
     assert (sz / 10.0 < 0).any()
     assert np.all(out[outside] == -1.0) and np.all(out[~outside] > 1000.0)
+
+
+def test_value_noise3d_hits_lattice_values_and_is_periodic():
+    rng = np.random.default_rng(7)
+    lat = rng.uniform(-1, 1, (3, 4, 5))
+    z, y, x = np.meshgrid(np.arange(3) * 20.0, np.arange(4) * 50.0, np.arange(5) * 70.0, indexing="ij")
+    assert np.abs(B.value_noise3d(lat, z, y, x, 20.0, 50.0, 70.0) - lat).max() < 1e-12
+    p = rng.uniform(0, 500, (3, 40))
+    a = B.value_noise3d(lat, p[0], p[1], p[2], 20.0, 50.0, 70.0)
+    b = B.value_noise3d(lat, p[0] + 3 * 20.0, p[1] + 4 * 50.0, p[2] + 5 * 70.0, 20.0, 50.0, 70.0)
+    assert np.abs(a - b).max() < 1e-9
+    assert np.abs(a).max() <= np.abs(lat).max() + 1e-12
+
+
+def _walk_bed(thick, z):
+    """Bed of depth z by walking the beds (thicknesses in cells)."""
+    top = 0.0
+    for k, h in enumerate(thick):
+        if z < top + h or k == len(thick) - 1:
+            return k
+        top += h
+
+
+def test_deposit_without_noise_is_beds_plus_trend_under_the_taper():
+    """a_B = a_eta = 0: each voxel is the mean velocity plus the depth trend
+    plus the taper times its bed's deviation; the bed of a depth found by
+    walking the beds; at depth 0 the taper is 0, inside the untapered middle
+    it is 1 (the bed velocity itself plus the trend)."""
+    rng = np.random.default_rng(8)
+    t, ny, nx, dz = 60, 2, 3, 5.0
+    thick = np.array([9.0, 12.0, 7.5, 11.0, 10.0, 10.5])
+    vbed = rng.normal(2500, 100, 6)
+    V = B.deposit(t, ny, nx, dz, 10.0, 10.0, thick, vbed, 0.5, rng.uniform(-1, 1, (5, ny, nx)), 0.0,
+                  rng.uniform(-1, 1, (4, 4, 4)), (40.0, 300.0, 300.0), np.zeros(6), 0.0, 0.2, 0.25)
+    vbar = vbed.mean()
+    assert np.all(V[0] == vbar)
+    for z in range(t):
+        tau = min(z / (0.2 * t), 1.0) * min((t - z) / (0.25 * t), 1.0)
+        ref = vbar + 0.5 * z * dz + tau * (vbed[_walk_bed(thick, z)] - vbar)
+        assert np.abs(V[z] - ref).max() < 1e-9, z
+    for z in range(12, 45):                      # tau = 1 there
+        assert np.abs(V[z] - (vbed[_walk_bed(thick, z)] + 0.5 * z * dz)).max() < 1e-9
+
+
+def test_deposit_boundary_noise_moves_bed_contacts_within_the_band():
+    rng = np.random.default_rng(9)
+    t, ny, nx = 50, 3, 4
+    thick = np.array([10.0, 10.0, 10.0, 10.0, 10.0])
+    vbed = np.array([2000.0, 2400.0, 2800.0, 3200.0, 3600.0])
+    eta = np.full((4, ny, nx), 0.5)
+    eta[:, 1, 2] = -1.0
+    V = B.deposit(t, ny, nx, 5.0, 10.0, 10.0, thick, vbed, 0.0, eta, 4.0,
+                  np.zeros((2, 2, 2)), (40.0, 300.0, 300.0), np.zeros(5), 0.0, 1e-9, 1e-9)
+    # with the taper 1 below depth 0 a contact moves by a_B * eta = +2 or -4 cells
+    # (depth 0 has taper 0: the mean velocity)
+    col = V[:, 0, 0]
+    assert col[0] == 2800.0
+    assert np.all(col[1:12] == 2000.0) and np.all(col[12:22] == 2400.0)
+    col = V[:, 1, 2]
+    assert np.all(col[1:6] == 2000.0) and np.all(col[6:16] == 2400.0)
