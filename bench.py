@@ -258,7 +258,8 @@ def residual_rate(passes=10):
 def builder_rate(passes=3):
     """Builder modules at the paper's model shape, 619 x 1000 x 1000 voxels at
     10 m (App. C): a 4-octave fractal-noise displacement (max 90 m) and the
-    Squish warp it drives, then one listric normal fault across the model.
+    Squish warp it drives, then one listric normal fault across the model;
+    and a Deposit band of 40 beds, 200 cells at 2.5 m over the same area.
     The input is a seeded layered volume built on the device.  Algorithmic
     traffic: each voxel read and written once (8 B)."""
     import torch
@@ -294,12 +295,32 @@ def builder_rate(passes=3):
     nvox = nz * ny * nx
     moved = float((out2 != out).float().mean())
     del v, out, out2
+    # Deposit: a 200-cell band of 40 beds over the same 1000 x 1000 area
+    tb, nb = 200, 40
+    thick = torch.clamp(torch.randn(nb, device="cuda", generator=gen) * 1.5 + tb / nb, min=0.5)
+    vbed = torch.randn(nb, device="cuda", generator=gen) * 150.0 + 2600.0
+    eta = torch.stack([sgwave.fractal_noise2d(torch.rand((3, 8, 8), device="cuda", generator=gen) * 2.0 - 1.0,
+                                              ny, nx, h, h, 1500.0, 2000.0, 10.0 * i, 1.0) for i in range(nb - 1)])
+    tex = torch.rand((16, 16, 16), device="cuda", generator=gen) * 2.0 - 1.0
+    off = torch.rand(nb, device="cuda", generator=gen) * 500.0
+    dargs = (tb, ny, nx, h / 4, h, h, thick, vbed, 0.3, eta, 3.0, tex, (12.0, 400.0, 400.0), off, 50.0, 0.1, 0.1)
+    band = sgwave.deposit(*dargs)     # warm-up
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(passes):
+        band = sgwave.deposit(*dargs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_d = ev[0].elapsed_time(ev[1]) / passes
+    del band, eta
     return {"workload": "619x1000x1000 voxels @10 m; squish 90 m max shift, 4 octaves; one fault "
                         "(R 6 km, slip 120 m, die-off 1.5 km / 4.5 km / 35 deg)",
             "squish_ms": ms_sq, "squish_Gvoxel_per_s": nvox / (ms_sq / 1e3) / 1e9,
             "squish_frac_of_hbm_peak": 8.0 * nvox / (ms_sq / 1e3) / 1e9 / HBM_PEAK_GBS,
             "fault_ms": ms_f, "fault_Gvoxel_per_s": nvox / (ms_f / 1e3) / 1e9,
-            "fault_moved_fraction": moved}
+            "fault_moved_fraction": moved,
+            "deposit_band": "200 x 1000 x 1000 cells (2.5 m vertical), 40 beds", "deposit_ms": ms_d,
+            "deposit_Gvoxel_per_s": tb * ny * nx / (ms_d / 1e3) / 1e9}
 
 
 def batched_gradient_rate(fwd_rate, shots_per_wave):
@@ -449,8 +470,8 @@ def main():
         out["physics_residual"] = residual_rate()
         log("physics residual: %.3f ms per 572-frame stack" % out["physics_residual"]["ms"])
         out["builder"] = builder_rate()
-        log("builder: squish %.2f ms, fault %.1f ms per 619x1000x1000 volume" % (
-            out["builder"]["squish_ms"], out["builder"]["fault_ms"]))
+        log("builder: squish %.2f ms, fault %.1f ms per 619x1000x1000 volume, deposit %.2f ms per band" % (
+            out["builder"]["squish_ms"], out["builder"]["fault_ms"], out["builder"]["deposit_ms"]))
     if args.batched_gradient:
         out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])

@@ -361,8 +361,9 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
                            void *stream);
 
 /*
- * Velocity-model builder modules (App. B): the vertical warp of Squish
- * (Alg. 2) and the listric normal fault of Fault (Alg. 3), on a device volume
+ * Velocity-model builder modules (App. B): the interbedded band of Deposit
+ * (Alg. 1), the vertical warp of Squish (Alg. 2) and the listric normal
+ * fault of Fault (Alg. 3), on a device volume
  * [nz][ny][nx] of floats (x fastest; a 2D slice is ny = 1), z = depth.  Both
  * pull-sample the input through an 8-point Kaiser-windowed sinc (beta 6,
  * weights normalised to sum 1, tap indices clamped to the axis), exact at
@@ -370,6 +371,28 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
  * allocation.  SG_EINVAL for NULL pointers, non-positive sizes or spacings,
  * aliasing, or parameters outside the ranges below.
  */
+
+/* Alg. 1 (Deposit, boundary path): an interbedded band out [t][ny][nx] of t
+ * cells.  The method's random draws are inputs (device floats): thick
+ * [nbeds] bed thicknesses in cells (drawn and clamped by the caller), vbed
+ * [nbeds] bed velocities [m/s], eta_b [nbeds-1][ny][nx] contact noise (e.g.
+ * from sg_fractal_noise2d with amplitude 1), tex_lattice [gz][gy][gx] a
+ * periodic value-noise lattice with node spacings lam_z/y/x [m], tex_off
+ * [nbeds] per-bed depth offsets into it [m].  Contacts H_i = thick_0 + ... +
+ * thick_{i-1} (i = 1..nbeds-1) move by taper(H_i) a_B eta_b[i-1] and are
+ * clamped to [0, t-1]; a voxel at depth z belongs to bed l = number of
+ * contacts <= z, which starts at the deepest of them (0 for bed 0); then
+ *   V = (vbar + beta z dz) + taper(z) [(vbed_l - vbar) + a_eta noise],
+ * vbar the mean bed velocity, noise the quintic-fade value noise at
+ * ((z - start) dz + tex_off_l, y dy, x dx), taper(z) = min(z / (f_top t), 1)
+ * min((t - z) / (f_base t), 1).  beta in m/s per m, a_B in cells, a_eta in
+ * m/s.  Placing the band under a topography is a per-column vertical warp
+ * (sg_squish). */
+sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, int32_t nbeds,
+                     const float *thick, const float *vbed, double beta, const float *eta_b, double a_B,
+                     const float *tex_lattice, int32_t gz, int32_t gy, int32_t gx, double lam_z, double lam_y,
+                     double lam_x, const float *tex_off, double a_eta, double f_top, double f_base, float *out,
+                     void *stream);
 
 /* Alg. 2, first step: the displacement field out [ny][nx] (metres, device)
  * as fractal value noise: per octave o = 0..noct-1 a periodic lattice

@@ -218,7 +218,7 @@ def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vb
     z = np.arange(t, dtype=np.float64)[:, None, None]
     le = Hyx[None, :, :, :] <= z[:, None, :, :]         # [t, n-1, ny, nx]
     bed = le.sum(axis=1)                               # [t, ny, nx]
-    start = np.where(le, Hyx[None], 0.0).max(axis=1)   # largest boundary <= z (0 if none)
+    start = np.where(le, Hyx[None], 0.0).max(axis=1, initial=0.0)   # largest boundary <= z (0 if none)
     Y = (np.arange(ny) * dy)[None, :, None]
     X = (np.arange(nx) * dx)[None, None, :]
     zt = (z - start) * dz + np.asarray(tex_off, np.float64)[bed]

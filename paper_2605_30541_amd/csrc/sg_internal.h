@@ -179,6 +179,16 @@ struct FaultFrame {
     double radius, theta0, shift, direction;
     double inv_die_r, inv_die_t, inv_die_s;
 };
+// Deposit (Alg. 1): band size, spacings, the bed tables (device, nbeds
+// entries; eta_b [nbeds-1][ny][nx]), the texture lattice [gz][gy][gx] with
+// reciprocal node spacings, amplitudes and taper fractions.
+struct DepositArgs {
+    int t, ny, nx, nbeds, gz, gy, gx;
+    double dz, dy, dx, inv_lam_z, inv_lam_y, inv_lam_x;
+    double beta, a_B, a_eta, f_top, f_base;
+    const float *thick, *vbed, *tex_off, *eta_b, *lattice;
+};
+hipError_t launch_deposit(const DepositArgs &A, float *out, hipStream_t st);
 hipError_t launch_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny, int nx, double dy,
                                   double dx, double lam_y, double lam_x, double azimuth_rad, double amplitude,
                                   float *out, hipStream_t st);

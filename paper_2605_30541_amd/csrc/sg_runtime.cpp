@@ -1740,6 +1740,50 @@ sg_status sg_fractal_noise2d(const float *lattice, int32_t noct, int32_t gy, int
     return SG_OK;
 }
 
+sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, int32_t nbeds,
+                     const float *thick, const float *vbed, double beta, const float *eta_b, double a_B,
+                     const float *tex_lattice, int32_t gz, int32_t gy, int32_t gx, double lam_z, double lam_y,
+                     double lam_x, const float *tex_off, double a_eta, double f_top, double f_base, float *out,
+                     void *stream)
+{
+    if (!thick || !vbed || !tex_lattice || !tex_off || !out || (nbeds > 1 && !eta_b))
+        return fail(SG_EINVAL, "NULL argument");
+    if (t < 1 || ny < 1 || nx < 1 || nbeds < 1 || gz < 1 || gy < 1 || gx < 1)
+        return fail(SG_EINVAL, "sizes must be >= 1");
+    if ((int64_t)t * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "band too large");
+    if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx) || !positive_finite(lam_z) ||
+        !positive_finite(lam_y) || !positive_finite(lam_x) || !positive_finite(f_top) || !positive_finite(f_base))
+        return fail(SG_EINVAL, "spacings, noise wavelengths and taper fractions must be finite and > 0");
+    if (!std::isfinite(beta) || !std::isfinite(a_B) || !std::isfinite(a_eta))
+        return fail(SG_EINVAL, "beta, a_B and a_eta must be finite");
+    sg::DepositArgs A{};
+    A.t = t;
+    A.ny = ny;
+    A.nx = nx;
+    A.nbeds = nbeds;
+    A.gz = gz;
+    A.gy = gy;
+    A.gx = gx;
+    A.dz = dz;
+    A.dy = dy;
+    A.dx = dx;
+    A.inv_lam_z = 1.0 / lam_z;
+    A.inv_lam_y = 1.0 / lam_y;
+    A.inv_lam_x = 1.0 / lam_x;
+    A.beta = beta;
+    A.a_B = a_B;
+    A.a_eta = a_eta;
+    A.f_top = f_top;
+    A.f_base = f_base;
+    A.thick = thick;
+    A.vbed = vbed;
+    A.tex_off = tex_off;
+    A.eta_b = eta_b;
+    A.lattice = tex_lattice;
+    SG_HIP(sg::launch_deposit(A, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
 sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, const float *shift, float *out,
                     void *stream)
 {

@@ -122,6 +122,13 @@ _SIGS = {
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_deposit": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
     "sg_squish": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sg_fault": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -447,6 +454,22 @@ def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: floa
     out = torch.empty((ny, nx), dtype=torch.float32, device=lattice.device)
     _check(lib().sg_fractal_noise2d(_ptr(lattice), noct, gy, gx, ny, nx, dy, dx, lam_y, lam_x, azimuth_deg,
                                     amplitude, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vbed, beta: float, eta_b,
+            a_B: float, tex_lattice, lam, tex_off, a_eta: float, f_top: float, f_base: float, stream=None):
+    """Interbedded band [t, ny, nx] of Alg. 1 from device float32 tables:
+    thick/vbed/tex_off [nbeds], eta_b [nbeds-1, ny, nx], tex_lattice
+    [gz, gy, gx]; lam = (lam_z, lam_y, lam_x) in metres."""
+    import torch
+    nbeds = thick.numel()
+    gz, gy, gx = tex_lattice.shape
+    out = torch.empty((t, ny, nx), dtype=torch.float32, device=thick.device)
+    _check(lib().sg_deposit(t, ny, nx, dz, dy, dx, nbeds, _ptr(thick), _ptr(vbed), beta,
+                            _ptr(eta_b) if eta_b is not None else None, a_B, _ptr(tex_lattice), gz, gy, gx,
+                            lam[0], lam[1], lam[2], _ptr(tex_off), a_eta, f_top, f_base, _ptr(out),
+                            _stream_ptr(stream)))
     return out
 
 

@@ -225,3 +225,15 @@ def test_builder_argument_errors_touch_nothing():
     assert L.sg_fractal_noise2d(a, 0, 4, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 4, 4, 10, 10, 10.0, 10.0, 0.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 0, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E
+
+
+def test_deposit_argument_errors_touch_nothing():
+    L = sgwave.lib()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    E = sgwave.SG_EINVAL
+    ok = [40, 3, 5, 5.0, 10.0, 10.0, 4, a, a, 0.5, a, 2.0, a, 2, 2, 2, 30.0, 100.0, 100.0, a, 10.0, 0.2, 0.2, b, None]
+    for i, bad in ((0, 0), (6, 0), (3, 0.0), (16, -1.0), (21, 0.0), (9, float("nan")), (7, None), (23, None),
+                   (10, None)):
+        args = list(ok)
+        args[i] = bad
+        assert L.sg_deposit(*args) == E, (i, bad)

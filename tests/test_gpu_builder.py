@@ -100,3 +100,26 @@ def test_fault_with_zero_slip_is_the_identity():
     V = _layered(30, 10, 40, 3)
     got = _host(sgwave.fault(_dev(V), 10.0, 10.0, 10.0, dict(FAULT, slip=0.0), 0.0))
     assert np.abs(got - V).max() <= 1e-6 * np.abs(V).max()
+
+
+@pytest.mark.parametrize("case", ["beds-only", "noisy", "crossing-contacts", "one-bed"])
+def test_deposit_matches_the_oracle(case):
+    rng = np.random.default_rng({"beds-only": 1, "noisy": 2, "crossing-contacts": 3, "one-bed": 4}[case])
+    t, ny, nx = 70, 6, 45
+    nb = 1 if case == "one-bed" else 9
+    thick = np.clip(rng.normal(t / nb, 2.0, nb), 0.5, None).astype(np.float32)
+    vbed = rng.normal(2600.0, 150.0, nb).astype(np.float32)
+    eta = rng.uniform(-1, 1, (max(nb - 1, 1), ny, nx)).astype(np.float32)
+    lat = rng.uniform(-1, 1, (5, 4, 6)).astype(np.float32)
+    off = rng.uniform(0, 300, nb).astype(np.float32)
+    a_B, a_eta = {"beds-only": (0.0, 0.0), "noisy": (3.0, 60.0), "crossing-contacts": (25.0, 40.0),
+                  "one-bed": (0.0, 80.0)}[case]
+    args = (t, ny, nx, 5.0, 10.0, 12.5)
+    lam = (35.0, 200.0, 260.0)
+    got = _host(sgwave.deposit(*args, _dev(thick), _dev(vbed), 0.4, _dev(eta) if nb > 1 else None, a_B,
+                               _dev(lat), lam, _dev(off), a_eta, 0.15, 0.2))
+    ref = OB.deposit(*args, thick.astype(np.float64), vbed.astype(np.float64), 0.4, eta[:nb - 1].astype(np.float64),
+                     a_B, lat.astype(np.float64), lam, off.astype(np.float64), a_eta, 0.15, 0.2)
+    e = rel_l2(got, ref)
+    print("%s: deposit rel-L2 %.2e" % (case, e), flush=True)
+    assert e <= TOL
