@@ -386,8 +386,8 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
  * vbar the mean bed velocity, noise the quintic-fade value noise at
  * ((z - start) dz + tex_off_l, y dy, x dx), taper(z) = min(z / (f_top t), 1)
  * min((t - z) / (f_base t), 1).  beta in m/s per m, a_B in cells, a_eta in
- * m/s.  Placing the band under a topography is a per-column vertical warp
- * (sg_squish). */
+ * m/s; nbeds in 1..129.  Placing the band under a topography is a
+ * per-column vertical warp (sg_squish). */
 sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, int32_t nbeds,
                      const float *thick, const float *vbed, double beta, const float *eta_b, double a_B,
                      const float *tex_lattice, int32_t gz, int32_t gy, int32_t gx, double lam_z, double lam_y,

@@ -9,11 +9,13 @@
 // so the 8 weights are computed once and the column streams through registers
 // in blocks of 8 rows: one load and 8 FMAs per voxel (HBM-bound, 8 B per voxel
 // read + written).
-// Deposit: one thread per voxel of the band, contacts and texture in FP64.
+// Deposit: one thread per column of the band, contacts and texture in FP64.
 // Fault: one thread per voxel.  The pull source is computed in FP64 (the
 // frame and the angles of Alg. 3); voxels outside the taper are copied, the
 // others take 8 x 8 x 8 taps (8 x 8 when ny = 1) with FP32 weights and sums.
 #include "sg_internal.h"
+
+#include <algorithm>
 
 namespace sg {
 
@@ -22,6 +24,7 @@ namespace {
 constexpr int kTaps = 8;
 constexpr float kBeta = 6.f;
 constexpr int kBrickZ = 16, kBrickY = 16, kBrickRows = kBrickZ * kBrickY;   // fault kernel
+constexpr int kDepositThreads = 64;   // one wave per workgroup; its contacts fill up to 64 KB of LDS
 
 // I0 by its power series sum_k ((x/2)^2)^k / (k!)^2; for x <= 6 the terms
 // after k = 16 are below 1e-10 of the sum.
@@ -203,21 +206,21 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
     out[q] = acc;
 }
 
-// Deposit (Alg. 1, boundary path): one thread per voxel of the band
-// [t][ny][nx].  The contacts are the cumulative bed thicknesses (summed in
-// FP64 in bed order), each moved by taper x a_B x its noise field and clamped
-// to the band; the voxel's bed is the number of contacts at or above it and
-// the bed starts at the deepest of those; the texture is value noise at the
-// depth below that start plus the bed's offset.
-__global__ void __launch_bounds__(256) k_deposit(DepositArgs A, float *__restrict__ out)
+// Deposit (Alg. 1, boundary path): one thread per (y, x) column, walking down
+// the band [t][ny][nx].  The contacts are the cumulative bed thicknesses
+// (summed in FP64 in bed order), each moved by taper x a_B x its noise and
+// clamped to the band; they are computed once per column into LDS (FP64,
+// [contact][lane]), and at every depth the voxel's bed is the number of
+// contacts at or above it, starting at the deepest of those; the texture is
+// value noise at the depth below that start plus the bed's offset.
+__global__ void __launch_bounds__(kDepositThreads) k_deposit(DepositArgs A, float *__restrict__ out)
 {
+    extern __shared__ double hcol[];   // [nbeds - 1][kDepositThreads]
     const int64_t plane = (int64_t)A.ny * A.nx;
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= plane * A.t) return;
-    const int iz = (int)(q / plane);
-    const int64_t col = q - (int64_t)iz * plane;
+    const int64_t col = (int64_t)blockIdx.x * kDepositThreads + threadIdx.x;
+    if (col >= plane) return;
     const int iy = (int)(col / A.nx), ix = (int)(col - (int64_t)iy * A.nx);
-    const double z = iz, t = A.t;
+    const double t = A.t;
     // taper min(d / (f_top t), 1) min((t - d) / (f_base t), 1), by reciprocals
     // (no division per contact)
     const double rt = 1.0 / (A.f_top * t), rb = 1.0 / (A.f_base * t);
@@ -225,39 +228,56 @@ __global__ void __launch_bounds__(256) k_deposit(DepositArgs A, float *__restric
     double vsum = 0.0;
     for (int k = 0; k < A.nbeds; ++k) vsum += (double)A.vbed[k];
     const double vbar = vsum / A.nbeds;
-    int bed = 0;
-    double start = 0.0, H = 0.0;
-    for (int i = 0; i + 1 < A.nbeds; ++i) {
-        H += (double)A.thick[i];
-        const double h = fmin(fmax(H + tau(H) * A.a_B * (double)A.eta_b[(int64_t)i * plane + col], 0.0), t - 1.0);
-        if (h <= z) {
-            ++bed;
-            start = fmax(start, h);
+    auto fade = [](double u) { return u * u * u * (u * (u * 6.0 - 15.0) + 10.0); };
+    auto wrap = [](double f, int g) { const int64_t i = (int64_t)f % g; return (int)(i < 0 ? i + g : i); };
+    auto L = [&](int a, int b, int c) { return (double)A.lattice[((int64_t)a * A.gy + b) * A.gx + c]; };
+    const double py = iy * A.dy * A.inv_lam_y, px = ix * A.dx * A.inv_lam_x;
+    const double fy = floor(py), fx = floor(px);
+    const double ty = fade(py - fy), tx = fade(px - fx);
+    const int y0 = wrap(fy, A.gy), x0 = wrap(fx, A.gx);
+    const int y1 = (y0 + 1) % A.gy, x1 = (x0 + 1) % A.gx;
+    {
+        double H = 0.0;
+        for (int i = 0; i + 1 < A.nbeds; ++i) {
+            H += (double)A.thick[i];
+            hcol[i * kDepositThreads + threadIdx.x] =
+                fmin(fmax(H + tau(H) * A.a_B * (double)A.eta_b[(int64_t)i * plane + col], 0.0), t - 1.0);
         }
     }
-    // texture: value noise at ((z - start) dz + offset, y dy, x dx)
-    const double pz = ((z - start) * A.dz + (double)A.tex_off[bed]) * A.inv_lam_z;
-    const double py = iy * A.dy * A.inv_lam_y, px = ix * A.dx * A.inv_lam_x;
-    const double fz = floor(pz), fy = floor(py), fx = floor(px);
-    auto fade = [](double u) { return u * u * u * (u * (u * 6.0 - 15.0) + 10.0); };
-    const double tz = fade(pz - fz), ty = fade(py - fy), tx = fade(px - fx);
-    auto wrap = [](double f, int g) { const int64_t i = (int64_t)f % g; return (int)(i < 0 ? i + g : i); };
-    const int z0 = wrap(fz, A.gz), y0 = wrap(fy, A.gy), x0 = wrap(fx, A.gx);
-    const int z1 = (z0 + 1) % A.gz, y1 = (y0 + 1) % A.gy, x1 = (x0 + 1) % A.gx;
-    auto L = [&](int a, int b, int c) { return (double)A.lattice[((int64_t)a * A.gy + b) * A.gx + c]; };
-    const double eta = (1 - tz) * ((1 - ty) * ((1 - tx) * L(z0, y0, x0) + tx * L(z0, y0, x1)) +
-                                   ty * ((1 - tx) * L(z0, y1, x0) + tx * L(z0, y1, x1))) +
-                       tz * ((1 - ty) * ((1 - tx) * L(z1, y0, x0) + tx * L(z1, y0, x1)) +
-                             ty * ((1 - tx) * L(z1, y1, x0) + tx * L(z1, y1, x1)));
-    out[q] = (float)((vbar + A.beta * z * A.dz) + tau(z) * (((double)A.vbed[bed] - vbar) + A.a_eta * eta));
+    for (int iz = 0; iz < A.t; ++iz) {
+        const double z = iz;
+        int bed = 0;
+        double start = 0.0;
+        for (int i = 0; i + 1 < A.nbeds; ++i) {
+            const double h = hcol[i * kDepositThreads + threadIdx.x];
+            if (h <= z) {
+                ++bed;
+                start = fmax(start, h);
+            }
+        }
+        // texture: value noise at ((z - start) dz + offset, y dy, x dx)
+        const double pz = ((z - start) * A.dz + (double)A.tex_off[bed]) * A.inv_lam_z;
+        const double fz = floor(pz);
+        const double tz = fade(pz - fz);
+        const int z0 = wrap(fz, A.gz), z1 = (z0 + 1) % A.gz;
+        const double eta = (1 - tz) * ((1 - ty) * ((1 - tx) * L(z0, y0, x0) + tx * L(z0, y0, x1)) +
+                                       ty * ((1 - tx) * L(z0, y1, x0) + tx * L(z0, y1, x1))) +
+                           tz * ((1 - ty) * ((1 - tx) * L(z1, y0, x0) + tx * L(z1, y0, x1)) +
+                                 ty * ((1 - tx) * L(z1, y1, x0) + tx * L(z1, y1, x1)));
+        out[(int64_t)iz * plane + col] =
+            (float)((vbar + A.beta * z * A.dz) + tau(z) * (((double)A.vbed[bed] - vbar) + A.a_eta * eta));
+    }
 }
 
 }  // namespace
 
 hipError_t launch_deposit(const DepositArgs &A, float *out, hipStream_t st)
 {
-    const int64_t n = (int64_t)A.t * A.ny * A.nx;
-    hipLaunchKernelGGL(k_deposit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, out);
+    if (A.nbeds < 1 || A.nbeds > kDepositMaxBeds) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)A.ny * A.nx;
+    const size_t lds = (size_t)std::max(A.nbeds - 1, 1) * kDepositThreads * sizeof(double);
+    hipLaunchKernelGGL(k_deposit, dim3((unsigned)((n + kDepositThreads - 1) / kDepositThreads)), dim3(kDepositThreads),
+                       lds, st, A, out);
     return hipGetLastError();
 }
 

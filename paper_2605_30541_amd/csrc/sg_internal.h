@@ -188,6 +188,7 @@ struct DepositArgs {
     double beta, a_B, a_eta, f_top, f_base;
     const float *thick, *vbed, *tex_off, *eta_b, *lattice;
 };
+constexpr int kDepositMaxBeds = 129;   // contacts of a column held in LDS (128 x 64 lanes x 8 B)
 hipError_t launch_deposit(const DepositArgs &A, float *out, hipStream_t st);
 hipError_t launch_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny, int nx, double dy,
                                   double dx, double lam_y, double lam_x, double azimuth_rad, double amplitude,

@@ -1750,6 +1750,7 @@ sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, do
         return fail(SG_EINVAL, "NULL argument");
     if (t < 1 || ny < 1 || nx < 1 || nbeds < 1 || gz < 1 || gy < 1 || gx < 1)
         return fail(SG_EINVAL, "sizes must be >= 1");
+    if (nbeds > sg::kDepositMaxBeds) return fail(SG_EINVAL, "at most %d beds per band", sg::kDepositMaxBeds);
     if ((int64_t)t * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "band too large");
     if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx) || !positive_finite(lam_z) ||
         !positive_finite(lam_y) || !positive_finite(lam_x) || !positive_finite(f_top) || !positive_finite(f_base))

@@ -232,8 +232,8 @@ def test_deposit_argument_errors_touch_nothing():
     a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
     E = sgwave.SG_EINVAL
     ok = [40, 3, 5, 5.0, 10.0, 10.0, 4, a, a, 0.5, a, 2.0, a, 2, 2, 2, 30.0, 100.0, 100.0, a, 10.0, 0.2, 0.2, b, None]
-    for i, bad in ((0, 0), (6, 0), (3, 0.0), (16, -1.0), (21, 0.0), (9, float("nan")), (7, None), (23, None),
-                   (10, None)):
+    for i, bad in ((0, 0), (6, 0), (6, 130), (3, 0.0), (16, -1.0), (21, 0.0), (9, float("nan")), (7, None),
+                   (23, None), (10, None)):
         args = list(ok)
         args[i] = bad
         assert L.sg_deposit(*args) == E, (i, bad)
