@@ -1,18 +1,20 @@
 // Velocity-model builder modules of SubsurfaceGen (arXiv 2605.30541, App. B):
 // the interbedded package of Deposit (Alg. 1), the fractal-noise displacement
-// and vertical warp of Squish (Alg. 2) and the
-// listric normal fault of Fault (Alg. 3), both pulling the model through an
-// 8-point Kaiser-windowed sinc (beta 6, weights normalised to sum 1, taps
-// clamped to the axis).  Volumes are [nz][ny][nx], x fastest.
+// and vertical warp of Squish (Alg. 2) and the listric normal fault of Fault
+// (Alg. 3); the last two pull the model through an 8-point Kaiser-windowed
+// sinc (beta 6, weights normalised to sum 1, taps clamped to the axis).
+// Volumes are [nz][ny][nx], x fastest.
 //
+// Deposit: one thread per (y, x) column of the band; the column's contacts in
+// FP64 in LDS, the texture noise in FP64.
 // Squish: one thread per (y, x) column.  The shift is constant down a column,
 // so the 8 weights are computed once and the column streams through registers
 // in blocks of 8 rows: one load and 8 FMAs per voxel (HBM-bound, 8 B per voxel
 // read + written).
-// Deposit: one thread per column of the band, contacts and texture in FP64.
-// Fault: one thread per voxel.  The pull source is computed in FP64 (the
-// frame and the angles of Alg. 3); voxels outside the taper are copied, the
-// others take 8 x 8 x 8 taps (8 x 8 when ny = 1) with FP32 weights and sums.
+// Fault: one thread per voxel, the volume walked in bricks (one XCD per
+// brick).  The pull source is computed in FP64 (the frame and the angles of
+// Alg. 3); voxels outside the taper are copied, the others take 8 x 8 x 8
+// taps (8 x 8 when ny = 1) with FP32 weights and sums.
 #include "sg_internal.h"
 
 #include <algorithm>
