@@ -229,3 +229,58 @@ def test_deposit_boundary_noise_moves_bed_contacts_within_the_band():
     assert np.all(col[1:12] == 2000.0) and np.all(col[12:22] == 2400.0)
     col = V[:, 1, 2]
     assert np.all(col[1:6] == 2000.0) and np.all(col[6:16] == 2400.0)
+
+
+def _salt(V, centres, radii, rots, grf, a, vw=0.0, minv=1, h=10.0):
+    return B.salt_sdt(V, h, h, h, centres, radii, rots, grf, a, 4500.0, vw, minv)
+
+
+def test_salt_ellipsoid_volume_and_rotation():
+    """No field: the salt is the rasterised ellipsoid (after the cleanup, which
+    a large smooth body survives up to a few boundary voxels): its volume
+    matches 4/3 pi abc; a rotation that permutes the axes permutes the radii."""
+    V = np.full((60, 60, 60), 2500.0)
+    zero = np.zeros((1, 60, 60, 60))
+    c = (295.0, 305.0, 300.0)
+    _, K = _salt(V, [c], [(200.0, 150.0, 120.0)], [np.eye(3)], zero, 0.0)
+    assert abs(K.sum() - 4 / 3 * np.pi * 20 * 15 * 12) < 0.03 * K.sum()
+    perm = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], np.float64)   # body axis 0 = world y, ...
+    _, K1 = _salt(V, [c], [(150.0, 120.0, 200.0)], [perm], zero, 0.0)
+    _, K2 = _salt(V, [c], [(200.0, 150.0, 120.0)], [np.eye(3)], zero, 0.0)
+    # perm maps world (z, y, x) offsets to body (y, x, z): radii (ry, rx, rz) = (150, 120, 200)
+    # along world (y, x, z) are the same ellipsoid as (200, 150, 120) along (z, y, x)
+    assert np.array_equal(K1, K2)
+
+
+def test_salt_constant_field_moves_the_boundary_by_amplitude_times_mean_radius():
+    """phi is a signed distance: with grf = 1 everywhere the boundary moves out
+    by amplitude * rbar, a sphere of radius R becomes one of R (1 + a)."""
+    V = np.full((64, 64, 64), 2500.0)
+    R, a = 150.0, 0.3
+    _, K = _salt(V, [(315.0, 315.0, 315.0)], [(R, R, R)], [np.eye(3)], np.ones((1, 64, 64, 64)), a)
+    vol = 4 / 3 * np.pi * (R * (1 + a) / 10.0) ** 3
+    assert abs(K.sum() - vol) < 0.03 * vol
+    _, K0 = _salt(V, [(315.0, 315.0, 315.0)], [(R, R, R)], [np.eye(3)], np.zeros((1, 64, 64, 64)), a)
+    assert K0.sum() < K.sum() and np.all(K[K0])
+
+
+def test_salt_water_small_bodies_empty_and_covering_bodies():
+    V = np.full((40, 40, 40), 2500.0)
+    V[:10] = 1500.0                                     # water layer
+    zero = np.zeros((2, 40, 40, 40))
+    big, tiny = (120.0, 120.0, 120.0), (25.0, 25.0, 25.0)
+    out, K = _salt(V, [(100.0, 200.0, 200.0), (300.0, 80.0, 80.0)], [big, tiny], [np.eye(3)] * 2, zero, 0.0,
+                   vw=1600.0, minv=100)
+    assert not K[:10].any() and np.all(out[:10] == 1500.0)     # water is never salted
+    assert K[10:20, 15:25, 15:25].any()                         # the big body below the water stays
+    assert not K[25:35, 5:12, 5:12].any()                       # the tiny one (~65 voxels) is dropped
+    assert np.all(out[K] == 4500.0) and np.all(out[~K] == V[~K])
+    # a body outside the model changes nothing; one covering it salts everything below the water
+    # except the outer one-voxel shell (the closing ends with an erosion, and outside the volume
+    # counts as empty)
+    o2, K2 = _salt(V, [(5000.0, 5000.0, 5000.0)], [big], [np.eye(3)], zero[:1], 0.0, vw=1600.0)
+    assert not K2.any() and np.array_equal(o2, V)
+    o3, K3 = _salt(V, [(200.0, 200.0, 200.0)], [(1e5, 1e5, 1e5)], [np.eye(3)], zero[:1], 0.0, vw=1600.0)
+    inner = np.zeros(V.shape, bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    assert np.array_equal(K3, inner & (V >= 1600.0))
