@@ -262,6 +262,7 @@ def builder_rate(passes=3):
     and a Deposit band of 40 beds, 200 cells at 2.5 m over the same area.
     The input is a seeded layered volume built on the device.  Algorithmic
     traffic: each voxel read and written once (8 B)."""
+    import numpy as np
     import torch
     from paper_2605_30541_amd import sgwave
     nz, ny, nx, h = 619, 1000, 1000, 10.0
@@ -313,8 +314,35 @@ def builder_rate(passes=3):
     torch.cuda.synchronize()
     ms_d = ev[0].elapsed_time(ev[1]) / passes
     del band, eta
+    # SaltSDT: three rotated ellipsoids (radii 0.8-2 km) under smooth unit-variance
+    # fields (coarse Gaussian noise, trilinearly upsampled), a = 0.15, water above 1500 m/s
+    import torch.nn.functional as F
+    nbody = 3
+    v = (1500.0 + 3.0 * z).expand(nz, ny, nx).contiguous()
+    grf = F.interpolate(torch.randn((1, nbody, 32, 48, 48), device="cuda", generator=gen), size=(nz, ny, nx),
+                        mode="trilinear", align_corners=True)[0]
+    grf = (grf / grf.flatten(1).std(dim=1)[:, None, None, None]).contiguous()
+    centres = np.array([[3000.0, 4000.0, 5000.0], [4200.0, 7000.0, 2500.0], [2000.0, 2500.0, 7500.0]])
+    radii = np.array([[1500.0, 2000.0, 1800.0], [1000.0, 1400.0, 900.0], [800.0, 900.0, 1200.0]])
+    ang = np.array([[0.3, -0.2, 0.8], [-0.5, 0.1, 0.3], [0.2, 0.4, -1.0]])
+    rots = []
+    for a, b, c in ang:
+        ca, sa, cb, sb, cc, sc = np.cos(a), np.sin(a), np.cos(b), np.sin(b), np.cos(c), np.sin(c)
+        rots.append(np.array([[1, 0, 0], [0, ca, -sa], [0, sa, ca]]) @ np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+                    @ np.array([[cc, -sc, 0], [sc, cc, 0], [0, 0, 1]]))
+    sargs = (v, h, h, h, centres, radii, np.array(rots), grf, 0.15, 4500.0, 1500.0, 1000)
+    salted, smask = sgwave.salt_sdt(*sargs)     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    salted, smask = sgwave.salt_sdt(*sargs)
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1e3
+    salt_frac = float(smask.float().mean())
+    del v, grf, salted, smask
     return {"workload": "619x1000x1000 voxels @10 m; squish 90 m max shift, 4 octaves; one fault "
                         "(R 6 km, slip 120 m, die-off 1.5 km / 4.5 km / 35 deg)",
+            "salt_bodies": nbody, "salt_ms": ms_s, "salt_Gvoxel_per_s": nvox / (ms_s / 1e3) / 1e9,
+            "salt_fraction": salt_frac,
             "squish_ms": ms_sq, "squish_Gvoxel_per_s": nvox / (ms_sq / 1e3) / 1e9,
             "squish_frac_of_hbm_peak": 8.0 * nvox / (ms_sq / 1e3) / 1e9 / HBM_PEAK_GBS,
             "fault_ms": ms_f, "fault_Gvoxel_per_s": nvox / (ms_f / 1e3) / 1e9,

@@ -437,6 +437,32 @@ typedef struct sg_fault_params {
 sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                    const sg_fault_params *p, float fill, float *out, void *stream);
 
+/* Alg. 4 (SaltSDT) on a device volume v [nz][ny][nx] (positions (z dz, y dy,
+ * x dx) in metres).  Body i (host arrays): centre centres[3i..3i+2] and radii
+ * radii[3i..3i+2] > 0 in metres as (z, y, x), rotation rotations[9i..9i+8]
+ * row-major taking world offsets to the body frame; the voxel centres with
+ * sum_k (u_k / r_k)^2 <= 1 (u = R (p - c)) form its raster.  phi = distance to
+ * the nearest voxel outside minus distance to the nearest voxel inside
+ * (exact Euclidean, metres, FP64), and K |= phi + amplitude rbar grf[i] > 0
+ * with rbar the mean radius and grf [nbodies][nz][ny][nx] device floats (the
+ * random field, e.g. a smoothed Gaussian).  A body covering no voxel adds
+ * nothing and one covering all adds all.  K is then opened and closed with
+ * the 6-neighbour cross (a voxel outside the volume counts as empty); its
+ * 6-connected components of fewer than min_voxels voxels are dropped, K is
+ * limited to v >= v_water and out = v_salt on K, v elsewhere.  mask_out
+ * [nz][ny][nx] bytes (device, may be NULL) receives K as 0/1.  ws:
+ * sg_salt_workspace_size bytes of caller-owned device scratch (256-byte
+ * aligned).  nbodies in 0..4096; nz ny nx < 2^31.  Stream-ordered (the body
+ * parameters are copied at the call; the device buffers must stay valid
+ * until the stream reaches the work).  SG_EINVAL for NULL pointers, bad sizes
+ * or non-finite or non-positive parameters and out aliasing v; SG_ENOSPACE
+ * for a short workspace. */
+sg_status sg_salt_workspace_size(int32_t nz, int32_t ny, int32_t nx, size_t *bytes);
+sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                      int32_t nbodies, const double *centres, const double *radii, const double *rotations,
+                      const float *grf, double amplitude, float v_salt, float v_water, int64_t min_voxels,
+                      float *out, uint8_t *mask_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Turn the graph replay of sg_forward and sg_batch_forward on (default) or
  * off (plain stream launches); process-wide. */
 sg_status sg_set_graphs(int32_t on);

@@ -198,6 +198,17 @@ hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, cons
 hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
                         hipStream_t st);
 
+// One salt body of Alg. 4: centre and radii in metres as (z, y, x); R row-major,
+// taking world offsets to the body frame.
+struct SaltBody {
+    double c[3], r[3], R[9];
+};
+size_t salt_workspace_bytes(int64_t nvoxels);
+// Stream-ordered; `ws` holds salt_workspace_bytes(nz * ny * nx), 256-byte aligned.
+hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, double dy, double dx, int nbodies,
+                           const SaltBody *bodies, const float *grf, double amplitude, float v_salt, float v_water,
+                           unsigned min_voxels, float *out, uint8_t *mask_out, void *ws, hipStream_t st);
+
 // Wave-equation residual of a frame stack: c_m / dz^2 and c_m / dx^2, m = 0..4.
 struct ResidualCoef {
     float cz[kHalo + 1];

@@ -1838,6 +1838,61 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
     return SG_OK;
 }
 
+namespace {
+sg_status salt_size_args(int32_t nz, int32_t ny, int32_t nx)
+{
+    if (nz < 1 || ny < 1 || nx < 1) return fail(SG_EINVAL, "nz, ny and nx must be >= 1");
+    if ((int64_t)nz * ny * nx > (int64_t)INT32_MAX) return fail(SG_EINVAL, "volume too large (at most 2^31 - 1 voxels)");
+    return SG_OK;
+}
+}  // namespace
+
+sg_status sg_salt_workspace_size(int32_t nz, int32_t ny, int32_t nx, size_t *bytes)
+{
+    if (!bytes) return fail(SG_EINVAL, "NULL argument");
+    sg_status rc = salt_size_args(nz, ny, nx);
+    if (rc != SG_OK) return rc;
+    *bytes = sg::salt_workspace_bytes((int64_t)nz * ny * nx);
+    return SG_OK;
+}
+
+sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                      int32_t nbodies, const double *centres, const double *radii, const double *rotations,
+                      const float *grf, double amplitude, float v_salt, float v_water, int64_t min_voxels,
+                      float *out, uint8_t *mask_out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!v || !out || !ws) return fail(SG_EINVAL, "NULL argument");
+    if (v == out) return fail(SG_EINVAL, "out must not alias the input volume");
+    sg_status rc = salt_size_args(nz, ny, nx);
+    if (rc != SG_OK) return rc;
+    if (nbodies < 0 || nbodies > 4096) return fail(SG_EINVAL, "nbodies must be in 0..4096");
+    if (nbodies > 0 && (!centres || !radii || !rotations || !grf)) return fail(SG_EINVAL, "NULL body argument");
+    if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx))
+        return fail(SG_EINVAL, "dz, dy and dx must be finite and > 0");
+    if (!std::isfinite(amplitude) || !std::isfinite(v_salt) || !std::isfinite(v_water))
+        return fail(SG_EINVAL, "amplitude, v_salt and v_water must be finite");
+    if (min_voxels < 0 || min_voxels > (int64_t)UINT32_MAX) return fail(SG_EINVAL, "min_voxels out of range");
+    if ((uintptr_t)ws % 256) return fail(SG_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = sg::salt_workspace_bytes((int64_t)nz * ny * nx);
+    if (ws_bytes < need) return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    std::vector<sg::SaltBody> B(nbodies);
+    for (int i = 0; i < nbodies; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            B[i].c[k] = centres[3 * i + k];
+            B[i].r[k] = radii[3 * i + k];
+            if (!std::isfinite(B[i].c[k])) return fail(SG_EINVAL, "body %d: centre must be finite", i);
+            if (!positive_finite(B[i].r[k])) return fail(SG_EINVAL, "body %d: radii must be finite and > 0", i);
+        }
+        for (int k = 0; k < 9; ++k) {
+            B[i].R[k] = rotations[9 * i + k];
+            if (!std::isfinite(B[i].R[k])) return fail(SG_EINVAL, "body %d: rotation must be finite", i);
+        }
+    }
+    SG_HIP(sg::launch_salt_sdt(v, nz, ny, nx, dz, dy, dx, nbodies, B.data(), grf, amplitude, v_salt, v_water,
+                               (unsigned)min_voxels, out, mask_out, ws, (hipStream_t)stream));
+    return SG_OK;
+}
+
 sg_status sg_set_graphs(int32_t on)
 {
     g_batch_graphs = on != 0;

@@ -134,6 +134,13 @@ _SIGS = {
     "sg_fault": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(sg_fault_params), ctypes.c_float,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_salt_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_salt_sdt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "sg_wave_residual_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "sg_wave_residual": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -493,6 +500,37 @@ def fault(v, dz: float, dy: float, dx: float, params: dict, fill: float, stream=
     out = torch.empty_like(v)
     _check(lib().sg_fault(_ptr(v), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out), _stream_ptr(stream)))
     return out
+
+
+def sg_salt_workspace_size(nz: int, ny: int, nx: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().sg_salt_workspace_size(nz, ny, nx, ctypes.byref(n)))
+    return n.value
+
+
+def salt_sdt(v, dz: float, dy: float, dx: float, centres, radii, rotations, grf, amplitude: float, v_salt: float,
+             v_water: float, min_voxels: int = 1000, stream=None):
+    """Alg. 4 on a float32 device volume v [nz, ny, nx]: centres, radii
+    [nbodies, 3] and rotations [nbodies, 3, 3] (host, metres, (z, y, x)),
+    grf [nbodies, nz, ny, nx] a float32 device tensor.  Returns (out, mask):
+    the salted volume and K as uint8."""
+    import torch
+    nz, ny, nx = v.shape
+    c = np.ascontiguousarray(centres, np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, np.float64).reshape(-1, 3)
+    R = np.ascontiguousarray(rotations, np.float64).reshape(-1, 9)
+    nb = c.shape[0]
+    if r.shape[0] != nb or R.shape[0] != nb:
+        raise ValueError("centres, radii and rotations must describe the same number of bodies")
+    if nb and tuple(grf.shape) != (nb, nz, ny, nx):
+        raise ValueError("grf must be [nbodies, nz, ny, nx]")
+    out = torch.empty_like(v)
+    mask = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
+    ws = torch.empty(sg_salt_workspace_size(nz, ny, nx), dtype=torch.uint8, device=v.device)
+    _check(lib().sg_salt_sdt(_ptr(v), nz, ny, nx, dz, dy, dx, nb, c.ctypes.data, r.ctypes.data, R.ctypes.data,
+                             _ptr(grf) if nb else None, amplitude, v_salt, v_water, min_voxels, _ptr(out),
+                             _ptr(mask), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return out, mask
 
 
 def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP_FREE, stream=None):

@@ -237,3 +237,29 @@ def test_deposit_argument_errors_touch_nothing():
         args = list(ok)
         args[i] = bad
         assert L.sg_deposit(*args) == E, (i, bad)
+
+
+def test_salt_argument_errors_touch_nothing():
+    """SaltSDT validates sizes, body parameters and the workspace before any
+    device work (fake device pointers; host body arrays are real)."""
+    L = sgwave.lib()
+    a, b, ws = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(1 << 20)
+    need = sgwave.sg_salt_workspace_size(10, 4, 6)
+    assert need >= 38 * 240
+    c = np.array([50.0, 20.0, 30.0])
+    r = np.array([20.0, 20.0, 20.0])
+    R = np.eye(3).ravel()
+    P = lambda x: x.ctypes.data
+    ok = [a, 10, 4, 6, 10.0, 10.0, 10.0, 1, P(c), P(r), P(R), a, 0.2, 4500.0, 1500.0, 10, b, None, ws, need, None]
+    r_bad, R_bad = np.array([20.0, 0.0, 20.0]), np.array([1.0, 0, 0, 0, float("nan"), 0, 0, 0, 1])
+    for i, bad in ((0, None), (16, None), (16, a), (1, 0), (7, -1), (7, 4097), (4, 0.0), (6, float("inf")),
+                   (12, float("nan")), (15, -1), (15, 1 << 33), (9, P(r_bad)), (10, P(R_bad)), (11, None),
+                   (18, ctypes.c_void_p((1 << 20) + 8))):
+        args = list(ok)
+        args[i] = bad
+        assert L.sg_salt_sdt(*args) == sgwave.SG_EINVAL, (i, bad)
+    args = list(ok)
+    args[19] = need - 1
+    assert L.sg_salt_sdt(*args) == sgwave.SG_ENOSPACE
+    n = ctypes.c_size_t(0)
+    assert L.sg_salt_workspace_size(1 << 12, 1 << 12, 1 << 8, ctypes.byref(n)) == sgwave.SG_EINVAL
