@@ -440,7 +440,8 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
 /* Alg. 4 (SaltSDT) on a device volume v [nz][ny][nx] (positions (z dz, y dy,
  * x dx) in metres).  Body i (host arrays): centre centres[3i..3i+2] and radii
  * radii[3i..3i+2] > 0 in metres as (z, y, x), rotation rotations[9i..9i+8]
- * row-major taking world offsets to the body frame; the voxel centres with
+ * row-major taking world offsets to the body frame (orthonormal: R R^T = I
+ * within 1e-7 per entry); the voxel centres with
  * sum_k (u_k / r_k)^2 <= 1 (u = R (p - c)) form its raster.  phi = distance to
  * the nearest voxel outside minus distance to the nearest voxel inside
  * (exact Euclidean, metres, FP64), and K |= phi + amplitude rbar grf[i] > 0
@@ -452,11 +453,13 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
  * limited to v >= v_water and out = v_salt on K, v elsewhere.  mask_out
  * [nz][ny][nx] bytes (device, may be NULL) receives K as 0/1.  ws:
  * sg_salt_workspace_size bytes of caller-owned device scratch (256-byte
- * aligned).  nbodies in 0..4096; nz ny nx < 2^31.  Stream-ordered (the body
- * parameters are copied at the call; the device buffers must stay valid
- * until the stream reaches the work).  SG_EINVAL for NULL pointers, bad sizes
- * or non-finite or non-positive parameters and out aliasing v; SG_ENOSPACE
- * for a short workspace. */
+ * aligned).  nbodies in 0..4096; nz ny nx < 2^31.  Synchronises the stream
+ * once: the extremes of the fields are read back to bound how far beyond its
+ * ellipsoid each body can reach, and each body's distances are computed only
+ * on that box (the result is the same as on the whole volume).  SG_EINVAL for
+ * NULL pointers, bad sizes or non-finite or non-positive parameters, a
+ * rotation that is not orthonormal and out aliasing v; SG_ENOSPACE for a short
+ * workspace. */
 sg_status sg_salt_workspace_size(int32_t nz, int32_t ny, int32_t nx, size_t *bytes);
 sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                       int32_t nbodies, const double *centres, const double *radii, const double *rotations,

@@ -203,8 +203,10 @@ hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame
 struct SaltBody {
     double c[3], r[3], R[9];
 };
+constexpr int kSaltMaxBodies = 4096;
 size_t salt_workspace_bytes(int64_t nvoxels);
-// Stream-ordered; `ws` holds salt_workspace_bytes(nz * ny * nx), 256-byte aligned.
+// Synchronises `st` once (to read the fields' extremes); `ws` holds
+// salt_workspace_bytes(nz * ny * nx), 256-byte aligned; R orthonormal.
 hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, double dy, double dx, int nbodies,
                            const SaltBody *bodies, const float *grf, double amplitude, float v_salt, float v_water,
                            unsigned min_voxels, float *out, uint8_t *mask_out, void *ws, hipStream_t st);

@@ -1865,7 +1865,8 @@ sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double
     if (v == out) return fail(SG_EINVAL, "out must not alias the input volume");
     sg_status rc = salt_size_args(nz, ny, nx);
     if (rc != SG_OK) return rc;
-    if (nbodies < 0 || nbodies > 4096) return fail(SG_EINVAL, "nbodies must be in 0..4096");
+    if (nbodies < 0 || nbodies > sg::kSaltMaxBodies)
+        return fail(SG_EINVAL, "nbodies must be in 0..%d", sg::kSaltMaxBodies);
     if (nbodies > 0 && (!centres || !radii || !rotations || !grf)) return fail(SG_EINVAL, "NULL body argument");
     if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx))
         return fail(SG_EINVAL, "dz, dy and dx must be finite and > 0");
@@ -1887,6 +1888,13 @@ sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double
             B[i].R[k] = rotations[9 * i + k];
             if (!std::isfinite(B[i].R[k])) return fail(SG_EINVAL, "body %d: rotation must be finite", i);
         }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double d = 0.0;
+                for (int k = 0; k < 3; ++k) d += B[i].R[3 * a + k] * B[i].R[3 * b + k];
+                if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-7)
+                    return fail(SG_EINVAL, "body %d: rotation must be orthonormal (R R^T = I within 1e-7)", i);
+            }
     }
     SG_HIP(sg::launch_salt_sdt(v, nz, ny, nx, dz, dy, dx, nbodies, B.data(), grf, amplitude, v_salt, v_water,
                                (unsigned)min_voxels, out, mask_out, ws, (hipStream_t)stream));

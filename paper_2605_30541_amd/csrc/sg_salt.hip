@@ -4,6 +4,8 @@
 // the model below the water.  Volumes are [nz][ny][nx], x fastest.
 //
 // Kernels, in launch order:
+//  * k_field_extremes: max(xi, 0) and max(-xi, 0) of every body's field,
+//    read back once so the host can bound each body's reach (below);
 //  * k_ellipsoid: the body raster on the voxel centres;
 //  * k_edt_x, k_edt_envelope (y, then z): the exact squared Euclidean distance
 //    to the nearest feature voxel as three separable passes.  Along x the
@@ -18,14 +20,28 @@
 //  * k_morph x4: opening then closing with the 6-neighbour cross, a voxel
 //    outside the volume counting as empty;
 //  * k_cc_init, k_cc_merge, k_cc_flatten: 6-connected components by a
-//    lock-free union-find (each salt voxel unites with its -x, -y, -z
-//    neighbours by atomicMin on the roots; then every label is pointed at its
-//    root), so each component ends labelled by its smallest voxel index;
-//  * k_cc_count, k_salt_write: component sizes (one atomic per wave when the
-//    wave's voxels share a label) and the final write.
-// Decisions (inside the ellipsoid, phi' > 0) are taken in FP64 without
-// fused multiply-adds, so they round as the plain definitions do.
+//    lock-free union-find (runs along x inside a wave are labelled by ballot;
+//    the rest is joined by atomicMin on the roots; then every label is
+//    pointed at its root), so each component ends labelled by its smallest
+//    voxel index;
+//  * k_cc_count, k_salt_write: component sizes and the final write.
+//
+// Each body is processed on boxes only.  d_out and phi' on the raster's
+// bounding box widened by B = max over the volume of (a rbar xi) plus two
+// voxels: outside it every voxel is outside the body and more than B from it,
+// so phi' < 0 and the body adds nothing there, and inside it d_out is exact
+// (every inside voxel is in the box).  d_in on the raster's bounding box plus
+// two voxels: it is needed only at inside voxels (it is 0 at outside ones),
+// and the nearest outside voxel of an inside voxel, clamped into that box, is
+// still outside and no farther.  Decisions (inside the
+// ellipsoid, phi' > 0) are taken in FP64 without fused multiply-adds, so they
+// round as the plain definitions do.
 #include "sg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #pragma clang fp contract(off)
 
@@ -34,31 +50,70 @@ namespace sg {
 namespace {
 
 constexpr int kSaltThreads = 256;
+constexpr int kRowsPerBlock = kSaltThreads / 64;
+constexpr int kCountPerThread = 32;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kSaltThreads - 1) / kSaltThreads); }
 
 __device__ inline double inf_d() { return __builtin_huge_val(); }
 
-// Voxel kernels launch ny * nz rows of xb = ceil(nx / 256) blocks each; a
+// Voxels [z0, z0 + bz) x [y0, y0 + by) x [x0, x0 + bx) of the volume.
+struct Box {
+    int z0, y0, x0, bz, by, bx;
+};
+
+inline unsigned row_blocks(const Box &b) { return (unsigned)((b.bx + kSaltThreads - 1) / kSaltThreads); }
+inline dim3 box_grid(const Box &b) { return dim3((unsigned)((int64_t)b.bz * b.by * row_blocks(b))); }
+
+// Voxel kernels launch bz * by rows of xb = ceil(bx / 256) blocks each; a
 // block covers 256 consecutive voxels of one row, so the row (and z, y) comes
-// from one division per block.  False for lanes past the end of the row.
-__device__ inline bool row_voxel(int ny, int nx, unsigned xb, int &iz, int &iy, int &ix, int64_t &q)
+// from one division per block, and each wave covers 64 voxels starting at a
+// multiple of 64 from x0.  Returns false for lanes past the end of the row.
+__device__ inline bool box_voxel(const Box &b, int ny, int nx, unsigned xb, int &iz, int &iy, int &ix, int64_t &q)
 {
     const unsigned row = blockIdx.x / xb;
-    ix = (int)((blockIdx.x - row * xb) * kSaltThreads + threadIdx.x);
-    if (ix >= nx) return false;
-    iz = (int)(row / (unsigned)ny);
-    iy = (int)(row - (unsigned)iz * (unsigned)ny);
-    q = (int64_t)row * nx + ix;
-    return true;
+    const int lx = (int)((blockIdx.x - row * xb) * kSaltThreads + threadIdx.x);
+    const unsigned lz = row / (unsigned)b.by;
+    iz = b.z0 + (int)lz;
+    iy = b.y0 + (int)(row - lz * (unsigned)b.by);
+    ix = b.x0 + lx;
+    q = ((int64_t)iz * ny + iy) * nx + ix;
+    return lx < b.bx;
 }
 
-__global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(int ny, int nx, unsigned xb, double dz, double dy,
+__device__ inline float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// ext[2 b] = max(xi_b, 0), ext[2 b + 1] = max(-xi_b, 0) as float bits (a
+// non-negative float orders as its bits); NaN values are ignored.  ext must
+// start at zero.  Body b = blockIdx.y.
+__global__ void __launch_bounds__(kSaltThreads) k_field_extremes(int64_t n, const float *grf, unsigned *ext)
+{
+    const float *xi = grf + (int64_t)blockIdx.y * n;
+    float hi = 0.0f, lo = 0.0f;
+    for (int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kSaltThreads) {
+        const float v = xi[q];
+        hi = fmaxf(hi, v);
+        lo = fmaxf(lo, -v);
+    }
+    hi = wave_max(hi);
+    lo = wave_max(lo);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&ext[2 * blockIdx.y], __float_as_uint(hi));
+        atomicMax(&ext[2 * blockIdx.y + 1], __float_as_uint(lo));
+    }
+}
+
+__global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(Box bx_, int ny, int nx, unsigned xb, double dz, double dy,
                                                             double dx, SaltBody B, uint8_t *mask)
 {
     int iz, iy, ix;
     int64_t q;
-    if (!row_voxel(ny, nx, xb, iz, iy, ix, q)) return;
+    if (!box_voxel(bx_, ny, nx, xb, iz, iy, ix, q)) return;
     const double p0 = iz * dz - B.c[0], p1 = iy * dy - B.c[1], p2 = ix * dx - B.c[2];
     double s = 0.0;
 #pragma unroll
@@ -69,121 +124,160 @@ __global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(int ny, int nx, unsi
     mask[q] = s <= 1.0;
 }
 
-// Along x, one wave per (z, y) row: g = (dx * distance in cells to the nearest
-// voxel of the row whose mask equals `feature`)^2, infinity if the row has
-// none.  The row is walked in blocks of 64 voxels, one per lane (coalesced);
-// a ballot gives the block's feature voxels, and the nearest one at or below
-// (forward walk) or at or above (backward walk) each lane comes from the
-// ballot bits, or from the carry of the blocks already walked.
-constexpr int kRowsPerBlock = kSaltThreads / 64;
-
-__global__ void __launch_bounds__(kSaltThreads) k_edt_x(int64_t rows, int nx, double dx, const uint8_t *mask,
-                                                        uint8_t feature, double *g)
+// Along x, one wave per row of the box: g = (dx * distance in cells to the
+// nearest voxel of the row segment whose mask equals the feature)^2, infinity
+// if it has none.  The segment is walked in blocks of 64 voxels, one per lane
+// (coalesced); a ballot gives the block's feature voxels, and the nearest one
+// at or below (forward walk) or at or above (backward walk) each lane comes
+// from the ballot bits, or from the carry of the blocks already walked.
+__global__ void __launch_bounds__(kSaltThreads) k_edt_x(Box b0, Box b1, int ny, int nx, double dx,
+                                                        const uint8_t *mask, double *g0, double *g1)
 {
+    // blockIdx.y = the feature value: 0 (distance to outside voxels) on box b0 into g0, 1 on b1 into g1
+    const uint8_t feature = (uint8_t)blockIdx.y;
+    double *g = blockIdx.y ? g1 : g0;
+    const Box b = blockIdx.y ? b1 : b0;
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
-    if (row >= rows) return;   // uniform over the wave
-    const uint8_t *m = mask + row * nx;
-    double *gr = g + row * nx;
+    if (row >= (int64_t)b.bz * b.by) return;   // uniform over the wave
+    const int lz = (int)(row / b.by), ly = (int)(row - (int64_t)lz * b.by);
+    const int64_t base = ((int64_t)(b.z0 + lz) * ny + (b.y0 + ly)) * nx + b.x0;
+    const uint8_t *m = mask + base;
+    double *gr = g + base;
+    const int n = b.bx;
     const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);   // bits 0..lane
     const unsigned long long from = ~0ull << lane;                                       // bits lane..63
     int carry = -1;   // last feature before the block
-    for (int x0 = 0; x0 < nx; x0 += 64) {
+    for (int x0 = 0; x0 < n; x0 += 64) {
         const int x = x0 + lane;
-        const unsigned long long b = __ballot(x < nx && m[x] == feature);
-        const unsigned long long mb = b & upto;
+        const unsigned long long bits = __ballot(x < n && m[x] == feature);
+        const unsigned long long mb = bits & upto;
         const int last = mb ? x0 + 63 - __clzll((long long)mb) : carry;
-        if (x < nx) {
+        if (x < n) {
             const double d = dx * (double)(x - last);
             gr[x] = last < 0 ? inf_d() : d * d;
         }
-        if (b) carry = x0 + 63 - __clzll((long long)b);
+        if (bits) carry = x0 + 63 - __clzll((long long)bits);
     }
     int next = -1;    // first feature after the block
-    for (int x0 = (nx - 1) / 64 * 64; x0 >= 0; x0 -= 64) {
+    for (int x0 = (n - 1) / 64 * 64; x0 >= 0; x0 -= 64) {
         const int x = x0 + lane;
-        const unsigned long long b = __ballot(x < nx && m[x] == feature);
-        const unsigned long long ma = b & from;
+        const unsigned long long bits = __ballot(x < n && m[x] == feature);
+        const unsigned long long ma = bits & from;
         const int nf = ma ? x0 + __ffsll((long long)ma) - 1 : next;
-        if (x < nx && nf >= 0) {
+        if (x < n && nf >= 0) {
             const double d = dx * (double)(nf - x);
             const double e = d * d;
             if (e < gr[x]) gr[x] = e;
         }
-        if (b) next = x0 + __ffsll((long long)b) - 1;
+        if (bits) next = x0 + __ffsll((long long)bits) - 1;
     }
 }
 
-// g(p) = min_q (w (p - q))^2 + f(q) along one line: the lower envelope of the
-// parabolas rooted at the finite samples.  axis 1: lines along y, one per
-// (z, x); axis 0: lines along z, one per (y, x); neighbouring lanes take
-// neighbouring x, so the reads of f and writes of g are coalesced.  v (int)
-// and zb (double) hold the envelope's roots and boundaries, in the volume's
-// own layout.
-__global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int nz, int ny, int nx, double w,
-                                                               const double *f, double *g, int *v, double *zb)
+// Buffers of the two distance transforms (feature 0 and 1) run side by side.
+struct EnvPair {
+    Box box[2];
+    const double *f[2];
+    double *g[2];
+    int *v[2];
+    double *zb[2];
+};
+
+// g(p) = min_q (w (p - q))^2 + f(q) along one line of the box: the lower
+// envelope of the parabolas rooted at the finite samples.  axis 1: lines
+// along y, one per (z, x); axis 0: lines along z, one per (y, x); neighbouring
+// lanes take neighbouring x, so the reads of f and writes of g are coalesced.
+// blockIdx.y picks the transform and its box.  v (int) and zb (double) hold the
+// envelope's roots and boundaries, in the volume's own layout; the top entry
+// also lives in registers (vk, hk, zk), so a sample that pops nothing reads no
+// stack memory, and f is read four samples ahead.
+__global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int ny, int nx, double w, EnvPair P)
 {
+    const Box b = P.box[blockIdx.y];
     const int64_t l = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
     const int64_t plane = (int64_t)ny * nx;
     int n;
     int64_t base, stride;
     if (axis == 1) {
-        if (l >= (int64_t)nz * nx) return;
-        const int64_t iz = l / nx, ix = l - iz * nx;
-        n = ny;
-        base = iz * plane + ix;
+        if (l >= (int64_t)b.bz * b.bx) return;
+        const int lz = (int)(l / b.bx), lx = (int)(l - (int64_t)lz * b.bx);
+        n = b.by;
+        base = ((int64_t)(b.z0 + lz) * ny + b.y0) * nx + b.x0 + lx;
         stride = nx;
     } else {
-        if (l >= plane) return;
-        n = nz;
-        base = l;
+        if (l >= (int64_t)b.by * b.bx) return;
+        const int ly = (int)(l / b.bx), lx = (int)(l - (int64_t)ly * b.bx);
+        n = b.bz;
+        base = ((int64_t)b.z0 * ny + b.y0 + ly) * nx + b.x0 + lx;
         stride = plane;
     }
+    const int t = blockIdx.y;
+    const double *f = P.f[t] + base;
+    double *g = P.g[t] + base;
+    int *v = P.v[t] + base;
+    double *zb = P.zb[t] + base;
     const double w2 = w * w;
     int k = -1;       // index of the last parabola of the envelope
-    double hk = 0.0;  // its f(v_k) + w^2 v_k^2
-    int vk = 0;
+    int vk = 0;       // its root
+    double hk = 0.0;  // f(v_k) + w^2 v_k^2
+    double zk = 0.0;  // where it starts
+    double f0 = n > 0 ? f[0] : 0.0, f1 = n > 1 ? f[stride] : 0.0, f2 = n > 2 ? f[2 * stride] : 0.0,
+           f3 = n > 3 ? f[3 * stride] : 0.0;
     for (int q = 0; q < n; ++q) {
-        const double fq = f[base + q * stride];
+        const double fq = f0;
+        f0 = f1;
+        f1 = f2;
+        f2 = f3;
+        f3 = q + 4 < n ? f[(int64_t)(q + 4) * stride] : 0.0;
         if (!(fq < inf_d())) continue;
         const double hq = fq + w2 * ((double)q * q);
         double s = 0.0;
         while (k >= 0) {
             // abscissa where parabola q starts to lie below parabola v_k
             s = (hq - hk) / (2.0 * w2 * (double)(q - vk));
-            if (k == 0 || s > zb[base + k * stride]) break;
+            if (k == 0 || s > zk) break;
             --k;
-            vk = v[base + k * stride];
-            hk = f[base + vk * stride] + w2 * ((double)vk * vk);
+            vk = v[k * stride];
+            zk = zb[k * stride];
+            hk = f[(int64_t)vk * stride] + w2 * ((double)vk * vk);
         }
         ++k;
-        v[base + k * stride] = q;
-        zb[base + k * stride] = k == 0 ? -inf_d() : s;
+        zk = k == 0 ? -inf_d() : s;
+        v[k * stride] = q;
+        zb[k * stride] = zk;
         vk = q;
         hk = hq;
     }
     if (k < 0) {
-        for (int p = 0; p < n; ++p) g[base + p * stride] = inf_d();
+        for (int p = 0; p < n; ++p) g[p * stride] = inf_d();
         return;
     }
     int j = 0;
-    int vj = v[base];
+    int vj = v[0];
+    double zn = k > 0 ? zb[stride] : inf_d();   // start of parabola j + 1
     for (int p = 0; p < n; ++p) {
-        while (j < k && zb[base + (j + 1) * stride] < (double)p) {
+        while (zn < (double)p) {
             ++j;
-            vj = v[base + j * stride];
+            vj = v[j * stride];
+            zn = j < k ? zb[(j + 1) * stride] : inf_d();
         }
         const double d = w * (double)(p - vj);
-        g[base + p * stride] = d * d + f[base + vj * stride];
+        g[p * stride] = d * d + f[(int64_t)vj * stride];
     }
 }
 
-__global__ void __launch_bounds__(kSaltThreads) k_salt_union(int64_t n, const double *din2, const double *dout2,
-                                                             const float *xi, double a_rbar, uint8_t *K)
+// Over box b (that of d_out); d_in is held on the inner box bi only and is 0
+// outside it (every voxel there is outside the body).
+__global__ void __launch_bounds__(kSaltThreads) k_salt_union(Box b, Box bi, int ny, int nx, unsigned xb,
+                                                             const double *din2, const double *dout2, const float *xi,
+                                                             double a_rbar, uint8_t *K)
 {
-    const int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
-    if (q >= n) return;
-    const double phi = sqrt(din2[q]) - sqrt(dout2[q]);
+    int iz, iy, ix;
+    int64_t q;
+    if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
+    const bool in_bi = iz >= bi.z0 && iz < bi.z0 + bi.bz && iy >= bi.y0 && iy < bi.y0 + bi.by && ix >= bi.x0 &&
+                       ix < bi.x0 + bi.bx;
+    const double phi = (in_bi ? sqrt(din2[q]) : 0.0) - sqrt(dout2[q]);
     if (phi + a_rbar * (double)xi[q] > 0.0) K[q] = 1;
 }
 
@@ -202,12 +296,12 @@ __global__ void __launch_bounds__(kSaltThreads) k_fill_u32(int64_t n, unsigned v
 // erode (op 0): set where the voxel and its six neighbours are all set;
 // dilate (op 1): set where the voxel or any neighbour is set.  A neighbour
 // outside the volume counts as empty.
-__global__ void __launch_bounds__(kSaltThreads) k_morph(int op, int nz, int ny, int nx, unsigned xb,
+__global__ void __launch_bounds__(kSaltThreads) k_morph(int op, Box b, int nz, int ny, int nx, unsigned xb,
                                                         const uint8_t *in, uint8_t *out)
 {
     int iz, iy, ix;
     int64_t q;
-    if (!row_voxel(ny, nx, xb, iz, iy, ix, q)) return;
+    if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
     const int64_t plane = (int64_t)ny * nx;
     const bool c = in[q];
     const bool zm = iz > 0 && in[q - plane], zp = iz < nz - 1 && in[q + plane];
@@ -216,13 +310,30 @@ __global__ void __launch_bounds__(kSaltThreads) k_morph(int op, int nz, int ny, 
     out[q] = op == 0 ? (c && zm && zp && ym && yp && xm && xp) : (c || zm || zp || ym || yp || xm || xp);
 }
 
-__global__ void __launch_bounds__(kSaltThreads) k_cc_init(int64_t n, const uint8_t *K, int *label)
+// k_morph on four voxels per lane (rows of a multiple of 4 voxels, so a
+// 32-bit word never straddles two rows): the voxel bytes are 0 or 1, the x
+// neighbours are the word shifted by one byte with the bytes of the adjacent
+// words filled in, and the result is a bytewise AND (erode) or OR (dilate).
+__global__ void __launch_bounds__(kSaltThreads) k_morph4(int op, int nz, int ny, int nx, unsigned xb,
+                                                         const uint8_t *in, uint8_t *out)
 {
-    const int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
-    if (q < n) label[q] = K[q] ? (int)q : -1;
+    const int nw = nx / 4;   // words per row
+    const unsigned row = blockIdx.x / xb;
+    const int lw = (int)((blockIdx.x - row * xb) * kSaltThreads + threadIdx.x);
+    if (lw >= nw) return;
+    const unsigned iz = row / (unsigned)ny, iy = row - iz * (unsigned)ny;
+    const int64_t q = (int64_t)row * nx + 4 * lw;      // first voxel of the word
+    const int64_t wq = q / 4, wplane = (int64_t)ny * nw;
+    const uint32_t *in4 = (const uint32_t *)in;
+    const uint32_t c = in4[wq];
+    const uint32_t zm = iz > 0 ? in4[wq - wplane] : 0u, zp = (int)iz < nz - 1 ? in4[wq + wplane] : 0u;
+    const uint32_t ym = iy > 0 ? in4[wq - nw] : 0u, yp = (int)iy < ny - 1 ? in4[wq + nw] : 0u;
+    const uint32_t left = lw > 0 ? in[q - 1] : 0u, right = lw < nw - 1 ? in[q + 4] : 0u;
+    const uint32_t xm = (c << 8) | left, xp = (c >> 8) | (right << 24);
+    ((uint32_t *)out)[wq] = op == 0 ? (c & zm & zp & ym & yp & xm & xp) : (c | zm | zp | ym | yp | xm | xp);
 }
 
-// Labels form a forest: label[x] <= x for every salt voxel, a root has
+// Labels form a forest over the salt voxels: label[x] <= x, a root has
 // label[r] == r, and every label names a voxel of the same component.  Labels
 // only ever decrease (atomicMin), so a chain strictly decreases and find ends;
 // a stale read returns an older ancestor, which is still an ancestor.
@@ -238,7 +349,7 @@ __device__ inline int find_root(const int *label, int x)
 // Link the roots of a and b, the larger under the smaller.  atomicMin returns
 // the previous value: equal to the root means linked; otherwise that root had
 // been linked meanwhile and the loop continues from its (smaller) parent.
-// Every retry lowers a or b, so the loop ends; no thread waits on another.
+// Every retry lowers a + b, so the loop ends; no thread waits on another.
 __device__ inline void unite(int *label, int a, int b)
 {
     for (;;) {
@@ -256,17 +367,39 @@ __device__ inline void unite(int *label, int a, int b)
     }
 }
 
-__global__ void __launch_bounds__(kSaltThreads) k_cc_merge(int ny, int nx, unsigned xb, const uint8_t *K,
+// Initial forest: a salt voxel points at the first voxel of its run along x
+// within its wave's 64 voxels (from the ballot); others get -1.
+__global__ void __launch_bounds__(kSaltThreads) k_cc_init(Box b, int ny, int nx, unsigned xb, const uint8_t *K,
+                                                          int *label)
+{
+    int iz, iy, ix;
+    int64_t q;
+    const bool valid = box_voxel(b, ny, nx, xb, iz, iy, ix, q);
+    const bool set = valid && K[q];
+    const unsigned long long bits = __ballot(set);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
+    const unsigned long long gaps = ~bits & upto;
+    const int start = gaps ? 64 - __clzll((long long)gaps) : 0;   // one past the last gap at or below the lane
+    if (valid) label[q] = set ? (int)(q - (lane - start)) : -1;
+}
+
+// Joins the runs: across a wave boundary along x, and along -y and -z unless
+// the voxel's left neighbour and that neighbour's own -y (-z) neighbour are
+// both salt, in which case the left neighbour's join (or one further left)
+// already connects the two runs.
+__global__ void __launch_bounds__(kSaltThreads) k_cc_merge(Box b, int ny, int nx, unsigned xb, const uint8_t *K,
                                                            int *label)
 {
     int iz, iy, ix;
     int64_t q;
-    if (!row_voxel(ny, nx, xb, iz, iy, ix, q)) return;
+    if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
     if (!K[q]) return;
     const int64_t plane = (int64_t)ny * nx;
-    if (ix > 0 && K[q - 1]) unite(label, (int)q, (int)(q - 1));
-    if (iy > 0 && K[q - nx]) unite(label, (int)q, (int)(q - nx));
-    if (iz > 0 && K[q - plane]) unite(label, (int)q, (int)(q - plane));
+    const bool left = ix > 0 && K[q - 1];
+    if (left && (threadIdx.x & 63) == 0) unite(label, (int)q, (int)(q - 1));
+    if (iy > 0 && K[q - nx] && !(left && K[q - 1 - nx])) unite(label, (int)q, (int)(q - nx));
+    if (iz > 0 && K[q - plane] && !(left && K[q - 1 - plane])) unite(label, (int)q, (int)(q - plane));
 }
 
 // After the merge has finished: every label becomes its root.  Only the
@@ -279,20 +412,60 @@ __global__ void __launch_bounds__(kSaltThreads) k_cc_flatten(int64_t n, int *lab
     if (l >= 0 && l != (int)q) label[q] = find_root(label, l);
 }
 
+// Component sizes: each thread counts runs of equal labels over
+// kCountPerThread consecutive voxels and adds each run to a small table of
+// (label, count) in LDS (linear probing by atomicCAS on the label slot); the
+// table goes to memory with one atomic per distinct label per workgroup, and
+// runs that find the table full go straight to memory.
+constexpr int kCountSlots = 32;
+
 __global__ void __launch_bounds__(kSaltThreads) k_cc_count(int64_t n, const int *label, unsigned *count)
 {
-    const int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
-    const int l = q < n ? label[q] : -1;
-    const unsigned long long set = __ballot(l >= 0);
-    if (!set) return;
-    const int lead = __ffsll((long long)set) - 1;
-    const int l_lead = __shfl(l, lead);
-    const unsigned long long same = __ballot(l == l_lead);
-    if (same == set) {
-        if ((int)(threadIdx.x & 63) == lead) atomicAdd(&count[l_lead], (unsigned)__popcll(set));
-    } else if (l >= 0) {
-        atomicAdd(&count[l], 1u);
+    __shared__ int tl[kCountSlots];
+    __shared__ unsigned tc[kCountSlots];
+    if (threadIdx.x < kCountSlots) {
+        tl[threadIdx.x] = -1;
+        tc[threadIdx.x] = 0u;
     }
+    __syncthreads();
+    auto add = [&](int l, unsigned c) {
+        for (int i = 0; i < kCountSlots; ++i) {
+            const int slot = (l + i) & (kCountSlots - 1);
+            const int old = atomicCAS(&tl[slot], -1, l);
+            if (old == -1 || old == l) {
+                atomicAdd(&tc[slot], c);
+                return;
+            }
+        }
+        atomicAdd(&count[l], c);
+    };
+    const int64_t q0 = ((int64_t)blockIdx.x * kSaltThreads + threadIdx.x) * kCountPerThread;
+    int cur = -1;
+    unsigned cnt = 0;
+    auto step = [&](int l) {
+        if (l != cur) {
+            if (cur >= 0) add(cur, cnt);
+            cur = l;
+            cnt = 0;
+        }
+        ++cnt;
+    };
+    if (q0 + kCountPerThread <= n) {
+        const int4 *p4 = (const int4 *)(label + q0);
+#pragma unroll
+        for (int i = 0; i < kCountPerThread / 4; ++i) {
+            const int4 w = p4[i];
+            step(w.x);
+            step(w.y);
+            step(w.z);
+            step(w.w);
+        }
+    } else {
+        for (int i = 0; i < kCountPerThread; ++i) step(q0 + i < n ? label[q0 + i] : -1);
+    }
+    if (cur >= 0) add(cur, cnt);
+    __syncthreads();
+    if (threadIdx.x < kCountSlots && tl[threadIdx.x] >= 0) atomicAdd(&count[tl[threadIdx.x]], tc[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(kSaltThreads) k_salt_write(int64_t n, const float *v, const int *label,
@@ -310,9 +483,10 @@ __global__ void __launch_bounds__(kSaltThreads) k_salt_write(int64_t n, const fl
 }
 
 struct SaltWorkspace {
-    double *din, *dout, *f, *zb;
-    int *v;
+    double *din, *dout, *f[2], *zb[2];
+    int *v[2];
     uint8_t *K, *m;
+    unsigned *ext;
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -321,70 +495,132 @@ SaltWorkspace carve(void *ws, int64_t n)
 {
     char *p = (char *)ws;
     SaltWorkspace W{};
-    W.din = (double *)p;
-    p += align256(8 * (size_t)n);
-    W.dout = (double *)p;
-    p += align256(8 * (size_t)n);
-    W.f = (double *)p;
-    p += align256(8 * (size_t)n);
-    W.zb = (double *)p;
-    p += align256(8 * (size_t)n);
-    W.v = (int *)p;
-    p += align256(4 * (size_t)n);
+    double **d8[6] = {&W.din, &W.dout, &W.f[0], &W.f[1], &W.zb[0], &W.zb[1]};
+    for (double **d : d8) {
+        *d = (double *)p;
+        p += align256(8 * (size_t)n);
+    }
+    for (int t = 0; t < 2; ++t) {
+        W.v[t] = (int *)p;
+        p += align256(4 * (size_t)n);
+    }
     W.K = (uint8_t *)p;
     p += align256((size_t)n);
     W.m = (uint8_t *)p;
+    p += align256((size_t)n);
+    W.ext = (unsigned *)p;
     return W;
+}
+
+// Index range [lo, hi] along one axis of spacing h and n voxels covering
+// centre +- reach (metres) plus two voxels; false if it misses the axis.
+bool axis_range(double centre, double reach, double h, int n, int &lo, int &hi)
+{
+    if (!std::isfinite(reach)) {
+        lo = 0;
+        hi = n - 1;
+        return true;
+    }
+    const double a = std::floor((centre - reach) / h) - 2.0, b = std::ceil((centre + reach) / h) + 2.0;
+    if (b < 0.0 || a > n - 1.0) return false;
+    lo = a < 0.0 ? 0 : (int)a;
+    hi = b > n - 1.0 ? n - 1 : (int)b;
+    return true;
 }
 
 }  // namespace
 
 size_t salt_workspace_bytes(int64_t n)
 {
-    return 4 * align256(8 * (size_t)n) + align256(4 * (size_t)n) + 2 * align256((size_t)n);
+    return 6 * align256(8 * (size_t)n) + 2 * align256(4 * (size_t)n) + 2 * align256((size_t)n) +
+           align256(2 * sizeof(unsigned) * kSaltMaxBodies);
 }
 
 hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, double dy, double dx, int nbodies,
                            const SaltBody *bodies, const float *grf, double amplitude, float v_salt, float v_water,
                            unsigned min_voxels, float *out, uint8_t *mask_out, void *ws, hipStream_t st)
 {
-    const int64_t plane = (int64_t)ny * nx, n = plane * nz;
+    const int64_t n = (int64_t)nz * ny * nx;
     const SaltWorkspace W = carve(ws, n);
     const dim3 blk(kSaltThreads);
-    const unsigned xb = (unsigned)((nx + kSaltThreads - 1) / kSaltThreads);
-    const dim3 vox((unsigned)((int64_t)nz * ny * xb));
+    const Box whole{0, 0, 0, nz, ny, nx};
+    const unsigned xw = row_blocks(whole);
+    hipError_t e;
     hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(n)), blk, 0, st, n, (uint8_t)0, W.K);
-    for (int b = 0; b < nbodies; ++b) {
-        const SaltBody &B = bodies[b];
-        hipLaunchKernelGGL(k_ellipsoid, vox, blk, 0, st, ny, nx, xb, dz, dy, dx, B, W.m);
-        // d_in: distance to the nearest voxel outside (feature 0); d_out: to the nearest inside (feature 1)
-        for (int which = 0; which < 2; ++which) {
-            double *D = which == 0 ? W.din : W.dout;
-            const int64_t rows = (int64_t)nz * ny;
-            hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock)), blk, 0, st,
-                               rows, nx, dx, (const uint8_t *)W.m, (uint8_t)which, D);
-            hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)nz * nx)), blk, 0, st, 1, nz, ny, nx, dy,
-                               (const double *)D, W.f, W.v, W.zb);
-            hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for(plane)), blk, 0, st, 0, nz, ny, nx, dz,
-                               (const double *)W.f, D, W.v, W.zb);
-        }
+    std::vector<unsigned> ext(2 * (size_t)nbodies, 0u);
+    if (nbodies > 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * nbodies)), blk, 0, st, (int64_t)2 * nbodies, 0u, W.ext);
+        const unsigned per_body = std::min(blocks_for(n), 1024u);
+        hipLaunchKernelGGL(k_field_extremes, dim3(per_body, nbodies), blk, 0, st, n, grf, W.ext);
+        if ((e = hipMemcpyAsync(ext.data(), W.ext, ext.size() * sizeof(unsigned), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    }
+    for (int i = 0; i < nbodies; ++i) {
+        const SaltBody &B = bodies[i];
         const double rbar = (B.r[0] + B.r[1] + B.r[2]) / 3.0;
-        hipLaunchKernelGGL(k_salt_union, dim3(blocks_for(n)), blk, 0, st, n, (const double *)W.din,
-                           (const double *)W.dout, grf + (int64_t)b * n, amplitude * rbar, W.K);
+        float hi, lo;
+        std::memcpy(&hi, &ext[2 * i], sizeof hi);
+        std::memcpy(&lo, &ext[2 * i + 1], sizeof lo);
+        // largest a rbar xi over the volume: how far beyond the raster the body can reach
+        const double reach = std::max(0.0, amplitude >= 0 ? amplitude * rbar * hi : -amplitude * rbar * lo);
+        // half extent of the rotated ellipsoid along world axis j: |column j of R^T diag(r)|
+        const double h[3] = {dz, dy, dx};
+        const int nn[3] = {nz, ny, nx};
+        // bo: the raster's box widened by the reach (where the body can add salt, and d_out is needed);
+        // bi: the raster's box alone (d_in is needed only at inside voxels)
+        int lo_o[3], hi_o[3], lo_n[3], hi_n[3];
+        bool hit = true;
+        for (int j = 0; j < 3 && hit; ++j) {
+            double e2 = 0.0;
+            for (int k = 0; k < 3; ++k) e2 += (B.R[3 * k + j] * B.r[k]) * (B.R[3 * k + j] * B.r[k]);
+            const double ext = std::sqrt(e2) * (1.0 + 1e-6);
+            hit = axis_range(B.c[j], ext, h[j], nn[j], lo_n[j], hi_n[j]) &&
+                  axis_range(B.c[j], ext + reach, h[j], nn[j], lo_o[j], hi_o[j]);
+        }
+        if (!hit) continue;   // the raster misses the volume: the body adds nothing
+        const Box bo{lo_o[0], lo_o[1], lo_o[2], hi_o[0] - lo_o[0] + 1, hi_o[1] - lo_o[1] + 1, hi_o[2] - lo_o[2] + 1};
+        const Box bi{lo_n[0], lo_n[1], lo_n[2], hi_n[0] - lo_n[0] + 1, hi_n[1] - lo_n[1] + 1, hi_n[2] - lo_n[2] + 1};
+        const unsigned xb = row_blocks(bo);
+        hipLaunchKernelGGL(k_ellipsoid, box_grid(bo), blk, 0, st, bo, ny, nx, xb, dz, dy, dx, B, W.m);
+        // d_in: distance to the nearest voxel outside (feature 0, on bi); d_out: to the nearest inside
+        // (feature 1, on bo); both transforms run in the same launches (blockIdx.y), sized for bo
+        const int64_t rows = (int64_t)bo.bz * bo.by;
+        hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock), 2), blk, 0, st, bi,
+                           bo, ny, nx, dx, (const uint8_t *)W.m, W.din, W.dout);
+        const EnvPair along_y{{bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
+        const EnvPair along_z{{bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
+        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, ny, nx, dy,
+                           along_y);
+        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.by * bo.bx), 2), blk, 0, st, 0, ny, nx, dz,
+                           along_z);
+        hipLaunchKernelGGL(k_salt_union, box_grid(bo), blk, 0, st, bo, bi, ny, nx, xb, (const double *)W.din,
+                           (const double *)W.dout, grf + (int64_t)i * n, amplitude * rbar, W.K);
     }
     // opening (erode, dilate) then closing (dilate, erode), ping-ponging K and m
-    hipLaunchKernelGGL(k_morph, vox, blk, 0, st, 0, nz, ny, nx, xb, (const uint8_t *)W.K, W.m);
-    hipLaunchKernelGGL(k_morph, vox, blk, 0, st, 1, nz, ny, nx, xb, (const uint8_t *)W.m, W.K);
-    hipLaunchKernelGGL(k_morph, vox, blk, 0, st, 1, nz, ny, nx, xb, (const uint8_t *)W.K, W.m);
-    hipLaunchKernelGGL(k_morph, vox, blk, 0, st, 0, nz, ny, nx, xb, (const uint8_t *)W.m, W.K);
+    const dim3 gw = box_grid(whole);
+    const int ops[4] = {0, 1, 1, 0};
+    for (int i = 0; i < 4; ++i) {
+        const uint8_t *src = i % 2 ? W.m : W.K;
+        uint8_t *dst = i % 2 ? W.K : W.m;
+        if (nx % 4 == 0) {
+            const unsigned xb4 = (unsigned)((nx / 4 + kSaltThreads - 1) / kSaltThreads);
+            hipLaunchKernelGGL(k_morph4, dim3((unsigned)((int64_t)nz * ny * xb4)), blk, 0, st, ops[i], nz, ny, nx,
+                               xb4, src, dst);
+        } else {
+            hipLaunchKernelGGL(k_morph, gw, blk, 0, st, ops[i], whole, nz, ny, nx, xw, src, dst);
+        }
+    }
     // components: labels in d_in's storage, sizes in d_out's
     int *label = (int *)W.din;
     unsigned *count = (unsigned *)W.dout;
-    hipLaunchKernelGGL(k_cc_init, dim3(blocks_for(n)), blk, 0, st, n, (const uint8_t *)W.K, label);
-    hipLaunchKernelGGL(k_cc_merge, vox, blk, 0, st, ny, nx, xb, (const uint8_t *)W.K, label);
+    hipLaunchKernelGGL(k_cc_init, gw, blk, 0, st, whole, ny, nx, xw, (const uint8_t *)W.K, label);
+    hipLaunchKernelGGL(k_cc_merge, gw, blk, 0, st, whole, ny, nx, xw, (const uint8_t *)W.K, label);
     hipLaunchKernelGGL(k_cc_flatten, dim3(blocks_for(n)), blk, 0, st, n, label);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), blk, 0, st, n, 0u, count);
-    hipLaunchKernelGGL(k_cc_count, dim3(blocks_for(n)), blk, 0, st, n, (const int *)label, count);
+    hipLaunchKernelGGL(k_cc_count, dim3(blocks_for((n + kCountPerThread - 1) / kCountPerThread)), blk, 0, st, n,
+                       (const int *)label, count);
     hipLaunchKernelGGL(k_salt_write, dim3(blocks_for(n)), blk, 0, st, n, v, (const int *)label,
                        (const unsigned *)count, min_voxels, v_salt, v_water, out, mask_out);
     return hipGetLastError();

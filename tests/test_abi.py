@@ -252,8 +252,10 @@ def test_salt_argument_errors_touch_nothing():
     P = lambda x: x.ctypes.data
     ok = [a, 10, 4, 6, 10.0, 10.0, 10.0, 1, P(c), P(r), P(R), a, 0.2, 4500.0, 1500.0, 10, b, None, ws, need, None]
     r_bad, R_bad = np.array([20.0, 0.0, 20.0]), np.array([1.0, 0, 0, 0, float("nan"), 0, 0, 0, 1])
+    R_skew = np.array([1.0, 0, 0, 0, 1.001, 0, 0, 0, 1])
     for i, bad in ((0, None), (16, None), (16, a), (1, 0), (7, -1), (7, 4097), (4, 0.0), (6, float("inf")),
-                   (12, float("nan")), (15, -1), (15, 1 << 33), (9, P(r_bad)), (10, P(R_bad)), (11, None),
+                   (12, float("nan")), (15, -1), (15, 1 << 33), (9, P(r_bad)), (10, P(R_bad)), (10, P(R_skew)),
+                   (11, None),
                    (18, ctypes.c_void_p((1 << 20) + 8))):
         args = list(ok)
         args[i] = bad

@@ -136,3 +136,21 @@ def test_tiny_slice_and_wide_volumes(shape):
         assert K.sum() > 0
     assert np.array_equal(mask, K)
     assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_field_reaching_far_from_the_body(sign):
+    """Each body's distances are computed on its ellipsoid's box widened by
+    the largest a rbar xi; a field spike far from the body (a 6-voxel cube
+    where a rbar xi exceeds the distance to the body) must still salt that
+    cube's core, for either sign of the amplitude."""
+    shape, h = (30, 40, 90), (10.0, 10.0, 10.0)
+    V = _model(shape, 8)
+    grf = (0.3 * _field(1, shape, 2.0, 9)).astype(np.float32)
+    grf[0, 20:26, 30:36, 75:81] = 200.0 * sign
+    c, r = [(120.0, 100.0, 150.0)], [(60.0, 50.0, 70.0)]
+    got, mask, ref, K = _run(V, h, c, r, [_rot(0.3, 0.2, 0.1)], grf, 0.2 * sign, 4500.0, 0.0, 20)
+    _report("far field, sign %+d" % sign, mask, K)
+    assert K[21:25, 31:35, 76:80].all()     # the cube's core (opening trims its edges)
+    assert np.array_equal(mask, K)
+    assert np.array_equal(got, ref.astype(np.float32))
