@@ -7,10 +7,10 @@
 //  * k_field_extremes: max(xi, 0) and max(-xi, 0) of every body's field,
 //    read back once so the host can bound each body's reach (below);
 //  * k_ellipsoid: the body raster on the voxel centres;
-//  * k_edt_x, k_edt_envelope (y, then z): the exact squared Euclidean distance
+//  * k_edt_x, k_edt_envelope (z, then y): the exact squared Euclidean distance
 //    to the nearest feature voxel as three separable passes.  Along x the
 //    distance to the nearest feature of the row (the 1D transform of a
-//    0/infinity function), one wave per row; along y and z the lower envelope
+//    0/infinity function), one wave per row; along z and y the lower envelope
 //    of parabolas in FP64, one thread per line (Felzenszwalb and
 //    Huttenlocher's 1D transform; the paper names Meijster's algorithm, which
 //    yields the same exact distances);
@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(Box bx_, int ny, int
 
 // Along x, one wave per row of the box: g = (dx * distance in cells to the
 // nearest voxel of the row segment whose mask equals the feature)^2, infinity
-// if it has none.  The segment is walked in blocks of 64 voxels, one per lane
+// if it has none, written in the box-local layout [y][z][x] (rows stay
+// contiguous, so the transposition is free and the z pass reads short strides).  The segment is walked in blocks of 64 voxels, one per lane
 // (coalesced); a ballot gives the block's feature voxels, and the nearest one
 // at or below (forward walk) or at or above (backward walk) each lane comes
 // from the ballot bits, or from the carry of the blocks already walked.
@@ -141,9 +142,8 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_x(Box b0, Box b1, int ny, 
     const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
     if (row >= (int64_t)b.bz * b.by) return;   // uniform over the wave
     const int lz = (int)(row / b.by), ly = (int)(row - (int64_t)lz * b.by);
-    const int64_t base = ((int64_t)(b.z0 + lz) * ny + (b.y0 + ly)) * nx + b.x0;
-    const uint8_t *m = mask + base;
-    double *gr = g + base;
+    const uint8_t *m = mask + ((int64_t)(b.z0 + lz) * ny + (b.y0 + ly)) * nx + b.x0;
+    double *gr = g + ((int64_t)ly * b.bz + lz) * b.bx;   // box-local [y][z][x]
     const int n = b.bx;
     const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);   // bits 0..lane
     const unsigned long long from = ~0ull << lane;                                       // bits lane..63
@@ -184,36 +184,43 @@ struct EnvPair {
 };
 
 // g(p) = min_q (w (p - q))^2 + f(q) along one line of the box: the lower
-// envelope of the parabolas rooted at the finite samples.  axis 1: lines
-// along y, one per (z, x); axis 0: lines along z, one per (y, x); neighbouring
-// lanes take neighbouring x, so the reads of f and writes of g are coalesced.
+// envelope of the parabolas rooted at the finite samples.  Box-local layouts:
+// axis 0, lines along z, one per (y, x), read [y][z][x] and write [z][y][x];
+// axis 1, lines along y, one per (z, x), in [z][y][x].  Samples of a line are
+// one row (bx values) apart; neighbouring lanes take neighbouring x, so the
+// reads of f and writes of g are coalesced.
 // blockIdx.y picks the transform and its box.  v (int) and zb (double) hold the
-// envelope's roots and boundaries, in the volume's own layout; the top entry
+// envelope's roots and boundaries, in the layout of f; the top entry
 // also lives in registers (vk, hk, zk), so a sample that pops nothing reads no
 // stack memory, and f is read four samples ahead.
 __global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int ny, int nx, double w, EnvPair P)
 {
     const Box b = P.box[blockIdx.y];
     const int64_t l = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
-    const int64_t plane = (int64_t)ny * nx;
     int n;
-    int64_t base, stride;
+    int64_t base, stride, obase, ostride;
     if (axis == 1) {
+        // along y in [z][y][x], in place of layout
         if (l >= (int64_t)b.bz * b.bx) return;
         const int lz = (int)(l / b.bx), lx = (int)(l - (int64_t)lz * b.bx);
         n = b.by;
-        base = ((int64_t)(b.z0 + lz) * ny + b.y0) * nx + b.x0 + lx;
-        stride = nx;
+        base = (int64_t)lz * b.by * b.bx + lx;
+        stride = b.bx;
+        obase = base;
+        ostride = stride;
     } else {
+        // along z: read [y][z][x], write [z][y][x]
         if (l >= (int64_t)b.by * b.bx) return;
         const int ly = (int)(l / b.bx), lx = (int)(l - (int64_t)ly * b.bx);
         n = b.bz;
-        base = ((int64_t)b.z0 * ny + b.y0 + ly) * nx + b.x0 + lx;
-        stride = plane;
+        base = (int64_t)ly * b.bz * b.bx + lx;
+        stride = b.bx;
+        obase = (int64_t)ly * b.bx + lx;
+        ostride = (int64_t)b.by * b.bx;
     }
     const int t = blockIdx.y;
     const double *f = P.f[t] + base;
-    double *g = P.g[t] + base;
+    double *g = P.g[t] + obase;
     int *v = P.v[t] + base;
     double *zb = P.zb[t] + base;
     const double w2 = w * w;
@@ -249,7 +256,7 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int ny,
         hk = hq;
     }
     if (k < 0) {
-        for (int p = 0; p < n; ++p) g[p * stride] = inf_d();
+        for (int p = 0; p < n; ++p) g[p * ostride] = inf_d();
         return;
     }
     int j = 0;
@@ -262,12 +269,13 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int ny,
             zn = j < k ? zb[(j + 1) * stride] : inf_d();
         }
         const double d = w * (double)(p - vj);
-        g[p * stride] = d * d + f[(int64_t)vj * stride];
+        g[p * ostride] = d * d + f[(int64_t)vj * stride];
     }
 }
 
 // Over box b (that of d_out); d_in is held on the inner box bi only and is 0
-// outside it (every voxel there is outside the body).
+// outside it (every voxel there is outside the body).  Both distance arrays
+// are box-local [z][y][x].
 __global__ void __launch_bounds__(kSaltThreads) k_salt_union(Box b, Box bi, int ny, int nx, unsigned xb,
                                                              const double *din2, const double *dout2, const float *xi,
                                                              double a_rbar, uint8_t *K)
@@ -275,9 +283,11 @@ __global__ void __launch_bounds__(kSaltThreads) k_salt_union(Box b, Box bi, int 
     int iz, iy, ix;
     int64_t q;
     if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
-    const bool in_bi = iz >= bi.z0 && iz < bi.z0 + bi.bz && iy >= bi.y0 && iy < bi.y0 + bi.by && ix >= bi.x0 &&
-                       ix < bi.x0 + bi.bx;
-    const double phi = (in_bi ? sqrt(din2[q]) : 0.0) - sqrt(dout2[q]);
+    const int iz_i = iz - bi.z0, iy_i = iy - bi.y0, ix_i = ix - bi.x0;
+    const bool in_bi = iz_i >= 0 && iz_i < bi.bz && iy_i >= 0 && iy_i < bi.by && ix_i >= 0 && ix_i < bi.bx;
+    const double di = in_bi ? sqrt(din2[((int64_t)iz_i * bi.by + iy_i) * bi.bx + ix_i]) : 0.0;
+    const double dout = sqrt(dout2[((int64_t)(iz - b.z0) * b.by + (iy - b.y0)) * b.bx + (ix - b.x0)]);
+    const double phi = di - dout;
     if (phi + a_rbar * (double)xi[q] > 0.0) K[q] = 1;
 }
 
@@ -589,12 +599,13 @@ hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, do
         const int64_t rows = (int64_t)bo.bz * bo.by;
         hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock), 2), blk, 0, st, bi,
                            bo, ny, nx, dx, (const uint8_t *)W.m, W.din, W.dout);
-        const EnvPair along_y{{bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
-        const EnvPair along_z{{bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
-        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, ny, nx, dy,
-                           along_y);
+        // then along z (box-local [y][z][x] -> [z][y][x]) and along y (in [z][y][x])
+        const EnvPair along_z{{bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
+        const EnvPair along_y{{bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
         hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.by * bo.bx), 2), blk, 0, st, 0, ny, nx, dz,
                            along_z);
+        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, ny, nx, dy,
+                           along_y);
         hipLaunchKernelGGL(k_salt_union, box_grid(bo), blk, 0, st, bo, bi, ny, nx, xb, (const double *)W.din,
                            (const double *)W.dout, grf + (int64_t)i * n, amplitude * rbar, W.K);
     }

@@ -1,0 +1,126 @@
+"""Builder modules at the paper's model shape, 619 x 1000 x 1000 voxels at
+10 m, checked against the FP64 oracle where it can follow: Squish on sampled
+columns (the warp acts per column) with the whole 1000 x 1000 displacement;
+Fault on a full-depth crop (the fault geometry moves with the crop origin;
+voxels whose sinc taps would reach past the crop are left out); SaltSDT on a
+crop that holds every voxel the bodies can reach (outside it the bodies add
+nothing, so the crop's own edges do not matter), bit-exact."""
+import numpy as np
+import pytest
+
+from oracle import builder as OB
+from paper_2605_30541_amd import sgwave
+
+pytestmark = pytest.mark.gpu
+NZ, NY, NX, H = 619, 1000, 1000, 10.0
+TOL = 1e-5
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def model():
+    """A layered volume with a lateral trend and a 3-cell water layer (numpy,
+    float32), and its device copy."""
+    import torch
+    z = np.arange(NZ, dtype=np.float32)[:, None, None]
+    y = np.arange(NY, dtype=np.float32)[None, :, None]
+    x = np.arange(NX, dtype=np.float32)[None, None, :]
+    lateral = (40.0 * np.sin(x / 37.0) * np.cos(y / 53.0)).astype(np.float32)
+    V = 1600.0 + 4.0 * z + lateral + 150.0 * np.remainder(np.floor(z / 12.0), 3.0).astype(np.float32)
+    V = np.ascontiguousarray(V, np.float32)
+    V[:3] = 1500.0
+    print("model built", flush=True)
+    return V, torch.from_numpy(V).cuda()
+
+
+def test_squish_full_size_sampled_columns(model):
+    import torch
+    V, Vd = model
+    rng = np.random.default_rng(21)
+    lat = rng.uniform(-1, 1, (4, 8, 8)).astype(np.float32)
+    args = (NY, NX, H, H, 2500.0, 4000.0, 20.0, 90.0)
+    shift_d = sgwave.fractal_noise2d(torch.from_numpy(lat).cuda(), *args)
+    out_d = sgwave.squish(Vd, H, shift_d)
+    torch.cuda.synchronize()
+    shift_ref = OB.fractal_noise2d(lat.astype(np.float64), *args)
+    e_shift = np.abs(shift_d.cpu().numpy() - shift_ref).max() / 90.0
+    cols = [(int(a), int(b)) for a, b in zip(rng.integers(0, NY, 200), rng.integers(0, NX, 200))]
+    cols += [(0, 0), (NY - 1, NX - 1), (0, NX - 1)]
+    got = np.stack([out_d[:, yy, xx].cpu().numpy() for yy, xx in cols], axis=1).astype(np.float64)
+    ref = np.stack([OB.squish(V[:, yy:yy + 1, xx:xx + 1], H, shift_ref[yy:yy + 1, xx:xx + 1])[:, 0, 0]
+                    for yy, xx in cols], axis=1)
+    e = rel_l2(got, ref)
+    print("squish full size: shift max err / amplitude %.2e, %d columns rel-L2 %.2e" % (e_shift, len(cols), e),
+          flush=True)
+    assert e_shift <= TOL and e <= TOL
+
+
+def test_fault_full_size_crop(model):
+    import torch
+    V, Vd = model
+    p = dict(cz=3000.0, cy=5000.0, cx=5000.0, azimuth_deg=30.0, dip_deg=60.0, radius=6000.0, slip=120.0,
+             direction=1, die_r=1500.0, die_strike=4500.0, die_theta_deg=35.0)
+    out_d = sgwave.fault(Vd, H, H, H, p, 1480.0)
+    torch.cuda.synchronize()
+    y0, x0, c = 470, 520, 36
+    got = out_d[:, y0:y0 + c, x0:x0 + c].cpu().numpy().astype(np.float64)
+    pc = dict(p, cy=p["cy"] - y0 * H, cx=p["cx"] - x0 * H)
+    crop = V[:, y0:y0 + c, x0:x0 + c]
+    ref = OB.fault(crop, H, H, H, pc, 1480.0)
+    (sz, sy, sx), w = OB.fault_source(crop.shape, H, H, H, pc)
+    sy, sx = sy / H, sx / H
+    keep = (w == 0) | ((np.floor(sy) >= 3) & (np.floor(sy) <= c - 5) & (np.floor(sx) >= 3) & (np.floor(sx) <= c - 5))
+    moved = int(np.count_nonzero(keep & (w > 0)))
+    e = rel_l2(got[keep], ref[keep])
+    print("fault full size: crop %dx%dx%d at (y %d, x %d), %d moved voxels compared, rel-L2 %.2e"
+          % (NZ, c, c, y0, x0, moved, e), flush=True)
+    assert moved > 100000
+    assert e <= TOL
+    assert np.array_equal(got[keep & (w == 0)], crop.astype(np.float64)[keep & (w == 0)])
+
+
+def test_salt_full_size_crop(model):
+    import torch
+    V, Vd = model
+    rng = np.random.default_rng(33)
+    # a smooth separable field: sums of three random sinusoids per axis, scaled to max |xi| <= 1.5
+    def axis_part(n, h):
+        t = np.arange(n) * h
+        k = rng.uniform(2 * np.pi / 3000.0, 2 * np.pi / 600.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        return (np.sin(t[:, None] * k + ph).sum(axis=1) / 6.0).astype(np.float32)
+    fz, fy, fx = axis_part(NZ, H), axis_part(NY, H), axis_part(NX, H)
+    xi = (fz[:, None, None] + fy[None, :, None] + fx[None, None, :]).astype(np.float32)
+    centres = np.array([[2000.0, 3000.0, 3000.0], [2600.0, 3450.0, 3300.0]])
+    radii = np.array([[350.0, 300.0, 420.0], [250.0, 280.0, 230.0]])
+    a1, a2 = 0.4, -0.7
+    rots = np.array([[[1, 0, 0], [0, np.cos(a1), -np.sin(a1)], [0, np.sin(a1), np.cos(a1)]],
+                     [[np.cos(a2), 0, np.sin(a2)], [0, 1, 0], [-np.sin(a2), 0, np.cos(a2)]]])
+    amp = 0.15
+    xid = torch.from_numpy(xi).cuda()
+    grf_d = torch.stack([xid, xid])
+    out_d, mask_d = sgwave.salt_sdt(Vd, H, H, H, centres, radii, rots, grf_d, amp, 4500.0, 1500.0, 1000)
+    torch.cuda.synchronize()
+    # every voxel the bodies can reach: within max radius + amp * rbar * max|xi| of a centre, plus margin
+    reach = radii.max() + amp * radii.mean(axis=1).max() * float(np.abs(xi).max()) + 60.0
+    lo = np.floor((centres.min(axis=0) - reach) / H).astype(int)
+    hi = np.ceil((centres.max(axis=0) + reach) / H).astype(int) + 1
+    lo, hi = np.maximum(lo, 0), np.minimum(hi, [NZ, NY, NX])
+    sl = tuple(slice(a, b) for a, b in zip(lo, hi))
+    crop_v = V[sl].astype(np.float64)
+    ref, K = OB.salt_sdt(crop_v, H, H, H, centres - lo * H, radii, rots,
+                         np.stack([xi[sl], xi[sl]]).astype(np.float64), amp, 4500.0, 1500.0, 1000)
+    mask = mask_d.cpu().numpy().astype(bool)
+    inside = np.zeros(mask.shape, bool)
+    inside[sl] = True
+    print("salt full size: crop %s, %d salt voxels, %d mismatched, %d salt outside the crop"
+          % (tuple(hi - lo), K.sum(), int((mask[sl] != K).sum()), int(mask[~inside].sum())), flush=True)
+    assert K.sum() > 100000
+    assert np.array_equal(mask[sl], K)
+    assert not mask[~inside].any()
+    out = out_d.cpu().numpy()
+    assert np.array_equal(out[sl], ref.astype(np.float32))
+    assert np.array_equal(out[~inside], V[~inside])
