@@ -24,6 +24,8 @@ namespace sg {
 namespace {
 
 constexpr int kTaps = 8;
+// four floats at any 4-byte-aligned address (one 16-byte load)
+typedef float Float4u __attribute__((ext_vector_type(4), aligned(4)));
 constexpr float kBeta = 6.f;
 constexpr int kBrickZ = 16, kBrickY = 16, kBrickRows = kBrickZ * kBrickY;   // fault kernel
 constexpr int kDepositThreads = 64;   // one wave per workgroup; its contacts fill up to 64 KB of LDS
@@ -183,24 +185,36 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
     int jx[kTaps];
 #pragma unroll
     for (int c = 0; c < kTaps; ++c) jx[c] = min(max(x0 + c, 0), nx - 1);
+    // away from the row ends the 8 x taps are consecutive: two 16-byte loads
+    const bool x_inner = x0 >= 0 && x0 + kTaps <= nx;
+    auto row_taps = [&](const float *row) {
+        float s = 0.f;
+        if (x_inner) {
+            const Float4u lo = *(const Float4u *)(row + x0), hi = *(const Float4u *)(row + x0 + 4);
+            s = fmaf(wx[0], lo.x, s);
+            s = fmaf(wx[1], lo.y, s);
+            s = fmaf(wx[2], lo.z, s);
+            s = fmaf(wx[3], lo.w, s);
+            s = fmaf(wx[4], hi.x, s);
+            s = fmaf(wx[5], hi.y, s);
+            s = fmaf(wx[6], hi.z, s);
+            s = fmaf(wx[7], hi.w, s);
+        } else {
+#pragma unroll
+            for (int c = 0; c < kTaps; ++c) s = fmaf(wx[c], row[jx[c]], s);
+        }
+        return s;
+    };
     float acc = 0.f;
     for (int a = 0; a < kTaps; ++a) {
         const int jz = min(max(z0 + a, 0), nz - 1);
         float accy = 0.f;
         if (ny == 1) {
-            const float *row = v + (int64_t)jz * plane;
-            float s = 0.f;
-#pragma unroll
-            for (int c = 0; c < kTaps; ++c) s = fmaf(wx[c], row[jx[c]], s);
-            accy = s;   // the y weights sum to 1 on a one-row axis
+            accy = row_taps(v + (int64_t)jz * plane);   // the y weights sum to 1 on a one-row axis
         } else {
             for (int b = 0; b < kTaps; ++b) {
                 const int jy = min(max(y0 + b, 0), ny - 1);
-                const float *row = v + (int64_t)jz * plane + (int64_t)jy * nx;
-                float s = 0.f;
-#pragma unroll
-                for (int c = 0; c < kTaps; ++c) s = fmaf(wx[c], row[jx[c]], s);
-                accy = fmaf(wy[b], s, accy);
+                accy = fmaf(wy[b], row_taps(v + (int64_t)jz * plane + (int64_t)jy * nx), accy);
             }
         }
         acc = fmaf(wz[a], accy, acc);
