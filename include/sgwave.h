@@ -437,6 +437,16 @@ typedef struct sg_fault_params {
 sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                    const sg_fault_params *p, float fill, float *out, void *stream);
 
+/* Alg. 3 for integer fields such as layer labels (the module resamples them
+ * by nearest neighbour): the same fault and pull source as sg_fault, with
+ * out(voxel) = labels at the voxel nearest the source (floor(s + 0.5) per axis
+ * in cell units, y and x clamped to the volume), `fill` where the source depth
+ * lies above depth 0 or at/below nz cells, the label itself outside the
+ * taper.  labels and out [nz][ny][nx] int32 (device), out must not alias
+ * labels.  Same argument errors as sg_fault. */
+sg_status sg_fault_labels(const int32_t *labels, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                          const sg_fault_params *p, int32_t fill, int32_t *out, void *stream);
+
 /* Alg. 4 (SaltSDT) on a device volume v [nz][ny][nx] (positions (z dz, y dy,
  * x dx) in metres).  Body i (host arrays): centre centres[3i..3i+2] and radii
  * radii[3i..3i+2] > 0 in metres as (z, y, x), rotation rotations[9i..9i+8]

@@ -1,8 +1,9 @@
-"""FP64 reference of two velocity-model builder modules of SubsurfaceGen
-(arXiv 2605.30541, App. B): Squish (Alg. 2, vertical warping by a fractal-noise
-displacement) and Fault (Alg. 3, one listric normal fault as a tapered
-rotation about a horizontal cylinder), both pull-sampling the model with a
-windowed sinc.
+"""FP64 reference of the velocity-model builder modules of SubsurfaceGen
+(arXiv 2605.30541, App. B): Deposit (Alg. 1, interbedded band), Squish
+(Alg. 2, vertical warping by a fractal-noise displacement), Fault (Alg. 3, one
+listric normal fault as a tapered rotation about a horizontal cylinder; sinc
+pull for velocities, nearest-neighbour pull for labels) and SaltSDT (Alg. 4,
+salt bodies from perturbed signed distances).
 
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU
 baseline use it; it shares no code with the HIP library.
@@ -164,6 +165,25 @@ def fault(V, dz: float, dy: float, dx: float, p: dict, fill: float):
     sz, sy, sx = sz / dz, sy / dy, sx / dx
     out = sinc_sample_3d(V, sz, sy, sx)
     out[(sz < 0) | (sz >= V.shape[0])] = fill
+    return out
+
+
+def fault_labels(L, dz: float, dy: float, dx: float, p: dict, fill: int):
+    """Alg. 3 for integer fields (layer labels), which the module resamples by
+    nearest neighbour: the voxel nearest each pull source of fault_source
+    (floor(s + 0.5) cells per axis, y and x clamped to the volume); `fill`
+    where the source depth falls outside [0, nz) cells; voxels outside the
+    taper keep their label."""
+    L = np.asarray(L)
+    nz, ny, nx = L.shape
+    (sz, sy, sx), w = fault_source(L.shape, dz, dy, dx, p)
+    sz, sy, sx = sz / dz, sy / dy, sx / dx
+    iz = np.minimum(np.floor(np.where((sz >= 0) & (sz < nz), sz, 0.0) + 0.5), nz - 1).astype(np.int64)
+    iy = np.clip(np.floor(sy + 0.5), 0, ny - 1).astype(np.int64)
+    ix = np.clip(np.floor(sx + 0.5), 0, nx - 1).astype(np.int64)
+    out = L[iz, iy, ix]
+    out = np.where(w == 0, L, out)
+    out[(w != 0) & ((sz < 0) | (sz >= nz))] = fill
     return out
 
 

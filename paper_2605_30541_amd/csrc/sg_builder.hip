@@ -129,27 +129,14 @@ __global__ void __launch_bounds__(256) k_squish(const float *__restrict__ v, int
     }
 }
 
-__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, FaultFrame F,
-                                               float fill, float *__restrict__ out)
+// Alg. 3's pull source of voxel (iz, iy, ix) in fractional cell indices.
+// Returns kFaultStill outside the taper (w = 0: the source is the voxel),
+// kFaultFill where the source depth leaves [0, nz), else kFaultMoved.
+constexpr int kFaultStill = 0, kFaultMoved = 1, kFaultFill = 2;
+
+__device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, int ix, double &sz, double &sy,
+                                   double &sx)
 {
-    // The volume is cut in bricks of kBrickZ x kBrickY rows of 256 columns,
-    // one workgroup per row.  Workgroups go to the 8 XCDs in turn; here all
-    // rows of a brick go to one XCD (the rows its voxels sample are then
-    // fetched into one L2) and the bricks are dealt round-robin (the moved
-    // region of a fault stays spread over the XCDs).
-    const int bx_n = (nx + 255) / 256, by_n = (ny + kBrickY - 1) / kBrickY;
-    const int64_t nbrick = (int64_t)bx_n * by_n * ((nz + kBrickZ - 1) / kBrickZ);
-    const int64_t t = blockIdx.x / 8;
-    const int64_t brick = (t / kBrickRows) * 8 + blockIdx.x % 8;
-    if (brick >= nbrick) return;
-    const int row = (int)(t % kBrickRows);
-    const int bx = (int)(brick % bx_n);
-    const int64_t rest = brick / bx_n;
-    const int by = (int)(rest % by_n), bz = (int)(rest / by_n);
-    const int iz = bz * kBrickZ + row / kBrickY, iy = by * kBrickY + row % kBrickY, ix = bx * 256 + threadIdx.x;
-    if (iz >= nz || iy >= ny || ix >= nx) return;
-    const int64_t plane = (int64_t)ny * nx;
-    const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
     const double Z = iz * F.dz, Y = iy * F.dy, X = ix * F.dx;
     const double qy = Y - F.cy, qx = X - F.cx, vv = Z - F.cz;
     const double h = qy * F.n_y + qx * F.n_x;
@@ -159,10 +146,7 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
     const double rho_r = fabs(r - F.radius) * F.inv_die_r;
     const double rho_t = fabs(t_old - F.theta0) * F.inv_die_t;
     const double rho_s = fabs(az) * F.inv_die_s;
-    if (!(rho_r < 1.0 && rho_t < 1.0 && rho_s < 1.0)) {   // w = 0: the source is the voxel itself
-        out[q] = v[q];
-        return;
-    }
+    if (!(rho_r < 1.0 && rho_t < 1.0 && rho_s < 1.0)) return kFaultStill;
     const double half_pi = 1.5707963267948966;
     const double wt = cos(half_pi * rho_r) * cos(half_pi * rho_t) * cos(half_pi * rho_s);
     const double chi = r >= F.radius ? 1.0 : -1.0;
@@ -170,8 +154,48 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
     // p_fwd - p in the (h, v) plane, exactly 0 where the rotation is 0
     const double mid = t_old + 0.5 * dth, hs = sin(0.5 * dth);
     const double dh = -2.0 * r * sin(mid) * hs, dv = 2.0 * r * cos(mid) * hs;
-    const double sz = (Z - dv) * F.inv_dz, sy = (Y - dh * F.n_y) * F.inv_dy, sx = (X - dh * F.n_x) * F.inv_dx;
-    if (!(sz >= 0.0 && sz < (double)nz)) {
+    sz = (Z - dv) * F.inv_dz;
+    sy = (Y - dh * F.n_y) * F.inv_dy;
+    sx = (X - dh * F.n_x) * F.inv_dx;
+    return sz >= 0.0 && sz < (double)nz ? kFaultMoved : kFaultFill;
+}
+
+// The volume is cut in bricks of kBrickZ x kBrickY rows of 256 columns, one
+// workgroup per row.  Workgroups go to the 8 XCDs in turn; here all rows of a
+// brick go to one XCD (the rows its voxels sample are then fetched into one
+// L2) and the bricks are dealt round-robin (the moved region of a fault stays
+// spread over the XCDs).  False for threads past the volume.
+__device__ inline bool brick_voxel(int nz, int ny, int nx, int &iz, int &iy, int &ix)
+{
+    const int bx_n = (nx + 255) / 256, by_n = (ny + kBrickY - 1) / kBrickY;
+    const int64_t nbrick = (int64_t)bx_n * by_n * ((nz + kBrickZ - 1) / kBrickZ);
+    const int64_t t = blockIdx.x / 8;
+    const int64_t brick = (t / kBrickRows) * 8 + blockIdx.x % 8;
+    if (brick >= nbrick) return false;
+    const int row = (int)(t % kBrickRows);
+    const int bx = (int)(brick % bx_n);
+    const int64_t rest = brick / bx_n;
+    const int by = (int)(rest % by_n), bz = (int)(rest / by_n);
+    iz = bz * kBrickZ + row / kBrickY;
+    iy = by * kBrickY + row % kBrickY;
+    ix = bx * 256 + threadIdx.x;
+    return iz < nz && iy < ny && ix < nx;
+}
+
+__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, FaultFrame F,
+                                               float fill, float *__restrict__ out)
+{
+    int iz, iy, ix;
+    if (!brick_voxel(nz, ny, nx, iz, iy, ix)) return;
+    const int64_t plane = (int64_t)ny * nx;
+    const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
+    double sz, sy, sx;
+    const int kind = fault_source(F, nz, iz, iy, ix, sz, sy, sx);
+    if (kind == kFaultStill) {   // w = 0: the source is the voxel itself
+        out[q] = v[q];
+        return;
+    }
+    if (kind == kFaultFill) {
         out[q] = fill;
         return;
     }
@@ -220,6 +244,32 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
         acc = fmaf(wz[a], accy, acc);
     }
     out[q] = acc;
+}
+
+// Alg. 3 for integer fields (e.g. layer labels): the same pull source,
+// sampled at the nearest voxel (floor(s + 0.5) per axis; y and x clamped to
+// the volume); `fill` where the source depth leaves [0, nz).
+__global__ void __launch_bounds__(256) k_fault_labels(const int32_t *__restrict__ lab, int nz, int ny, int nx,
+                                                      FaultFrame F, int32_t fill, int32_t *__restrict__ out)
+{
+    int iz, iy, ix;
+    if (!brick_voxel(nz, ny, nx, iz, iy, ix)) return;
+    const int64_t plane = (int64_t)ny * nx;
+    const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
+    double sz, sy, sx;
+    const int kind = fault_source(F, nz, iz, iy, ix, sz, sy, sx);
+    if (kind == kFaultStill) {
+        out[q] = lab[q];
+        return;
+    }
+    if (kind == kFaultFill) {
+        out[q] = fill;
+        return;
+    }
+    const int jz = min((int)floor(sz + 0.5), nz - 1);
+    const int jy = (int)fmin(fmax(floor(sy + 0.5), 0.0), (double)(ny - 1));
+    const int jx = (int)fmin(fmax(floor(sx + 0.5), 0.0), (double)(nx - 1));
+    out[q] = lab[(int64_t)jz * plane + (int64_t)jy * nx + jx];
 }
 
 // Deposit (Alg. 1, boundary path): one thread per (y, x) column, walking down
@@ -326,6 +376,16 @@ hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame
     const int64_t blocks = (nbrick + 7) / 8 * 8 * kBrickRows;
     if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, F, fill, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fault_labels(const int32_t *lab, int nz, int ny, int nx, const FaultFrame &F, int32_t fill,
+                               int32_t *out, hipStream_t st)
+{
+    const int64_t nbrick = (int64_t)((nx + 255) / 256) * ((ny + kBrickY - 1) / kBrickY) * ((nz + kBrickZ - 1) / kBrickZ);
+    const int64_t blocks = (nbrick + 7) / 8 * 8 * kBrickRows;
+    if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fault_labels, dim3((unsigned)blocks), dim3(256), 0, st, lab, nz, ny, nx, F, fill, out);
     return hipGetLastError();
 }
 

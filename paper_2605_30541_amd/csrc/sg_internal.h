@@ -197,6 +197,8 @@ hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, cons
                          hipStream_t st);
 hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
                         hipStream_t st);
+hipError_t launch_fault_labels(const int32_t *lab, int nz, int ny, int nx, const FaultFrame &F, int32_t fill,
+                               int32_t *out, hipStream_t st);
 
 // One salt body of Alg. 4: centre and radii in metres as (z, y, x); R row-major,
 // taking world offsets to the body frame.

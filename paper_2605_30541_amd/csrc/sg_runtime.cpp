@@ -1796,11 +1796,10 @@ sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double d
     return SG_OK;
 }
 
-sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
-                   const sg_fault_params *p, float fill, float *out, void *stream)
+namespace {
+// Validates the fault parameters and spacings and builds the device frame.
+sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx, sg::FaultFrame &F)
 {
-    sg_status rc = volume_args(v, nz, ny, nx, out);
-    if (rc != SG_OK) return rc;
     if (!p) return fail(SG_EINVAL, "NULL argument");
     if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx))
         return fail(SG_EINVAL, "dz, dy and dx must be finite and > 0");
@@ -1812,7 +1811,7 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
         return fail(SG_EINVAL, "radius and die-off extents must be finite and > 0");
     if (p->direction != 1 && p->direction != -1) return fail(SG_EINVAL, "direction must be +1 or -1");
     const double a = p->azimuth_deg * kPi / 180.0, th = p->dip_deg * kPi / 180.0, R = p->radius;
-    sg::FaultFrame F{};
+    F = sg::FaultFrame{};
     F.dz = dz;
     F.dy = dy;
     F.dx = dx;
@@ -1834,7 +1833,29 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
     F.inv_die_r = 1.0 / p->die_r;
     F.inv_die_t = 1.0 / (p->die_theta_deg * kPi / 180.0);
     F.inv_die_s = 1.0 / p->die_strike;
+    return SG_OK;
+}
+}  // namespace
+
+sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                   const sg_fault_params *p, float fill, float *out, void *stream)
+{
+    sg_status rc = volume_args(v, nz, ny, nx, out);
+    if (rc != SG_OK) return rc;
+    sg::FaultFrame F;
+    if ((rc = fault_frame(p, dz, dy, dx, F)) != SG_OK) return rc;
     SG_HIP(sg::launch_fault(v, nz, ny, nx, F, fill, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_fault_labels(const int32_t *labels, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                          const sg_fault_params *p, int32_t fill, int32_t *out, void *stream)
+{
+    sg_status rc = volume_args(labels, nz, ny, nx, out);
+    if (rc != SG_OK) return rc;
+    sg::FaultFrame F;
+    if ((rc = fault_frame(p, dz, dy, dx, F)) != SG_OK) return rc;
+    SG_HIP(sg::launch_fault_labels(labels, nz, ny, nx, F, fill, out, (hipStream_t)stream));
     return SG_OK;
 }
 

@@ -108,12 +108,12 @@ __global__ void __launch_bounds__(kSaltThreads) k_field_extremes(int64_t n, cons
     }
 }
 
-__global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(Box bx_, int ny, int nx, unsigned xb, double dz, double dy,
+__global__ void __launch_bounds__(kSaltThreads) k_ellipsoid(Box b, int ny, int nx, unsigned xb, double dz, double dy,
                                                             double dx, SaltBody B, uint8_t *mask)
 {
     int iz, iy, ix;
     int64_t q;
-    if (!box_voxel(bx_, ny, nx, xb, iz, iy, ix, q)) return;
+    if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
     const double p0 = iz * dz - B.c[0], p1 = iy * dy - B.c[1], p2 = ix * dx - B.c[2];
     double s = 0.0;
 #pragma unroll
@@ -193,7 +193,7 @@ struct EnvPair {
 // envelope's roots and boundaries, in the layout of f; the top entry
 // also lives in registers (vk, hk, zk), so a sample that pops nothing reads no
 // stack memory, and f is read four samples ahead.
-__global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, int ny, int nx, double w, EnvPair P)
+__global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, double w, EnvPair P)
 {
     const Box b = P.box[blockIdx.y];
     const int64_t l = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
@@ -602,10 +602,8 @@ hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, do
         // then along z (box-local [y][z][x] -> [z][y][x]) and along y (in [z][y][x])
         const EnvPair along_z{{bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
         const EnvPair along_y{{bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
-        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.by * bo.bx), 2), blk, 0, st, 0, ny, nx, dz,
-                           along_z);
-        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, ny, nx, dy,
-                           along_y);
+        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.by * bo.bx), 2), blk, 0, st, 0, dz, along_z);
+        hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, dy, along_y);
         hipLaunchKernelGGL(k_salt_union, box_grid(bo), blk, 0, st, bo, bi, ny, nx, xb, (const double *)W.din,
                            (const double *)W.dout, grf + (int64_t)i * n, amplitude * rbar, W.K);
     }

@@ -141,6 +141,10 @@ _SIGS = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "sg_fault_labels": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(sg_fault_params), ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "sg_wave_residual_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "sg_wave_residual": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -531,6 +535,19 @@ def salt_sdt(v, dz: float, dy: float, dx: float, centres, radii, rotations, grf,
                              _ptr(grf) if nb else None, amplitude, v_salt, v_water, min_voxels, _ptr(out),
                              _ptr(mask), _ptr(ws), ws.numel(), _stream_ptr(stream)))
     return out, mask
+
+
+def fault_labels(labels, dz: float, dy: float, dx: float, params: dict, fill: int, stream=None):
+    """int32 device labels [nz, ny, nx] through one listric normal fault,
+    nearest-neighbour pull; params holds the fields of sg_fault_params."""
+    import torch
+    nz, ny, nx = labels.shape
+    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
+                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    out = torch.empty_like(labels)
+    _check(lib().sg_fault_labels(_ptr(labels), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out),
+                                 _stream_ptr(stream)))
+    return out
 
 
 def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP_FREE, stream=None):

@@ -222,6 +222,11 @@ def test_builder_argument_errors_touch_nothing():
     p = sgwave.sg_fault_params(**good)
     assert L.sg_fault(a, 10, 2, 3, 10.0, -1.0, 10.0, ctypes.byref(p), 0.0, b, None) == E
     assert L.sg_fault(a, 10, 2, 3, 10.0, 10.0, 10.0, None, 0.0, b, None) == E
+    assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 10.0, ctypes.byref(p), 0, a, None) == E   # aliasing
+    assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 0.0, ctypes.byref(p), 0, b, None) == E
+    assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 10.0, None, 0, b, None) == E
+    bad = sgwave.sg_fault_params(**dict(good, direction=2))
+    assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 10.0, ctypes.byref(bad), 0, b, None) == E
     assert L.sg_fractal_noise2d(a, 0, 4, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 4, 4, 10, 10, 10.0, 10.0, 0.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 0, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E

@@ -123,3 +123,41 @@ def test_deposit_matches_the_oracle(case):
     e = rel_l2(got, ref)
     print("%s: deposit rel-L2 %.2e" % (case, e), flush=True)
     assert e <= TOL
+
+
+def _near_half(s):
+    return np.abs(s - np.floor(s) - 0.5) < 1e-9
+
+
+@pytest.mark.parametrize("case", ["3d", "3d-reverse", "2d-slice", "through-top", "steep-oblique"])
+def test_fault_labels_match_the_oracle(case):
+    """Nearest-neighbour pull of an int32 label volume: equal to the oracle
+    everywhere except, possibly, where a source coordinate sits on a .5 tie
+    (there either neighbour is nearest); there the GPU label must be one of
+    the two."""
+    import torch
+    nz, ny, nx, p = 48, 24, 56, dict(FAULT)
+    if case == "3d-reverse":
+        p["direction"] = -1
+    elif case == "2d-slice":
+        ny, p["cy"], p["azimuth_deg"] = 1, 0.0, 0.0
+    elif case == "through-top":
+        p.update(cz=20.0, slip=140.0, die_r=400.0, die_strike=600.0, die_theta_deg=60.0)
+    elif case == "steep-oblique":
+        p.update(azimuth_deg=-70.0, dip_deg=80.0, radius=3000.0, slip=70.0, die_theta_deg=10.0)
+    z = np.arange(nz)[:, None, None]
+    x = np.arange(nx)[None, None, :]
+    L = (np.floor((z + 3.0 * np.sin(x / 11.0)) / 5.0) * 7 + np.zeros((1, ny, 1))).astype(np.int32)
+    L += np.arange(ny, dtype=np.int32)[None, :, None] * 1000
+    got = sgwave.fault_labels(torch.from_numpy(L).cuda(), 10.0, 10.0, 10.0, p, -1).cpu().numpy()
+    ref = OB.fault_labels(L, 10.0, 10.0, 10.0, p, -1)
+    (sz, sy, sx), w = OB.fault_source(L.shape, 10.0, 10.0, 10.0, p)
+    tie = _near_half(sz / 10.0) | _near_half(sy / 10.0) | _near_half(sx / 10.0)
+    diff = got != ref
+    changed = int(np.count_nonzero(ref != L))
+    print("%s: %d labels changed by the fault, %d differ from the oracle (%d at .5 ties)"
+          % (case, changed, int(diff.sum()), int((diff & tie).sum())), flush=True)
+    assert changed > 50
+    assert not (diff & ~tie).any()
+    if case == "through-top":
+        assert np.count_nonzero(ref == -1) > 0

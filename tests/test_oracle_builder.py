@@ -284,3 +284,33 @@ def test_salt_water_small_bodies_empty_and_covering_bodies():
     inner = np.zeros(V.shape, bool)
     inner[1:-1, 1:-1, 1:-1] = True
     assert np.array_equal(K3, inner & (V >= 1600.0))
+
+
+def test_fault_labels_take_the_voxel_nearest_the_source():
+    """Nearest-neighbour pull of integer fields: each moved voxel gets the label
+    of the voxel centre nearest its source (brute force over all centres, the
+    y and x sources past the volume landing on its faces), fill where the
+    source depth leaves the volume, its own label outside the taper."""
+    shape, h = (12, 7, 9), 10.0
+    L = np.arange(np.prod(shape), dtype=np.int64).reshape(shape)    # every label unique
+    p = dict(cz=30.0, cy=30.0, cx=40.0, azimuth_deg=20.0, dip_deg=55.0, radius=300.0, slip=35.0, direction=1,
+             die_r=150.0, die_strike=200.0, die_theta_deg=60.0)
+    out = B.fault_labels(L, h, h, h, p, -1)
+    (sz, sy, sx), w = B.fault_source(shape, h, h, h, p)
+    sz, sy, sx = sz / h, sy / h, sx / h
+    Z, Y, X = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    moved = fill = 0
+    for idx in zip(*np.nonzero(w > 0)):
+        s = np.array([sz[idx], sy[idx], sx[idx]])
+        if not 0.0 <= s[0] < shape[0]:
+            assert out[idx] == -1
+            fill += 1
+            continue
+        d = (Z - s[0]) ** 2 + (Y - s[1]) ** 2 + (X - s[2]) ** 2
+        best = np.argmin(d)
+        if np.sort(d.ravel())[1] - d.ravel()[best] > 1e-9:      # no tie
+            assert out[idx] == L.ravel()[best], idx
+            moved += 1
+    assert moved > 100 and fill > 0
+    assert np.array_equal(out[w == 0], L[w == 0])
+    assert np.array_equal(B.fault_labels(L, h, h, h, dict(p, slip=0.0), -1), L)
