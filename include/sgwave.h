@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 1
+#define SG_ABI_VERSION 2
 
 typedef int32_t sg_status;
 enum {
@@ -433,6 +433,20 @@ typedef struct sg_fault_params {
     double die_r;           /* die-off across the fault [m] */
     double die_strike;      /* die-off along strike [m] */
     double die_theta_deg;   /* die-off in angle about the axis [deg] */
+    /* Optional rough fault surface (the module perturbs the fault radius with
+     * fractal noise): with rough_lattice non-NULL the surface lies at radius
+     * R + rough_amplitude N(u, w), N = normalised fractal value noise as in
+     * sg_fractal_noise2d (octave o: lattice o, frequency 2^o, weight 2^-o, sum
+     * divided by sum_o 2^-o, so |N| <= max |lattice|) at u = along-strike
+     * offset / rough_lam_strike and w = R (theta - theta0) / rough_lam_dip
+     * (down-dip arc length).  It moves the side test (chi) and the
+     * across-fault taper; the rotation stays slip / R.  rough_lattice:
+     * device floats [rough_noct][rough_gd][rough_gs] (rows down dip, columns
+     * along strike), rough_noct in 1..24, rough_gd, rough_gs >= 1, lam > 0. */
+    const float *rough_lattice;
+    int32_t rough_noct, rough_gd, rough_gs;
+    double rough_amplitude; /* [m] */
+    double rough_lam_strike, rough_lam_dip; /* [m] */
 } sg_fault_params;
 sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                    const sg_fault_params *p, float fill, float *out, void *stream);

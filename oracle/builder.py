@@ -87,8 +87,19 @@ def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: floa
     X = np.arange(nx)[None, :] * dx
     u = (X * math.cos(a) + Y * math.sin(a)) / lam_x      # along the azimuth
     w = (-X * math.sin(a) + Y * math.cos(a)) / lam_y     # across it
+    return amplitude * fractal_value(lattice, u, w)
+
+
+def fractal_value(lattice, u, w):
+    """Normalised fractal value noise at lattice coordinates (u, w) (arrays of
+    one shape; u runs along the lattice's columns): per octave o a periodic
+    lattice [gy, gx] sampled with a quintic fade at (u, w) * 2^o, weight 2^-o;
+    the sum divided by sum_o 2^-o, so the result lies within the lattice's range."""
+    lattice = np.asarray(lattice, np.float64)
+    noct, gy, gx = lattice.shape
+    u, w = np.asarray(u, np.float64), np.asarray(w, np.float64)
     fade = lambda t: t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
-    total = np.zeros((ny, nx))
+    total = np.zeros(np.broadcast(u, w).shape)
     norm = 0.0
     for o in range(noct):
         f = 2.0 ** o
@@ -104,7 +115,7 @@ def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: floa
         n = (v00 * (1 - tu) + v01 * tu) * (1 - tw) + (v10 * (1 - tu) + v11 * tu) * tw
         total += n / f
         norm += 1.0 / f
-    return amplitude * total / norm
+    return total / norm
 
 
 def squish(V, dz: float, shift):
@@ -121,7 +132,15 @@ def squish(V, dz: float, shift):
 def fault_source(shape, dz: float, dy: float, dx: float, p: dict):
     """Alg. 3: for every voxel, the pull source (metres, three arrays z, y, x)
     and the taper w.  p holds cz, cy, cx [m], azimuth_deg, dip_deg, radius,
-    slip, direction (+1/-1), die_r, die_strike [m], die_theta_deg."""
+    slip, direction (+1/-1), die_r, die_strike [m], die_theta_deg, and
+    optionally a rough surface: rough_lattice [noct, gd, gs] (rows down dip,
+    columns along strike; None = smooth),
+    rough_amplitude, rough_lam_strike, rough_lam_dip [m].  A rough surface
+    has radius R + rough_amplitude * N(u, w), N the normalised fractal value
+    noise (fractal_value) at u = along-strike offset / rough_lam_strike and
+    w = R (theta - theta0) / rough_lam_dip (the down-dip arc length); it
+    moves where the fault is (the side test and the across-fault taper) and
+    leaves the rotation angle slip / R as it is."""
     nz, ny, nx = shape
     a, th, R = math.radians(p["azimuth_deg"]), math.radians(p["dip_deg"]), p["radius"]
     ny_, nx_ = math.sin(a), math.cos(a)            # n: offset direction of the axis
@@ -141,12 +160,16 @@ def fault_source(shape, dz: float, dy: float, dx: float, p: dict):
     az = qy * sy_ + qx * sx_
     r = np.hypot(h, v)
     t_old = np.arctan2(v, h)
-    rho_r = np.abs(r - R) / p["die_r"]
+    Rs = R
+    if p.get("rough_lattice") is not None:
+        Rs = R + p["rough_amplitude"] * fractal_value(p["rough_lattice"], az / p["rough_lam_strike"],
+                                                      R * (t_old - theta0) / p["rough_lam_dip"])
+    rho_r = np.abs(r - Rs) / p["die_r"]
     rho_t = np.abs(t_old - theta0) / math.radians(p["die_theta_deg"])
     rho_s = np.abs(az) / p["die_strike"]
     inside = (rho_r < 1) & (rho_t < 1) & (rho_s < 1)
     wt = np.where(inside, np.cos(0.5 * np.pi * rho_r) * np.cos(0.5 * np.pi * rho_t) * np.cos(0.5 * np.pi * rho_s), 0.0)
-    chi = np.where(r >= R, 1.0, -1.0)
+    chi = np.where(r >= Rs, 1.0, -1.0)
     dth = -chi * p["direction"] * wt * shift       # theta_new - theta_old
     # p_fwd - p = r (cos t_new - cos t_old, sin t_new - sin t_old) in the (h, v)
     # plane, the along-strike offset unchanged; written with half-angle

@@ -64,17 +64,11 @@ __device__ inline void sinc_weights(float f, float (&w)[kTaps])
     for (int j = 0; j < kTaps; ++j) w[j] *= inv;
 }
 
-__global__ void __launch_bounds__(256) k_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny,
-                                                          int nx, double dy, double dx, double inv_lam_y,
-                                                          double inv_lam_x, double ca, double sa, double scale,
-                                                          float *out)
+// Sum over octaves o of the periodic value noise of lattice o [gy][gx] at
+// (u, w) 2^o (u along the columns), quintic fade, weight 2^-o (not yet divided
+// by the sum of the weights).  FP64 coordinates; u, w bounded by the caller.
+__device__ inline double fractal_sum(const float *lattice, int noct, int gy, int gx, double u, double w)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= (int64_t)ny * nx) return;
-    const int iy = (int)(q / nx), ix = (int)(q - (int64_t)iy * nx);
-    const double Y = iy * dy, X = ix * dx;
-    const double u = (X * ca + Y * sa) * inv_lam_x;
-    const double w = (-X * sa + Y * ca) * inv_lam_y;
     double total = 0.0, f = 1.0;
     for (int o = 0; o < noct; ++o, f *= 2.0) {
         const double pu = u * f, pw = w * f;
@@ -89,7 +83,21 @@ __global__ void __launch_bounds__(256) k_fractal_noise2d(const float *lattice, i
         const double v00 = L[w0 * gx + u0], v01 = L[w0 * gx + u1], v10 = L[w1 * gx + u0], v11 = L[w1 * gx + u1];
         total += ((v00 * (1 - tu) + v01 * tu) * (1 - tw) + (v10 * (1 - tu) + v11 * tu) * tw) / f;
     }
-    out[q] = (float)(total * scale);
+    return total;
+}
+
+__global__ void __launch_bounds__(256) k_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny,
+                                                          int nx, double dy, double dx, double inv_lam_y,
+                                                          double inv_lam_x, double ca, double sa, double scale,
+                                                          float *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)ny * nx) return;
+    const int iy = (int)(q / nx), ix = (int)(q - (int64_t)iy * nx);
+    const double Y = iy * dy, X = ix * dx;
+    const double u = (X * ca + Y * sa) * inv_lam_x;
+    const double w = (-X * sa + Y * ca) * inv_lam_y;
+    out[q] = (float)(fractal_sum(lattice, noct, gy, gx, u, w) * scale);
 }
 
 __global__ void __launch_bounds__(256) k_squish(const float *__restrict__ v, int nz, int ny, int nx, double inv_dz,
@@ -129,7 +137,8 @@ __global__ void __launch_bounds__(256) k_squish(const float *__restrict__ v, int
     }
 }
 
-// Alg. 3's pull source of voxel (iz, iy, ix) in fractional cell indices.
+// Alg. 3's pull source of voxel (iz, iy, ix) in fractional cell indices (a
+// rough surface moves the side test and the across-fault taper).
 // Returns kFaultStill outside the taper (w = 0: the source is the voxel),
 // kFaultFill where the source depth leaves [0, nz), else kFaultMoved.
 constexpr int kFaultStill = 0, kFaultMoved = 1, kFaultFill = 2;
@@ -143,13 +152,19 @@ __device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, 
     const double az = qy * F.s_y + qx * F.s_x;
     const double r = sqrt(h * h + vv * vv);
     const double t_old = atan2(vv, h);
-    const double rho_r = fabs(r - F.radius) * F.inv_die_r;
     const double rho_t = fabs(t_old - F.theta0) * F.inv_die_t;
     const double rho_s = fabs(az) * F.inv_die_s;
+    double R = F.radius;   // where the fault surface is, at this (along strike, down dip) position
+    if (F.rough && rho_t < 1.0 && rho_s < 1.0 && fabs(r - F.radius) < F.rough_reach) {
+        const double u = fmin(fmax(az * F.inv_lam_s, -1e12), 1e12);
+        const double w = fmin(fmax(F.radius * (t_old - F.theta0) * F.inv_lam_d, -1e12), 1e12);
+        R = F.radius + F.rough_scale * fractal_sum(F.rough, F.rough_noct, F.rough_gd, F.rough_gs, u, w);
+    }
+    const double rho_r = fabs(r - R) * F.inv_die_r;
     if (!(rho_r < 1.0 && rho_t < 1.0 && rho_s < 1.0)) return kFaultStill;
     const double half_pi = 1.5707963267948966;
     const double wt = cos(half_pi * rho_r) * cos(half_pi * rho_t) * cos(half_pi * rho_s);
-    const double chi = r >= F.radius ? 1.0 : -1.0;
+    const double chi = r >= R ? 1.0 : -1.0;
     const double dth = -chi * F.direction * wt * F.shift;
     // p_fwd - p in the (h, v) plane, exactly 0 where the rotation is 0
     const double mid = t_old + 0.5 * dth, hs = sin(0.5 * dth);

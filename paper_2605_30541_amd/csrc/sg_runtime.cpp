@@ -1833,6 +1833,23 @@ sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx,
     F.inv_die_r = 1.0 / p->die_r;
     F.inv_die_t = 1.0 / (p->die_theta_deg * kPi / 180.0);
     F.inv_die_s = 1.0 / p->die_strike;
+    if (p->rough_lattice) {
+        if (p->rough_noct < 1 || p->rough_noct > 24) return fail(SG_EINVAL, "rough_noct must be in 1..24");
+        if (p->rough_gd < 1 || p->rough_gs < 1) return fail(SG_EINVAL, "rough lattice sizes must be >= 1");
+        if (!std::isfinite(p->rough_amplitude)) return fail(SG_EINVAL, "rough_amplitude must be finite");
+        if (!positive_finite(p->rough_lam_strike) || !positive_finite(p->rough_lam_dip))
+            return fail(SG_EINVAL, "rough wavelengths must be finite and > 0");
+        double norm = 0.0, f = 1.0;
+        for (int o = 0; o < p->rough_noct; ++o, f *= 2.0) norm += 1.0 / f;
+        F.rough = p->rough_lattice;
+        F.rough_noct = p->rough_noct;
+        F.rough_gd = p->rough_gd;
+        F.rough_gs = p->rough_gs;
+        F.rough_scale = p->rough_amplitude / norm;
+        F.inv_lam_s = 1.0 / p->rough_lam_strike;
+        F.inv_lam_d = 1.0 / p->rough_lam_dip;
+        F.rough_reach = p->die_r + std::fabs(p->rough_amplitude);
+    }
     return SG_OK;
 }
 }  // namespace

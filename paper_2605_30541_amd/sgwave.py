@@ -76,7 +76,26 @@ class sg_fault_params(ctypes.Structure):
     _fields_ = [("cz", ctypes.c_double), ("cy", ctypes.c_double), ("cx", ctypes.c_double),
                 ("azimuth_deg", ctypes.c_double), ("dip_deg", ctypes.c_double), ("radius", ctypes.c_double),
                 ("slip", ctypes.c_double), ("direction", ctypes.c_int32), ("die_r", ctypes.c_double),
-                ("die_strike", ctypes.c_double), ("die_theta_deg", ctypes.c_double)]
+                ("die_strike", ctypes.c_double), ("die_theta_deg", ctypes.c_double),
+                ("rough_lattice", ctypes.c_void_p), ("rough_noct", ctypes.c_int32), ("rough_gd", ctypes.c_int32),
+                ("rough_gs", ctypes.c_int32), ("rough_amplitude", ctypes.c_double),
+                ("rough_lam_strike", ctypes.c_double), ("rough_lam_dip", ctypes.c_double)]
+
+
+def _fault_params(params: dict) -> sg_fault_params:
+    """sg_fault_params from a dict of its fields; an optional rough surface is
+    given by rough_lattice (a float32 device tensor [noct, gd, gs]),
+    rough_amplitude, rough_lam_strike and rough_lam_dip."""
+    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
+                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    lat = params.get("rough_lattice")
+    if lat is not None:
+        p.rough_lattice = lat.data_ptr()
+        p.rough_noct, p.rough_gd, p.rough_gs = lat.shape
+        p.rough_amplitude = params["rough_amplitude"]
+        p.rough_lam_strike = params["rough_lam_strike"]
+        p.rough_lam_dip = params["rough_lam_dip"]
+    return p
 
 
 _SIGS = {
@@ -496,11 +515,10 @@ def squish(v, dz: float, shift, stream=None):
 
 def fault(v, dz: float, dy: float, dx: float, params: dict, fill: float, stream=None):
     """v [nz, ny, nx] through one listric normal fault; params holds the
-    fields of sg_fault_params."""
+    fields of sg_fault_params (see _fault_params for a rough surface)."""
     import torch
     nz, ny, nx = v.shape
-    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
-                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    p = _fault_params(params)
     out = torch.empty_like(v)
     _check(lib().sg_fault(_ptr(v), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out), _stream_ptr(stream)))
     return out
@@ -542,8 +560,7 @@ def fault_labels(labels, dz: float, dy: float, dx: float, params: dict, fill: in
     nearest-neighbour pull; params holds the fields of sg_fault_params."""
     import torch
     nz, ny, nx = labels.shape
-    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
-                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    p = _fault_params(params)
     out = torch.empty_like(labels)
     _check(lib().sg_fault_labels(_ptr(labels), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out),
                                  _stream_ptr(stream)))

@@ -18,7 +18,7 @@ def test_library_exports_every_header_function():
     L = sgwave.lib()
     for n in names:
         assert hasattr(L, n), n
-    assert sgwave.sg_abi_version() == 1
+    assert sgwave.sg_abi_version() == 2
     assert set(names) == set(sgwave._SIGS)
 
 
@@ -227,6 +227,13 @@ def test_builder_argument_errors_touch_nothing():
     assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 10.0, None, 0, b, None) == E
     bad = sgwave.sg_fault_params(**dict(good, direction=2))
     assert L.sg_fault_labels(a, 10, 2, 3, 10.0, 10.0, 10.0, ctypes.byref(bad), 0, b, None) == E
+    for field, val in (("rough_noct", 0), ("rough_noct", 25), ("rough_gd", 0), ("rough_amplitude", float("nan")),
+                       ("rough_lam_dip", 0.0)):
+        rp = sgwave.sg_fault_params(**good)
+        rp.rough_lattice, rp.rough_noct, rp.rough_gd, rp.rough_gs = 4096, 2, 3, 3
+        rp.rough_amplitude, rp.rough_lam_strike, rp.rough_lam_dip = 10.0, 100.0, 100.0
+        setattr(rp, field, val)
+        assert L.sg_fault(a, 10, 2, 3, 10.0, 10.0, 10.0, ctypes.byref(rp), 0.0, b, None) == E, field
     assert L.sg_fractal_noise2d(a, 0, 4, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 4, 4, 10, 10, 10.0, 10.0, 0.0, 100.0, 0.0, 5.0, b, None) == E
     assert L.sg_fractal_noise2d(a, 2, 0, 4, 10, 10, 10.0, 10.0, 100.0, 100.0, 0.0, 5.0, b, None) == E

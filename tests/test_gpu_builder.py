@@ -161,3 +161,38 @@ def test_fault_labels_match_the_oracle(case):
     assert not (diff & ~tie).any()
     if case == "through-top":
         assert np.count_nonzero(ref == -1) > 0
+
+
+@pytest.mark.parametrize("case", ["3d", "2d-slice", "strong"])
+def test_rough_fault_matches_the_oracle(case):
+    """A rough fault surface (radius perturbed by fractal noise over
+    along-strike and down-dip coordinates): velocities and labels."""
+    import torch
+    nz, ny, nx, p = 48, 24, 56, dict(FAULT)
+    amp, lam_s, lam_d, noct = 40.0, 150.0, 120.0, 3
+    if case == "2d-slice":
+        ny, p["cy"], p["azimuth_deg"] = 1, 0.0, 0.0
+    elif case == "strong":
+        amp, lam_s, lam_d, noct = 120.0, 60.0, 50.0, 5
+    lat = np.random.default_rng({"3d": 1, "2d-slice": 2, "strong": 3}[case]).uniform(-1, 1, (noct, 6, 7))
+    lat = lat.astype(np.float32)
+    rough = dict(rough_amplitude=amp, rough_lam_strike=lam_s, rough_lam_dip=lam_d)
+    p_gpu = dict(p, rough_lattice=torch.from_numpy(lat).cuda(), **rough)
+    p_ref = dict(p, rough_lattice=lat.astype(np.float64), **rough)
+    V = _layered(nz, ny, nx, 7)
+    got = _host(sgwave.fault(_dev(V), 10.0, 10.0, 10.0, p_gpu, 1480.0))
+    ref = OB.fault(V.astype(np.float64), 10.0, 10.0, 10.0, p_ref, 1480.0)
+    smooth = OB.fault(V.astype(np.float64), 10.0, 10.0, 10.0, p, 1480.0)
+    e = rel_l2(got, ref)
+    differs = int(np.count_nonzero(np.abs(ref - smooth) > 1.0))
+    print("%s: rough fault rel-L2 %.2e, %d voxels differ from the smooth fault by > 1 m/s" % (case, e, differs),
+          flush=True)
+    assert differs > 100
+    assert e <= TOL
+    z = np.arange(nz)[:, None, None]
+    L = (np.floor(z / 4.0) + np.zeros((1, ny, nx))).astype(np.int32)
+    gl = sgwave.fault_labels(torch.from_numpy(L).cuda(), 10.0, 10.0, 10.0, p_gpu, -1).cpu().numpy()
+    rl = OB.fault_labels(L, 10.0, 10.0, 10.0, p_ref, -1)
+    (sz, sy, sx), w = OB.fault_source(L.shape, 10.0, 10.0, 10.0, p_ref)
+    tie = _near_half(sz / 10.0) | _near_half(sy / 10.0) | _near_half(sx / 10.0)
+    assert not ((gl != rl) & ~tie).any()

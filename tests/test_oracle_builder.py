@@ -314,3 +314,39 @@ def test_fault_labels_take_the_voxel_nearest_the_source():
     assert moved > 100 and fill > 0
     assert np.array_equal(out[w == 0], L[w == 0])
     assert np.array_equal(B.fault_labels(L, h, h, h, dict(p, slip=0.0), -1), L)
+
+
+def test_rough_fault_surface_moves_the_fault_by_the_noise():
+    """A rough surface of zero amplitude is the smooth fault; with a constant
+    lattice c the noise is exactly c, so the slip changes side exactly where
+    the distance from the axis crosses R + amplitude * c (not at R)."""
+    shape, h = (40, 6, 50), 10.0
+    p = dict(cz=150.0, cy=25.0, cx=250.0, azimuth_deg=0.0, dip_deg=50.0, radius=400.0, slip=30.0, direction=1,
+             die_r=200.0, die_strike=500.0, die_theta_deg=80.0)
+    lat = np.random.default_rng(3).uniform(-1, 1, (3, 4, 5))
+    (s0, w0) = B.fault_source(shape, h, h, h, p)
+    (s1, w1) = B.fault_source(shape, h, h, h, dict(p, rough_lattice=lat, rough_amplitude=0.0,
+                                                   rough_lam_strike=100.0, rough_lam_dip=80.0))
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1)) and np.array_equal(w0, w1)
+    c, A = 0.6, 50.0
+    rough = dict(p, rough_lattice=np.full((2, 3, 3), c), rough_amplitude=A, rough_lam_strike=100.0,
+                 rough_lam_dip=80.0)
+    (sz, sy, sx), w = B.fault_source(shape, h, h, h, rough)
+    # geometry of the frame, from the fault's definition: axis offset R cos(dip) along n = (0, 1) in (y, x)
+    R, dip = p["radius"], math.radians(p["dip_deg"])
+    Z, Y, X = np.meshgrid(*[np.arange(n) * h for n in shape], indexing="ij")
+    hh, vv = X - (p["cx"] - R * math.cos(dip)), Z - (p["cz"] - R * math.sin(dip))
+    r = np.hypot(hh, vv)
+    moved = w > 0
+    # the displacement's rotation sense: its component along the tangent (-sin t, cos t) in (h, v)
+    dh, dv = X - sx, Z - sz          # p - src = (p_fwd - p)
+    t = np.arctan2(vv, hh)
+    tang = -np.sin(t) * dh + np.cos(t) * dv
+    far = r >= R + A * c
+    band = moved & (np.abs(tang) > 1e-9)
+    assert band.sum() > 200
+    # rotation -chi * direction: chi = +1 beyond the surface, -1 inside it
+    assert np.all(np.sign(tang[band]) == np.where(far[band], -1.0, 1.0) * p["direction"])
+    # voxels between R and R + A c are on the near side now: the smooth fault had them on the far side
+    between = band & (r >= R) & (r < R + A * c)
+    assert between.sum() > 20
