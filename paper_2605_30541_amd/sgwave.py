@@ -193,7 +193,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libsgwave.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            raise RuntimeError("libsgwave.so is not built (%s); run python -m paper_2605_30541_amd.build" % LIB_PATH)
         # torch (which owns device memory and streams here) is loaded first:
         # loading this library before torch's HIP runtime has left the
         # library's later HIP calls without a device
