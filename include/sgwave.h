@@ -437,7 +437,8 @@ typedef struct sg_fault_params {
      * fractal noise): with rough_lattice non-NULL the surface lies at radius
      * R + rough_amplitude N(u, w), N = normalised fractal value noise as in
      * sg_fractal_noise2d (octave o: lattice o, frequency 2^o, weight 2^-o, sum
-     * divided by sum_o 2^-o, so |N| <= max |lattice|) at u = along-strike
+     * divided by sum_o 2^-o) clamped to [-1, 1] (the clamp never acts on a
+     * lattice within [-1, 1]), at u = along-strike
      * offset / rough_lam_strike and w = R (theta - theta0) / rough_lam_dip
      * (down-dip arc length).  It moves the side test (chi) and the
      * across-fault taper; the rotation stays slip / R.  rough_lattice:

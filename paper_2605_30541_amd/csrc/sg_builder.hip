@@ -18,6 +18,7 @@
 #include "sg_internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace sg {
 
@@ -158,7 +159,9 @@ __device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, 
     if (F.rough && rho_t < 1.0 && rho_s < 1.0 && fabs(r - F.radius) < F.rough_reach) {
         const double u = fmin(fmax(az * F.inv_lam_s, -1e12), 1e12);
         const double w = fmin(fmax(F.radius * (t_old - F.theta0) * F.inv_lam_d, -1e12), 1e12);
-        R = F.radius + F.rough_scale * fractal_sum(F.rough, F.rough_noct, F.rough_gd, F.rough_gs, u, w);
+        const double N = fmin(fmax(fractal_sum(F.rough, F.rough_noct, F.rough_gd, F.rough_gs, u, w) * F.rough_inv_norm,
+                                   -1.0), 1.0);
+        R = F.radius + F.rough_amp * N;
     }
     const double rho_r = fabs(r - R) * F.inv_die_r;
     if (!(rho_r < 1.0 && rho_t < 1.0 && rho_s < 1.0)) return kFaultStill;
@@ -175,15 +178,20 @@ __device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, 
     return sz >= 0.0 && sz < (double)nz ? kFaultMoved : kFaultFill;
 }
 
-// The volume is cut in bricks of kBrickZ x kBrickY rows of 256 columns, one
+// Voxels [z0, z0 + bz) x [y0, y0 + by) x [x0, x0 + bx) of the volume.
+struct VoxBox {
+    int z0, y0, x0, bz, by, bx;
+};
+
+// The box is cut in bricks of kBrickZ x kBrickY rows of 256 columns, one
 // workgroup per row.  Workgroups go to the 8 XCDs in turn; here all rows of a
 // brick go to one XCD (the rows its voxels sample are then fetched into one
 // L2) and the bricks are dealt round-robin (the moved region of a fault stays
-// spread over the XCDs).  False for threads past the volume.
-__device__ inline bool brick_voxel(int nz, int ny, int nx, int &iz, int &iy, int &ix)
+// spread over the XCDs).  False for threads past the box.
+__device__ inline bool brick_voxel(const VoxBox &B, int &iz, int &iy, int &ix)
 {
-    const int bx_n = (nx + 255) / 256, by_n = (ny + kBrickY - 1) / kBrickY;
-    const int64_t nbrick = (int64_t)bx_n * by_n * ((nz + kBrickZ - 1) / kBrickZ);
+    const int bx_n = (B.bx + 255) / 256, by_n = (B.by + kBrickY - 1) / kBrickY;
+    const int64_t nbrick = (int64_t)bx_n * by_n * ((B.bz + kBrickZ - 1) / kBrickZ);
     const int64_t t = blockIdx.x / 8;
     const int64_t brick = (t / kBrickRows) * 8 + blockIdx.x % 8;
     if (brick >= nbrick) return false;
@@ -191,17 +199,18 @@ __device__ inline bool brick_voxel(int nz, int ny, int nx, int &iz, int &iy, int
     const int bx = (int)(brick % bx_n);
     const int64_t rest = brick / bx_n;
     const int by = (int)(rest % by_n), bz = (int)(rest / by_n);
-    iz = bz * kBrickZ + row / kBrickY;
-    iy = by * kBrickY + row % kBrickY;
-    ix = bx * 256 + threadIdx.x;
-    return iz < nz && iy < ny && ix < nx;
+    const int lz = bz * kBrickZ + row / kBrickY, ly = by * kBrickY + row % kBrickY, lx = bx * 256 + threadIdx.x;
+    iz = B.z0 + lz;
+    iy = B.y0 + ly;
+    ix = B.x0 + lx;
+    return lz < B.bz && ly < B.by && lx < B.bx;
 }
 
-__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, FaultFrame F,
-                                               float fill, float *__restrict__ out)
+__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, VoxBox B,
+                                               FaultFrame F, float fill, float *__restrict__ out)
 {
     int iz, iy, ix;
-    if (!brick_voxel(nz, ny, nx, iz, iy, ix)) return;
+    if (!brick_voxel(B, iz, iy, ix)) return;
     const int64_t plane = (int64_t)ny * nx;
     const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
     double sz, sy, sx;
@@ -265,10 +274,11 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
 // sampled at the nearest voxel (floor(s + 0.5) per axis; y and x clamped to
 // the volume); `fill` where the source depth leaves [0, nz).
 __global__ void __launch_bounds__(256) k_fault_labels(const int32_t *__restrict__ lab, int nz, int ny, int nx,
-                                                      FaultFrame F, int32_t fill, int32_t *__restrict__ out)
+                                                      VoxBox B, FaultFrame F, int32_t fill,
+                                                      int32_t *__restrict__ out)
 {
     int iz, iy, ix;
-    if (!brick_voxel(nz, ny, nx, iz, iy, ix)) return;
+    if (!brick_voxel(B, iz, iy, ix)) return;
     const int64_t plane = (int64_t)ny * nx;
     const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
     double sz, sy, sx;
@@ -384,23 +394,115 @@ hipError_t launch_squish(const float *v, int nz, int ny, int nx, double dz, cons
     return hipGetLastError();
 }
 
+namespace {
+
+// Index range along one axis (spacing d, n voxels) covering [lo, hi] metres
+// plus two voxels; false if it misses the axis.
+bool axis_cover(double lo, double hi, double d, int n, int &a, int &b)
+{
+    const double fa = std::floor(lo / d) - 2.0, fb = std::ceil(hi / d) + 2.0;
+    if (!(fb >= 0.0 && fa <= n - 1.0)) return false;
+    a = fa < 0.0 ? 0 : (int)fa;
+    b = fb > n - 1.0 ? n - 1 : (int)fb;
+    return true;
+}
+
+// A box holding every voxel the fault can move: the cylinder shell
+// |r - R| < die_r (+ |rough amplitude|), the angle band |theta - theta0| <
+// die_theta and |along-strike offset| < die_strike, bounded in the (h, v)
+// plane across strike by its corners and axis crossings, then carried to
+// (z, y, x) by interval arithmetic; two voxels of margin.  Outside it every
+// voxel keeps its value.  False if it misses the volume.
+bool fault_box(const FaultFrame &F, int nz, int ny, int nx, VoxBox &B)
+{
+    const double pi = 3.14159265358979323846;
+    const double die_r = 1.0 / F.inv_die_r, die_t = 1.0 / F.inv_die_t, die_s = 1.0 / F.inv_die_s;
+    const double extra = F.rough ? std::fabs(F.rough_amp) : 0.0;
+    const double r_hi = F.radius + die_r + extra, r_lo = std::max(0.0, F.radius - die_r - extra);
+    double h_lo, h_hi, v_lo, v_hi;
+    if (die_t >= pi) {
+        h_lo = v_lo = -r_hi;
+        h_hi = v_hi = r_hi;
+    } else {
+        const double t0 = F.theta0 - die_t, t1 = F.theta0 + die_t;
+        double ts[16];
+        int nt = 0;
+        ts[nt++] = t0;
+        ts[nt++] = t1;
+        for (int k = (int)std::ceil(t0 / (0.5 * pi)); k * 0.5 * pi < t1 && nt < 16; ++k) ts[nt++] = k * 0.5 * pi;
+        h_lo = v_lo = 1e300;
+        h_hi = v_hi = -1e300;
+        for (int i = 0; i < nt; ++i)
+            for (double r : {r_lo, r_hi}) {
+                h_lo = std::min(h_lo, r * std::cos(ts[i]));
+                h_hi = std::max(h_hi, r * std::cos(ts[i]));
+                v_lo = std::min(v_lo, r * std::sin(ts[i]));
+                v_hi = std::max(v_hi, r * std::sin(ts[i]));
+            }
+    }
+    // y = cy + h n_y + az s_y, x = cx + h n_x + az s_x, az in [-die_s, die_s]
+    auto span = [&](double c, double ny_, double sy_, double &lo, double &hi) {
+        lo = c + std::min(h_lo * ny_, h_hi * ny_) - die_s * std::fabs(sy_);
+        hi = c + std::max(h_lo * ny_, h_hi * ny_) + die_s * std::fabs(sy_);
+    };
+    double y_lo, y_hi, x_lo, x_hi;
+    span(F.cy, F.n_y, F.s_y, y_lo, y_hi);
+    span(F.cx, F.n_x, F.s_x, x_lo, x_hi);
+    int za, zb, ya, yb, xa, xb;
+    if (!axis_cover(F.cz + v_lo, F.cz + v_hi, F.dz, nz, za, zb) || !axis_cover(y_lo, y_hi, F.dy, ny, ya, yb) ||
+        !axis_cover(x_lo, x_hi, F.dx, nx, xa, xb))
+        return false;
+    B = VoxBox{za, ya, xa, zb - za + 1, yb - ya + 1, xb - xa + 1};
+    return true;
+}
+
+int64_t fault_blocks(const VoxBox &B)
+{
+    const int64_t nbrick =
+        (int64_t)((B.bx + 255) / 256) * ((B.by + kBrickY - 1) / kBrickY) * ((B.bz + kBrickZ - 1) / kBrickZ);
+    return (nbrick + 7) / 8 * 8 * kBrickRows;
+}
+
+// Copies the volume when the fault's box is smaller than it (the kernel then
+// writes the box only); returns whether the kernel has anything to do.
+template <typename T>
+hipError_t fault_prologue(const T *in, int nz, int ny, int nx, const FaultFrame &F, T *out, hipStream_t st,
+                          VoxBox &B, bool &run)
+{
+    const VoxBox whole{0, 0, 0, nz, ny, nx};
+    run = fault_box(F, nz, ny, nx, B);
+    const bool partial = !run || B.bz < nz || B.by < ny || B.bx < nx;
+    if (!run) B = whole;
+    if (partial)
+        return hipMemcpyAsync(out, in, (size_t)nz * ny * nx * sizeof(T), hipMemcpyDeviceToDevice, st);
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame &F, float fill, float *out,
                         hipStream_t st)
 {
-    const int64_t nbrick = (int64_t)((nx + 255) / 256) * ((ny + kBrickY - 1) / kBrickY) * ((nz + kBrickZ - 1) / kBrickZ);
-    const int64_t blocks = (nbrick + 7) / 8 * 8 * kBrickRows;
+    VoxBox B;
+    bool run;
+    hipError_t e = fault_prologue(v, nz, ny, nx, F, out, st, B, run);
+    if (e != hipSuccess || !run) return e;
+    const int64_t blocks = fault_blocks(B);
     if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, F, fill, out);
+    hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, B, F, fill, out);
     return hipGetLastError();
 }
 
 hipError_t launch_fault_labels(const int32_t *lab, int nz, int ny, int nx, const FaultFrame &F, int32_t fill,
                                int32_t *out, hipStream_t st)
 {
-    const int64_t nbrick = (int64_t)((nx + 255) / 256) * ((ny + kBrickY - 1) / kBrickY) * ((nz + kBrickZ - 1) / kBrickZ);
-    const int64_t blocks = (nbrick + 7) / 8 * 8 * kBrickRows;
+    VoxBox B;
+    bool run;
+    hipError_t e = fault_prologue(lab, nz, ny, nx, F, out, st, B, run);
+    if (e != hipSuccess || !run) return e;
+    const int64_t blocks = fault_blocks(B);
     if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fault_labels, dim3((unsigned)blocks), dim3(256), 0, st, lab, nz, ny, nx, F, fill, out);
+    hipLaunchKernelGGL(k_fault_labels, dim3((unsigned)blocks), dim3(256), 0, st, lab, nz, ny, nx, B, F, fill, out);
     return hipGetLastError();
 }
 

@@ -178,12 +178,13 @@ struct FaultFrame {
     double n_y, n_x, s_y, s_x;
     double radius, theta0, shift, direction;
     double inv_die_r, inv_die_t, inv_die_s;
-    // rough surface (rough == nullptr: smooth): radius + rough_scale * noise sum
-    // at (along-strike offset * inv_lam_s, radius (theta - theta0) * inv_lam_d);
-    // rough_reach = die_r + |amplitude| bounds where the noise can matter
+    // rough surface (rough == nullptr: smooth): radius + rough_amp * N, N the
+    // noise sum times rough_inv_norm clamped to [-1, 1], at (along-strike
+    // offset * inv_lam_s, radius (theta - theta0) * inv_lam_d); rough_reach =
+    // die_r + |rough_amp| bounds where the noise can matter
     const float *rough;      // [rough_noct][rough_gd][rough_gs], device
     int rough_noct, rough_gd, rough_gs;
-    double rough_scale, inv_lam_s, inv_lam_d, rough_reach;
+    double rough_amp, rough_inv_norm, inv_lam_s, inv_lam_d, rough_reach;
 };
 // Deposit (Alg. 1): band size, spacings, the bed tables (device, nbeds
 // entries; eta_b [nbeds-1][ny][nx]), the texture lattice [gz][gy][gx] with

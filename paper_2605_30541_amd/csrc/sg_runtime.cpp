@@ -1845,7 +1845,8 @@ sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx,
         F.rough_noct = p->rough_noct;
         F.rough_gd = p->rough_gd;
         F.rough_gs = p->rough_gs;
-        F.rough_scale = p->rough_amplitude / norm;
+        F.rough_amp = p->rough_amplitude;
+        F.rough_inv_norm = 1.0 / norm;
         F.inv_lam_s = 1.0 / p->rough_lam_strike;
         F.inv_lam_d = 1.0 / p->rough_lam_dip;
         F.rough_reach = p->die_r + std::fabs(p->rough_amplitude);

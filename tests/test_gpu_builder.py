@@ -70,7 +70,7 @@ FAULT = dict(cz=250.0, cy=110.0, cx=280.0, azimuth_deg=25.0, dip_deg=55.0, radiu
              direction=1, die_r=180.0, die_strike=200.0, die_theta_deg=25.0)
 
 
-@pytest.mark.parametrize("case", ["3d", "3d-reverse", "2d-slice", "through-top", "steep-oblique"])
+@pytest.mark.parametrize("case", ["3d", "3d-reverse", "2d-slice", "through-top", "steep-oblique", "small"])
 def test_fault_matches_the_oracle(case):
     nz, ny, nx, p, fill = 48, 24, 56, dict(FAULT), 1480.0
     if case == "3d-reverse":
@@ -81,6 +81,10 @@ def test_fault_matches_the_oracle(case):
         p.update(cz=20.0, slip=140.0, die_r=400.0, die_strike=600.0, die_theta_deg=60.0)
     elif case == "steep-oblique":
         p.update(azimuth_deg=-70.0, dip_deg=80.0, radius=3000.0, slip=70.0, die_theta_deg=10.0)
+    elif case == "small":   # a subsidiary-size fault: only a small box of the volume is processed
+        nz, ny, nx = 60, 40, 90
+        p.update(cz=300.0, cy=200.0, cx=450.0, radius=300.0, slip=25.0, die_r=50.0, die_strike=70.0,
+                 die_theta_deg=15.0)
     V = _layered(nz, ny, nx, 7)
     got = _host(sgwave.fault(_dev(V), 10.0, 10.0, 10.0, p, fill))
     ref = OB.fault(V.astype(np.float64), 10.0, 10.0, 10.0, p, fill)
@@ -163,7 +167,7 @@ def test_fault_labels_match_the_oracle(case):
         assert np.count_nonzero(ref == -1) > 0
 
 
-@pytest.mark.parametrize("case", ["3d", "2d-slice", "strong"])
+@pytest.mark.parametrize("case", ["3d", "2d-slice", "strong", "wide-lattice"])
 def test_rough_fault_matches_the_oracle(case):
     """A rough fault surface (radius perturbed by fractal noise over
     along-strike and down-dip coordinates): velocities and labels."""
@@ -174,7 +178,9 @@ def test_rough_fault_matches_the_oracle(case):
         ny, p["cy"], p["azimuth_deg"] = 1, 0.0, 0.0
     elif case == "strong":
         amp, lam_s, lam_d, noct = 120.0, 60.0, 50.0, 5
-    lat = np.random.default_rng({"3d": 1, "2d-slice": 2, "strong": 3}[case]).uniform(-1, 1, (noct, 6, 7))
+    span = 3.0 if case == "wide-lattice" else 1.0     # a lattice beyond [-1, 1]: the noise is clamped
+    lat = np.random.default_rng({"3d": 1, "2d-slice": 2, "strong": 3, "wide-lattice": 4}[case]).uniform(
+        -span, span, (noct, 6, 7))
     lat = lat.astype(np.float32)
     rough = dict(rough_amplitude=amp, rough_lam_strike=lam_s, rough_lam_dip=lam_d)
     p_gpu = dict(p, rough_lattice=torch.from_numpy(lat).cuda(), **rough)
