@@ -94,11 +94,21 @@ __global__ void __launch_bounds__(kSaltThreads) k_field_extremes(int64_t n, cons
 {
     const float *xi = grf + (int64_t)blockIdx.y * n;
     float hi = 0.0f, lo = 0.0f;
-    for (int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * kSaltThreads) {
-        const float v = xi[q];
-        hi = fmaxf(hi, v);
-        lo = fmaxf(lo, -v);
+    const int64_t stride = (int64_t)gridDim.x * kSaltThreads;
+    int64_t q = (int64_t)blockIdx.x * kSaltThreads + threadIdx.x;
+    if (n % 4 == 0 && ((uintptr_t)grf & 15) == 0) {   // every field 16-byte aligned: four values per load
+        const float4 *x4 = (const float4 *)xi;
+        for (; q < n / 4; q += stride) {
+            const float4 v = x4[q];
+            hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+            lo = fmaxf(lo, fmaxf(fmaxf(-v.x, -v.y), fmaxf(-v.z, -v.w)));
+        }
+    } else {
+        for (; q < n; q += stride) {
+            const float v = xi[q];
+            hi = fmaxf(hi, v);
+            lo = fmaxf(lo, -v);
+        }
     }
     hi = wave_max(hi);
     lo = wave_max(lo);
@@ -176,6 +186,8 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_x(Box b0, Box b1, int ny, 
 
 // Buffers of the two distance transforms (feature 0 and 1) run side by side.
 struct EnvPair {
+    const uint8_t *skip_mask;   // with axis 1: transform 0 skips lines holding no voxel set here
+    int ny, nx;                 // volume rows and columns (to index skip_mask)
     Box box[2];
     const double *f[2];
     double *g[2];
@@ -219,6 +231,14 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, double 
         ostride = (int64_t)b.by * b.bx;
     }
     const int t = blockIdx.y;
+    if (axis == 1 && t == 0 && P.skip_mask) {
+        // d_in's last pass: its values are read at inside voxels only
+        const int lz = (int)(l / b.bx), lx = (int)(l - (int64_t)lz * b.bx);
+        const uint8_t *m = P.skip_mask + ((int64_t)(b.z0 + lz) * P.ny + b.y0) * P.nx + b.x0 + lx;
+        bool any = false;
+        for (int q = 0; q < n && !any; ++q) any = m[(int64_t)q * P.nx] != 0;
+        if (!any) return;
+    }
     const double *f = P.f[t] + base;
     double *g = P.g[t] + obase;
     int *v = P.v[t] + base;
@@ -273,21 +293,21 @@ __global__ void __launch_bounds__(kSaltThreads) k_edt_envelope(int axis, double 
     }
 }
 
-// Over box b (that of d_out); d_in is held on the inner box bi only and is 0
-// outside it (every voxel there is outside the body).  Both distance arrays
-// are box-local [z][y][x].
+// Over box b (that of d_out); d_in is held on the inner box bi (every inside
+// voxel is in it) and read at inside voxels only, d_out at outside voxels only.
+// Both distance arrays are box-local [z][y][x].
 __global__ void __launch_bounds__(kSaltThreads) k_salt_union(Box b, Box bi, int ny, int nx, unsigned xb,
-                                                             const double *din2, const double *dout2, const float *xi,
-                                                             double a_rbar, uint8_t *K)
+                                                             const uint8_t *mask, const double *din2,
+                                                             const double *dout2, const float *xi, double a_rbar,
+                                                             uint8_t *K)
 {
     int iz, iy, ix;
     int64_t q;
     if (!box_voxel(b, ny, nx, xb, iz, iy, ix, q)) return;
-    const int iz_i = iz - bi.z0, iy_i = iy - bi.y0, ix_i = ix - bi.x0;
-    const bool in_bi = iz_i >= 0 && iz_i < bi.bz && iy_i >= 0 && iy_i < bi.by && ix_i >= 0 && ix_i < bi.bx;
-    const double di = in_bi ? sqrt(din2[((int64_t)iz_i * bi.by + iy_i) * bi.bx + ix_i]) : 0.0;
-    const double dout = sqrt(dout2[((int64_t)(iz - b.z0) * b.by + (iy - b.y0)) * b.bx + (ix - b.x0)]);
-    const double phi = di - dout;
+    // d_in - d_out with one of them exactly 0: d_in at an inside voxel (always in bi), -d_out outside
+    const double phi = mask[q]
+        ? sqrt(din2[((int64_t)(iz - bi.z0) * bi.by + (iy - bi.y0)) * bi.bx + (ix - bi.x0)])
+        : -sqrt(dout2[((int64_t)(iz - b.z0) * b.by + (iy - b.y0)) * b.bx + (ix - b.x0)]);
     if (phi + a_rbar * (double)xi[q] > 0.0) K[q] = 1;
 }
 
@@ -600,11 +620,14 @@ hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, do
         hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock), 2), blk, 0, st, bi,
                            bo, ny, nx, dx, (const uint8_t *)W.m, W.din, W.dout);
         // then along z (box-local [y][z][x] -> [z][y][x]) and along y (in [z][y][x])
-        const EnvPair along_z{{bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
-        const EnvPair along_y{{bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]}, {W.zb[0], W.zb[1]}};
+        const EnvPair along_z{nullptr, ny, nx, {bi, bo}, {W.din, W.dout}, {W.f[0], W.f[1]}, {W.v[0], W.v[1]},
+                              {W.zb[0], W.zb[1]}};
+        const EnvPair along_y{W.m, ny, nx, {bi, bo}, {W.f[0], W.f[1]}, {W.din, W.dout}, {W.v[0], W.v[1]},
+                              {W.zb[0], W.zb[1]}};
         hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.by * bo.bx), 2), blk, 0, st, 0, dz, along_z);
         hipLaunchKernelGGL(k_edt_envelope, dim3(blocks_for((int64_t)bo.bz * bo.bx), 2), blk, 0, st, 1, dy, along_y);
-        hipLaunchKernelGGL(k_salt_union, box_grid(bo), blk, 0, st, bo, bi, ny, nx, xb, (const double *)W.din,
+        hipLaunchKernelGGL(k_salt_union, box_grid(bo), blk, 0, st, bo, bi, ny, nx, xb, (const uint8_t *)W.m,
+                           (const double *)W.din,
                            (const double *)W.dout, grf + (int64_t)i * n, amplitude * rbar, W.K);
     }
     // opening (erode, dilate) then closing (dilate, erode), ping-ponging K and m
