@@ -58,12 +58,19 @@ def test_squish_full_size_sampled_columns(model):
     assert e_shift <= TOL and e <= TOL
 
 
-def test_fault_full_size_crop(model):
+@pytest.mark.parametrize("surface", ["smooth", "rough"])
+def test_fault_full_size_crop(model, surface):
     import torch
     V, Vd = model
     p = dict(cz=3000.0, cy=5000.0, cx=5000.0, azimuth_deg=30.0, dip_deg=60.0, radius=6000.0, slip=120.0,
              direction=1, die_r=1500.0, die_strike=4500.0, die_theta_deg=35.0)
-    out_d = sgwave.fault(Vd, H, H, H, p, 1480.0)
+    p_gpu = dict(p)
+    if surface == "rough":
+        lat = np.random.default_rng(44).uniform(-1, 1, (4, 8, 9)).astype(np.float32)
+        rough = dict(rough_amplitude=150.0, rough_lam_strike=900.0, rough_lam_dip=700.0)
+        p_gpu.update(rough_lattice=torch.from_numpy(lat).cuda(), **rough)
+        p.update(rough_lattice=lat.astype(np.float64), **rough)
+    out_d = sgwave.fault(Vd, H, H, H, p_gpu, 1480.0)
     torch.cuda.synchronize()
     y0, x0, c = 470, 520, 36
     got = out_d[:, y0:y0 + c, x0:x0 + c].cpu().numpy().astype(np.float64)
@@ -75,11 +82,30 @@ def test_fault_full_size_crop(model):
     keep = (w == 0) | ((np.floor(sy) >= 3) & (np.floor(sy) <= c - 5) & (np.floor(sx) >= 3) & (np.floor(sx) <= c - 5))
     moved = int(np.count_nonzero(keep & (w > 0)))
     e = rel_l2(got[keep], ref[keep])
-    print("fault full size: crop %dx%dx%d at (y %d, x %d), %d moved voxels compared, rel-L2 %.2e"
-          % (NZ, c, c, y0, x0, moved, e), flush=True)
+    print("fault full size (%s): crop %dx%dx%d at (y %d, x %d), %d moved voxels compared, rel-L2 %.2e"
+          % (surface, NZ, c, c, y0, x0, moved, e), flush=True)
     assert moved > 100000
     assert e <= TOL
     assert np.array_equal(got[keep & (w == 0)], crop.astype(np.float64)[keep & (w == 0)])
+    # integer labels through the same fault (nearest neighbour): exact but for .5 ties
+    del out_d
+    Ld = torch.floor(Vd / 37.0).to(torch.int32)
+    lab_d = sgwave.fault_labels(Ld, H, H, H, p_gpu, -1)
+    torch.cuda.synchronize()
+    gl = lab_d[:, y0:y0 + c, x0:x0 + c].cpu().numpy()
+    Lc = Ld[:, y0:y0 + c, x0:x0 + c].cpu().numpy()
+    del lab_d, Ld
+    rl = OB.fault_labels(Lc, H, H, H, pc, -1)
+    szc = sz / H
+    tie = (np.abs(szc - np.floor(szc) - 0.5) < 1e-9) | (np.abs(sy - np.floor(sy) - 0.5) < 1e-9) | \
+        (np.abs(sx - np.floor(sx) - 0.5) < 1e-9)
+    keep_l = (w == 0) | ((np.floor(sy + 0.5) >= 0) & (np.floor(sy + 0.5) <= c - 1) & (np.floor(sx + 0.5) >= 0) &
+                         (np.floor(sx + 0.5) <= c - 1))
+    changed = int(np.count_nonzero(keep_l & (rl != Lc)))
+    print("fault labels full size (%s): %d labels changed in the crop, %d differ off ties"
+          % (surface, changed, int(((gl != rl) & keep_l & ~tie).sum())), flush=True)
+    assert changed > 10000
+    assert not ((gl != rl) & keep_l & ~tie).any()
 
 
 def test_salt_full_size_crop(model):
