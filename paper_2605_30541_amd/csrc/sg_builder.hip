@@ -254,6 +254,40 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
         return s;
     };
     float acc = 0.f;
+    if (x_inner && ny > 1) {
+        // the 16 row loads of a z tap are all issued before any is used (load
+        // latency overlaps across rows); same arithmetic order as row_taps
+        int64_t ry[kTaps];
+#pragma unroll
+        for (int b = 0; b < kTaps; ++b) ry[b] = (int64_t)min(max(y0 + b, 0), ny - 1) * nx + x0;
+#pragma unroll
+        for (int a = 0; a < kTaps; ++a) {
+            const float *pl = v + (int64_t)min(max(z0 + a, 0), nz - 1) * plane;
+            Float4u lo[kTaps], hi[kTaps];
+#pragma unroll
+            for (int b = 0; b < kTaps; ++b) {
+                lo[b] = *(const Float4u *)(pl + ry[b]);
+                hi[b] = *(const Float4u *)(pl + ry[b] + 4);
+            }
+            float accy = 0.f;
+#pragma unroll
+            for (int b = 0; b < kTaps; ++b) {
+                float s = 0.f;
+                s = fmaf(wx[0], lo[b].x, s);
+                s = fmaf(wx[1], lo[b].y, s);
+                s = fmaf(wx[2], lo[b].z, s);
+                s = fmaf(wx[3], lo[b].w, s);
+                s = fmaf(wx[4], hi[b].x, s);
+                s = fmaf(wx[5], hi[b].y, s);
+                s = fmaf(wx[6], hi[b].z, s);
+                s = fmaf(wx[7], hi[b].w, s);
+                accy = fmaf(wy[b], s, accy);
+            }
+            acc = fmaf(wz[a], accy, acc);
+        }
+        out[q] = acc;
+        return;
+    }
     for (int a = 0; a < kTaps; ++a) {
         const int jz = min(max(z0 + a, 0), nz - 1);
         float accy = 0.f;
