@@ -277,3 +277,14 @@ def test_salt_argument_errors_touch_nothing():
     assert L.sg_salt_sdt(*args) == sgwave.SG_ENOSPACE
     n = ctypes.c_size_t(0)
     assert L.sg_salt_workspace_size(1 << 12, 1 << 12, 1 << 8, ctypes.byref(n)) == sgwave.SG_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback exists behind the binding: with the library missing,
+    the first call raises instead of computing anything."""
+    monkeypatch.setattr(sgwave, "LIB_PATH", str(tmp_path / "libsgwave.so"))
+    monkeypatch.setattr(sgwave, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        sgwave.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        sgwave.sg_salt_workspace_size(4, 4, 4)
