@@ -154,3 +154,28 @@ def test_field_reaching_far_from_the_body(sign):
     assert K[21:25, 31:35, 76:80].all()     # the cube's core (opening trims its edges)
     assert np.array_equal(mask, K)
     assert np.array_equal(got, ref.astype(np.float32))
+
+
+def test_many_bodies_and_the_size_cut_boundary():
+    """Twelve small bodies leave many components; the size cut is set to one
+    component's exact size, which must be kept (components of fewer voxels go)."""
+    from scipy.ndimage import label, generate_binary_structure
+    shape, h = (40, 48, 56), (10.0, 10.0, 10.0)
+    rng = np.random.default_rng(77)
+    ext = np.array(shape) * 10.0
+    centres = rng.uniform(0.15, 0.85, (12, 3)) * ext
+    radii = rng.uniform(25.0, 70.0, (12, 3))
+    rots = [_rot(*rng.uniform(-1, 1, 3)) for _ in range(12)]
+    grf = _field(12, shape, 2.0, 78)
+    V = _model(shape, 79)
+    _, K1 = OB.salt_sdt(V.astype(np.float64), *h, centres, radii, rots, grf.astype(np.float64), 0.1, 4500.0, 0.0, 1)
+    lab, nc = label(K1, structure=generate_binary_structure(3, 1))
+    sizes = np.sort(np.bincount(lab.ravel())[1:])
+    assert nc >= 6
+    cut = int(sizes[len(sizes) // 2])
+    got, mask, ref, K = _run(V, h, centres, radii, rots, grf, 0.1, 4500.0, 0.0, cut)
+    _report("12 bodies, %d components, cut %d" % (nc, cut), mask, K)
+    kept = np.bincount(label(K, structure=generate_binary_structure(3, 1))[0].ravel())[1:]
+    assert cut in kept and kept.min() >= cut and len(kept) < nc
+    assert np.array_equal(mask, K)
+    assert np.array_equal(got, ref.astype(np.float32))
