@@ -1,5 +1,7 @@
 // Internal declarations shared by the host runtime (sg_runtime.cpp) and the
-// HIP kernels (sg_kernels.hip).  Not part of the public ABI.
+// HIP kernels (sg_kernels.hip: propagator and adjoint; sg_residual.hip: wave
+// residual; sg_builder.hip and sg_salt.hip: model-builder modules).  Not part
+// of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
