@@ -179,3 +179,26 @@ def test_many_bodies_and_the_size_cut_boundary():
     assert cut in kept and kept.min() >= cut and len(kept) < nc
     assert np.array_equal(mask, K)
     assert np.array_equal(got, ref.astype(np.float32))
+
+
+def test_salt_without_a_mask_output_through_the_c_abi():
+    """mask_out may be NULL: the volume is the same as with a mask."""
+    import ctypes
+    import torch
+    shape, h = (24, 20, 28), (10.0, 10.0, 10.0)
+    V = _model(shape, 31)
+    c, r, R = np.array([[120.0, 100.0, 140.0]]), np.array([[70.0, 60.0, 80.0]]), _rot(0.2, 0.3, 0.1).reshape(1, 9)
+    grf = _field(1, shape, 2.0, 32)
+    Vd, gd = _dev(V), _dev(grf)
+    ref, _ = sgwave.salt_sdt(Vd, *h, c, r, R.reshape(1, 3, 3), gd, 0.2, 4500.0, 1600.0, 10)
+    out = torch.empty_like(Vd)
+    ws = torch.empty(sgwave.sg_salt_workspace_size(*shape), dtype=torch.uint8, device="cuda")
+    c64, r64, R64 = (np.ascontiguousarray(a, np.float64) for a in (c, r, R))
+    st = sgwave.lib().sg_salt_sdt(ctypes.c_void_p(Vd.data_ptr()), *shape, *h, 1, c64.ctypes.data, r64.ctypes.data,
+                                  R64.ctypes.data, ctypes.c_void_p(gd.data_ptr()), 0.2, 4500.0, 1600.0, 10,
+                                  ctypes.c_void_p(out.data_ptr()), None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                  None)
+    torch.cuda.synchronize()
+    assert st == sgwave.SG_OK
+    assert torch.equal(out, ref)
+    assert (ref == 4500.0).any()
