@@ -442,8 +442,8 @@ __global__ void __launch_bounds__(kSaltThreads) k_cc_flatten(int64_t n, int *lab
     if (l >= 0 && l != (int)q) label[q] = find_root(label, l);
 }
 
-// Component sizes: each thread counts runs of equal labels over
-// kCountPerThread consecutive voxels and adds each run to a small table of
+// Component sizes: each thread counts runs of equal labels over its
+// kCountPerThread voxels and adds each run to a small table of
 // (label, count) in LDS (linear probing by atomicCAS on the label slot); the
 // table goes to memory with one atomic per distinct label per workgroup, and
 // runs that find the table full go straight to memory.
@@ -469,10 +469,12 @@ __global__ void __launch_bounds__(kSaltThreads) k_cc_count(int64_t n, const int 
         }
         atomicAdd(&count[l], c);
     };
-    const int64_t q0 = ((int64_t)blockIdx.x * kSaltThreads + threadIdx.x) * kCountPerThread;
+    // the workgroup covers kSaltThreads * kCountPerThread consecutive voxels in
+    // chunks of 4 per lane, the lanes on consecutive chunks (coalesced loads)
+    const int64_t blk0 = (int64_t)blockIdx.x * kSaltThreads * kCountPerThread;
     int cur = -1;
     unsigned cnt = 0;
-    auto step = [&](int l) {
+    auto step = [&](int l) {   // runs of equal labels (adjacency does not matter to a count)
         if (l != cur) {
             if (cur >= 0) add(cur, cnt);
             cur = l;
@@ -480,18 +482,18 @@ __global__ void __launch_bounds__(kSaltThreads) k_cc_count(int64_t n, const int 
         }
         ++cnt;
     };
-    if (q0 + kCountPerThread <= n) {
-        const int4 *p4 = (const int4 *)(label + q0);
 #pragma unroll
-        for (int i = 0; i < kCountPerThread / 4; ++i) {
-            const int4 w = p4[i];
+    for (int i = 0; i < kCountPerThread / 4; ++i) {
+        const int64_t q0 = blk0 + ((int64_t)i * kSaltThreads + threadIdx.x) * 4;
+        if (q0 + 4 <= n) {
+            const int4 w = *(const int4 *)(label + q0);
             step(w.x);
             step(w.y);
             step(w.z);
             step(w.w);
+        } else {
+            for (int j = 0; j < 4; ++j) step(q0 + j < n ? label[q0 + j] : -1);
         }
-    } else {
-        for (int i = 0; i < kCountPerThread; ++i) step(q0 + i < n ? label[q0 + i] : -1);
     }
     if (cur >= 0) add(cur, cnt);
     __syncthreads();
