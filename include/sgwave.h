@@ -364,8 +364,8 @@ sg_status sg_wave_residual(const float *frames, int32_t nframes, int32_t nz, int
  * Velocity-model builder modules (App. B): the interbedded band of Deposit
  * (Alg. 1), the vertical warp of Squish (Alg. 2) and the listric normal
  * fault of Fault (Alg. 3), on a device volume
- * [nz][ny][nx] of floats (x fastest; a 2D slice is ny = 1), z = depth.  Both
- * pull-sample the input through an 8-point Kaiser-windowed sinc (beta 6,
+ * [nz][ny][nx] of floats (x fastest; a 2D slice is ny = 1), z = depth.  Squish
+ * and Fault pull-sample the input through an 8-point Kaiser-windowed sinc (beta 6,
  * weights normalised to sum 1, tap indices clamped to the axis), exact at
  * integer positions.  out must not alias the input.  Stream-ordered, no
  * allocation.  SG_EINVAL for NULL pointers, non-positive sizes or spacings,
@@ -411,7 +411,7 @@ sg_status sg_fractal_noise2d(const float *lattice, int32_t noct, int32_t gy, int
 sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, const float *shift, float *out,
                     void *stream);
 
-/* Alg. 3 (one fault; no rough surface or subsidiary faults).  Positions in
+/* Alg. 3 (one fault, smooth or rough; subsidiary faults are further calls).  Positions in
  * metres are (z dz, y dy, x dx).  The cylinder axis runs along the strike
  * s = (cos a, -sin a) in (y, x); it sits at c~ = c - (R sin(dip), R cos(dip) n)
  * with n = (sin a, cos a), a = azimuth.  Each voxel, in the plane across the
@@ -437,13 +437,16 @@ typedef struct sg_fault_params {
      * fractal noise): with rough_lattice non-NULL the surface lies at radius
      * R + rough_amplitude N(u, w), N = normalised fractal value noise as in
      * sg_fractal_noise2d (octave o: lattice o, frequency 2^o, weight 2^-o, sum
-     * divided by sum_o 2^-o) clamped to [-1, 1] (the clamp never acts on a
-     * lattice within [-1, 1]), at u = along-strike
+     * divided by sum_o 2^-o; |N| <= max |lattice|), at u = along-strike
      * offset / rough_lam_strike and w = R (theta - theta0) / rough_lam_dip
      * (down-dip arc length).  It moves the side test (chi) and the
      * across-fault taper; the rotation stays slip / R.  rough_lattice:
      * device floats [rough_noct][rough_gd][rough_gs] (rows down dip, columns
-     * along strike), rough_noct in 1..24, rough_gd, rough_gs >= 1, lam > 0. */
+     * along strike), rough_noct in 1..24, rough_gd, rough_gs >= 1, at most
+     * 2^26 finite values, lam > 0.  With a rough lattice the call reads the
+     * lattice back once to bound the region the fault can move: it
+     * synchronises `stream` (the only builder call besides sg_salt_sdt that
+     * does). */
     const float *rough_lattice;
     int32_t rough_noct, rough_gd, rough_gs;
     double rough_amplitude; /* [m] */

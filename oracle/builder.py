@@ -137,8 +137,8 @@ def fault_source(shape, dz: float, dy: float, dx: float, p: dict):
     columns along strike; None = smooth),
     rough_amplitude, rough_lam_strike, rough_lam_dip [m].  A rough surface
     has radius R + rough_amplitude * N(u, w), N the normalised fractal value
-    noise (fractal_value) clamped to [-1, 1] (no effect on a lattice within
-    [-1, 1]) at u = along-strike offset / rough_lam_strike and
+    noise (fractal_value; it lies within the lattice's range) at
+    u = along-strike offset / rough_lam_strike and
     w = R (theta - theta0) / rough_lam_dip (the down-dip arc length); it
     moves where the fault is (the side test and the across-fault taper) and
     leaves the rotation angle slip / R as it is."""
@@ -164,7 +164,7 @@ def fault_source(shape, dz: float, dy: float, dx: float, p: dict):
     Rs = R
     if p.get("rough_lattice") is not None:
         N = fractal_value(p["rough_lattice"], az / p["rough_lam_strike"], R * (t_old - theta0) / p["rough_lam_dip"])
-        Rs = R + p["rough_amplitude"] * np.clip(N, -1.0, 1.0)
+        Rs = R + p["rough_amplitude"] * N
     rho_r = np.abs(r - Rs) / p["die_r"]
     rho_t = np.abs(t_old - theta0) / math.radians(p["die_theta_deg"])
     rho_s = np.abs(az) / p["die_strike"]

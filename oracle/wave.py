@@ -326,12 +326,13 @@ def c_damp(nbl: int, R: float = 1e-3) -> float:
 
 
 def bandpass_ricker(f0: float, band: tuple[float, float], dt: float, nt: int,
-                    bandwidth_ref: float = 24.0) -> np.ndarray:
-    """Band-limited source of App. E.4: Ricker(f0) centred at 1/f0, 4th-order
-    zero-phase Butterworth band-pass (forward-backward second-order sections),
-    divided by its l2 norm, then scaled by sqrt(B / 24 Hz), B = band width."""
+                    bandwidth_ref: float = 24.0, t0: float | None = None) -> np.ndarray:
+    """Band-limited source of App. E.4: Ricker(f0) centred at t0 (default
+    1/f0), 4th-order zero-phase Butterworth band-pass (forward-backward
+    second-order sections), divided by its l2 norm, then scaled by
+    sqrt(B / 24 Hz), B = band width."""
     from scipy.signal import butter, sosfiltfilt
-    w = ricker(f0, dt, nt)
+    w = ricker(f0, dt, nt, t0=t0)
     sos = butter(4, [band[0], band[1]], btype="bandpass", fs=1.0 / dt, output="sos")
     y = sosfiltfilt(sos, w)
     y = y / np.linalg.norm(y)

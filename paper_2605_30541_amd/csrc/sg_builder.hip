@@ -159,8 +159,7 @@ __device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, 
     if (F.rough && rho_t < 1.0 && rho_s < 1.0 && fabs(r - F.radius) < F.rough_reach) {
         const double u = fmin(fmax(az * F.inv_lam_s, -1e12), 1e12);
         const double w = fmin(fmax(F.radius * (t_old - F.theta0) * F.inv_lam_d, -1e12), 1e12);
-        const double N = fmin(fmax(fractal_sum(F.rough, F.rough_noct, F.rough_gd, F.rough_gs, u, w) * F.rough_inv_norm,
-                                   -1.0), 1.0);
+        const double N = fractal_sum(F.rough, F.rough_noct, F.rough_gd, F.rough_gs, u, w) * F.rough_inv_norm;
         R = F.radius + F.rough_amp * N;
     }
     const double rho_r = fabs(r - R) * F.inv_die_r;
@@ -442,7 +441,7 @@ bool axis_cover(double lo, double hi, double d, int n, int &a, int &b)
 }
 
 // A box holding every voxel the fault can move: the cylinder shell
-// |r - R| < die_r (+ |rough amplitude|), the angle band |theta - theta0| <
+// |r - R| < die_r (+ |rough amplitude| max |lattice|), the angle band |theta - theta0| <
 // die_theta and |along-strike offset| < die_strike, bounded in the (h, v)
 // plane across strike by its corners and axis crossings, then carried to
 // (z, y, x) by interval arithmetic; two voxels of margin.  Outside it every
@@ -451,7 +450,7 @@ bool fault_box(const FaultFrame &F, int nz, int ny, int nx, VoxBox &B)
 {
     const double pi = 3.14159265358979323846;
     const double die_r = 1.0 / F.inv_die_r, die_t = 1.0 / F.inv_die_t, die_s = 1.0 / F.inv_die_s;
-    const double extra = F.rough ? std::fabs(F.rough_amp) : 0.0;
+    const double extra = F.rough ? F.rough_reach - die_r : 0.0;
     const double r_hi = F.radius + die_r + extra, r_lo = std::max(0.0, F.radius - die_r - extra);
     double h_lo, h_hi, v_lo, v_hi;
     if (die_t >= pi) {

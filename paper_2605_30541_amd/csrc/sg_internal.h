@@ -181,9 +181,11 @@ struct FaultFrame {
     double radius, theta0, shift, direction;
     double inv_die_r, inv_die_t, inv_die_s;
     // rough surface (rough == nullptr: smooth): radius + rough_amp * N, N the
-    // noise sum times rough_inv_norm clamped to [-1, 1], at (along-strike
-    // offset * inv_lam_s, radius (theta - theta0) * inv_lam_d); rough_reach =
-    // die_r + |rough_amp| bounds where the noise can matter
+    // noise sum times rough_inv_norm, at (along-strike offset * inv_lam_s,
+    // radius (theta - theta0) * inv_lam_d); |N| <= max |lattice| (each octave
+    // is a convex combination of lattice values and the weights sum to 1), so
+    // rough_reach = die_r + |rough_amp| max |lattice| bounds where the noise
+    // can matter
     const float *rough;      // [rough_noct][rough_gd][rough_gs], device
     int rough_noct, rough_gd, rough_gs;
     double rough_amp, rough_inv_norm, inv_lam_s, inv_lam_d, rough_reach;

@@ -1798,7 +1798,7 @@ sg_status sg_squish(const float *v, int32_t nz, int32_t ny, int32_t nx, double d
 
 namespace {
 // Validates the fault parameters and spacings and builds the device frame.
-sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx, sg::FaultFrame &F)
+sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx, sg::FaultFrame &F, hipStream_t st)
 {
     if (!p) return fail(SG_EINVAL, "NULL argument");
     if (!positive_finite(dz) || !positive_finite(dy) || !positive_finite(dx))
@@ -1849,7 +1849,20 @@ sg_status fault_frame(const sg_fault_params *p, double dz, double dy, double dx,
         F.rough_inv_norm = 1.0 / norm;
         F.inv_lam_s = 1.0 / p->rough_lam_strike;
         F.inv_lam_d = 1.0 / p->rough_lam_dip;
-        F.rough_reach = p->die_r + std::fabs(p->rough_amplitude);
+        // the noise never exceeds the lattice's largest |value|: read it once
+        // (stream-ordered after the caller's work, then synchronised) to bound
+        // the region a rough fault can move
+        const size_t nl = (size_t)p->rough_noct * p->rough_gd * p->rough_gs;
+        if (nl > ((size_t)1 << 26)) return fail(SG_EINVAL, "rough lattice larger than 2^26 values");
+        std::vector<float> lat(nl);
+        SG_HIP(hipMemcpyAsync(lat.data(), p->rough_lattice, nl * sizeof(float), hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+        double amax = 0.0;
+        for (float x : lat) {
+            if (!std::isfinite(x)) return fail(SG_EINVAL, "rough lattice holds a non-finite value");
+            amax = std::max(amax, (double)std::fabs(x));
+        }
+        F.rough_reach = p->die_r + std::fabs(p->rough_amplitude) * amax;
     }
     return SG_OK;
 }
@@ -1861,7 +1874,7 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
     sg_status rc = volume_args(v, nz, ny, nx, out);
     if (rc != SG_OK) return rc;
     sg::FaultFrame F;
-    if ((rc = fault_frame(p, dz, dy, dx, F)) != SG_OK) return rc;
+    if ((rc = fault_frame(p, dz, dy, dx, F, (hipStream_t)stream)) != SG_OK) return rc;
     SG_HIP(sg::launch_fault(v, nz, ny, nx, F, fill, out, (hipStream_t)stream));
     return SG_OK;
 }
@@ -1872,7 +1885,7 @@ sg_status sg_fault_labels(const int32_t *labels, int32_t nz, int32_t ny, int32_t
     sg_status rc = volume_args(labels, nz, ny, nx, out);
     if (rc != SG_OK) return rc;
     sg::FaultFrame F;
-    if ((rc = fault_frame(p, dz, dy, dx, F)) != SG_OK) return rc;
+    if ((rc = fault_frame(p, dz, dy, dx, F, (hipStream_t)stream)) != SG_OK) return rc;
     SG_HIP(sg::launch_fault_labels(labels, nz, ny, nx, F, fill, out, (hipStream_t)stream));
     return SG_OK;
 }

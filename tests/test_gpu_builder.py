@@ -167,7 +167,7 @@ def test_fault_labels_match_the_oracle(case):
         assert np.count_nonzero(ref == -1) > 0
 
 
-@pytest.mark.parametrize("case", ["3d", "2d-slice", "strong", "wide-lattice"])
+@pytest.mark.parametrize("case", ["3d", "2d-slice", "strong", "wide-lattice", "wide-lattice-box"])
 def test_rough_fault_matches_the_oracle(case):
     """A rough fault surface (radius perturbed by fractal noise over
     along-strike and down-dip coordinates): velocities and labels."""
@@ -178,9 +178,14 @@ def test_rough_fault_matches_the_oracle(case):
         ny, p["cy"], p["azimuth_deg"] = 1, 0.0, 0.0
     elif case == "strong":
         amp, lam_s, lam_d, noct = 120.0, 60.0, 50.0, 5
-    span = 3.0 if case == "wide-lattice" else 1.0     # a lattice beyond [-1, 1]: the noise is clamped
-    lat = np.random.default_rng({"3d": 1, "2d-slice": 2, "strong": 3, "wide-lattice": 4}[case]).uniform(
-        -span, span, (noct, 6, 7))
+    elif case == "wide-lattice-box":
+        # a volume much larger than the region the fault can move, so the
+        # launch runs on a box: the box must reach die_r + amplitude max|lattice|
+        nz, ny, nx, amp = 80, 12, 200, 60.0
+    # a lattice beyond [-1, 1]: the noise itself goes past 1 (no clamp)
+    span = 3.0 if case.startswith("wide-lattice") else 1.0
+    lat = np.random.default_rng({"3d": 1, "2d-slice": 2, "strong": 3, "wide-lattice": 4,
+                                 "wide-lattice-box": 5}[case]).uniform(-span, span, (noct, 6, 7))
     lat = lat.astype(np.float32)
     rough = dict(rough_amplitude=amp, rough_lam_strike=lam_s, rough_lam_dip=lam_d)
     p_gpu = dict(p, rough_lattice=torch.from_numpy(lat).cuda(), **rough)

@@ -316,10 +316,13 @@ def test_fault_labels_take_the_voxel_nearest_the_source():
     assert np.array_equal(B.fault_labels(L, h, h, h, dict(p, slip=0.0), -1), L)
 
 
-def test_rough_fault_surface_moves_the_fault_by_the_noise():
+@pytest.mark.parametrize("c", [0.6, 2.5, -1.8])
+def test_rough_fault_surface_moves_the_fault_by_the_noise(c):
     """A rough surface of zero amplitude is the smooth fault; with a constant
     lattice c the noise is exactly c, so the slip changes side exactly where
-    the distance from the axis crosses R + amplitude * c (not at R)."""
+    the distance from the axis crosses R + amplitude * c (not at R), also for
+    a lattice outside [-1, 1] (the paper perturbs the radius by the noise
+    itself; nothing bounds it)."""
     shape, h = (40, 6, 50), 10.0
     p = dict(cz=150.0, cy=25.0, cx=250.0, azimuth_deg=0.0, dip_deg=50.0, radius=400.0, slip=30.0, direction=1,
              die_r=200.0, die_strike=500.0, die_theta_deg=80.0)
@@ -328,7 +331,7 @@ def test_rough_fault_surface_moves_the_fault_by_the_noise():
     (s1, w1) = B.fault_source(shape, h, h, h, dict(p, rough_lattice=lat, rough_amplitude=0.0,
                                                    rough_lam_strike=100.0, rough_lam_dip=80.0))
     assert all(np.array_equal(a, b) for a, b in zip(s0, s1)) and np.array_equal(w0, w1)
-    c, A = 0.6, 50.0
+    A = 50.0
     rough = dict(p, rough_lattice=np.full((2, 3, 3), c), rough_amplitude=A, rough_lam_strike=100.0,
                  rough_lam_dip=80.0)
     (sz, sy, sx), w = B.fault_source(shape, h, h, h, rough)
@@ -347,6 +350,106 @@ def test_rough_fault_surface_moves_the_fault_by_the_noise():
     assert band.sum() > 200
     # rotation -chi * direction: chi = +1 beyond the surface, -1 inside it
     assert np.all(np.sign(tang[band]) == np.where(far[band], -1.0, 1.0) * p["direction"])
-    # voxels between R and R + A c are on the near side now: the smooth fault had them on the far side
-    between = band & (r >= R) & (r < R + A * c)
+    # voxels between R and R + A c changed side: the smooth fault had them on the other one
+    between = band & (r >= min(R, R + A * c)) & (r < max(R, R + A * c))
     assert between.sum() > 20
+
+
+@pytest.mark.parametrize("o", range(4))
+def test_fractal_octave_frequency_and_weight(o):
+    """Octave o of the fractal noise runs at frequency 2^o with weight 2^-o of
+    the sum sum_k 2^-k: a lattice that is non-zero only in octave o gives
+    exactly (2^-o / sum_k 2^-k) times that octave's lattice value at every node
+    of the 2^o-refined grid (the fade is 0 there).  A linear frequency ladder
+    (o + 1) misses the nodes of octaves 2 and 3; weights growing with o, or
+    no normalisation, scale every octave wrongly."""
+    rng = np.random.default_rng(20 + o)
+    noct, gy, gx = 4, 5, 7
+    lat = np.zeros((noct, gy, gx))
+    lat[o] = rng.uniform(-1, 1, (gy, gx))
+    f = 2.0 ** o
+    i = np.arange(-3, 3 * gx + 2)
+    j = np.arange(-2, 2 * gy + 3)
+    U, Wd = np.meshgrid(i / f, j / f)
+    got = B.fractal_value(lat, U, Wd)
+    weight = (1.0 / f) / sum(2.0 ** -k for k in range(noct))
+    ref = weight * lat[o][np.mod(j, gy)[:, None], np.mod(i, gx)[None, :]]
+    assert np.abs(got - ref).max() < 1e-13
+    # the octaves add: the sum of one-octave fields is the field of the sum
+    full = rng.uniform(-1, 1, (noct, gy, gx))
+    u, w = rng.uniform(-5, 20, 300), rng.uniform(-5, 20, 300)
+    parts = sum(B.fractal_value(np.where(np.arange(noct)[:, None, None] == k, full, 0.0), u, w) for k in range(noct))
+    assert np.abs(B.fractal_value(full, u, w) - parts).max() < 1e-13
+
+
+def test_fractal_noise_azimuth_rotates_the_lattice():
+    """Azimuth 90 deg, one octave, grid spacing = wavelength: the along-azimuth
+    coordinate is y and the across coordinate is -x, so the field at node
+    (y, x) is the lattice value at row -x, column y (periodic)."""
+    rng = np.random.default_rng(24)
+    lat = rng.uniform(-1, 1, (1, 6, 6))
+    ny, nx = 9, 11
+    got = B.fractal_noise2d(lat, ny, nx, 50.0, 50.0, 50.0, 50.0, 90.0, 7.0)
+    y, x = np.arange(ny)[:, None], np.arange(nx)[None, :]
+    assert np.abs(got - 7.0 * lat[0][np.mod(-x, 6), np.mod(y, 6)]).max() < 1e-12
+
+
+@pytest.mark.parametrize("which", ["fractal", "value3d"])
+def test_noise_is_twice_continuously_differentiable_across_lattice_nodes(which):
+    """The fade between lattice nodes has zero first and second derivatives at
+    both ends, so the noise is C2 across nodes; midway between two nodes it is
+    their mean.  Linear interpolation (a kink) or the cubic smoothstep (a jump
+    of the second derivative) fails it."""
+    rng = np.random.default_rng(25)
+    h = 1e-4
+    if which == "fractal":
+        lat = rng.uniform(-1, 1, (1, 4, 8))
+        f = lambda u: B.fractal_value(lat, u, np.full_like(u, 2.0))
+        row = lat[0][2]
+    else:
+        lat = rng.uniform(-1, 1, (3, 3, 8))
+        f = lambda u: B.value_noise3d(lat, np.full_like(u, 10.0), np.full_like(u, 20.0), u * 30.0, 10.0, 20.0, 30.0)
+        row = lat[1, 1]
+    for node in range(1, 7):
+        d2 = []
+        for side in (-1, 1):
+            x = node + side * 2 * h
+            v = f(np.array([x - h, x, x + h]))
+            d2.append((v[0] - 2 * v[1] + v[2]) / h ** 2)
+        scale = np.abs(np.diff(row)).max()
+        assert abs(d2[0] - d2[1]) < 0.05 * scale, (node, d2)
+        assert abs(d2[0]) < 0.05 * scale and abs(d2[1]) < 0.05 * scale
+        mid = f(np.array([node + 0.5]))[0]
+        assert mid == pytest.approx(0.5 * (row[node] + row[node + 1]), abs=1e-13)
+
+
+def test_deposit_texture_restarts_at_each_bed_start_with_its_offset():
+    """Alg. 1's texture term a_eta eta_3D(z - S_l, y, x), with the per-bed
+    depth offset into the shared field: with a_B = 0 the bed starts S_l are
+    the cumulative thicknesses; with dy, dx equal to the lattice spacing and
+    lam_z = 2 dz every sample sits on a lattice node (even z - S_l) or midway
+    between two (odd: their mean), so each voxel has a closed form.  Sampling
+    at absolute depth (bed starts not multiples of the lattice period), in
+    cells instead of metres, or without the offsets fails it."""
+    rng = np.random.default_rng(26)
+    t, ny, nx, dz, dy, dx = 64, 3, 5, 4.0, 30.0, 25.0
+    lam = (2 * dz, dy, dx)
+    thick = np.array([7.0, 11.0, 9.0, 13.0, 10.0, 14.0])
+    starts = np.concatenate([[0.0], np.cumsum(thick)[:-1]])
+    vbed = rng.normal(2600, 120, thick.size)
+    gz, gy, gx = 5, 4, 6
+    lat = rng.uniform(-1, 1, (gz, gy, gx))
+    koff = np.array([0, 3, 1, 4, 2, 7])
+    a_eta, beta = 35.0, 0.3
+    V = B.deposit(t, ny, nx, dz, dy, dx, thick, vbed, beta, np.zeros((thick.size - 1, ny, nx)), 0.0, lat, lam,
+                  koff * lam[0], a_eta, 1e-9, 1e-9)
+    vbar = vbed.mean()
+    y, x = np.arange(ny)[:, None], np.arange(nx)[None, :]
+    for z in range(1, t):
+        bed = int(np.searchsorted(starts, z, side="right") - 1)
+        q2 = (z - int(starts[bed])) + 2 * koff[bed]          # twice the lattice coordinate
+        a = lat[(q2 // 2) % gz][y % gy, x % gx]
+        b = lat[(q2 // 2 + 1) % gz][y % gy, x % gx]
+        eta = a if q2 % 2 == 0 else 0.5 * (a + b)
+        ref = vbar + beta * z * dz + (vbed[bed] - vbar) + a_eta * eta
+        assert np.abs(V[z] - ref).max() < 1e-9, z

@@ -144,3 +144,48 @@ def test_bandpass_wavelet_energy_scaling():
         f = np.fft.rfftfreq(nt, dt)
         inside = W[(f >= b["fmin"]) & (f <= b["fmax"])].sum()
         assert inside / W.sum() > 0.8
+
+
+def _butterworth_bandpass_power(f, band, fs, order):
+    """Squared gain of a band-pass Butterworth filter whose low-pass prototype
+    has `order` poles, designed through the bilinear map with the corners
+    pre-warped: with t = tan(pi f / fs) and t1, t2 the warped corners,
+    |H|^2 = 1 / (1 + x^(2 order)), x = (t^2 - t1 t2) / (t (t2 - t1)).
+    Forward-backward filtering multiplies by H(z) H(1/z) = |H|^2 on the unit
+    circle, so this is the whole gain of the zero-phase filter, real and
+    non-negative (-6 dB in amplitude at each corner)."""
+    t = np.tan(np.pi * f / fs)
+    t1, t2 = np.tan(np.pi * band[0] / fs), np.tan(np.pi * band[1] / fs)
+    x = (t * t - t1 * t2) / (t * (t2 - t1))
+    return 1.0 / (1.0 + x ** (2 * order))
+
+
+@pytest.mark.parametrize("ib", range(5))
+def test_bandpass_wavelet_is_the_zero_phase_4th_order_butterworth(ib):
+    """App. E.4: 4th-order zero-phase Butterworth.  A Ricker centred in a long
+    trace (zero at both ends, so the filter acts as on an infinite sequence)
+    gives an output whose spectrum over the Ricker's is real, non-negative and
+    proportional to the closed-form squared Butterworth gain of order 4.
+    Order 2 or 8, or a single causal pass (complex ratio, |H| not |H|^2),
+    fails it; so does a filter that is not symmetric in time."""
+    dt, nt = 1e-3, 1 << 15
+    f0 = GOLDEN["peak_frequencies_hz"]["value"][ib]
+    b = GOLDEN["bands"][ib]
+    band = (b["fmin"], b["fmax"])
+    c = nt // 2
+    y = oracle.bandpass_ricker(f0, band, dt, nt, t0=c * dt)
+    r = oracle.ricker(f0, dt, nt, t0=c * dt)
+    # zero phase: the output is as symmetric about the centre as the input
+    assert np.abs(y[c + 1:c + 4000] - y[c - 1:c - 4000:-1]).max() < 1e-10 * np.abs(y).max()
+    Y, R = np.fft.rfft(y), np.fft.rfft(r)
+    f = np.fft.rfftfreq(nt, dt)
+    ok = (np.abs(R) > 1e-6 * np.abs(R).max()) & (f > 0)
+    ratio = Y[ok] / R[ok]
+    G = _butterworth_bandpass_power(f[ok], band, 1.0 / dt, 4)
+    scale = np.sum(ratio.real * G) / np.sum(G * G)
+    assert scale > 0
+    assert np.abs(ratio.imag).max() < 1e-7 * scale
+    assert np.abs(ratio.real - scale * G).max() < 1e-7 * scale
+    # the -6 dB points sit at the band corners
+    for fc in band:
+        assert _butterworth_bandpass_power(np.array([fc]), band, 1.0 / dt, 4)[0] == pytest.approx(0.5, rel=1e-12)
