@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the acoustic propagator on one MI355X.
 
-Workload (one "step"): the field-scale single shot -- a seeded 620 x 1001
-velocity slice at 10 m with a 40-cell sponge and a free surface, dt 0.8 ms,
-nt 10000 levels (8 s), a 12 Hz Ricker source at (10 m, 5000 m), 1001
-receivers at 10 m, snapshots every 100 steps over the first 5 s.  Inputs are
-resident in HBM before the timed region.
+Workload (one "step"): the batched forward of 8 seeded field slices of
+uneven size (nz 400-620, nx 601-1001 at 10 m, 40-cell sponge, free surface;
+sizes from rng(42), slice i seeded 42 + i) x 64 shots each at 10 m depth
+evenly spaced on [1.1 km, W - 1.1 km], dt 0.8 ms, nt 10000 levels (8 s), a
+12 Hz Ricker, receivers on every surface column, all shots of all slices in
+one time-blocked launch per time block, replayed from a hipGraph with the
+batch-autotuned tiling.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line: grid-point updates per second over the padded grid
-(660 x 1081 points x 9999 updates per step), the HBM-roofline position of the
-time-stepping kernel, and the FP64 oracle timed on a bounded sample on the
-host cores.  Beside it, on the same GPU: the forward + adjoint-gradient rate
-(16 shots on the same slice, checkpoints every 100 levels), the batched rate
-(8 slices of uneven size x 64 shots in one launch per time block) and the
+Prints one JSON line: grid-point updates per second over the padded grids
+(points x 9999 updates x 64 shots summed over the slices), the HBM-roofline
+position of the time-stepping kernel (k_tiled_batch), and the FP64 oracle
+timed on a bounded sample of the same workload on the host cores.  Beside
+it, on the same GPU: the field-scale single shot (620 x 1001), the
+forward + adjoint-gradient rate (16 shots on that slice, checkpoints every
+100 levels), the full-density batched gradient (4 slices x 100 shots), the
 paper's production shape (4 slices of 619 x 1000, 64 shots, 8001 levels,
-gathers decimated by 14); optionally the 4 x 100-shot batched gradient.
+gathers decimated by 14), the physics-residual pass and the builder modules.
 """
 import argparse
 import hashlib
@@ -28,30 +31,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_UPDATE = 16.0        # read p^n, p^{n-1}, coefficient; write p^{n+1}
+LEGS = ("batch", "field_shot", "gradient", "batched_gradient", "paper", "residual", "builder")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--variant", type=int, default=None)
-    ap.add_argument("--tile-x", type=int, default=0)
-    ap.add_argument("--tile-z", type=int, default=0)
-    ap.add_argument("--time-block", type=int, default=0)
-    ap.add_argument("--rows-per-thread", type=int, default=0)
+    ap.add_argument("--only", choices=LEGS, default=None,
+                    help="run one workload only (for profiling runs); 'batch' is the headline")
+    ap.add_argument("--levels", type=int, default=10000,
+                    help="time levels of the headline batch (shorter runs for counter profiles)")
+    ap.add_argument("--batch-tuning", type=str, default="",
+                    help="tile_x,tile_z,time_block for the headline batch instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-levels", type=int, default=10000)
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the gradient and batched comparisons")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--batched-gradient", action="store_true",
-                    help="also run the 4 slices x 100 shots batched gradient (about a minute)")
+    ap.add_argument("--cpu-sample-slices", type=int, default=3)
     ap.add_argument("--shots-per-wave", type=int, default=25)
-    ap.add_argument("--residual-only", action="store_true",
-                    help="time only the physics-residual pass over the 572-frame stack and print its record")
-    ap.add_argument("--builder-only", action="store_true",
-                    help="time only the builder modules on a 619x1000x1000 volume and print their record")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -68,33 +64,181 @@ def kernel_source_sha():
 
 
 def traffic_record(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
+    """Counter record of a kernel on a workload from profiles/, if it was taken
+    on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
     if rec.get("kernel_src_sha") != kernel_source_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
-def cpu_baseline(v, geom, src, rec, f0, levels):
+def kernel_shape(tuning):
+    """Template arguments <K, NWX, NWZ> of the tiled kernel a tuning runs."""
+    k = tuning.get("rows_per_thread") or 8
+    return {(128, 64, 8): "8, 2, 8", (64, 128, 16): "16, 1, 8", (64, 64, 8): "8, 1, 8",
+            (128, 64, 16): "16, 2, 4"}.get((tuning["tile_x"], tuning["tile_z"], k), "?")
+
+
+def batch_items(levels):
+    """The headline batch: 8 uneven slices x 64 shots; returns (items, padded
+    points x shots, [(geom, v, src, rec)] per slice)."""
+    import torch
+    from paper_2605_30541_amd import sgwave, synth
+    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
+    dt = 8e-4
+    items, points, cases = [], 0, []
+    for i, (nz, nx) in enumerate(synth.uneven_sizes(42, 8)):
+        geom = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=dt, nt=levels, nbl=40, vmax_hint=4500.0)
+        plan = Plan(geom)
+        W = (nx - 1) * 10.0
+        src = synth.shot_line(64, 1100.0, W - 1100.0)
+        rec = synth.surface_receivers(nx, 10.0)
+        v = synth.field_slice(42 + i, nz, nx)
+        shots = Shots(src, rec, sgwave.ricker_tensor(12.0, dt, levels))
+        gathers = torch.empty((64, geom.nrow, nx), dtype=torch.float32, device="cuda")
+        items.append((plan, torch.from_numpy(v).cuda(), shots, gathers, None))
+        Nz, Nx = plan.padded_shape
+        points += Nz * Nx * 64
+        cases.append((geom, v, src, rec))
+    return items, points, cases
+
+
+def batch_headline(args):
+    """Times K replays of the headline batch (after W untimed ones), and the
+    average launch of its time-stepping kernel from events on the stream the
+    graph is launched on."""
+    import torch
+    from paper_2605_30541_amd import sgwave
+    levels = args.levels
+    items, points, cases = batch_items(levels)
+    ws = torch.empty(sgwave.sg_batch_workspace_size(items), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    if args.batch_tuning:
+        tx, tz, tb = (int(x) for x in args.batch_tuning.split(","))
+        tuning = dict(variant=2, tile_x=tx, tile_z=tz, time_block=tb, rows_per_thread=0)
+    else:
+        tuning = sgwave.sg_batch_autotune(items, ws, 32)          # untimed
+    log("headline batch: tuning %s" % tuning)
+
+    def step():
+        sgwave.sg_batch_forward(items, ws, tuning, stream)
+
+    for _ in range(args.warmup):
+        step()                     # the first one records and instantiates the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(args.steps):
+        step()
+        torch.cuda.synchronize()   # (progress line per step; a step is seconds of GPU work)
+        log("headline batch: step %d of %d done" % (k + 1, args.steps))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    for it in items:
+        sgwave.sg_check_finite(it[3], ws)
+    updates = points * (levels - 1)
+    value = updates * args.steps / (ms / 1e3) / 1e9
+    tb = tuning["time_block"] or 3
+    launches = -(-(levels - 1) // tb)
+    # each replay is `launches` time-stepping launches (plus one small record
+    # launch for the last level): their average duration, gaps included
+    avg_ms = ms / args.steps / launches
+    bytes_per_launch = BYTES_PER_UPDATE * updates / launches
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    shape = kernel_shape(tuning)
+    rec = traffic_record("k_tiled_batch", "uneven_batch")
+    traffic = None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_tiled_batch<%s, 0, true>" % shape, "launches_per_step": launches,
+            "avg_launch_us": avg_ms * 1e3, "bytes_per_update": BYTES_PER_UPDATE,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+    if rec is not None and rec.get("tuning") == [tuning["tile_x"], tuning["tile_z"], tb]:
+        traffic = rec["hbm_bytes_per_launch"]
+        roof["traffic"] = traffic
+        roof["measured_hbm_GBs"] = traffic / (avg_ms / 1e3) / 1e9
+        roof["measured_hbm_frac"] = roof["measured_hbm_GBs"] / HBM_PEAK_GBS
+        if rec.get("valu_insts_per_update") is not None:
+            roof["valu_insts_per_update"] = rec["valu_insts_per_update"]
+        roof["counters"] = rec.get("source")
+    return {"value": value, "ms": ms, "tuning": tuning, "roofline": roof, "updates_per_step": updates,
+            "points": points}, cases
+
+
+def cpu_baseline(cases, nslices):
+    """The FP64 oracle on a bounded sample of the headline workload: shot 0
+    of each of the first `nslices` slices over all levels."""
     import numpy as np
     import oracle
     threads = min(16, os.cpu_count() or 1)
     used = oracle.set_threads(threads)
-    og = oracle.Geometry(nz=geom.nz, nx=geom.nx, dz=geom.dz, dx=geom.dx, dt=geom.dt, nt=levels,
-                         nbl=geom.nbl, top_free=True, R=geom.damp_R)
-    w = oracle.ricker(f0, geom.dt, levels)
-    t0 = time.perf_counter()
-    oracle.forward(og, v.astype(np.float64), src, w, rec)
-    sec = time.perf_counter() - t0
-    Nz, Nx = og.padded_shape
-    rate = Nz * Nx * (levels - 1) / sec / 1e9
-    return {"value": rate, "unit": "Gpt-updates/s", "cores": used, "kind": "oracle",
-            "sample": "FP64 oracle, one shot of the same 620x1001 slice and acquisition, "
-                      "%d of 10000 levels (%.1f s wall)" % (levels, sec)}
+    upd, sec = 0, 0.0
+    for geom, v, src, rec in cases[:nslices]:
+        og = oracle.Geometry(nz=geom.nz, nx=geom.nx, dz=geom.dz, dx=geom.dx, dt=geom.dt, nt=geom.nt,
+                             nbl=geom.nbl, top_free=True, R=geom.damp_R)
+        w = oracle.ricker(12.0, geom.dt, geom.nt)
+        t0 = time.perf_counter()
+        oracle.forward(og, v.astype(np.float64), src[:1], w, rec)
+        sec += time.perf_counter() - t0
+        Nz, Nx = og.padded_shape
+        upd += Nz * Nx * (geom.nt - 1)
+    return {"value": upd / sec / 1e9, "unit": "Gpt-updates/s", "cores": used, "kind": "oracle",
+            "sample": "FP64 oracle, shot 0 of each of the first %d of the 8 slices, all %d levels "
+                      "(%.1f s wall)" % (nslices, cases[0][0].nt, sec)}
+
+
+def field_shot_rate(steps=20):
+    """The field-scale single shot: a 620 x 1001 slice (seed 42) at 10 m with a
+    40-cell sponge, dt 0.8 ms, nt 10000, a 12 Hz Ricker at (10 m, 5000 m), 1001
+    receivers, 63 snapshots every 100 levels; single-call path, autotuned."""
+    import numpy as np
+    import torch
+    from paper_2605_30541_amd import sgwave, synth
+    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
+    nz, nx, h, dt, nt, f0 = 620, 1001, 10.0, 8e-4, 10000, 12.0
+    geom = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0,
+                    snap_every=100, snap_count=63)
+    v = synth.field_slice(42, nz, nx)
+    plan = Plan(geom)
+    vp = torch.from_numpy(v).cuda()
+    shots = Shots(np.array([[10.0, 5000.0]]), synth.surface_receivers(nx, h), sgwave.ricker_tensor(f0, dt, nt))
+    gathers = torch.empty((1, geom.nrow, nx), dtype=torch.float32, device="cuda")
+    snaps = torch.empty((1, geom.snap_count, nz, nx), dtype=torch.float32, device="cuda")
+    ws = torch.empty(sgwave.sg_forward_workspace_size(plan, 1, nx), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    sgwave.sg_autotune(plan, vp, shots, 64, ws, stream)
+    tuning = plan.get_tuning(1)
+
+    def step():
+        sgwave.sg_forward(plan, vp, shots, gathers, snaps, ws, stream)
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    Nz, Nx = plan.padded_shape
+    updates = Nz * Nx * (nt - 1)
+    plan.set_profiling(True)
+    step()
+    kms, launches = plan.profile()
+    plan.set_profiling(False)
+    torch.cuda.synchronize()
+    avg_ms = kms / launches
+    achieved = BYTES_PER_UPDATE * updates / launches / (avg_ms / 1e3) / 1e9
+    sgwave.sg_check_finite(gathers, ws)
+    return {"workload": "field-scale single shot forward: 620x1001 @10 m + 40-cell sponge (660x1081 padded), "
+                        "dt 0.8 ms, nt 10000, 12 Hz Ricker, 1001 receivers, 63 snapshots every 100 steps",
+            "ms": ms, "value": updates / (ms / 1e3) / 1e9, "unit": "Gpt-updates/s", "tuning": tuning,
+            "kernel": "k_tiled", "avg_launch_us": avg_ms * 1e3, "launches": launches,
+            "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}, v
 
 
 def gradient_rate(v, fwd_rate):
@@ -132,46 +276,7 @@ def gradient_rate(v, fwd_rate):
     return {"workload": "forward with checkpoints + adjoint-state gradient, 16 shots on the 620x1001 "
                         "slice, nt 10000, checkpoints every 100 levels (segment recompute)",
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
-            "ratio_to_forward_value": rate / fwd_rate}
-
-
-def batched_rate(fwd_rate):
-    """8 field slices of uneven size (nz 400-620, nx 601-1001) x 64 shots,
-    nt 10000 at 0.8 ms, receivers on every column, one launch per time block."""
-    import numpy as np
-    import torch
-    from paper_2605_30541_amd import sgwave, synth
-    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
-    dt, nt = 8e-4, 10000
-    items, points = [], 0
-    for i, (nz, nx) in enumerate(synth.uneven_sizes(42, 8)):
-        geom = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
-        plan = Plan(geom)
-        W = (nx - 1) * 10.0
-        shots = Shots(synth.shot_line(64, 1100.0, W - 1100.0), synth.surface_receivers(nx, 10.0),
-                      sgwave.ricker_tensor(12.0, dt, nt))
-        items.append((plan, torch.from_numpy(synth.field_slice(42 + i, nz, nx)).cuda(), shots))
-        Nz, Nx = plan.padded_shape
-        points += Nz * Nx * 64
-    full = [(p_, v_, s_, torch.empty((64, p_.geom.nrow, s_.nrec), dtype=torch.float32, device="cuda"), None)
-            for p_, v_, s_ in items]
-    ws = torch.empty(sgwave.sg_batch_workspace_size(full), dtype=torch.uint8, device="cuda")
-    tuning = sgwave.sg_batch_autotune(full, ws, 32)   # untimed
-    sgwave.sg_batch_forward(full, ws, tuning)  # warm-up: captures and instantiates the graph
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    sgwave.sg_batch_forward(full, ws, tuning)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    rate = points * (nt - 1) / (ms / 1e3) / 1e9
-    launches = -(-(nt - 1) // tuning["time_block"])
-    achieved = BYTES_PER_UPDATE * points * (nt - 1) / (ms / 1e3) / 1e9
-    return {"workload": "8 uneven field slices (nz 400-620, nx 601-1001, 40-cell sponge) x 64 shots, "
-                        "nt 10000, 1 launch per time block, graph replay, batch-autotuned tiling",
-            "ms": ms, "value": rate, "unit": "Gpt-updates/s", "ratio_to_forward_value": rate / fwd_rate,
-            "tuning": tuning, "launches": launches, "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}
+            "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
 
 def paper_workload_rate(fwd_rate):
@@ -209,7 +314,7 @@ def paper_workload_rate(fwd_rate):
     return {"workload": "4 field slices 619x1000 @10 m + 60-cell sponge (679x1120 padded) x 64 shots, dt 1 ms, "
                         "nt 8001, 1000 receivers, gathers decimated by 14 -> [64][572][1000] per slice",
             "ms": ms, "value": rate, "unit": "Gpt-updates/s", "tuning": tuning,
-            "ratio_to_forward_value": rate / fwd_rate}
+            "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
 
 def copy_reference(mib):
@@ -402,7 +507,7 @@ def batched_gradient_rate(fwd_rate, shots_per_wave):
                         "forward with checkpoints every 100 levels + segment recompute + adjoint, "
                         "%d shots per slice per wave" % shots_per_wave,
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
-            "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate}
+            "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
 
 def main():
@@ -412,68 +517,32 @@ def main():
               "(shots shard across GPUs with no communication, see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.residual_only or args.builder_only:
-        out = {"physics_residual": residual_rate()} if args.residual_only else {"builder": builder_rate()}
+    import torch
+    torch.cuda.set_device(0)
+    want = (lambda leg: args.only in (None, leg))
+    out = {}
+    if args.only not in (None, "batch"):
+        # a profiling run of one sub-workload: print its record only
+        if args.only == "field_shot":
+            out["field_shot"], _ = field_shot_rate()
+        elif args.only == "gradient":
+            from paper_2605_30541_amd import synth
+            out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None)
+        elif args.only == "batched_gradient":
+            out["batched_gradient"] = batched_gradient_rate(None, args.shots_per_wave)
+        elif args.only == "paper":
+            out["paper_workload"] = paper_workload_rate(None)
+        elif args.only == "residual":
+            out["physics_residual"] = residual_rate()
+        elif args.only == "builder":
+            out["builder"] = builder_rate()
         copy_reference(args.copy_mib)
         print(json.dumps(out), flush=True)
         return
-    import numpy as np
-    import torch
 
-    from paper_2605_30541_amd import sgwave, synth
-    from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
-
-    torch.cuda.set_device(0)
-    nz, nx, h, dt, nt, f0 = 620, 1001, 10.0, 8e-4, 10000, 12.0
-    geom = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0,
-                    snap_every=100, snap_count=63)
-    v = synth.field_slice(42, nz, nx)
-    src = np.array([[10.0, 5000.0]])
-    rec = synth.surface_receivers(nx, h)
-    plan = Plan(geom)
-    vp = torch.from_numpy(v).cuda()
-    shots = Shots(src, rec, sgwave.ricker_tensor(f0, dt, nt))
-    gathers = torch.empty((1, geom.nrow, nx), dtype=torch.float32, device="cuda")
-    snaps = torch.empty((1, geom.snap_count, nz, nx), dtype=torch.float32, device="cuda")
-    ws = torch.empty(sgwave.sg_forward_workspace_size(plan, 1, nx), dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
-    if args.variant is not None:
-        plan.set_tuning(variant=args.variant, tile_x=args.tile_x, tile_z=args.tile_z,
-                        time_block=args.time_block, rows_per_thread=args.rows_per_thread)
-    elif not args.no_autotune:
-        sgwave.sg_autotune(plan, vp, shots, 64, ws, stream)     # untimed, part of warm-up
-    tuning = plan.get_tuning(1)
-
-    def step():
-        sgwave.sg_forward(plan, vp, shots, gathers, snaps, ws, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    Nz, Nx = plan.padded_shape
-    updates = Nz * Nx * (nt - 1)
-    value = updates * args.steps / (ms / 1e3) / 1e9
-
-    # dominant kernel: the time-stepping launches, timed as one back-to-back run
-    plan.set_profiling(True)
-    step()
-    kms, launches = plan.profile()
-    plan.set_profiling(False)
-    torch.cuda.synchronize()
-    avg_ms = kms / launches
-    bytes_per_launch = BYTES_PER_UPDATE * updates / launches
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    kernel = "k_step_naive" if tuning["variant"] == 1 else "k_tiled"
-    traffic = traffic_record(kernel, "field_shot")
-    sgwave.sg_check_finite(gathers, ws)
-
+    head, cases = batch_headline(args)
+    value = head["value"]
+    log("headline batch: %.1f Gpt-updates/s" % value)
     out = {
         "metric": "Gpt-updates/s & %HBM roofline: fwd vs fwd+adjoint grad, 1 MI355X, <=1e-4 rel L2",
         "value": value,
@@ -481,30 +550,28 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": head["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "field-scale single shot forward: 620x1001 @10 m + 40-cell sponge "
-                               "(660x1081 padded), dt 0.8 ms, nt 10000, 12 Hz Ricker, 1001 receivers, "
-                               "63 snapshots every 100 steps",
-                   "shots": 1, "padded_points": Nz * Nx, "updates_per_step": updates,
-                   "tuning": tuning},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel, "launches_per_step": launches,
-                     "avg_launch_us": avg_ms * 1e3,
-                     "bytes_per_update": BYTES_PER_UPDATE},
+        "config": {"workload": "batched forward: 8 field slices of uneven size (nz 400-620 x nx 601-1001 @10 m, "
+                               "seeds 42-49, 40-cell sponge, free surface) x 64 shots each, dt 0.8 ms, nt %d, "
+                               "12 Hz Ricker, receivers on every surface column, one launch per time block "
+                               "replayed from a hipGraph, batch-autotuned tiling" % args.levels,
+                   "slices": 8, "shots_per_slice": 64, "padded_points_x_shots": head["points"],
+                   "updates_per_step": head["updates_per_step"], "tuning": head["tuning"]},
+        "roofline": head["roofline"],
         "cpu_baseline": None,
     }
-    log("field shot: %.1f Gpt-updates/s" % value)
-    if not args.no_extras:
+    if args.only is None:
+        out["field_shot"], v = field_shot_rate()
+        log("field shot: %.1f Gpt-updates/s" % out["field_shot"]["value"])
         out["gradient"] = gradient_rate(v, value)
         log("gradient: %.1f Gpt-steps/s" % out["gradient"]["value"])
-        out["batched"] = batched_rate(value)
-        log("batched: %.1f Gpt-updates/s" % out["batched"]["value"])
+        out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
+        log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
         out["paper_workload"] = paper_workload_rate(value)
         log("paper-shaped batch: %.1f Gpt-updates/s" % out["paper_workload"]["value"])
         out["physics_residual"] = residual_rate()
@@ -512,13 +579,10 @@ def main():
         out["builder"] = builder_rate()
         log("builder: squish %.2f ms, fault %.1f ms per 619x1000x1000 volume, deposit %.2f ms per band" % (
             out["builder"]["squish_ms"], out["builder"]["fault_ms"], out["builder"]["deposit_ms"]))
-    if args.batched_gradient:
-        out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
-        log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
     copy_reference(args.copy_mib)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.levels == 10000:
         log("timing the oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(v, geom, src, rec, f0, args.cpu_sample_levels)
+        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_sample_slices)
     print(json.dumps(out), flush=True)
 
 

@@ -22,9 +22,14 @@
  *     a workspace whose size the *_workspace_size calls report.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *     their work on it and return without waiting for the device.  Host
- *     tables are staged in pinned host memory owned by the plan and copied to
- *     the workspace with hipMemcpyAsync; a plan's staging buffer is reused
- *     only after its previous copy has completed.
+ *     tables are staged in pinned host memory owned by the plan (four slots
+ *     used in turn) and copied to the workspace with hipMemcpyAsync; a slot
+ *     is reused only after its previous copy has completed, so the host runs
+ *     up to three calls on a plan ahead of the GPU without blocking.  The
+ *     slots are sized at sg_plan_create for the forward tables of up to 64
+ *     shots and 2 nx receivers; a call needing more grows them once (a
+ *     pinned host allocation), which sg_plan_reserve does beforehand.
+ *     Calls that share a workspace must be ordered on one stream.
  *   - Inputs are validated before anything is enqueued: on an error return
  *     no output and no workspace byte is touched.  No C++ exception crosses
  *     the ABI.  sg_last_error() returns a thread-local message for the last
@@ -155,7 +160,8 @@ const char *sg_status_string(sg_status s);
 const char *sg_last_error(void);
 
 /*
- * Validate a geometry and create a plan (host only, no device work).
+ * Validate a geometry and create a plan (no device work; where a device is
+ * present it reserves the plan's pinned staging, see the conventions above).
  * Returns SG_EINVAL for bad sizes (among them a stored padded field, guard
  * ring included, of more than 2^29 cells: the kernels address a field with
  * 32-bit byte offsets, the FP64 gradient accumulator included), SG_ECFL when
@@ -166,6 +172,14 @@ sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out);
 
 /* Destroy a plan; NULL is accepted. */
 sg_status sg_plan_destroy(sg_plan *p);
+
+/* Size the plan's pinned table staging for calls of up to nshot shots and
+ * nrec receivers: the forward calls, and with ckpt_every > 0 also the
+ * gradient calls with that checkpoint spacing (their residual-injection
+ * tables are larger).  Later calls within those sizes allocate nothing on
+ * the host.  SG_EINVAL for nshot < 1, nrec < 0 or ckpt_every < 0, SG_EHIP if
+ * pinned memory cannot be allocated. */
+sg_status sg_plan_reserve(sg_plan *p, int32_t nshot, int32_t nrec, int32_t ckpt_every);
 
 /* Warning bits (SG_WARN_*) raised by sg_plan_create. */
 uint32_t sg_plan_warnings(const sg_plan *p);

@@ -22,10 +22,21 @@ def sources():
                   if f.endswith((".hip", ".cpp", ".h")))
 
 
-def build(verbose: bool = False) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (in parallel) and links the library.  With
+    `incremental`, objects newer than their source and every header are
+    kept."""
     os.makedirs(OUT_DIR, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    objs = []
+    objs, procs = [], []
+    hdr = _headers_mtime()
     for f in sorted(os.listdir(CSRC)):
         src = os.path.join(CSRC, f)
         if f.endswith(".hip"):
@@ -35,11 +46,16 @@ def build(verbose: bool = False) -> str:
         else:
             continue
         obj = os.path.join(OUT_DIR, f + ".o")
+        objs.append(obj)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), hdr):
+            continue
         cmd = [HIPCC, "-c", *flags, *inc, src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    for cmd, pr in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     # export only the C ABI (sg_*)
     vscript = os.path.join(OUT_DIR, "exports.map")
     with open(vscript, "w") as f:
@@ -55,4 +71,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

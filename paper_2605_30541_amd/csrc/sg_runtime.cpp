@@ -70,6 +70,19 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+// Pinned host staging of the per-call tables.  A call fills one slot and
+// copies it into the workspace on the caller's stream; the slot's event marks
+// the end of that copy.  Slots are used in turn, so a slot is waited for only
+// when kStageSlots calls are still queued ahead of its last copy: the host
+// runs up to kStageSlots - 1 calls ahead of the GPU without blocking.
+constexpr int kStageSlots = 4;
+struct StageSlot {
+    void *buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;      // done was recorded after the last copy
+};
+
 struct sg_plan {
     sg_geometry g;
     int32_t Nz, Nx, ztop, xleft, pitch, nrow;
@@ -77,10 +90,8 @@ struct sg_plan {
     uint32_t warnings;
     sg_tuning tuning;          // zeros = library choice
     std::vector<float> gx, gz; // eta / (2 dt) per padded column / row
-    // pinned staging for the per-call tables, reused across calls
-    void *stage = nullptr;
-    size_t stage_bytes = 0;
-    hipEvent_t stage_done = nullptr;
+    StageSlot stage[kStageSlots];
+    int stage_next = 0;
     std::mutex mu;
     // optional per-launch timing of the time-stepping kernels
     bool profiling = false;
@@ -334,25 +345,54 @@ sg_status tiling_for(const sg_plan *p, const sg_tuning &t, int *config, sg::Tili
     return SG_OK;
 }
 
+// Grows every staging slot of the plan to at least `bytes` (pinned host
+// memory) and creates the slots' events.  Caller holds p->mu.
+sg_status reserve_stage(sg_plan *p, size_t bytes)
+{
+    for (StageSlot &sl : p->stage) {
+        if (!sl.done) SG_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+        if (sl.bytes >= bytes) continue;
+        if (sl.pending) SG_HIP(hipEventSynchronize(sl.done));
+        sl.pending = false;
+        if (sl.buf) SG_HIP(hipHostFree(sl.buf));
+        sl.buf = nullptr;
+        sl.bytes = 0;
+        SG_HIP(hipHostMalloc(&sl.buf, bytes, hipHostMallocDefault));
+        sl.bytes = bytes;
+    }
+    return SG_OK;
+}
+
+// Table bytes (staged per call) of a call with nshot shots and nrec receivers.
+size_t table_bytes(const sg_plan *p, int nshot, int nrec, int ckpt)
+{
+    const Layout L = layout_of(p, nshot, nrec, ckpt);
+    return L.tables_end - L.gx;
+}
+
 // Copy the 1D damping tables and the acquisition tables of `sh` into the
-// workspace (pinned staging + async copy; the staging buffer is reused only
-// after the previous copy out of it has finished).  `T` (may be null) gives
-// the tiling whose per-tile receiver lists are built.
+// workspace: filled in the plan's next staging slot, copied on `st`.  A slot
+// smaller than the tables grows (one pinned allocation) unless `may_alloc`
+// is false, which gives SG_ENOSPACE instead.  `T` (may be null) gives the
+// tiling whose per-tile receiver lists are built.
 sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *sh, const sg::Tiling *T,
-                        hipStream_t st)
+                        hipStream_t st, bool may_alloc = true)
 {
     const size_t bytes = L.tables_end - L.gx;
     std::lock_guard<std::mutex> lock(p->mu);
-    if (p->stage_done) SG_HIP(hipEventSynchronize(p->stage_done));
-    if (p->stage_bytes < bytes) {
-        if (p->stage) SG_HIP(hipHostFree(p->stage));
-        p->stage = nullptr;
-        p->stage_bytes = 0;
-        SG_HIP(hipHostMalloc(&p->stage, bytes, hipHostMallocDefault));
-        p->stage_bytes = bytes;
+    StageSlot &slot = p->stage[p->stage_next];
+    if (slot.bytes < bytes || !slot.done) {
+        if (!may_alloc)
+            return fail(SG_ENOSPACE, "the plan's pinned staging holds %zu bytes of tables, this call needs %zu "
+                        "(sg_plan_reserve sizes it)", slot.bytes, bytes);
+        sg_status rc = reserve_stage(p, bytes);
+        if (rc != SG_OK) return rc;
     }
-    if (!p->stage_done) SG_HIP(hipEventCreateWithFlags(&p->stage_done, hipEventDisableTiming));
-    char *h = (char *)p->stage;
+    // the copy out of this slot kStageSlots calls ago must have finished
+    if (slot.pending) SG_HIP(hipEventSynchronize(slot.done));
+    slot.pending = false;
+    p->stage_next = (p->stage_next + 1) % kStageSlots;
+    char *h = (char *)slot.buf;
     auto at = [&](size_t off) { return h + (off - L.gx); };
     std::memset(h, 0, bytes);
     std::memcpy(at(L.gx), p->gx.data(), p->gx.size() * sizeof(float));
@@ -455,7 +495,8 @@ sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *s
         cps[ncell] = (int32_t)npair;
     }
     SG_HIP(hipMemcpyAsync(ws + L.gx, h, bytes, hipMemcpyHostToDevice, st));
-    SG_HIP(hipEventRecord(p->stage_done, st));
+    SG_HIP(hipEventRecord(slot.done, st));
+    slot.pending = true;
     return SG_OK;
 }
 
@@ -581,31 +622,35 @@ sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *w
     return SG_OK;
 }
 
-// Small pinned staging area for per-call device headers (batch item
-// tables); reused only after the previous copy out of it has completed.
+// Pinned staging of the per-call device headers of batched calls (item
+// tables), used in turn like a plan's table slots; a slot grows (one pinned
+// allocation) when a larger batch arrives.
 struct Stage {
     std::mutex mu;
-    void *buf = nullptr;
-    size_t bytes = 0;
-    hipEvent_t done = nullptr;
+    StageSlot slot[kStageSlots];
+    int next = 0;
 };
 Stage g_stage;
 
 sg_status stage_upload(void *dst, const void *src, size_t bytes, hipStream_t st)
 {
     std::lock_guard<std::mutex> lock(g_stage.mu);
-    if (g_stage.done) SG_HIP(hipEventSynchronize(g_stage.done));
-    if (g_stage.bytes < bytes) {
-        if (g_stage.buf) SG_HIP(hipHostFree(g_stage.buf));
-        g_stage.buf = nullptr;
-        g_stage.bytes = 0;
-        SG_HIP(hipHostMalloc(&g_stage.buf, bytes, hipHostMallocDefault));
-        g_stage.bytes = bytes;
+    StageSlot &sl = g_stage.slot[g_stage.next];
+    g_stage.next = (g_stage.next + 1) % kStageSlots;
+    if (!sl.done) SG_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    if (sl.pending) SG_HIP(hipEventSynchronize(sl.done));
+    sl.pending = false;
+    if (sl.bytes < bytes) {
+        if (sl.buf) SG_HIP(hipHostFree(sl.buf));
+        sl.buf = nullptr;
+        sl.bytes = 0;
+        SG_HIP(hipHostMalloc(&sl.buf, std::max(bytes, (size_t)4096), hipHostMallocDefault));
+        sl.bytes = std::max(bytes, (size_t)4096);
     }
-    if (!g_stage.done) SG_HIP(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
-    std::memcpy(g_stage.buf, src, bytes);
-    SG_HIP(hipMemcpyAsync(dst, g_stage.buf, bytes, hipMemcpyHostToDevice, st));
-    SG_HIP(hipEventRecord(g_stage.done, st));
+    std::memcpy(sl.buf, src, bytes);
+    SG_HIP(hipMemcpyAsync(dst, sl.buf, bytes, hipMemcpyHostToDevice, st));
+    SG_HIP(hipEventRecord(sl.done, st));
+    sl.pending = true;
     return SG_OK;
 }
 
@@ -641,6 +686,7 @@ struct GraphCache {
     struct Entry {
         GraphKey key;
         hipGraphExec_t exec;
+        hipEvent_t done;             // recorded after each launch of exec
         int aux;                     // a count the caller keeps with the graph
     };
     std::vector<Entry> entries;      // most recent last
@@ -649,20 +695,29 @@ struct GraphCache {
 GraphCache g_graphs;
 constexpr size_t kGraphCacheSize = 8;
 
-// The instantiated graph for `key`, recorded with `enqueue` on first use.
-// *aux (optional) is stored with a new graph and returned with a cached one.
+// Launches the instantiated graph for `key` on `st`, recording it with
+// `enqueue` on first use; an event recorded after the launch lets an evicted
+// graph be destroyed only once its last launch has finished.  *aux
+// (optional) is stored with a new graph and returned with a cached one;
+// `before` (optional) is recorded on `st` just before the launch.
 template <class Enqueue>
-sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hipGraphExec_t *out, int *aux = nullptr)
+sg_status graph_run(const GraphKey &key, hipStream_t st, Enqueue enqueue, int *aux = nullptr,
+                    hipEvent_t before = nullptr)
 {
     std::lock_guard<std::mutex> lock(g_graphs.mu);
+    auto launch = [&](GraphCache::Entry &e) -> sg_status {
+        if (before) SG_HIP(hipEventRecord(before, st));
+        SG_HIP(hipGraphLaunch(e.exec, st));
+        SG_HIP(hipEventRecord(e.done, st));
+        return SG_OK;
+    };
     for (size_t i = 0; i < g_graphs.entries.size(); ++i)
         if (g_graphs.entries[i].key == key) {
             auto e = g_graphs.entries[i];
             g_graphs.entries.erase(g_graphs.entries.begin() + i);
             g_graphs.entries.push_back(e);
-            *out = e.exec;
             if (aux) *aux = e.aux;
-            return SG_OK;
+            return launch(g_graphs.entries.back());
         }
     // record on a private stream (the caller's may be the legacy default
     // stream, which cannot be captured); the graph is launched on `st`
@@ -681,13 +736,22 @@ sg_status graph_lookup(const GraphKey &key, hipStream_t st, Enqueue enqueue, hip
     hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return fail(SG_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+    hipEvent_t done = nullptr;
+    hipError_t e4 = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e4 != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(SG_EHIP, "hipEventCreateWithFlags failed: %s", hipGetErrorString(e4));
+    }
     if (g_graphs.entries.size() >= kGraphCacheSize) {
-        (void)hipGraphExecDestroy(g_graphs.entries.front().exec);
+        // the oldest graph may still run on some stream: wait for its last launch
+        GraphCache::Entry &old = g_graphs.entries.front();
+        (void)hipEventSynchronize(old.done);
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipEventDestroy(old.done);
         g_graphs.entries.erase(g_graphs.entries.begin());
     }
-    g_graphs.entries.push_back({key, exec, aux ? *aux : 0});
-    *out = exec;
-    return SG_OK;
+    g_graphs.entries.push_back({key, exec, done, aux ? *aux : 0});
+    return launch(g_graphs.entries.back());
 }
 
 // FNV-1a over a slice descriptor (every pointer and size its launches take by value).
@@ -723,21 +787,16 @@ sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
     const bool prof = p->profiling;
     GraphKey key{(uintptr_t)s.fields, -1, t.variant == 2 ? T.ntx * T.ntz * s.nshot : 0, nt,
                  t.variant == 2 ? t.time_block : 0, t.variant == 2 ? config : -1, desc_signature(s)};
-    hipGraphExec_t exec = nullptr;
     auto record = [&](hipStream_t s2) -> sg_status {
         p->profiling = false;          // the replay is bracketed instead
         sg_status rc = enqueue(s2);
         p->profiling = prof;
         return rc;
     };
-    sg_status rc = graph_lookup(key, st, record, &exec, &launches);
-    if (rc != SG_OK) return rc;
+    sg_status rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof) {
-        if ((rc = prof_pair(p, 0, &e0, &e1)) != SG_OK) return rc;
-        SG_HIP(hipEventRecord(e0, st));
-    }
-    SG_HIP(hipGraphLaunch(exec, st));
+    if (prof && (rc = prof_pair(p, 0, &e0, &e1)) != SG_OK) return rc;
+    if ((rc = graph_run(key, st, record, &launches, e0)) != SG_OK) return rc;
     if (prof) {
         SG_HIP(hipEventRecord(e1, st));
         p->prof_used = 1;
@@ -869,18 +928,40 @@ sg_status sg_plan_create(const sg_geometry *g, uint32_t flags, sg_plan **out)
         const double eta = sponge_eta(db, g->nbl, g->dz, g->damp_R) + sponge_eta(dtp, g->nbl, g->dz, g->damp_R);
         p->gz[Iz] = (float)(eta / (2.0 * g->dt));
     }
+    // pinned staging for the forward tables of up to 64 shots and two
+    // receivers per column, where a device is present (without one the
+    // plan is still usable for host-only calls; a later call grows it)
+    if (hipHostMalloc(&p->stage[0].buf, 1, hipHostMallocDefault) == hipSuccess) {
+        (void)hipHostFree(p->stage[0].buf);
+        p->stage[0].buf = nullptr;
+        std::lock_guard<std::mutex> lock(p->mu);
+        (void)reserve_stage(p, table_bytes(p, 64, 2 * g->nx, 0));
+    }
+    (void)hipGetLastError();
     *out = p;
     return SG_OK;
+}
+
+sg_status sg_plan_reserve(sg_plan *p, int32_t nshot, int32_t nrec, int32_t ckpt_every)
+{
+    if (!p) return fail(SG_EINVAL, "plan is NULL");
+    if (nshot < 1 || nrec < 0 || ckpt_every < 0)
+        return fail(SG_EINVAL, "nshot must be >= 1, nrec >= 0, ckpt_every >= 0");
+    const int ckpt = ckpt_every > 0 ? ckpt_spacing(p, ckpt_every) : 0;
+    std::lock_guard<std::mutex> lock(p->mu);
+    return reserve_stage(p, table_bytes(p, nshot, nrec, ckpt));
 }
 
 sg_status sg_plan_destroy(sg_plan *p)
 {
     if (!p) return SG_OK;
-    if (p->stage_done) {
-        (void)hipEventSynchronize(p->stage_done);
-        (void)hipEventDestroy(p->stage_done);
+    for (StageSlot &sl : p->stage) {
+        if (sl.done) {
+            if (sl.pending) (void)hipEventSynchronize(sl.done);
+            (void)hipEventDestroy(sl.done);
+        }
+        if (sl.buf) (void)hipHostFree(sl.buf);
     }
-    if (p->stage) (void)hipHostFree(p->stage);
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
     delete p;
     return SG_OK;
@@ -1341,10 +1422,7 @@ sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const s
     // per-item launch arguments never change for the same workspace and batch
     // shape, so one instantiated graph per such key is replayed
     GraphKey key{(uintptr_t)ws, nitems, (int)total_blocks, nt, tb, config, items_signature(hb)};
-    hipGraphExec_t exec = nullptr;
-    if ((rc = graph_lookup(key, st, enqueue, &exec)) != SG_OK) return rc;
-    SG_HIP(hipGraphLaunch(exec, st));
-    return SG_OK;
+    return graph_run(key, st, enqueue);
 }
 
 }  // namespace

@@ -82,14 +82,15 @@ class sg_fault_params(ctypes.Structure):
                 ("rough_lam_strike", ctypes.c_double), ("rough_lam_dip", ctypes.c_double)]
 
 
-def _fault_params(params: dict) -> sg_fault_params:
+def _fault_params(params: dict, device=None) -> sg_fault_params:
     """sg_fault_params from a dict of its fields; an optional rough surface is
-    given by rough_lattice (a float32 device tensor [noct, gd, gs]),
-    rough_amplitude, rough_lam_strike and rough_lam_dip."""
+    given by rough_lattice (a float32 device tensor [noct, gd, gs] on
+    `device`), rough_amplitude, rough_lam_strike and rough_lam_dip."""
     p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
                                                   "direction", "die_r", "die_strike", "die_theta_deg")})
     lat = params.get("rough_lattice")
     if lat is not None:
+        _need(lat, "rough_lattice", "float32", (None, None, None), device)
         p.rough_lattice = lat.data_ptr()
         p.rough_noct, p.rough_gd, p.rough_gs = lat.shape
         p.rough_amplitude = params["rough_amplitude"]
@@ -106,6 +107,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "sg_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "sg_plan_warnings": (ctypes.c_uint32, [ctypes.c_void_p]),
+    "sg_plan_reserve": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "sg_plan_padded_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
     "sg_plan_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sg_tuning)]),
@@ -301,6 +303,10 @@ class Plan:
         t = sg_tuning(variant, tile_x, tile_z, time_block, rows_per_thread)
         _check(lib().sg_plan_set_tuning(self.handle, ctypes.byref(t)))
 
+    def reserve(self, nshot: int, nrec: int, ckpt_every: int = 0):
+        """Size the plan's pinned table staging (sg_plan_reserve)."""
+        _check(lib().sg_plan_reserve(self.handle, nshot, nrec, ckpt_every))
+
     def clear_tuning(self):
         _check(lib().sg_plan_set_tuning(self.handle, None))
 
@@ -328,14 +334,21 @@ class Shots:
     wavelet: object
     _keep: list = field(default_factory=list, repr=False)
 
-    def c(self) -> sg_shots:
+    def c(self, nt: int) -> sg_shots:
+        """The C struct for a plan of `nt` levels; the wavelet must be a
+        contiguous float32 CUDA tensor [nt], [1, >= nt] or [nshot, nt]."""
         src = np.ascontiguousarray(np.asarray(self.src_zx, np.float64).reshape(-1, 2))
         rec = np.ascontiguousarray(np.asarray(self.rec_zx, np.float64).reshape(-1, 2))
         self._keep = [src, rec]
         w = self.wavelet
+        _need(w, "wavelet", "float32")
+        if w.dim() not in (1, 2):
+            raise ValueError("wavelet must be [nt], [1, nt] or [nshot, nt]")
         per_shot = 1 if (w.dim() == 2 and w.shape[0] > 1) else 0
         if per_shot and w.shape[0] != src.shape[0]:
             raise ValueError("wavelet rows must be 1 or nshot")
+        if (per_shot and w.shape[-1] != nt) or w.shape[-1] < nt:
+            raise ValueError("wavelet rows hold %d samples; the plan needs %d" % (w.shape[-1], nt))
         return sg_shots(src.shape[0], src.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                         rec.shape[0], rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                         ctypes.c_void_p(w.data_ptr()), per_shot)
@@ -360,6 +373,52 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _need(t, name, dtype, shape=None, device=None, optional=False):
+    """Raise ValueError unless `t` is a contiguous CUDA tensor of `dtype`
+    ("float32", "float64", "int32" or "uint8") whose shape equals `shape`
+    (None entries match any extent) and that lives on `device` when given.
+    The library dereferences these pointers on the GPU: a host tensor, a
+    wrong element type or a short buffer would be read out of bounds."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP device) tensor" % name)
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and (t.dim() != len(shape) or
+                              any(e is not None and a != e for a, e in zip(t.shape, shape))):
+        want = "[" + ", ".join("*" if e is None else str(e) for e in shape) + "]"
+        raise ValueError("%s has shape %s; expected %s" % (name, list(t.shape), want))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s; expected %s" % (name, t.device, device))
+
+
+def _need_ws(ws, device):
+    _need(ws, "workspace", "uint8", device=device)
+
+
+def _check_slice_args(plan: "Plan", vp, shots: "Shots", gathers=None, snaps=None, resid=None, grad=None,
+                      gathers_optional=True):
+    """Validates the device tensors of a call on one slice against its plan."""
+    g = plan.geom
+    _need(vp, "vp", "float32", (g.nz, g.nx))
+    dev = vp.device
+    ns, nr = shots.nshot, shots.nrec
+    _need(shots.wavelet, "wavelet", "float32", device=dev)
+    _need(gathers, "gathers", "float32", (ns, g.nrow, nr), dev, optional=gathers_optional)
+    _need(snaps, "snaps", "float32", (ns, g.snap_count, g.nz, g.nx), dev, optional=True)
+    _need(resid, "resid", "float32", (ns, g.nrow, nr), dev, optional=resid is None)
+    _need(grad, "grad", "float32", (g.nz, g.nx), dev, optional=grad is None)
+    return dev
+
+
 def sg_forward_workspace_size(plan: Plan, nshot: int, nrec: int) -> int:
     n = ctypes.c_size_t()
     _check(lib().sg_forward_workspace_size(plan.handle, nshot, nrec, ctypes.byref(n)))
@@ -367,7 +426,8 @@ def sg_forward_workspace_size(plan: Plan, nshot: int, nrec: int) -> int:
 
 
 def sg_forward(plan: Plan, vp, shots: Shots, gathers, snaps, ws, stream=None):
-    sh = shots.c()
+    _need_ws(ws, _check_slice_args(plan, vp, shots, gathers, snaps))
+    sh = shots.c(plan.geom.nt)
     _check(lib().sg_forward(plan.handle, _ptr(vp), ctypes.byref(sh), _ptr(gathers), _ptr(snaps),
                             _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
@@ -379,13 +439,15 @@ def sg_grad_workspace_size(plan: Plan, nshot: int, nrec: int, ckpt_every: int = 
 
 
 def sg_forward_ckpt(plan: Plan, vp, shots: Shots, ckpt_every: int, gathers, ws, stream=None):
-    sh = shots.c()
+    _need_ws(ws, _check_slice_args(plan, vp, shots, gathers))
+    sh = shots.c(plan.geom.nt)
     _check(lib().sg_forward_ckpt(plan.handle, _ptr(vp), ctypes.byref(sh), ckpt_every, _ptr(gathers),
                                  _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
 
 def sg_adjoint_gradient(plan: Plan, vp, shots: Shots, ckpt_every: int, resid, grad, ws, stream=None):
-    sh = shots.c()
+    _need_ws(ws, _check_slice_args(plan, vp, shots, resid=resid, grad=grad))
+    sh = shots.c(plan.geom.nt)
     _check(lib().sg_adjoint_gradient(plan.handle, _ptr(vp), ctypes.byref(sh), ckpt_every, _ptr(resid),
                                      _ptr(grad), _ptr(ws), ws.numel() * ws.element_size(),
                                      _stream_ptr(stream)))
@@ -396,7 +458,8 @@ def _batch_items(items):
     keep = []
     arr = (sg_batch_item * len(items))()
     for i, (plan, vp, shots, gathers, snaps) in enumerate(items):
-        sh = shots.c()
+        _check_slice_args(plan, vp, shots, gathers, snaps)
+        sh = shots.c(plan.geom.nt)
         keep.append(sh)
         arr[i] = sg_batch_item(plan.handle, vp.data_ptr(), ctypes.pointer(sh),
                                gathers.data_ptr() if gathers is not None else None,
@@ -413,6 +476,7 @@ def sg_batch_workspace_size(items) -> int:
 
 def sg_batch_forward(items, ws, tuning=None, stream=None):
     arr, keep = _batch_items(items)
+    _need_ws(ws, items[0][1].device if items else None)
     t = None
     if tuning is not None:
         t = ctypes.byref(sg_tuning(tuning.get("variant", 2), tuning.get("tile_x", 0), tuning.get("tile_z", 0),
@@ -424,6 +488,7 @@ def sg_batch_forward(items, ws, tuning=None, stream=None):
 def sg_batch_autotune(items, ws, trial_levels: int = 64, stream=None) -> dict:
     """Fastest tuning for the whole batch (a dict for sg_batch_forward's `tuning`)."""
     arr, keep = _batch_items(items)
+    _need_ws(ws, items[0][1].device if items else None)
     t = sg_tuning()
     _check(lib().sg_batch_autotune(arr, len(items), trial_levels, _ptr(ws), ws.numel() * ws.element_size(),
                                    _stream_ptr(stream), ctypes.byref(t)))
@@ -432,7 +497,8 @@ def sg_batch_autotune(items, ws, trial_levels: int = 64, stream=None) -> dict:
 
 
 def sg_autotune(plan: Plan, vp, shots: Shots, trial_levels: int, ws, stream=None) -> dict:
-    sh = shots.c()
+    _need_ws(ws, _check_slice_args(plan, vp, shots))
+    sh = shots.c(plan.geom.nt)
     t = sg_tuning()
     _check(lib().sg_autotune(plan.handle, _ptr(vp), ctypes.byref(sh), trial_levels, _ptr(ws),
                              ws.numel() * ws.element_size(), _stream_ptr(stream), ctypes.byref(t)))
@@ -445,7 +511,8 @@ def _grad_items(items):
     keep = []
     arr = (sg_batch_grad_item * len(items))()
     for i, (plan, vp, shots, resid, grad) in enumerate(items):
-        sh = shots.c()
+        _check_slice_args(plan, vp, shots, resid=resid, grad=grad)
+        sh = shots.c(plan.geom.nt)
         keep.append(sh)
         arr[i] = sg_batch_grad_item(plan.handle, vp.data_ptr(), ctypes.pointer(sh), resid.data_ptr(),
                                     grad.data_ptr())
@@ -461,6 +528,7 @@ def sg_batch_grad_workspace_size(items, ckpt_every=0, shots_per_wave=0) -> int:
 
 def sg_batch_adjoint_gradient(items, ws, ckpt_every=0, shots_per_wave=0, tuning=None, stream=None):
     arr, keep = _grad_items(items)
+    _need_ws(ws, items[0][1].device if items else None)
     t = None
     if tuning is not None:
         t = ctypes.byref(sg_tuning(tuning.get("variant", 2), tuning.get("tile_x", 0), tuning.get("tile_z", 0),
@@ -480,6 +548,7 @@ def fractal_noise2d(lattice, ny: int, nx: int, dy: float, dx: float, lam_y: floa
     """Displacement field [ny, nx] (float32 device tensor, metres) from the
     per-octave lattices [noct, gy, gx] (float32 device)."""
     import torch
+    _need(lattice, "lattice", "float32", (None, None, None))
     noct, gy, gx = lattice.shape
     out = torch.empty((ny, nx), dtype=torch.float32, device=lattice.device)
     _check(lib().sg_fractal_noise2d(_ptr(lattice), noct, gy, gx, ny, nx, dy, dx, lam_y, lam_x, azimuth_deg,
@@ -493,7 +562,13 @@ def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vb
     thick/vbed/tex_off [nbeds], eta_b [nbeds-1, ny, nx], tex_lattice
     [gz, gy, gx]; lam = (lam_z, lam_y, lam_x) in metres."""
     import torch
+    _need(thick, "thick", "float32", (None,))
     nbeds = thick.numel()
+    dev = thick.device
+    _need(vbed, "vbed", "float32", (nbeds,), dev)
+    _need(tex_off, "tex_off", "float32", (nbeds,), dev)
+    _need(eta_b, "eta_b", "float32", (nbeds - 1, ny, nx), dev, optional=nbeds <= 1 or eta_b is None)
+    _need(tex_lattice, "tex_lattice", "float32", (None, None, None), dev)
     gz, gy, gx = tex_lattice.shape
     out = torch.empty((t, ny, nx), dtype=torch.float32, device=thick.device)
     _check(lib().sg_deposit(t, ny, nx, dz, dy, dx, nbeds, _ptr(thick), _ptr(vbed), beta,
@@ -507,7 +582,9 @@ def squish(v, dz: float, shift, stream=None):
     """v [nz, ny, nx] pulled from depth z + shift(y, x) (shift [ny, nx] in
     metres); float32 device tensors in, a new one out."""
     import torch
+    _need(v, "v", "float32", (None, None, None))
     nz, ny, nx = v.shape
+    _need(shift, "shift", "float32", (ny, nx), v.device)
     out = torch.empty_like(v)
     _check(lib().sg_squish(_ptr(v), nz, ny, nx, dz, _ptr(shift), _ptr(out), _stream_ptr(stream)))
     return out
@@ -517,8 +594,9 @@ def fault(v, dz: float, dy: float, dx: float, params: dict, fill: float, stream=
     """v [nz, ny, nx] through one listric normal fault; params holds the
     fields of sg_fault_params (see _fault_params for a rough surface)."""
     import torch
+    _need(v, "v", "float32", (None, None, None))
     nz, ny, nx = v.shape
-    p = _fault_params(params)
+    p = _fault_params(params, v.device)
     out = torch.empty_like(v)
     _check(lib().sg_fault(_ptr(v), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out), _stream_ptr(stream)))
     return out
@@ -537,6 +615,7 @@ def salt_sdt(v, dz: float, dy: float, dx: float, centres, radii, rotations, grf,
     grf [nbodies, nz, ny, nx] a float32 device tensor.  Returns (out, mask):
     the salted volume and K as uint8."""
     import torch
+    _need(v, "v", "float32", (None, None, None))
     nz, ny, nx = v.shape
     c = np.ascontiguousarray(centres, np.float64).reshape(-1, 3)
     r = np.ascontiguousarray(radii, np.float64).reshape(-1, 3)
@@ -544,8 +623,8 @@ def salt_sdt(v, dz: float, dy: float, dx: float, centres, radii, rotations, grf,
     nb = c.shape[0]
     if r.shape[0] != nb or R.shape[0] != nb:
         raise ValueError("centres, radii and rotations must describe the same number of bodies")
-    if nb and tuple(grf.shape) != (nb, nz, ny, nx):
-        raise ValueError("grf must be [nbodies, nz, ny, nx]")
+    if nb:
+        _need(grf, "grf", "float32", (nb, nz, ny, nx), v.device)
     out = torch.empty_like(v)
     mask = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
     ws = torch.empty(sg_salt_workspace_size(nz, ny, nx), dtype=torch.uint8, device=v.device)
@@ -559,8 +638,9 @@ def fault_labels(labels, dz: float, dy: float, dx: float, params: dict, fill: in
     """int32 device labels [nz, ny, nx] through one listric normal fault,
     nearest-neighbour pull; params holds the fields of sg_fault_params."""
     import torch
+    _need(labels, "labels", "int32", (None, None, None))
     nz, ny, nx = labels.shape
-    p = _fault_params(params)
+    p = _fault_params(params, labels.device)
     out = torch.empty_like(labels)
     _check(lib().sg_fault_labels(_ptr(labels), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out),
                                  _stream_ptr(stream)))
@@ -572,7 +652,9 @@ def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP
     frame stack [T][nz][nx] (float32) on velocity vp [nz][nx]; returns two
     float64 device tensors of T entries."""
     import torch
+    _need(frames, "frames", "float32", (None, None, None))
     T, nz, nx = frames.shape
+    _need(vp, "vp", "float32", (nz, nx), frames.device)
     res2 = torch.empty(T, dtype=torch.float64, device=frames.device)
     dtt2 = torch.empty_like(res2)
     ws = torch.empty(sg_wave_residual_workspace_size(T, nz, nx, top), dtype=torch.uint8, device=frames.device)
@@ -586,6 +668,8 @@ def sg_set_graphs(on: bool):
 
 
 def sg_check_finite(x, ws, stream=None):
+    _need(x, "x", "float32")
+    _need_ws(ws, x.device)
     _check(lib().sg_check_finite(_ptr(x), x.numel(), _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))
 

@@ -288,3 +288,24 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         sgwave.lib()
     with pytest.raises(RuntimeError, match="not built"):
         sgwave.sg_salt_workspace_size(4, 4, 4)
+
+
+def test_binding_rejects_host_tensors_before_the_library():
+    """The binding checks every tensor before marshalling: host (CPU) tensors
+    are refused with ValueError, so the kernels never see a host address."""
+    import torch
+    p = Plan(_geom())
+    g = p.geom
+    src = np.array([[20.0, 640.0]])
+    rec = np.stack([np.full(128, 10.0), np.arange(128) * 10.0], 1)
+    w = torch.zeros((1, g.nt), dtype=torch.float32)
+    vp = torch.full((g.nz, g.nx), 2000.0)
+    ws = torch.empty(16, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="CUDA"):
+        sgwave.sg_forward(p, vp, sgwave.Shots(src, rec, w), None, None, ws)
+    with pytest.raises(ValueError, match="required"):
+        sgwave.sg_forward(p, None, sgwave.Shots(src, rec, w), None, None, ws)
+    with pytest.raises(ValueError, match="CUDA"):
+        sgwave.squish(torch.zeros((4, 2, 3)), 10.0, torch.zeros((2, 3)))
+    with pytest.raises(ValueError, match="CUDA"):
+        sgwave.wave_residual(torch.zeros((5, 9, 9)), torch.zeros((9, 9)), 10.0, 10.0, 1e-3)

@@ -164,3 +164,34 @@ def test_short_records_gradient(nt, ckpt):
     e = rel_l2(got, ref)
     print("gradient rel-L2 %.3e" % e, flush=True)
     assert e <= TOL
+
+
+def test_binding_rejects_mismatched_device_tensors():
+    """Wrong dtype, shape, contiguity or wavelet length are refused by the
+    binding with ValueError before anything reaches the library."""
+    import torch
+    g = Geometry(nz=30, nx=40, dz=10.0, dx=10.0, dt=1e-3, nt=50, nbl=5, vmax_hint=3000.0)
+    plan = Plan(g)
+    src = np.array([[10.0, 200.0]])
+    rec = np.stack([np.full(40, 10.0), np.arange(40) * 10.0], 1)
+    w = torch.zeros((1, g.nt), dtype=torch.float32, device="cuda")
+    vp = torch.full((g.nz, g.nx), 2000.0, device="cuda")
+    ws = torch.empty(sgwave.sg_forward_workspace_size(plan, 1, 40), dtype=torch.uint8, device="cuda")
+    gathers = torch.empty((1, g.nrow, 40), device="cuda")
+    sh = Shots(src, rec, w)
+    bad = [
+        dict(vp=vp.double()),                                          # float64 velocity
+        dict(vp=vp[:, :39]),                                           # short rows
+        dict(vp=torch.full((g.nx, g.nz), 2000.0, device="cuda").t()),  # transposed view
+        dict(gathers=torch.empty((1, g.nrow - 1, 40), device="cuda")), # short gathers
+        dict(shots=Shots(src, rec, w[:, :g.nt - 1])),                  # short wavelet
+        dict(shots=Shots(src, rec, torch.zeros((2, g.nt), device="cuda"))),   # 2 wavelet rows, 1 shot
+        dict(ws=torch.empty(64, dtype=torch.float32, device="cuda")),  # workspace not bytes
+    ]
+    for case in bad:
+        args = dict(vp=vp, shots=sh, gathers=gathers, ws=ws)
+        args.update(case)
+        with pytest.raises(ValueError):
+            sgwave.sg_forward(plan, args["vp"], args["shots"], args["gathers"], None, args["ws"])
+    sgwave.sg_forward(plan, vp, sh, gathers, None, ws)       # the good call passes
+    torch.cuda.synchronize()
