@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--levels", type=int, default=10000,
                     help="time levels of the headline batch (shorter runs for counter profiles)")
     ap.add_argument("--batch-tuning", type=str, default="",
-                    help="tile_x,tile_z,time_block for the headline batch instead of the autotuner")
+                    help="tile_x,tile_z,time_block (tiled) or strip_width,time_block (column sweep) "
+                         "for the headline batch instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=3)
     ap.add_argument("--shots-per-wave", type=int, default=25)
@@ -117,8 +118,11 @@ def batch_headline(args):
     ws = torch.empty(sgwave.sg_batch_workspace_size(items), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     if args.batch_tuning:
-        tx, tz, tb = (int(x) for x in args.batch_tuning.split(","))
-        tuning = dict(variant=2, tile_x=tx, tile_z=tz, time_block=tb, rows_per_thread=0)
+        parts = [int(x) for x in args.batch_tuning.split(",")]
+        if len(parts) == 2:      # column sweep: strip width, time block
+            tuning = dict(variant=3, tile_x=parts[0], tile_z=0, time_block=parts[1], rows_per_thread=0)
+        else:                    # tiled: tile_x, tile_z, time block
+            tuning = dict(variant=2, tile_x=parts[0], tile_z=parts[1], time_block=parts[2], rows_per_thread=0)
     else:
         tuning = sgwave.sg_batch_autotune(items, ws, 32)          # untimed
     log("headline batch: tuning %s" % tuning)
@@ -150,11 +154,13 @@ def batch_headline(args):
     bytes_per_launch = BYTES_PER_UPDATE * updates / launches
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     shape = kernel_shape(tuning)
-    rec = traffic_record("k_tiled_batch", "uneven_batch")
+    kname = ("k_sweep_batch<%d, %d>" % (tuning["tile_x"] // 64, tb) if tuning["variant"] == 3
+             else "k_tiled_batch<%s, 0, true>" % shape)
+    rec = traffic_record("k_sweep_batch" if tuning["variant"] == 3 else "k_tiled_batch", "uneven_batch")
     traffic = None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_tiled_batch<%s, 0, true>" % shape, "launches_per_step": launches,
+            "kernel": kname, "launches_per_step": launches,
             "avg_launch_us": avg_ms * 1e3, "bytes_per_update": BYTES_PER_UPDATE,
             "algorithmic_bytes_per_launch": bytes_per_launch}
     if rec is not None and rec.get("tuning") == [tuning["tile_x"], tuning["tile_z"], tb]:

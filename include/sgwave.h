@@ -126,7 +126,12 @@ typedef struct {
  * Kernel tuning of the time-stepping launches.
  *   variant      0 = library default; 1 = one launch per time step with the
  *                stencil read from global memory; 2 = LDS-tiled, time-blocked
- *                launches
+ *                launches; 3 = column sweep: a workgroup walks the whole
+ *                height of a strip of tile_x columns (128 or 256, 0 = 256)
+ *                advancing time_block (1..6, 0 = 4) levels in a skewed
+ *                pipeline, so only the x halo of 4*time_block per side is
+ *                recomputed (forward calls with dz == dx; the gradient calls
+ *                run variant 2 instead); tile_z and rows_per_thread are 0
  *   tile_x, tile_z   cells (x by z) of the LDS tile one workgroup loads
  *                (variant 2), one of the built shapes 128x64, 64x128, 64x64;
  *                the output tile is that minus a halo of 4*time_block per side
@@ -196,7 +201,8 @@ sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t);
 
 /*
  * Autotuner: times every built tile shape with every admissible time block
- * (1..8) on this call's real shape -- trial_levels (>= 8) levels of the
+ * (1..8), and the column sweep (variant 3, strips of 128 and 256 columns,
+ * time blocks 2..6) where dz == dx, on this call's real shape -- trial_levels (>= 8) levels of the
  * time-stepping launches for `shots` on `vp`, after one untimed pass -- and
  * keeps the fastest as the plan's tuning (also returned in *best).  Uses the
  * workspace of sg_forward (no outputs are written).  Synchronises the stream.
@@ -312,7 +318,8 @@ sg_status sg_batch_forward(const sg_batch_item *items, int32_t nitems, const sg_
 
 /*
  * Batched autotuner: times every built tile shape with every admissible time
- * block that tiles every item, on the whole batch -- trial_levels (>= 8)
+ * block that tiles every item, and the column sweep (variant 3) where every
+ * item has dz == dx, on the whole batch -- trial_levels (>= 8)
  * levels of the batched time-stepping launches after one untimed pass -- and
  * returns the fastest in *best, to pass to sg_batch_forward (or to
  * sg_batch_adjoint_gradient).  Uses the workspace of sg_batch_forward; no

@@ -134,8 +134,14 @@ struct Tiling {
     int ex, ez, k, tb;
     int tx, tz, tz_top, ntx, ntz;
     bool ok;
+    int sweep_nw;   // > 0: column sweep (sg_sweep.hip) over strips of 64 sweep_nw columns, ntz = 1
 };
 Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb);
+// Strips of ex = 64 nw loaded columns for the column-sweep kernel: output
+// width ex - 8 tb, the whole height in one tile row.
+Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb);
+// Largest time block of the column-sweep kernel, and its strip widths (waves).
+constexpr int kSweepMaxTimeBlock = 6;
 
 // Instantiated shapes of the time-blocked kernel (extended tile ex x ez,
 // k rows per thread); `config` indexes this list.
@@ -150,6 +156,12 @@ hipError_t launch_zero(float *p, size_t n, hipStream_t st);
 hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);
 hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
 hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
+// Column-sweep forward (sg_sweep.hip, dz == dx only): t.nsteps levels (1..6)
+// over strips of 64 nw columns (nw 2 or 4); the batched form like
+// launch_step_tiled_batch.
+hipError_t launch_sweep(const SliceDesc &s, const TileArgs &t, int nw, hipStream_t st);
+hipError_t launch_sweep_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps, int in_pair,
+                              int nw, hipStream_t st);
 // Batched launches: items[0..nitems) in device memory, total_blocks = sum of
 // the items' blocks (items[i].block_start is the prefix sum).
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,

@@ -321,6 +321,12 @@ sg_tuning resolve_tuning(const sg_plan *p, int nshot, bool gradient = false)
         t.time_block = 1;
         return t;
     }
+    if (t.variant == 3) {         // column sweep: strip width, whole height
+        if (t.tile_x == 0) t.tile_x = 256;
+        t.tile_z = t.rows_per_thread = 0;
+        if (t.time_block <= 0) t.time_block = 4;
+        return t;
+    }
     if (t.tile_x == 0 || t.tile_z == 0) {
         t.tile_x = 128;
         t.tile_z = 64;
@@ -333,6 +339,17 @@ sg_tuning resolve_tuning(const sg_plan *p, int nshot, bool gradient = false)
 
 sg_status tiling_for(const sg_plan *p, const sg_tuning &t, int *config, sg::Tiling *T)
 {
+    if (t.variant == 3) {
+        *config = -1;
+        if (p->g.dz != p->g.dx) return fail(SG_EUNSUPPORTED, "the column-sweep kernel needs dz == dx");
+        if (t.tile_x != 128 && t.tile_x != 256) return fail(SG_EUNSUPPORTED, "sweep strips are 128 or 256 columns");
+        if (t.time_block < 1 || t.time_block > sg::kSweepMaxTimeBlock)
+            return fail(SG_EINVAL, "sweep time_block must be in 1..%d", sg::kSweepMaxTimeBlock);
+        *T = sg::make_sweep_tiling(p->Nz, p->Nx, t.tile_x / 64, t.time_block);
+        if (!T->ok) return fail(SG_EUNSUPPORTED, "time block %d leaves no output strip", t.time_block);
+        if ((int64_t)T->ntx > max_tiles(p)) return fail(SG_EUNSUPPORTED, "tiling too fine");
+        return SG_OK;
+    }
     *config = shape_of(t);
     if (*config < 0) return fail(SG_EUNSUPPORTED, "no kernel built for a %d x %d tile", t.tile_x, t.tile_z);
     if (t.time_block < 1 || t.time_block > sg::kMaxTimeBlock)
@@ -438,14 +455,22 @@ sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *s
         for (int q = 0; q <= tiles; ++q) start[q] = count[q];
         for (int i = 0; i < sh->nrec; ++i) {
             const int tile = rtile[i], tzi = tile / T->ntx, txi = tile % T->ntx;
-            const int ez0 = free_top ? (tzi == 0 ? -T->k : T->tz_top + (tzi - 1) * T->tz - halo) : tzi * T->tz - halo;
+            const int ez0 = T->sweep_nw > 0 ? 0
+                            : free_top ? (tzi == 0 ? -T->k : T->tz_top + (tzi - 1) * T->tz - halo)
+                                       : tzi * T->tz - halo;
             const int ex0 = txi * T->tx - halo;
             sg::RecEntry &e = list[count[tile]++];
             const int32_t biz = ((const int32_t *)at(L.rec_iz))[i], bix = ((const int32_t *)at(L.rec_ix))[i];
-            e.lds = (biz - ez0 + sg::kHalo) * LW + (bix - ex0 + sg::kHalo);
+            // tiled: index in the tile's LDS buffer; sweep: base row * LW + column in the strip's LDS row
+            e.lds = T->sweep_nw > 0 ? biz * LW + (bix - ex0 + sg::kHalo)
+                                    : (biz - ez0 + sg::kHalo) * LW + (bix - ex0 + sg::kHalo);
             e.r = i;
             for (int k = 0; k < sg::kNodes; ++k) e.w[k] = ((const float *)at(L.rec_w))[i * sg::kNodes + k];
         }
+        if (T->sweep_nw > 0)   // the sweep reads a strip's entries by base row
+            for (int q = 0; q < tiles; ++q)
+                std::stable_sort(list + start[q], list + start[q + 1],
+                                 [](const sg::RecEntry &a, const sg::RecEntry &b) { return a.lds < b.lds; });
     }
     if (T && L.inj_cap > 0) {
         // adjoint residual injection: receiver nodes inside each tile's loaded
@@ -542,7 +567,7 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
 {
     const int step = t.variant == 1 ? 1 : t.time_block;
     // the tiled kernel leaves snapshots to launch boundaries at snapshot levels
-    const bool snap_cuts = t.variant == 2 && s.snaps != nullptr;
+    const bool snap_cuts = t.variant >= 2 && s.snaps != nullptr;
     const int se = s.snap_every, slast = (s.snap_count - 1) * s.snap_every;
     auto snap_due = [&](int level) { return snap_cuts && level % se == 0 && level <= slast; };
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -565,7 +590,12 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
             a.ring = ring;
             a.ring_lo = ring_lo;
             a.ring_shot = ring_shot;
-            SG_HIP(sg::launch_step_tiled(s, a, config, st));
+            if (T.sweep_nw > 0) {
+                if (ring) return fail(SG_EUNSUPPORTED, "the column-sweep kernel has no recompute mode");
+                SG_HIP(sg::launch_sweep(s, a, T.sweep_nw, st));
+            } else {
+                SG_HIP(sg::launch_step_tiled(s, a, config, st));
+            }
             *pair ^= 1;
         }
         n += k;
@@ -612,13 +642,13 @@ sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *w
         return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, c->L.total);
     const bool gradient = need_tiled && ckpt > 0;
     c->t = resolve_tuning(p, shots->nshot, gradient);
-    if (need_tiled && c->t.variant == 1) {   // the gradient path runs on the tiled kernels
+    if (need_tiled && (c->t.variant == 1 || c->t.variant == 3)) {   // the gradient path runs on the tiled kernels
         sg_tuning keep = p->tuning;
         p->tuning = sg_tuning{};
         c->t = resolve_tuning(p, shots->nshot, gradient);
         p->tuning = keep;
     }
-    if (c->t.variant == 2 && (rc = tiling_for(p, c->t, &c->config, &c->T)) != SG_OK) return rc;
+    if (c->t.variant >= 2 && (rc = tiling_for(p, c->t, &c->config, &c->T)) != SG_OK) return rc;
     return SG_OK;
 }
 
@@ -785,8 +815,9 @@ sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
     SG_HIP(hipStreamIsCapturing(st, &cap));
     if (cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
     const bool prof = p->profiling;
-    GraphKey key{(uintptr_t)s.fields, -1, t.variant == 2 ? T.ntx * T.ntz * s.nshot : 0, nt,
-                 t.variant == 2 ? t.time_block : 0, t.variant == 2 ? config : -1, desc_signature(s)};
+    GraphKey key{(uintptr_t)s.fields, -1, t.variant >= 2 ? T.ntx * T.ntz * s.nshot : 0, nt,
+                 t.variant >= 2 ? t.time_block : 0, t.variant >= 2 ? config + 16 * T.sweep_nw : -1,
+                 desc_signature(s)};
     auto record = [&](hipStream_t s2) -> sg_status {
         p->profiling = false;          // the replay is bracketed instead
         sg_status rc = enqueue(s2);
@@ -825,6 +856,18 @@ std::vector<sg_tuning> tuning_candidates(const sg_plan *p)
             out.push_back(t);
         }
     }
+    // column sweep (dz == dx): strips of 128 or 256 columns
+    if (p->g.dz == p->g.dx)
+        for (int nw : {2, 4})
+            for (int tb = 2; tb <= sg::kSweepMaxTimeBlock; ++tb) {
+                const sg::Tiling T = sg::make_sweep_tiling(p->Nz, p->Nx, nw, tb);
+                if (!T.ok || (int64_t)T.ntx > max_tiles(p)) continue;
+                sg_tuning t{};
+                t.variant = 3;
+                t.tile_x = 64 * nw;
+                t.time_block = tb;
+                out.push_back(t);
+            }
     return out;
 }
 
@@ -1006,7 +1049,17 @@ sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t)
         p->tuning = sg_tuning{};
         return SG_OK;
     }
-    if (t->variant < 0 || t->variant > 2) return fail(SG_EINVAL, "variant must be 0, 1 or 2");
+    if (t->variant < 0 || t->variant > 3) return fail(SG_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (t->variant == 3) {
+        if (t->tile_x != 0 && t->tile_x != 128 && t->tile_x != 256)
+            return fail(SG_EUNSUPPORTED, "sweep strips are 128 or 256 columns");
+        if (t->tile_z != 0 || t->rows_per_thread != 0)
+            return fail(SG_EINVAL, "sweep tunings take tile_z = rows_per_thread = 0");
+        if (t->time_block < 0 || t->time_block > sg::kSweepMaxTimeBlock)
+            return fail(SG_EINVAL, "sweep time_block must be in 0..%d", sg::kSweepMaxTimeBlock);
+        p->tuning = *t;
+        return SG_OK;
+    }
     if (t->time_block < 0 || t->time_block > sg::kMaxTimeBlock)
         return fail(SG_EINVAL, "time_block must be in 0..%d", sg::kMaxTimeBlock);
     if (t->tile_x < 0 || t->tile_z < 0) return fail(SG_EINVAL, "tile sizes must be >= 0");
@@ -1174,7 +1227,7 @@ sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots, float *
     if (rc != SG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
-    if ((rc = upload_tables(p, c.L, w, shots, c.t.variant == 2 ? &c.T : nullptr, st)) != SG_OK) return rc;
+    if ((rc = upload_tables(p, c.L, w, shots, c.t.variant >= 2 ? &c.T : nullptr, st)) != SG_OK) return rc;
     const sg::SliceDesc s = describe(p, c.L, w, shots, gathers, snaps);
     SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
     SG_HIP(sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st));
@@ -1337,8 +1390,10 @@ sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const s
         if (items[i].plan->g.nt != nt) return fail(SG_EINVAL, "batch items must share nt (%d vs %d)", items[i].plan->g.nt, nt);
     sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot);
     if (t.variant == 0) t = resolve_tuning(items[0].plan, items[0].shots->nshot);
-    if (t.variant != 2) return fail(SG_EUNSUPPORTED, "batched launches use the tiled kernel (variant 2)");
+    if (t.variant != 2 && t.variant != 3)
+        return fail(SG_EUNSUPPORTED, "batched launches use the tiled (2) or column-sweep (3) kernel");
     if (t.time_block <= 0) t.time_block = 4;
+    if (t.variant == 3 && t.tile_x == 0) t.tile_x = 256;
     // validate everything before enqueueing anything
     std::vector<CallSetup> cs(nitems);
     std::vector<size_t> base(nitems);
@@ -1376,7 +1431,7 @@ sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const s
 
     // the time-stepping launches (one per time block over the whole batch),
     // replayed from a captured graph unless the caller is capturing already
-    const int config = cs[0].config, tb = t.time_block;
+    const int config = cs[0].config, tb = t.time_block, sweep_nw = cs[0].T.sweep_nw;
     // the isotropic kernel form needs dz == dx on every item
     bool iso = true;
     for (int i = 0; i < nitems; ++i)
@@ -1404,7 +1459,10 @@ sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const s
         const int nlast = std::min(levels, nt) - 1;
         for (int n = 0; n < nlast;) {
             const int k = std::min(std::min(tb, nlast - n), next_cut(n) - n);
-            SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, iso, s2));
+            if (sweep_nw > 0)
+                SG_HIP(sg::launch_sweep_batch(dev_items, nitems, (int)total_blocks, n, k, pair, sweep_nw, s2));
+            else
+                SG_HIP(sg::launch_step_tiled_batch(dev_items, nitems, (int)total_blocks, n, k, pair, config, iso, s2));
             pair ^= 1;
             n += k;
             if (n < nlast)
@@ -1421,7 +1479,7 @@ sg_status batch_forward_impl(const sg_batch_item *items, int32_t nitems, const s
     if (trial || cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
     // per-item launch arguments never change for the same workspace and batch
     // shape, so one instantiated graph per such key is replayed
-    GraphKey key{(uintptr_t)ws, nitems, (int)total_blocks, nt, tb, config, items_signature(hb)};
+    GraphKey key{(uintptr_t)ws, nitems, (int)total_blocks, nt, tb, config + 16 * sweep_nw, items_signature(hb)};
     return graph_run(key, st, enqueue);
 }
 
