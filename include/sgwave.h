@@ -270,6 +270,26 @@ sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots,
                      void *stream);
 
 /*
+ * sg_forward without a workspace argument, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid allocation).
+ * The workspace is a static device array of SG_NOALLOC_SCRATCH_BYTES per
+ * device, held from library load until the process ends.  Same arguments,
+ * outputs and errors as sg_forward, plus SG_ENOSPACE when the call would need
+ * more than that (sg_forward_workspace_size > SG_NOALLOC_SCRATCH_BYTES; e.g.
+ * the 620 x 1001 slice with a 40-cell sponge fits two shots) or when the
+ * plan's pinned table staging is smaller than this call's tables (it is
+ * sized at sg_plan_create for 64 shots and 2 nx receivers; sg_plan_reserve
+ * sizes it up).  The call allocates nothing: no device or host allocation,
+ * no graph recording (its launches are enqueued directly).  Every call on a
+ * device shares that device's array, which keeps the last call's contents:
+ * calls that overlap on one device (another stream, another thread) race and
+ * must be serialised by the caller.
+ */
+#define SG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sg_status sg_forward_noalloc(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers, float *snaps,
+                             void *stream);
+
+/*
  * Differentiation (adjoint-state velocity gradient).
  * sg_grad_workspace_size: bytes for nshot shots and nrec receivers with
  * checkpoints every ckpt_every levels (<= 0: ceil(sqrt(nt))).  sg_forward_ckpt runs the forward

@@ -9,7 +9,19 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "sgwave.h"
+
 namespace sg {
+
+// Shared by the C ABI files (sg_runtime.cpp, sg_static.hip).  forward_call is
+// the body of sg_forward on a workspace of ws_bytes; with no_alloc it
+// allocates nothing: the launches are enqueued directly (recording a graph
+// allocates) and the plan's pinned staging must already hold the tables
+// (SG_ENOSPACE otherwise).  report_error sets the thread-local last-error
+// message and returns st.
+sg_status forward_call(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers, float *snaps, void *ws,
+                       size_t ws_bytes, void *stream, bool no_alloc);
+sg_status report_error(sg_status st, const char *msg);
 
 // Stencil half width: the 8th-order central difference reaches 4 cells on
 // each side (M = 4, App. E.3 / Table "params").

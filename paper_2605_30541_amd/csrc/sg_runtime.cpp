@@ -798,7 +798,7 @@ uint64_t desc_signature(const sg::SliceDesc &d)
 // (descriptor, tiling, nt) and replayed, unless graphs are off or the caller
 // is capturing the stream already; plan profiling brackets the replay.
 sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, int config,
-                      const sg::Tiling &T, hipStream_t st)
+                      const sg::Tiling &T, hipStream_t st, bool use_graph = true)
 {
     const int nt = p->g.nt;
     p->prof_used = 0;
@@ -813,7 +813,7 @@ sg_status run_forward(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
     };
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     SG_HIP(hipStreamIsCapturing(st, &cap));
-    if (cap != hipStreamCaptureStatusNone || !g_batch_graphs) return enqueue(st);
+    if (cap != hipStreamCaptureStatusNone || !g_batch_graphs || !use_graph) return enqueue(st);
     const bool prof = p->profiling;
     GraphKey key{(uintptr_t)s.fields, -1, t.variant >= 2 ? T.ntx * T.ntz * s.nshot : 0, nt,
                  t.variant >= 2 ? t.time_block : 0, t.variant >= 2 ? config + 16 * T.sweep_nw : -1,
@@ -884,6 +884,30 @@ sg_shots shots_view(const sg_shots *sh, int s0, int cnt, int nt)
 int wave_shots(int nshot, int per_wave) { return per_wave > 0 ? std::min(nshot, per_wave) : nshot; }
 
 }  // namespace
+
+namespace sg {
+
+sg_status forward_call(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers, float *snaps, void *ws,
+                       size_t ws_bytes, void *stream, bool no_alloc)
+{
+    CallSetup c;
+    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, 0, false, &c);
+    if (rc != SG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    if ((rc = upload_tables(p, c.L, w, shots, c.t.variant >= 2 ? &c.T : nullptr, st, !no_alloc)) != SG_OK)
+        return rc;
+    const sg::SliceDesc s = describe(p, c.L, w, shots, gathers, snaps);
+    SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
+    SG_HIP(sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st));
+    // recording and instantiating a graph allocates: without allocation the
+    // launches are enqueued directly
+    return run_forward(p, s, c.t, c.config, c.T, st, !no_alloc);
+}
+
+sg_status report_error(sg_status st, const char *msg) { return fail(st, "%s", msg); }
+
+}  // namespace sg
 
 extern "C" {
 
@@ -1222,16 +1246,7 @@ sg_status sg_forward_workspace_size(const sg_plan *p, int32_t nshot, int32_t nre
 sg_status sg_forward(sg_plan *p, const float *vp, const sg_shots *shots, float *gathers,
                      float *snaps, void *ws, size_t ws_bytes, void *stream)
 {
-    CallSetup c;
-    sg_status rc = setup_call(p, vp, shots, ws, ws_bytes, 0, false, &c);
-    if (rc != SG_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    char *w = (char *)ws;
-    if ((rc = upload_tables(p, c.L, w, shots, c.t.variant >= 2 ? &c.T : nullptr, st)) != SG_OK) return rc;
-    const sg::SliceDesc s = describe(p, c.L, w, shots, gathers, snaps);
-    SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
-    SG_HIP(sg::launch_zero(s.fields, (size_t)shots->nshot * sg::kFramesPerShot * p->frame, st));
-    return run_forward(p, s, c.t, c.config, c.T, st);
+    return sg::forward_call(p, vp, shots, gathers, snaps, ws, ws_bytes, stream, false);
 }
 
 sg_status sg_check_finite(const float *x, size_t n, void *ws, size_t ws_bytes, void *stream)

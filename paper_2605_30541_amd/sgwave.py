@@ -123,6 +123,8 @@ _SIGS = {
     "sg_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
+    "sg_forward_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sg_grad_workspace_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "sg_forward_ckpt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(sg_shots),
@@ -430,6 +432,14 @@ def sg_forward(plan: Plan, vp, shots: Shots, gathers, snaps, ws, stream=None):
     sh = shots.c(plan.geom.nt)
     _check(lib().sg_forward(plan.handle, _ptr(vp), ctypes.byref(sh), _ptr(gathers), _ptr(snaps),
                             _ptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def sg_forward_noalloc(plan: Plan, vp, shots: Shots, gathers, snaps, stream=None):
+    """sg_forward with the library's static device scratch as its workspace."""
+    _check_slice_args(plan, vp, shots, gathers, snaps)
+    sh = shots.c(plan.geom.nt)
+    _check(lib().sg_forward_noalloc(plan.handle, _ptr(vp), ctypes.byref(sh), _ptr(gathers), _ptr(snaps),
+                                    _stream_ptr(stream)))
 
 
 def sg_grad_workspace_size(plan: Plan, nshot: int, nrec: int, ckpt_every: int = 0) -> int:
