@@ -112,43 +112,70 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
         for (int q = 0; q < TB; ++q)
             if ((t.n + q) % s.rec_every == 0 && q < t.nsteps) due |= 1u << q;
     }
+    // steps at which some due level records a receiver row (one range test per step)
+    const int rec_j0 = due && rend > rbeg ? rrow_lo + 6 : 1 << 30;
+    const int rec_j1 = due && rend > rbeg ? rrow_hi + 4 * (TB - 1) + 6 : -(1 << 30);
 
     float Q[TB][kQ];
 #pragma unroll
     for (int a = 0; a < TB; ++a)
 #pragma unroll
         for (int c = 0; c < kQ; ++c) Q[a][c] = 0.f;
-    float *my = lds + lx + kHalo;    // this lane's column in ring row 0 of level 0
+    // this lane's column in ring row 0 of level 0, as a byte address
+    const int lane_b = (lx + kHalo) * 4;
+    float *const my = lds + lx + kHalo;
     // zero the rings (pad columns included: read only by discarded halo cells)
     for (int q = threadIdx.x; q < TB * RING; q += NTHR) lds[q] = 0.f;
-    __syncthreads();
+
+    // Loads run two steps ahead of their use: step j takes level n at row j,
+    // level n-1 at row j-4 and W, 2a at the rows j-4q its levels compute from
+    // prefetch slot j mod 3 (3 divides the unroll of 9, so slots are
+    // compile-time too) and issues the loads of step j+2 into slot (j+2) mod 3.
+    constexpr int kPf = 3;
+    float pc[kPf], pp[kPf], pw[kPf][TB], pa[kPf][TB];
+    auto issue = [&](const int slotp, const int jj) {
+        pc[slotp] = gld_at(in_cur, rowb(jj) + xo4);
+        pp[slotp] = gld_at(in_prev, rowb(jj - 4) + xo4);
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+            const uint32_t o = rowb(jj - 4 * (q + 1)) + xo4;
+            pw[slotp][q] = gld_at(s.W, o);
+            pa[slotp][q] = gld_at(s.A2, o);
+        }
+    };
+    const int j0 = -kQ;
+#pragma unroll
+    for (int q = 0; q < kPf; ++q) {   // (registers of every slot defined; slot 2 is refilled at the first step)
+        pc[q] = pp[q] = 0.f;
+#pragma unroll
+        for (int r = 0; r < TB; ++r) pw[q][r] = pa[q][r] = 0.f;
+    }
+    issue(0, j0);
+    issue(1, j0 + 1);
 
     auto step = [&](auto ph, const int j) {
         constexpr int PH = decltype(ph)::value;
-        // loads of this step: level n at row j, level n-1 at row j-4 (the old
-        // level of the first new level), W and 2a at the rows the levels compute
-        const float cin = gld_at(in_cur, rowb(j) + xo4);
-        const float pin = gld_at(in_prev, rowb(j - 4) + xo4);
-        float Wv[TB], Av[TB];
-#pragma unroll
-        for (int q = 0; q < TB; ++q) {
-            const uint32_t o = rowb(j - 4 * (q + 1)) + xo4;
-            Wv[q] = gld_at(s.W, o);
-            Av[q] = gld_at(s.A2, o);
-        }
-        __syncthreads();    // ring rows written by earlier steps are visible; rows read at the last step are free
+        constexpr int PS = PH % kPf;
+        // loads of step j+2 (slot (PH+2) mod 3 was last read at step j-1)
+        issue((PH + 2) % kPf, j + 2);
+        // A level's ring row written at step j is read by other waves at step
+        // j+4 (x neighbours of the next level) and rows written at steps j-6,
+        // j-5 by the receivers; the slot it overwrites was last read at step
+        // j-5.  A barrier every third step orders both.
+        if (PH % 3 == 0) __syncthreads();
         // level n, row j
+        const float cin = pc[PS];
         Q[0][slot(PH)] = cin;
         my[slot(PH) * LW] = cin;
         if (free_top && j >= 1 && j <= kHalo) Q[0][slot(-PH)] = -cin;
-        // receivers of levels n..n+TB-1 at base row j - 4q - 2 (rows written at earlier steps)
-        if (due && rend > rbeg) {
+        // receivers of levels n..n+TB-1 at base row j - 4q - 6
+        if (j >= rec_j0 && j <= rec_j1) {
 #pragma unroll
             for (int q = 0; q < TB; ++q) {
-                const int Rb = j - 4 * q - 2;
+                const int Rb = j - 4 * q - 6;
                 if (((due >> q) & 1u) && Rb >= rrow_lo && Rb <= rrow_hi) {
-                    const float *L0 = lds + q * RING + slot(PH - 4 * q - 2) * LW;
-                    const float *L1 = lds + q * RING + slot(PH - 4 * q - 1) * LW;
+                    const float *L0 = lds + q * RING + slot(PH - 4 * q - 6) * LW;
+                    const float *L1 = lds + q * RING + slot(PH - 4 * q - 5) * LW;
                     float *row = s.gathers + ((int64_t)shot * s.nrow + (t.n + q) / s.rec_every) * s.nrec;
                     for (int e = rbeg + (int)threadIdx.x; e < rend; e += NTHR) {
                         const int code = gld(&s.rec_list[e].lds);
@@ -168,22 +195,28 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
             const int R = j - 4 * q;
             const float(&P)[kQ] = Q[q - 1];
             const float c = P[slot(PH - 4 * q)];
-            const float *xr = my + (q - 1) * RING + slot(PH - 4 * q) * LW;
+            // x neighbours of level q-1 at row R: one address register per
+            // read group (the empty asm keeps the compiler from folding the
+            // ring offset into every read, which costs an add per pair)
+            int xa = lane_b + ((q - 1) * RING + slot(PH - 4 * q) * LW - kHalo) * 4;   // column x - 4
+            asm volatile("" : "+v"(xa));
+            const float *xr = (const float *)((const char *)lds + xa);
             const float c4 = -4.f * c;
             float lap = 0.f;
 #pragma unroll
             for (int m = 1; m <= kHalo; ++m) {
                 const float zs = P[slot(PH - 4 * q + m)] + P[slot(PH - 4 * q - m)];
-                lap = fmaf(s.cz[m], (zs + (xr[m] + xr[-m])) + c4, lap);
+                lap = fmaf(s.cz[m], (zs + (xr[kHalo + m] + xr[kHalo - m])) + c4, lap);
             }
-            const float old = q == 1 ? pin : Q[q - 2][slot(PH - 4 * q)];
-            float v = fmaf(Wv[q - 1], lap, fmaf(Av[q - 1], c - old, old));
+            const float old = q == 1 ? pp[PS] : Q[q - 2][slot(PH - 4 * q)];
+            const float Wq = pw[PS][q - 1];
+            float v = fmaf(Wq, lap, fmaf(pa[PS][q - 1], c - old, old));
             if (R >= srow_lo && R <= srow_hi) {
                 const float wq = gld(wshot + (q - 1));
 #pragma unroll
                 for (int k = 0; k < kNodes; ++k) {
                     const float wk = gld(nw_ + k);
-                    if (gld(nz_ + k) == R && X == gld(nx_ + k) && wk != 0.f) v = fmaf(Wv[q - 1], wk * wq, v);
+                    if (gld(nz_ + k) == R && X == gld(nx_ + k) && wk != 0.f) v = fmaf(Wq, wk * wq, v);
                 }
             }
             if (q < TB) {
@@ -204,8 +237,8 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
     };
 
     // steps j0 .. j1-1: the first loads row -9 (guard rows below -4 read as
-    // the clamped guard row), the last computes level n+TB at row Nz-1
-    const int j0 = -kQ;
+    // the clamped guard row), the last computes level n+TB at row Nz-1; the
+    // rings were zeroed before the first step's barrier
     const int nsteps = Nz + 4 * TB + kQ;
     const int j1 = j0 + (nsteps + kQ - 1) / kQ * kQ;
     for (int j = j0; j < j1; j += kQ) {
