@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--levels", type=int, default=10000,
                     help="time levels of the headline batch (shorter runs for counter profiles)")
     ap.add_argument("--batch-tuning", type=str, default="",
-                    help="tile_x,tile_z,time_block (tiled) or strip_width,time_block (column sweep) "
-                         "for the headline batch instead of the autotuner")
+                    help="tile_x,tile_z,time_block (tiled) or s<strip_width>,<segment rows>,<time_block> "
+                         "(column sweep) for the headline batch instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=3)
     ap.add_argument("--shots-per-wave", type=int, default=25)
@@ -118,9 +118,11 @@ def batch_headline(args):
     ws = torch.empty(sgwave.sg_batch_workspace_size(items), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     if args.batch_tuning:
-        parts = [int(x) for x in args.batch_tuning.split(",")]
-        if len(parts) == 2:      # column sweep: strip width, time block
-            tuning = dict(variant=3, tile_x=parts[0], tile_z=0, time_block=parts[1], rows_per_thread=0)
+        parts = [int(x) for x in args.batch_tuning.replace("s", "").split(",")]
+        if args.batch_tuning.startswith("s") or len(parts) == 2:
+            # column sweep: strip width, [segment rows,] time block
+            z = parts[1] if len(parts) == 3 else 0
+            tuning = dict(variant=3, tile_x=parts[0], tile_z=z, time_block=parts[-1], rows_per_thread=0)
         else:                    # tiled: tile_x, tile_z, time block
             tuning = dict(variant=2, tile_x=parts[0], tile_z=parts[1], time_block=parts[2], rows_per_thread=0)
     else:

@@ -126,12 +126,14 @@ typedef struct {
  * Kernel tuning of the time-stepping launches.
  *   variant      0 = library default; 1 = one launch per time step with the
  *                stencil read from global memory; 2 = LDS-tiled, time-blocked
- *                launches; 3 = column sweep: a workgroup walks the whole
- *                height of a strip of tile_x columns (128 or 256, 0 = 256)
- *                advancing time_block (1..6, 0 = 4) levels in a skewed
- *                pipeline, so only the x halo of 4*time_block per side is
- *                recomputed (forward calls with dz == dx; the gradient calls
- *                run variant 2 instead); tile_z and rows_per_thread are 0
+ *                launches; 3 = column sweep: a workgroup walks a strip of
+ *                tile_x columns (128 or 256, 0 = 256) from top to bottom --
+ *                the whole height, or one segment of tile_z output rows
+ *                (0 = whole height, else >= 8) -- advancing time_block (1..6,
+ *                0 = 4) levels in a skewed pipeline, so only the x halo of
+ *                4*time_block per side (and 4*time_block + 4 rows above a
+ *                segment) is recomputed (forward calls with dz == dx; the
+ *                gradient calls run variant 2 instead); rows_per_thread is 0
  *   tile_x, tile_z   cells (x by z) of the LDS tile one workgroup loads
  *                (variant 2), one of the built shapes 128x64, 64x128, 64x64;
  *                the output tile is that minus a halo of 4*time_block per side
@@ -202,7 +204,8 @@ sg_status sg_plan_get_tuning(const sg_plan *p, int32_t nshot, sg_tuning *t);
 /*
  * Autotuner: times every built tile shape with every admissible time block
  * (1..8), and the column sweep (variant 3, strips of 128 and 256 columns,
- * time blocks 2..6) where dz == dx, on this call's real shape -- trial_levels (>= 8) levels of the
+ * time blocks 2..6, whole height or segments of 160, 224 or 320 rows) where
+ * dz == dx, on this call's real shape -- trial_levels (>= 8) levels of the
  * time-stepping launches for `shots` on `vp`, after one untimed pass -- and
  * keeps the fastest as the plan's tuning (also returned in *best).  Uses the
  * workspace of sg_forward (no outputs are written).  Synchronises the stream.

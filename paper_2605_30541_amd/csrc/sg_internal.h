@@ -150,8 +150,9 @@ struct Tiling {
 };
 Tiling make_tiling(int Nz, int Nx, bool free_top, int ex, int ez, int k, int tb);
 // Strips of ex = 64 nw loaded columns for the column-sweep kernel: output
-// width ex - 8 tb, the whole height in one tile row.
-Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb);
+// width ex - 8 tb; each strip cut in segments of seg_h output rows (0 = the
+// whole height), one tile row per segment.
+Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb, int seg_h = 0);
 // Largest time block of the column-sweep kernel, and its strip widths (waves).
 constexpr int kSweepMaxTimeBlock = 6;
 

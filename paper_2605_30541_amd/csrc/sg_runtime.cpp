@@ -321,9 +321,9 @@ sg_tuning resolve_tuning(const sg_plan *p, int nshot, bool gradient = false)
         t.time_block = 1;
         return t;
     }
-    if (t.variant == 3) {         // column sweep: strip width, whole height
+    if (t.variant == 3) {         // column sweep: strip width, segment height (0 = whole)
         if (t.tile_x == 0) t.tile_x = 256;
-        t.tile_z = t.rows_per_thread = 0;
+        t.rows_per_thread = 0;
         if (t.time_block <= 0) t.time_block = 4;
         return t;
     }
@@ -345,9 +345,10 @@ sg_status tiling_for(const sg_plan *p, const sg_tuning &t, int *config, sg::Tili
         if (t.tile_x != 128 && t.tile_x != 256) return fail(SG_EUNSUPPORTED, "sweep strips are 128 or 256 columns");
         if (t.time_block < 1 || t.time_block > sg::kSweepMaxTimeBlock)
             return fail(SG_EINVAL, "sweep time_block must be in 1..%d", sg::kSweepMaxTimeBlock);
-        *T = sg::make_sweep_tiling(p->Nz, p->Nx, t.tile_x / 64, t.time_block);
+        if (t.tile_z != 0 && t.tile_z < 8) return fail(SG_EINVAL, "sweep segments are 0 (whole height) or >= 8 rows");
+        *T = sg::make_sweep_tiling(p->Nz, p->Nx, t.tile_x / 64, t.time_block, t.tile_z);
         if (!T->ok) return fail(SG_EUNSUPPORTED, "time block %d leaves no output strip", t.time_block);
-        if ((int64_t)T->ntx > max_tiles(p)) return fail(SG_EUNSUPPORTED, "tiling too fine");
+        if ((int64_t)T->ntx * T->ntz > max_tiles(p)) return fail(SG_EUNSUPPORTED, "tiling too fine");
         return SG_OK;
     }
     *config = shape_of(t);
@@ -859,15 +860,17 @@ std::vector<sg_tuning> tuning_candidates(const sg_plan *p)
     // column sweep (dz == dx): strips of 128 or 256 columns
     if (p->g.dz == p->g.dx)
         for (int nw : {2, 4})
-            for (int tb = 2; tb <= sg::kSweepMaxTimeBlock; ++tb) {
-                const sg::Tiling T = sg::make_sweep_tiling(p->Nz, p->Nx, nw, tb);
-                if (!T.ok || (int64_t)T.ntx > max_tiles(p)) continue;
-                sg_tuning t{};
-                t.variant = 3;
-                t.tile_x = 64 * nw;
-                t.time_block = tb;
-                out.push_back(t);
-            }
+            for (int tb = 2; tb <= sg::kSweepMaxTimeBlock; ++tb)
+                for (int seg : {0, 160, 224, 320}) {
+                    const sg::Tiling T = sg::make_sweep_tiling(p->Nz, p->Nx, nw, tb, seg);
+                    if (!T.ok || (int64_t)T.ntx * T.ntz > max_tiles(p) || (seg > 0 && T.ntz < 2)) continue;
+                    sg_tuning t{};
+                    t.variant = 3;
+                    t.tile_x = 64 * nw;
+                    t.tile_z = seg;
+                    t.time_block = tb;
+                    out.push_back(t);
+                }
     return out;
 }
 
@@ -1077,8 +1080,8 @@ sg_status sg_plan_set_tuning(sg_plan *p, const sg_tuning *t)
     if (t->variant == 3) {
         if (t->tile_x != 0 && t->tile_x != 128 && t->tile_x != 256)
             return fail(SG_EUNSUPPORTED, "sweep strips are 128 or 256 columns");
-        if (t->tile_z != 0 || t->rows_per_thread != 0)
-            return fail(SG_EINVAL, "sweep tunings take tile_z = rows_per_thread = 0");
+        if ((t->tile_z != 0 && t->tile_z < 8) || t->rows_per_thread != 0)
+            return fail(SG_EINVAL, "sweep tunings take tile_z = 0 or >= 8 (segment rows) and rows_per_thread = 0");
         if (t->time_block < 0 || t->time_block > sg::kSweepMaxTimeBlock)
             return fail(SG_EINVAL, "sweep time_block must be in 0..%d", sg::kSweepMaxTimeBlock);
         p->tuning = *t;

@@ -62,9 +62,14 @@ template <int NW, int TB>
 __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t, int b, float *lds)
 {
     constexpr int EX = 64 * NW, LW = EX + 2 * kHalo, NTHR = 64 * NW, RING = kQ * LW;
-    const int strips = t.ntx;
-    const int shot = b / strips;
-    const int strip = b - shot * strips;
+    // block b: (shot, segment, strip); a segment is the output rows
+    // [zs0, zs1) of the strip (t.tz rows; one segment = the whole height)
+    const int tiles = t.ntx * t.ntz;
+    const int shot = b / tiles;
+    const int tile = b - shot * tiles;
+    const int seg = tile / t.ntx;
+    const int strip = tile - seg * t.ntx;
+    const int zs0 = seg * t.tz, zs1 = min(zs0 + t.tz, s.Nz);
     const int ox = strip * t.tx, ox_end = min(ox + t.tx, s.Nx), ex0 = ox - kHalo * t.tb;
     const int lx = (int)threadIdx.x;
     const int X = ex0 + lx;
@@ -102,8 +107,8 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
     int rbeg = 0, rend = 0, rrow_lo = 1 << 30, rrow_hi = -(1 << 30);
     unsigned due = 0;
     if (s.gathers) {
-        rbeg = gld(s.tile_rec + strip);
-        rend = gld(s.tile_rec + strip + 1);
+        rbeg = gld(s.tile_rec + tile);
+        rend = gld(s.tile_rec + tile + 1);
         if (rend > rbeg) {
             rrow_lo = gld(&s.rec_list[rbeg].lds) / LW;
             rrow_hi = gld(&s.rec_list[rend - 1].lds) / LW;
@@ -143,7 +148,13 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
             pa[slotp][q] = gld_at(s.A2, o);
         }
     };
-    const int j0 = -kQ;
+    // first step: the top segment starts at row -9 (every row above 0 is a
+    // guard or ghost row); a lower one TB levels of 4 rows, plus the 4 rows
+    // level n+1 reads above, before its first output row, on a multiple of 9
+    // (the unrolled loop's phase 0): rows computed before then are not exact,
+    // and no output row reads them
+    const int jf = zs0 - 4 * TB - kHalo;
+    const int j0 = zs0 == 0 ? -kQ : jf - (jf % kQ + kQ) % kQ;
 #pragma unroll
     for (int q = 0; q < kPf; ++q) {   // (registers of every slot defined; slot 2 is refilled at the first step)
         pc[q] = pp[q] = 0.f;
@@ -229,17 +240,17 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
         }
         // output: levels n+TB and n+TB-1 at row j - 4TB
         const int R = j - 4 * TB;
-        if (R >= 0 && R < Nz && xout) {
+        if (R >= zs0 && R < zs1 && xout) {
             const uint32_t o = (uint32_t)((R + kGuard) * pitch) * 4u + xs4;
             gst_at(out_cur, o, vlast);
             gst_at(out_prev, o, Q[TB - 1][slot(PH - 4 * TB)]);
         }
     };
 
-    // steps j0 .. j1-1: the first loads row -9 (guard rows below -4 read as
-    // the clamped guard row), the last computes level n+TB at row Nz-1; the
-    // rings were zeroed before the first step's barrier
-    const int nsteps = Nz + 4 * TB + kQ;
+    // steps j0 .. j1-1: guard rows outside [-4, Nz+4) read as the clamped
+    // guard row; the last step computes level n+TB at row zs1-1; the rings
+    // were zeroed before the first step's barrier
+    const int nsteps = zs1 + 4 * TB - j0;
     const int j1 = j0 + (nsteps + kQ - 1) / kQ * kQ;
     for (int j = j0; j < j1; j += kQ) {
         step(std::integral_constant<int, 0>{}, j);
@@ -314,7 +325,7 @@ hipError_t launch_sweep_nw(const SliceDesc *s, const TileArgs *t, const BatchIte
 
 }  // namespace
 
-Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb)
+Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb, int seg_h)
 {
     Tiling T{};
     T.ex = 64 * nw;
@@ -322,19 +333,19 @@ Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb)
     T.k = 0;
     T.tb = tb;
     T.tx = T.ex - 2 * kHalo * tb;
-    T.tz = Nz;
-    T.tz_top = Nz;
+    T.tz = seg_h > 0 && seg_h < Nz ? seg_h : Nz;
+    T.tz_top = T.tz;          // segments are equal from the top (free top or not)
     T.sweep_nw = nw;
-    T.ok = (nw == 2 || nw == 4) && tb >= 1 && tb <= kSweepMaxTimeBlock && T.tx >= 1;
+    T.ok = (nw == 2 || nw == 4) && tb >= 1 && tb <= kSweepMaxTimeBlock && T.tx >= 1 && seg_h >= 0;
     if (!T.ok) return T;
     T.ntx = (Nx + T.tx - 1) / T.tx;
-    T.ntz = 1;
+    T.ntz = (Nz + T.tz - 1) / T.tz;
     return T;
 }
 
 hipError_t launch_sweep(const SliceDesc &s, const TileArgs &t, int nw, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)(t.ntx * s.nshot);
+    const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
     switch (nw) {
     case 2: return launch_sweep_nw<2>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, st);
     case 4: return launch_sweep_nw<4>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, st);

@@ -145,7 +145,9 @@ def test_tuning_validation():
     assert p.get_tuning(1) == dict(variant=3, tile_x=256, tile_z=0, time_block=4, rows_per_thread=0)
     p.set_tuning(variant=3, tile_x=128, time_block=6)
     assert p.get_tuning(1) == dict(variant=3, tile_x=128, tile_z=0, time_block=6, rows_per_thread=0)
-    for bad in (dict(tile_x=192), dict(time_block=7), dict(tile_z=64), dict(rows_per_thread=8)):
+    p.set_tuning(variant=3, tile_x=256, tile_z=160, time_block=4)
+    assert p.get_tuning(1)["tile_z"] == 160
+    for bad in (dict(tile_x=192), dict(time_block=7), dict(tile_z=4), dict(rows_per_thread=8)):
         with pytest.raises(SGError):
             p.set_tuning(variant=3, **bad)
     p.clear_tuning()

@@ -1,7 +1,9 @@
 """GPU parity of the column-sweep forward kernel (tuning variant 3): the same
 update expression as the tiled kernel, so every gather and snapshot equals
 the tiled kernel's bit for bit, and the FP64 oracle's to relative L2 <= 1e-4.
-Covers strips of 128 and 256 columns with time blocks 1..6, free and
+Covers strips of 128 and 256 columns with time blocks 1..6, the whole height
+or segments of 8 to 45 rows (several per strip, receivers and sources in
+every segment), free and
 absorbing tops, sources and receivers on and next to the free-surface rows,
 off-grid positions, decimated receivers, snapshots, grids narrower than a
 strip or only a few rows high, and the batched launch over uneven slices."""
@@ -64,24 +66,27 @@ def check(g, v, src, rec, wl, tuning):
 
 
 SWEEPS = [dict(variant=3, tile_x=128, time_block=tb) for tb in (1, 2, 3, 4, 5, 6)] + \
-         [dict(variant=3, tile_x=256, time_block=tb) for tb in (1, 3, 4, 6)]
-SIDS = ["s128b%d" % t for t in (1, 2, 3, 4, 5, 6)] + ["s256b%d" % t for t in (1, 3, 4, 6)]
+         [dict(variant=3, tile_x=256, time_block=tb) for tb in (1, 3, 4, 6)] + \
+         [dict(variant=3, tile_x=256, tile_z=z, time_block=tb) for z, tb in ((8, 1), (17, 4), (30, 6), (45, 3))]
+SIDS = ["s128b%d" % t for t in (1, 2, 3, 4, 5, 6)] + ["s256b%d" % t for t in (1, 3, 4, 6)] + \
+       ["s256z%db%d" % zt for zt in ((8, 1), (17, 4), (30, 6), (45, 3))]
 
 
 @pytest.mark.parametrize("tuning", SWEEPS, ids=SIDS)
 @pytest.mark.parametrize("top", [sgwave.SG_TOP_FREE, sgwave.SG_TOP_ABSORBING], ids=["free", "absorbing"])
 def test_sweep_equals_tiled_and_oracle(tuning, top):
     """A ragged field slice (91 x 301 at 10 m, 12-cell sponge), three shots:
-    one on row 1, one off-grid at 23.4 m depth, one on row 2; receivers on row
-    1 at every column plus off-grid ones at 17.5 m and 41 m depth; snapshots
-    every 37 levels."""
+    one on row 1, one off-grid at 23.4 m depth, one off-grid at 503.3 m;
+    receivers on row 1 at every column plus off-grid ones from 17.5 m to 555.5
+    m depth and one on the last row; snapshots every 37 levels."""
     nz, nx, h, nt = 91, 301, 10.0, 260
     g = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=8e-4, nt=nt, nbl=12, vmax_hint=4500.0, top=top,
                  snap_every=37, snap_count=7)
     v = synth.field_slice(11, nz, nx)
-    src = np.array([[10.0, 400.0], [23.4, 1513.7], [20.0, 2907.0]])
+    src = np.array([[10.0, 400.0], [23.4, 1513.7], [503.3, 2907.0]])
     rec = np.concatenate([synth.surface_receivers(nx, h),
-                          np.array([[17.5, 55.5], [41.0, 1777.7], [17.5, 2996.0], [0.0, 1200.0]])])
+                          np.array([[17.5, 55.5], [41.0, 1777.7], [17.5, 2996.0], [0.0, 1200.0],
+                                    [400.0, 1500.0], [555.5, 2222.2], [899.0, 640.0]])])
     wl = np.stack([oracle.ricker(14.0 + 3 * k, g.dt, nt) for k in range(3)])
     check(g, v, src, rec, wl, tuning)
 
@@ -101,7 +106,9 @@ def test_sweep_small_and_narrow_grids(tuning, nz, nx, nbl, nt, rec_every):
 
 
 @pytest.mark.parametrize("tuning", [dict(variant=3, tile_x=128, time_block=3),
-                                    dict(variant=3, tile_x=256, time_block=5)], ids=["s128b3", "s256b5"])
+                                    dict(variant=3, tile_x=256, time_block=5),
+                                    dict(variant=3, tile_x=256, tile_z=20, time_block=4)],
+                         ids=["s128b3", "s256b5", "s256z20b4"])
 def test_sweep_batched_uneven_slices(tuning):
     """The batched launch over four uneven slices with 3, 1, 2, 2 shots:
     equal to the tiled batch bit for bit and to the oracle."""
