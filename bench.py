@@ -49,6 +49,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=3)
     ap.add_argument("--shots-per-wave", type=int, default=25)
+    ap.add_argument("--grad-tuning", type=str, default="",
+                    help="tuning of the forward and recompute passes of the 16-shot gradient, in the "
+                         "form of --batch-tuning (the adjoint always runs the tiled kernel)")
+    ap.add_argument("--batched-grad-tuning", type=str, default="s256,160,3",
+                    help="the same for the full-density batched gradient (default: column sweep, 256-column "
+                         "strips, 160-row segments, time block 3, the fastest measured; '' = tiled)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -107,6 +113,17 @@ def batch_items(levels):
     return items, points, cases
 
 
+def parse_tuning(spec):
+    """tile_x,tile_z,time_block (tiled) or s<strip>,<segment rows>,<time block> (column sweep)."""
+    if not spec:
+        return None
+    parts = [int(x) for x in spec.replace("s", "").split(",")]
+    if spec.startswith("s") or len(parts) == 2:
+        z = parts[1] if len(parts) == 3 else 0
+        return dict(variant=3, tile_x=parts[0], tile_z=z, time_block=parts[-1], rows_per_thread=0)
+    return dict(variant=2, tile_x=parts[0], tile_z=parts[1], time_block=parts[2], rows_per_thread=0)
+
+
 def batch_headline(args):
     """Times K replays of the headline batch (after W untimed ones), and the
     average launch of its time-stepping kernel from events on the stream the
@@ -118,13 +135,7 @@ def batch_headline(args):
     ws = torch.empty(sgwave.sg_batch_workspace_size(items), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     if args.batch_tuning:
-        parts = [int(x) for x in args.batch_tuning.replace("s", "").split(",")]
-        if args.batch_tuning.startswith("s") or len(parts) == 2:
-            # column sweep: strip width, [segment rows,] time block
-            z = parts[1] if len(parts) == 3 else 0
-            tuning = dict(variant=3, tile_x=parts[0], tile_z=z, time_block=parts[-1], rows_per_thread=0)
-        else:                    # tiled: tile_x, tile_z, time block
-            tuning = dict(variant=2, tile_x=parts[0], tile_z=parts[1], time_block=parts[2], rows_per_thread=0)
+        tuning = parse_tuning(args.batch_tuning)
     else:
         tuning = sgwave.sg_batch_autotune(items, ws, 32)          # untimed
     log("headline batch: tuning %s" % tuning)
@@ -249,7 +260,7 @@ def field_shot_rate(steps=20):
             "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}, v
 
 
-def gradient_rate(v, fwd_rate):
+def gradient_rate(v, fwd_rate, tuning=None):
     """Forward with checkpoints + adjoint gradient: 16 shots on the field
     slice (1D-smoothed start model), checkpoints every 100 levels."""
     import numpy as np
@@ -259,6 +270,8 @@ def gradient_rate(v, fwd_rate):
     nz, nx, h, dt, nt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 10000, 16, 100
     geom = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
     plan = Plan(geom)
+    if tuning:
+        plan.set_tuning(**tuning)
     v0 = torch.from_numpy(synth.smoothed_1d(v, 500.0, h)).cuda()
     shots = Shots(synth.shot_line(nshot, 1100.0, 8900.0), synth.surface_receivers(nx, h),
                   sgwave.ricker_tensor(12.0, dt, nt))
@@ -283,6 +296,7 @@ def gradient_rate(v, fwd_rate):
     sgwave.sg_check_finite(grad, ws)
     return {"workload": "forward with checkpoints + adjoint-state gradient, 16 shots on the 620x1001 "
                         "slice, nt 10000, checkpoints every 100 levels (segment recompute)",
+            "tuning": plan.get_tuning(nshot),
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
             "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
@@ -476,7 +490,7 @@ def builder_rate(passes=3):
             "deposit_Gvoxel_per_s": tb * ny * nx / (ms_d / 1e3) / 1e9}
 
 
-def batched_gradient_rate(fwd_rate, shots_per_wave):
+def batched_gradient_rate(fwd_rate, shots_per_wave, tuning=None):
     """4 field slices of uneven size (nz 500-620, nx 801-1001) x 100 shots
     spread evenly over the full width, nt 10000 at 0.8 ms, receivers on every
     column: forward with checkpoints every 100 levels, segment recompute and
@@ -504,7 +518,7 @@ def batched_gradient_rate(fwd_rate, shots_per_wave):
                      device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    sgwave.sg_batch_adjoint_gradient(items, ws, ckpt, shots_per_wave)
+    sgwave.sg_batch_adjoint_gradient(items, ws, ckpt, shots_per_wave, tuning=tuning)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -515,7 +529,7 @@ def batched_gradient_rate(fwd_rate, shots_per_wave):
                         "forward with checkpoints every 100 levels + segment recompute + adjoint, "
                         "%d shots per slice per wave" % shots_per_wave,
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
-            "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
+            "forward_tuning": tuning, "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
 
 def main():
@@ -535,9 +549,10 @@ def main():
             out["field_shot"], _ = field_shot_rate()
         elif args.only == "gradient":
             from paper_2605_30541_amd import synth
-            out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None)
+            out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None, parse_tuning(args.grad_tuning))
         elif args.only == "batched_gradient":
-            out["batched_gradient"] = batched_gradient_rate(None, args.shots_per_wave)
+            out["batched_gradient"] = batched_gradient_rate(None, args.shots_per_wave,
+                                                            parse_tuning(args.batched_grad_tuning))
         elif args.only == "paper":
             out["paper_workload"] = paper_workload_rate(None)
         elif args.only == "residual":
@@ -576,9 +591,10 @@ def main():
     if args.only is None:
         out["field_shot"], v = field_shot_rate()
         log("field shot: %.1f Gpt-updates/s" % out["field_shot"]["value"])
-        out["gradient"] = gradient_rate(v, value)
+        out["gradient"] = gradient_rate(v, value, parse_tuning(args.grad_tuning))
         log("gradient: %.1f Gpt-steps/s" % out["gradient"]["value"])
-        out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave)
+        out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave,
+                                                        parse_tuning(args.batched_grad_tuning))
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
         out["paper_workload"] = paper_workload_rate(value)
         log("paper-shaped batch: %.1f Gpt-updates/s" % out["paper_workload"]["value"])

@@ -170,11 +170,12 @@ hipError_t launch_step_naive(const SliceDesc &s, int n, hipStream_t st);
 hipError_t launch_step_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
 hipError_t launch_adjoint_tiled(const SliceDesc &s, const TileArgs &t, int config, hipStream_t st);
 // Column-sweep forward (sg_sweep.hip, dz == dx only): t.nsteps levels (1..6)
-// over strips of 64 nw columns (nw 2 or 4); the batched form like
-// launch_step_tiled_batch.
+// over strips of 64 nw columns (nw 2 or 4); with t.ring (ring for the batched
+// form) also the second time differences into the ring, as the tiled kernel's
+// recompute mode.  The batched form like launch_step_tiled_batch.
 hipError_t launch_sweep(const SliceDesc &s, const TileArgs &t, int nw, hipStream_t st);
 hipError_t launch_sweep_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps, int in_pair,
-                              int nw, hipStream_t st);
+                              int nw, hipStream_t st, bool ring = false, int ring_lo = 0);
 // Batched launches: items[0..nitems) in device memory, total_blocks = sum of
 // the items' blocks (items[i].block_start is the prefix sum).
 hipError_t launch_step_tiled_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps,

@@ -592,7 +592,6 @@ sg_status forward_run(sg_plan *p, const sg::SliceDesc &s, const sg_tuning &t, in
             a.ring_lo = ring_lo;
             a.ring_shot = ring_shot;
             if (T.sweep_nw > 0) {
-                if (ring) return fail(SG_EUNSUPPORTED, "the column-sweep kernel has no recompute mode");
                 SG_HIP(sg::launch_sweep(s, a, T.sweep_nw, st));
             } else {
                 SG_HIP(sg::launch_step_tiled(s, a, config, st));
@@ -622,12 +621,18 @@ int level_slot(const sg_tuning &t, int m, int pair) { return t.variant == 1 ? (m
 // Runs levels 0 .. nt-1 of every shot: records each level while stepping
 // from it, then records the last level.
 
-// Shared validation and set-up of the calls on one slice.
+// Shared validation and set-up of the calls on one slice.  The gradient
+// calls keep two tilings: T for the adjoint (always the tiled kernel) and Tf
+// for the forward and its recompute (the column sweep when the plan's tuning
+// asks for it, else the same as T).
 struct CallSetup {
     Layout L;
     sg_tuning t;
     int config = -1;
     sg::Tiling T{};
+    sg_tuning tf;
+    int config_f = -1;
+    sg::Tiling Tf{};
 };
 
 sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *ws, size_t ws_bytes, int ckpt,
@@ -643,13 +648,22 @@ sg_status setup_call(sg_plan *p, const float *vp, const sg_shots *shots, void *w
         return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, c->L.total);
     const bool gradient = need_tiled && ckpt > 0;
     c->t = resolve_tuning(p, shots->nshot, gradient);
-    if (need_tiled && (c->t.variant == 1 || c->t.variant == 3)) {   // the gradient path runs on the tiled kernels
+    const bool sweep_fwd = gradient && c->t.variant == 3;
+    if (sweep_fwd) c->tf = c->t;
+    if (need_tiled && (c->t.variant == 1 || c->t.variant == 3)) {   // the adjoint runs on the tiled kernel
         sg_tuning keep = p->tuning;
         p->tuning = sg_tuning{};
         c->t = resolve_tuning(p, shots->nshot, gradient);
         p->tuning = keep;
     }
     if (c->t.variant >= 2 && (rc = tiling_for(p, c->t, &c->config, &c->T)) != SG_OK) return rc;
+    if (sweep_fwd) {
+        if ((rc = tiling_for(p, c->tf, &c->config_f, &c->Tf)) != SG_OK) return rc;
+    } else {
+        c->tf = c->t;
+        c->config_f = c->config;
+        c->Tf = c->T;
+    }
     return SG_OK;
 }
 
@@ -1286,7 +1300,7 @@ sg_status sg_forward_ckpt(sg_plan *p, const float *vp, const sg_shots *shots, in
     if (rc != SG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
-    if ((rc = upload_tables(p, c.L, w, shots, &c.T, st)) != SG_OK) return rc;
+    if ((rc = upload_tables(p, c.L, w, shots, &c.Tf, st)) != SG_OK) return rc;
     sg::SliceDesc s = describe(p, c.L, w, shots, gathers, nullptr);
     s.snaps = nullptr;
     SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
@@ -1306,9 +1320,9 @@ sg_status sg_forward_ckpt(sg_plan *p, const float *vp, const sg_shots *shots, in
                                (int64_t)sg::kFramesPerShot * p->frame, 2 * p->frame, nshot, st));
         return SG_OK;
     };
-    rc = forward_run(p, s, c.t, c.config, c.T, 0, nt - 1, C, &pair, nullptr, 0, 0, on_cut, st);
+    rc = forward_run(p, s, c.tf, c.config_f, c.Tf, 0, nt - 1, C, &pair, nullptr, 0, 0, on_cut, st);
     if (rc != SG_OK) return rc;
-    SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(c.t, nt - 1, pair), st));
+    SG_HIP(sg::launch_record_slot(s, nt - 1, level_slot(c.tf, nt - 1, pair), st));
     return SG_OK;
 }
 
@@ -1353,7 +1367,7 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
         SG_HIP(sg::launch_copy(s.fields, fshot, ckj, ck_shot, 2 * F, nshot, st));
         int pair = 0;
         if (last > lo) {
-            rc = forward_run(p, s, c.t, c.config, c.T, lo, last, 0, &pair, ring, lo, ring_shot,
+            rc = forward_run(p, s, c.tf, c.config_f, c.Tf, lo, last, 0, &pair, ring, lo, ring_shot,
                              [](int, int) { return SG_OK; }, st);
             if (rc != SG_OK) return rc;
         }
@@ -1659,6 +1673,15 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         if ((rc = check_shots(items[i].plan, items[i].shots)) != SG_OK) return rc;
     }
     sg_tuning t = tuning ? *tuning : resolve_tuning(items[0].plan, items[0].shots->nshot, true);
+    // a column-sweep tuning runs the forward and its recompute; the adjoint
+    // always runs the tiled kernel (with the default tiling unless a tiled
+    // tuning is given)
+    sg_tuning tf = t;
+    const bool sweep_fwd = t.variant == 3;
+    if (sweep_fwd) {
+        if (tf.tile_x == 0) tf.tile_x = 256;
+        if (tf.time_block <= 0) tf.time_block = 4;
+    }
     if (t.variant != 2) {
         sg_plan *p0 = items[0].plan;
         sg_tuning keep = p0->tuning;
@@ -1666,10 +1689,13 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         t = resolve_tuning(p0, items[0].shots->nshot, true);
         p0->tuning = keep;
     }
-    std::vector<sg::Tiling> T(nitems);
-    int config = -1;
-    for (int i = 0; i < nitems; ++i)
+    if (!sweep_fwd) tf = t;
+    std::vector<sg::Tiling> T(nitems), Tf(nitems);
+    int config = -1, config_f = -1;
+    for (int i = 0; i < nitems; ++i) {
         if ((rc = tiling_for(items[i].plan, t, &config, &T[i])) != SG_OK) return rc;
+        if ((rc = tiling_for(items[i].plan, tf, &config_f, &Tf[i])) != SG_OK) return rc;
+    }
     bool iso = true;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
@@ -1683,9 +1709,9 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         std::vector<int> act;
         std::vector<sg_shots> views;
         std::vector<Layout> Ls;
-        std::vector<sg::BatchItem> hb;
+        std::vector<sg::BatchItem> hb, hb_adj;
         size_t o = 0;
-        int32_t start = 0;
+        int32_t start = 0, start_adj = 0;
         views.reserve(nitems);
         for (int i = 0; i < nitems; ++i) {
             const sg_batch_grad_item &it = items[i];
@@ -1712,7 +1738,7 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             SG_HIP(sg::launch_zero(b.s.fields, (size_t)cnt * sg::kFramesPerShot * F, st));
             SG_HIP(sg::launch_zero((float *)(wi + L.mu), (size_t)cnt * sg::kFramesPerShot * F, st));
             SG_HIP(sg::launch_zero((float *)(wi + L.hsum), (size_t)cnt * 2 * F, st));
-            b.t = tile_args(T[i], b.s.fields, 0, 0, 0);
+            b.t = tile_args(Tf[i], b.s.fields, 0, 0, 0);
             b.t.ring = (float *)(wi + L.ring);
             b.t.ring_shot = (int64_t)L.ring_levels * F;
             b.t.resid = it.resid + (size_t)s0 * it.plan->nrow * it.shots->nrec;
@@ -1726,8 +1752,21 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             b.t.inj.rid = (const int32_t *)(wi + L.inj_rid);
             b.t.inj.w = (const float *)(wi + L.inj_w);
             b.block_start = start;
-            start += T[i].ntx * T[i].ntz * cnt;
+            start += Tf[i].ntx * Tf[i].ntz * cnt;
             hb.push_back(b);
+            // the adjoint's entry: its tiling, fields in the adjoint pair
+            sg::BatchItem ba = b;
+            const sg::TileArgs keep_t = b.t;
+            ba.t = tile_args(T[i], (float *)(wi + L.mu), 0, 0, 0);
+            ba.t.ring = keep_t.ring;
+            ba.t.ring_shot = keep_t.ring_shot;
+            ba.t.resid = keep_t.resid;
+            ba.t.hsum = keep_t.hsum;
+            ba.t.nt = keep_t.nt;
+            ba.t.inj = keep_t.inj;
+            ba.block_start = start_adj;
+            start_adj += T[i].ntx * T[i].ntz * cnt;
+            hb_adj.push_back(ba);
             // checkpoint 0: levels -1 and 0, both zero
             SG_HIP(sg::launch_copy((float *)(wi + L.ckpt), (int64_t)L.nseg * 2 * F, b.s.fields,
                                    (int64_t)sg::kFramesPerShot * F, 2 * F, cnt, st));
@@ -1741,9 +1780,6 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         {
             std::vector<char> both(2 * tbl, 0);
             std::memcpy(both.data(), hb.data(), hb.size() * sizeof(sg::BatchItem));
-            std::vector<sg::BatchItem> hb_adj = hb;
-            for (int q = 0; q < na; ++q)
-                hb_adj[q].t.fields = (float *)((char *)hb[q].s.fields - Ls[q].fields + Ls[q].mu);
             std::memcpy(both.data() + tbl, hb_adj.data(), hb_adj.size() * sizeof(sg::BatchItem));
             if ((rc = stage_upload(dev_fwd, both.data(), 2 * tbl, st)) != SG_OK) return rc;
         }
@@ -1763,8 +1799,11 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         // forward with checkpoints (no outputs)
         int pair = 0;
         for (int n = 0; n < nt - 1;) {
-            const int k = std::min(std::min(t.time_block, nt - 1 - n), C - n % C);
-            SG_HIP(sg::launch_step_tiled_batch(dev_fwd, na, start, n, k, pair, config, iso, st));
+            const int k = std::min(std::min(tf.time_block, nt - 1 - n), C - n % C);
+            if (sweep_fwd)
+                SG_HIP(sg::launch_sweep_batch(dev_fwd, na, start, n, k, pair, Tf[0].sweep_nw, st));
+            else
+                SG_HIP(sg::launch_step_tiled_batch(dev_fwd, na, start, n, k, pair, config, iso, st));
             pair ^= 1;
             n += k;
             if (n % C == 0 && n / C < Ls[0].nseg) {
@@ -1800,14 +1839,18 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             if (rc != SG_OK) return rc;
             int fp = 0;
             for (int n = lo; n < last;) {
-                const int k = std::min(t.time_block, last - n);
-                SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo, st));
+                const int k = std::min(tf.time_block, last - n);
+                if (sweep_fwd)
+                    SG_HIP(sg::launch_sweep_batch(dev_fwd, na, start, n, k, fp, Tf[0].sweep_nw, st, true, lo));
+                else
+                    SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo, st));
                 fp ^= 1;
                 n += k;
             }
             for (int k0 = hi; k0 >= lo;) {
                 const int ns = std::min(t.time_block, k0 - lo + 1);
-                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start, k0, ns, mpair, config, iso, lo, last - 1, st));
+                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start_adj, k0, ns, mpair, config, iso, lo, last - 1,
+                                                      st));
                 mpair ^= 1;
                 k0 -= ns;
             }

@@ -58,7 +58,11 @@ __device__ inline int xcd_block(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
-template <int NW, int TB>
+// RECOMP (the forward recompute of the gradient): also stores, for every level
+// n+q-1 advanced, the second time difference D = (p^{n+q} - p^{n+q-1}) -
+// (p^{n+q-1} - p^{n+q-2}) of the output cells in ring slot n+q-1 - t.ring_lo
+// (streaming stores: read back only by the adjoint after the segment).
+template <int NW, int TB, bool RECOMP>
 __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t, int b, float *lds)
 {
     constexpr int EX = 64 * NW, LW = EX + 2 * kHalo, NTHR = 64 * NW, RING = kQ * LW;
@@ -230,6 +234,12 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
                     if (gld(nz_ + k) == R && X == gld(nx_ + k) && wk != 0.f) v = fmaf(Wq, wk * wq, v);
                 }
             }
+            if (RECOMP && R >= zs0 && R < zs1 && xout) {
+                float *rl = t.ring + (int64_t)shot * t.ring_shot + (int64_t)(t.n + q - 1 - t.ring_lo) * s.frame;
+                __builtin_nontemporal_store((v - c) - (c - old),
+                                            (__attribute__((address_space(1))) float *)((char *)rl +
+                                                (uint32_t)((R + kGuard) * pitch) * 4u + xs4));
+            }
             if (q < TB) {
                 Q[q][slot(PH - 4 * q)] = v;
                 my[q * RING + slot(PH - 4 * q) * LW] = v;
@@ -265,16 +275,16 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
     }
 }
 
-template <int NW, int TB>
+template <int NW, int TB, bool RECOMP>
 __global__ void __launch_bounds__(64 * NW) k_sweep(SliceDesc s, TileArgs t)
 {
     __shared__ float lds[TB * kQ * (64 * NW + 2 * kHalo)];
-    sweep_body<NW, TB>(s, t, xcd_block(blockIdx.x, gridDim.x), lds);
+    sweep_body<NW, TB, RECOMP>(s, t, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
-template <int NW, int TB>
+template <int NW, int TB, bool RECOMP>
 __global__ void __launch_bounds__(64 * NW) k_sweep_batch(const BatchItem *__restrict__ items, int nitems, int n,
-                                                          int in_pair)
+                                                          int in_pair, int ring_lo)
 {
     __shared__ float lds[TB * kQ * (64 * NW + 2 * kHalo)];
     const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -295,20 +305,21 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_batch(const BatchItem *__rest
     t.nsteps = TB;
     t.in_pair = in_pair;
     t.out_pair = in_pair ^ 1;
-    sweep_body<NW, TB>(s, t, b - items[it].block_start, lds);
+    t.ring_lo = ring_lo;
+    sweep_body<NW, TB, RECOMP>(s, t, b - items[it].block_start, lds);
 }
 
-template <int NW>
+template <int NW, bool RECOMP>
 hipError_t launch_sweep_nw(const SliceDesc *s, const TileArgs *t, const BatchItem *items, int nitems,
-                           unsigned blocks, int n, int nsteps, int in_pair, hipStream_t st)
+                           unsigned blocks, int n, int nsteps, int in_pair, int ring_lo, hipStream_t st)
 {
-#define SG_SWEEP(TBV)                                                                                            \
-    case TBV:                                                                                                    \
-        if (items)                                                                                               \
-            hipLaunchKernelGGL((k_sweep_batch<NW, TBV>), dim3(blocks), dim3(64 * NW), 0, st, items, nitems, n, \
-                               in_pair);                                                                         \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_sweep<NW, TBV>), dim3(blocks), dim3(64 * NW), 0, st, *s, *t);              \
+#define SG_SWEEP(TBV)                                                                                                \
+    case TBV:                                                                                                        \
+        if (items)                                                                                                   \
+            hipLaunchKernelGGL((k_sweep_batch<NW, TBV, RECOMP>), dim3(blocks), dim3(64 * NW), 0, st, items, nitems, \
+                               n, in_pair, ring_lo);                                                                 \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_sweep<NW, TBV, RECOMP>), dim3(blocks), dim3(64 * NW), 0, st, *s, *t);            \
         break
     switch (nsteps) {
         SG_SWEEP(1);
@@ -346,19 +357,25 @@ Tiling make_sweep_tiling(int Nz, int Nx, int nw, int tb, int seg_h)
 hipError_t launch_sweep(const SliceDesc &s, const TileArgs &t, int nw, hipStream_t st)
 {
     const unsigned blocks = (unsigned)(t.ntx * t.ntz * s.nshot);
-    switch (nw) {
-    case 2: return launch_sweep_nw<2>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, st);
-    case 4: return launch_sweep_nw<4>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, st);
+    const bool ring = t.ring != nullptr;
+    switch (nw * 2 + (ring ? 1 : 0)) {
+    case 4: return launch_sweep_nw<2, false>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, 0, st);
+    case 5: return launch_sweep_nw<2, true>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, 0, st);
+    case 8: return launch_sweep_nw<4, false>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, 0, st);
+    case 9: return launch_sweep_nw<4, true>(&s, &t, nullptr, 0, blocks, t.n, t.nsteps, t.in_pair, 0, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep_batch(const BatchItem *items, int nitems, int total_blocks, int n, int nsteps, int in_pair,
-                              int nw, hipStream_t st)
+                              int nw, hipStream_t st, bool ring, int ring_lo)
 {
-    switch (nw) {
-    case 2: return launch_sweep_nw<2>(nullptr, nullptr, items, nitems, (unsigned)total_blocks, n, nsteps, in_pair, st);
-    case 4: return launch_sweep_nw<4>(nullptr, nullptr, items, nitems, (unsigned)total_blocks, n, nsteps, in_pair, st);
+    const unsigned b = (unsigned)total_blocks;
+    switch (nw * 2 + (ring ? 1 : 0)) {
+    case 4: return launch_sweep_nw<2, false>(nullptr, nullptr, items, nitems, b, n, nsteps, in_pair, 0, st);
+    case 5: return launch_sweep_nw<2, true>(nullptr, nullptr, items, nitems, b, n, nsteps, in_pair, ring_lo, st);
+    case 8: return launch_sweep_nw<4, false>(nullptr, nullptr, items, nitems, b, n, nsteps, in_pair, 0, st);
+    case 9: return launch_sweep_nw<4, true>(nullptr, nullptr, items, nitems, b, n, nsteps, in_pair, ring_lo, st);
     default: return hipErrorInvalidValue;
     }
 }
