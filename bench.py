@@ -65,21 +65,26 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
-    p = os.path.join(ROOT, "paper_2605_30541_amd", "csrc", "sg_kernels.hip")
+def kernel_source_sha(kernel: str):
+    """sha256[:16] of the source file holding a kernel."""
+    f = "sg_sweep.hip" if kernel.startswith("k_sweep") else "sg_kernels.hip"
+    p = os.path.join(ROOT, "paper_2605_30541_amd", "csrc", f)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_record(kernel: str, workload: str):
-    """Counter record of a kernel on a workload from profiles/, if it was taken
-    on the current kernel source; else None."""
+def traffic_record(kernel: str, workload: str, tuning):
+    """Counter record (profiles/<kernel>_<workload>_traffic.json) of a kernel
+    on a workload under `tuning`, if it was taken on the current kernel
+    source; else None."""
     p = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
     if not os.path.exists(p):
         return None
-    rec = json.load(open(p))
-    if rec.get("kernel_src_sha") != kernel_source_sha():
+    recs = json.load(open(p))
+    key = "%d,%d,%d,%d" % (tuning["variant"], tuning["tile_x"], tuning["tile_z"], tuning["time_block"])
+    rec = recs.get("by_tuning", {}).get(key)
+    if rec is None or recs.get("kernel_src_sha") != kernel_source_sha(kernel):
         return None
-    return rec
+    return dict(rec, source=recs.get("source"))
 
 
 def kernel_shape(tuning):
@@ -169,14 +174,14 @@ def batch_headline(args):
     shape = kernel_shape(tuning)
     kname = ("k_sweep_batch<%d, %d>" % (tuning["tile_x"] // 64, tb) if tuning["variant"] == 3
              else "k_tiled_batch<%s, 0, true>" % shape)
-    rec = traffic_record("k_sweep_batch" if tuning["variant"] == 3 else "k_tiled_batch", "uneven_batch")
+    rec = traffic_record("k_sweep_batch" if tuning["variant"] == 3 else "k_tiled_batch", "uneven_batch", tuning)
     traffic = None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": kname, "launches_per_step": launches,
             "avg_launch_us": avg_ms * 1e3, "bytes_per_update": BYTES_PER_UPDATE,
             "algorithmic_bytes_per_launch": bytes_per_launch}
-    if rec is not None and rec.get("tuning") == [tuning["tile_x"], tuning["tile_z"], tb]:
+    if rec is not None:
         traffic = rec["hbm_bytes_per_launch"]
         roof["traffic"] = traffic
         roof["measured_hbm_GBs"] = traffic / (avg_ms / 1e3) / 1e9
