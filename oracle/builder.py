@@ -314,3 +314,28 @@ def salt_sdt(V, dz: float, dy: float, dx: float, centres, radii, rotations, grf,
     out = V.copy()
     out[K] = v_salt
     return out, K
+
+
+def grf_grid(nz: int, ny: int, nx: int):
+    """The periodic grid the random field of Alg. 4 is sampled on: the
+    smallest power of two >= each extent (reading: the field is sampled on a
+    periodic grid containing the volume and cropped to it)."""
+    return tuple(1 << max(0, int(n - 1).bit_length()) for n in (nz, ny, nx))
+
+
+def grf(noise, shape, ell, p: float):
+    """Alg. 4, the random field xi of one body: white noise (an input, [Pz, Py,
+    Px] on grf_grid(*shape)) shaped in Fourier space by sqrt(P(k)),
+    P(k) = (1 + sum_k (k_k ell_k)^2)^-p, k_k the angular wavenumber in radians
+    per cell of the periodic grid along axis k and ell_k in cells; the real
+    part of the inverse transform cropped to shape = (nz, ny, nx), then scaled
+    to zero mean and unit variance over the volume (the paper fixes neither;
+    the amplitude a of Alg. 4 multiplies this field)."""
+    noise = np.asarray(noise, np.float64)
+    nz, ny, nx = shape
+    assert noise.shape == grf_grid(nz, ny, nx), noise.shape
+    ks = [2.0 * np.pi * np.fft.fftfreq(n) for n in noise.shape]
+    kz, ky, kx = np.meshgrid(*ks, indexing="ij")
+    amp = (1.0 + (kz * ell[0]) ** 2 + (ky * ell[1]) ** 2 + (kx * ell[2]) ** 2) ** (-0.5 * p)
+    xi = np.fft.ifftn(np.fft.fftn(noise) * amp).real[:nz, :ny, :nx]
+    return (xi - xi.mean()) / xi.std()

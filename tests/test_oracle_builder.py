@@ -453,3 +453,47 @@ def test_deposit_texture_restarts_at_each_bed_start_with_its_offset():
         eta = a if q2 % 2 == 0 else 0.5 * (a + b)
         ref = vbar + beta * z * dz + (vbed[bed] - vbar) + a_eta * eta
         assert np.abs(V[z] - ref).max() < 1e-9, z
+
+
+def test_grf_with_p2_has_the_exponential_covariance_along_each_axis():
+    """Alg. 4's spectrum with p = 2 is the Matern spectrum of smoothness 1/2 in
+    3D, whose covariance is exp(-|h| / ell) (closed form): the normalised
+    field's correlation at lag h along axis k is exp(-h / ell_k), for
+    anisotropic correlation lengths.  (Amplitude P instead of sqrt(P) gives
+    0.86 at h = ell instead of 0.37; lengths on the wrong axes or a wrong
+    frequency order fail the per-axis checks.)  The grid's missing
+    wavenumbers past the Nyquist limit and the sampling error leave < 0.05."""
+    rng = np.random.default_rng(40)
+    n = 128
+    ell = (6.0, 9.0, 13.0)
+    acc = {k: np.zeros(4) for k in range(3)}
+    reps = 3
+    for _ in range(reps):
+        xi = B.grf(rng.standard_normal((n, n, n)), (n, n, n), ell, 2.0)
+        assert abs(xi.mean()) < 1e-12 and abs(xi.std() - 1.0) < 1e-12
+        for k in range(3):
+            for i, f in enumerate((0.5, 1.0, 1.5, 2.0)):
+                h = int(round(f * ell[k]))
+                acc[k][i] += np.mean(xi * np.roll(xi, -h, axis=k)) / reps
+    for k in range(3):
+        for i, f in enumerate((0.5, 1.0, 1.5, 2.0)):
+            h = round(f * ell[k])
+            assert abs(acc[k][i] - np.exp(-h / ell[k])) < 0.05, (k, h, acc[k][i])
+
+
+def test_grf_special_cases_and_axis_assignment():
+    """ell = 0 makes P = 1: the field is the (cropped, normalised) noise
+    itself; transposing the noise's axes with the lengths transposes the
+    field; the periodic grid is the next power of two."""
+    rng = np.random.default_rng(41)
+    assert B.grf_grid(37, 50, 64) == (64, 64, 64) and B.grf_grid(1, 2, 3) == (1, 2, 4)
+    shape = (20, 33, 12)
+    noise = rng.standard_normal(B.grf_grid(*shape))
+    xi = B.grf(noise, shape, (0.0, 0.0, 0.0), 1.7)
+    cut = noise[:20, :33, :12]
+    assert np.abs(xi - (cut - cut.mean()) / cut.std()).max() < 1e-12
+    cube = (32, 32, 32)
+    n3 = rng.standard_normal(cube)
+    a = B.grf(n3, cube, (2.0, 5.0, 3.0), 1.3)
+    b = B.grf(np.transpose(n3, (2, 0, 1)).copy(), cube, (3.0, 2.0, 5.0), 1.3)
+    assert np.abs(np.transpose(a, (2, 0, 1)) - b).max() < 1e-10
