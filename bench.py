@@ -458,16 +458,29 @@ def builder_rate(passes=3):
     torch.cuda.synchronize()
     ms_d = ev[0].elapsed_time(ev[1]) / passes
     del band, eta
-    # SaltSDT: three rotated ellipsoids (radii 0.8-2 km) under smooth unit-variance
-    # fields (coarse Gaussian noise, trilinearly upsampled), a = 0.15, water above 1500 m/s
-    import torch.nn.functional as F
+    # SaltSDT: three rotated ellipsoids (radii 0.8-2 km); each body's field from
+    # the GRF step (sg_grf: white noise on the 1024^3 periodic grid, spectral
+    # exponent p = 2, correlation lengths l_k = max(r_k f_k, 5) cells with
+    # f = (0.2, 0.2, 0.3)), a = 0.15, water above 1500 m/s
     nbody = 3
     v = (1500.0 + 3.0 * z).expand(nz, ny, nx).contiguous()
-    grf = F.interpolate(torch.randn((1, nbody, 32, 48, 48), device="cuda", generator=gen), size=(nz, ny, nx),
-                        mode="trilinear", align_corners=True)[0]
-    grf = (grf / grf.flatten(1).std(dim=1)[:, None, None, None]).contiguous()
     centres = np.array([[3000.0, 4000.0, 5000.0], [4200.0, 7000.0, 2500.0], [2000.0, 2500.0, 7500.0]])
     radii = np.array([[1500.0, 2000.0, 1800.0], [1000.0, 1400.0, 900.0], [800.0, 900.0, 1200.0]])
+    grid, gbytes = sgwave.grf_grid(nz, ny, nx)
+    gws = torch.empty(gbytes, dtype=torch.uint8, device="cuda")
+    grf = torch.empty((nbody, nz, ny, nx), dtype=torch.float32, device="cuda")
+    ms_grf = 0.0
+    for i in range(nbody):
+        noise = torch.randn(grid, dtype=torch.float32, device="cuda", generator=gen)
+        ell = tuple(max(r / h * f, 5.0) for r, f in zip(radii[i], (0.2, 0.2, 0.3)))
+        torch.cuda.synchronize()
+        ev[0].record()
+        grf[i] = sgwave.grf(noise, (nz, ny, nx), ell, 2.0, ws=gws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms_grf += ev[0].elapsed_time(ev[1])
+        del noise
+    del gws
     ang = np.array([[0.3, -0.2, 0.8], [-0.5, 0.1, 0.3], [0.2, 0.4, -1.0]])
     rots = []
     for a, b, c in ang:
@@ -485,7 +498,8 @@ def builder_rate(passes=3):
     del v, grf, salted, smask
     return {"workload": "619x1000x1000 voxels @10 m; squish 90 m max shift, 4 octaves; one fault "
                         "(R 6 km, slip 120 m, die-off 1.5 km / 4.5 km / 35 deg)",
-            "salt_bodies": nbody, "salt_ms": ms_s, "salt_Gvoxel_per_s": nvox / (ms_s / 1e3) / 1e9,
+            "salt_bodies": nbody, "grf_ms_per_body": ms_grf / nbody,
+            "grf_grid": list(grid), "salt_ms": ms_s, "salt_Gvoxel_per_s": nvox / (ms_s / 1e3) / 1e9,
             "salt_fraction": salt_frac,
             "squish_ms": ms_sq, "squish_Gvoxel_per_s": nvox / (ms_sq / 1e3) / 1e9,
             "squish_frac_of_hbm_peak": 8.0 * nvox / (ms_sq / 1e3) / 1e9 / HBM_PEAK_GBS,

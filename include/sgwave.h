@@ -538,6 +538,26 @@ sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double
                       const float *grf, double amplitude, float v_salt, float v_water, int64_t min_voxels,
                       float *out, uint8_t *mask_out, void *ws, size_t ws_bytes, void *stream);
 
+/* Alg. 4, the random field xi of one salt body: white noise shaped in
+ * Fourier space by sqrt(P(k)), P(k) = (1 + sum_k (k_k l_k)^2)^-p, the
+ * spectrum of the paper's GRF step.  The field lives on a periodic grid of
+ * grid[0] x grid[1] x grid[2] cells (the smallest powers of two >= nz, ny, nx;
+ * sg_grf_workspace_size reports it), k_k is the angular wavenumber in radians
+ * per cell along axis k, l_k (lz, ly, lx) the correlation lengths in cells
+ * (the module takes l_k = max(r_k f_lk, 5)); the real part of the transform
+ * back is cropped to [nz][ny][nx] and scaled to zero mean and unit variance
+ * over the volume (the paper fixes neither).
+ *   noise  device floats [grid[0]][grid[1]][grid[2]], white noise (the draw
+ *          is the caller's, e.g. standard normal)
+ *   out    device floats [nz][ny][nx] (for sg_salt_sdt's grf), not aliasing noise
+ *   ws     device workspace of sg_grf_workspace_size bytes (two complex grids)
+ * Extents 1..1024; lengths finite and >= 0 (0 leaves an axis white); p >= 0.
+ * The 3D transforms are hand-written radix-2 FFTs in FP32.  Stream-ordered,
+ * no allocation; SG_EINVAL / SG_ENOSPACE as usual. */
+sg_status sg_grf_workspace_size(int32_t nz, int32_t ny, int32_t nx, int32_t *grid, size_t *bytes);
+sg_status sg_grf(const float *noise, int32_t nz, int32_t ny, int32_t nx, double lz, double ly, double lx, double p,
+                 float *out, void *ws, size_t ws_bytes, void *stream);
+
 /* Turn the graph replay of sg_forward and sg_batch_forward on (default) or
  * off (plain stream launches); process-wide. */
 sg_status sg_set_graphs(int32_t on);

@@ -338,4 +338,5 @@ def grf(noise, shape, ell, p: float):
     kz, ky, kx = np.meshgrid(*ks, indexing="ij")
     amp = (1.0 + (kz * ell[0]) ** 2 + (ky * ell[1]) ** 2 + (kx * ell[2]) ** 2) ** (-0.5 * p)
     xi = np.fft.ifftn(np.fft.fftn(noise) * amp).real[:nz, :ny, :nx]
-    return (xi - xi.mean()) / xi.std()
+    sd = xi.std()
+    return (xi - xi.mean()) / sd if sd > 0 else np.zeros_like(xi)   # one cell: no variance to scale

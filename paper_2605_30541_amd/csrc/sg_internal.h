@@ -250,6 +250,14 @@ hipError_t launch_salt_sdt(const float *v, int nz, int ny, int nx, double dz, do
                            const SaltBody *bodies, const float *grf, double amplitude, float v_salt, float v_water,
                            unsigned min_voxels, float *out, uint8_t *mask_out, void *ws, hipStream_t st);
 
+// Random field of Alg. 4 (sg_grf.hip): the periodic grid (powers of two >=
+// the extents, each <= 1024), the workspace (two complex grids and the
+// partial sums) and the launch: noise [P0][P1][P2] -> out [nz][ny][nx].
+void grf_grid(int nz, int ny, int nx, int P[3]);
+size_t grf_workspace_bytes(int nz, int ny, int nx);
+hipError_t launch_grf(const float *noise, int nz, int ny, int nx, double lz, double ly, double lx, double p, float *out,
+                      void *ws, hipStream_t st);
+
 // Wave-equation residual of a frame stack: c_m / dz^2 and c_m / dx^2, m = 0..4.
 struct ResidualCoef {
     float cz[kHalo + 1];

@@ -2150,6 +2150,35 @@ sg_status sg_salt_sdt(const float *v, int32_t nz, int32_t ny, int32_t nx, double
     return SG_OK;
 }
 
+sg_status sg_grf_workspace_size(int32_t nz, int32_t ny, int32_t nx, int32_t *grid, size_t *bytes)
+{
+    if (!bytes) return fail(SG_EINVAL, "NULL argument");
+    if (nz < 1 || ny < 1 || nx < 1 || nz > 1024 || ny > 1024 || nx > 1024)
+        return fail(SG_EINVAL, "extents must be in 1..1024 (got %d x %d x %d)", nz, ny, nx);
+    int P[3];
+    sg::grf_grid(nz, ny, nx, P);
+    if (grid)
+        for (int k = 0; k < 3; ++k) grid[k] = P[k];
+    *bytes = sg::grf_workspace_bytes(nz, ny, nx);
+    return SG_OK;
+}
+
+sg_status sg_grf(const float *noise, int32_t nz, int32_t ny, int32_t nx, double lz, double ly, double lx, double p,
+                 float *out, void *ws, size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    sg_status rc = sg_grf_workspace_size(nz, ny, nx, nullptr, &need);
+    if (rc != SG_OK) return rc;
+    if (!noise || !out || !ws) return fail(SG_EINVAL, "NULL argument");
+    if (!(std::isfinite(lz) && std::isfinite(ly) && std::isfinite(lx) && lz >= 0 && ly >= 0 && lx >= 0))
+        return fail(SG_EINVAL, "correlation lengths must be finite and >= 0");
+    if (!std::isfinite(p) || p < 0) return fail(SG_EINVAL, "p must be finite and >= 0");
+    if (ws_bytes < need) return fail(SG_ENOSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    if ((const void *)out == (const void *)noise) return fail(SG_EINVAL, "out must not alias noise");
+    SG_HIP(sg::launch_grf(noise, nz, ny, nx, lz, ly, lx, p, out, ws, (hipStream_t)stream));
+    return SG_OK;
+}
+
 sg_status sg_set_graphs(int32_t on)
 {
     g_batch_graphs = on != 0;

@@ -108,6 +108,11 @@ _SIGS = {
     "sg_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "sg_plan_warnings": (ctypes.c_uint32, [ctypes.c_void_p]),
     "sg_plan_reserve": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "sg_grf_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_grf": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_size_t, ctypes.c_void_p]),
     "sg_plan_padded_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
     "sg_plan_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sg_tuning)]),
@@ -671,6 +676,31 @@ def wave_residual(frames, vp, dz: float, dx: float, dt: float, top: int = SG_TOP
     _check(lib().sg_wave_residual(_ptr(frames), T, nz, nx, _ptr(vp), dz, dx, dt, top, _ptr(res2), _ptr(dtt2),
                                   _ptr(ws), ws.numel(), _stream_ptr(stream)))
     return res2, dtt2
+
+
+def grf_grid(nz: int, ny: int, nx: int):
+    """(periodic grid of the random field, workspace bytes) for a volume."""
+    g = (ctypes.c_int32 * 3)()
+    n = ctypes.c_size_t()
+    _check(lib().sg_grf_workspace_size(nz, ny, nx, g, ctypes.byref(n)))
+    return (g[0], g[1], g[2]), n.value
+
+
+def grf(noise, shape, ell, p: float, ws=None, stream=None):
+    """Alg. 4's random field [nz, ny, nx] (float32 device tensor) from white
+    noise on grf_grid(*shape)[0] (float32 device), lengths ell = (lz, ly, lx)
+    in cells and spectral exponent p."""
+    import torch
+    nz, ny, nx = shape
+    grid, nbytes = grf_grid(nz, ny, nx)
+    _need(noise, "noise", "float32", grid)
+    out = torch.empty((nz, ny, nx), dtype=torch.float32, device=noise.device)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=noise.device)
+    _need_ws(ws, noise.device)
+    _check(lib().sg_grf(_ptr(noise), nz, ny, nx, float(ell[0]), float(ell[1]), float(ell[2]), float(p), _ptr(out),
+                        _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return out
 
 
 def sg_set_graphs(on: bool):

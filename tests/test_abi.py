@@ -319,3 +319,24 @@ def test_binding_rejects_host_tensors_before_the_library():
         sgwave.squish(torch.zeros((4, 2, 3)), 10.0, torch.zeros((2, 3)))
     with pytest.raises(ValueError, match="CUDA"):
         sgwave.wave_residual(torch.zeros((5, 9, 9)), torch.zeros((9, 9)), 10.0, 10.0, 1e-3)
+
+
+def test_grf_grid_and_argument_errors():
+    """The random field's periodic grid is the next power of two per axis;
+    extents past 1024, negative lengths or exponent, NULL or aliased buffers
+    and a short workspace are refused before any device work."""
+    assert sgwave.grf_grid(37, 50, 27)[0] == (64, 64, 32)
+    assert sgwave.grf_grid(619, 1000, 1000)[0] == (1024, 1024, 1024)
+    assert sgwave.grf_grid(1, 1, 1)[0] == (1, 1, 1)
+    L = sgwave.lib()
+    with pytest.raises(SGError):
+        sgwave.grf_grid(1025, 2, 2)
+    fake = ctypes.c_void_p(0x1000)
+    other = ctypes.c_void_p(0x2000)
+    need = sgwave.grf_grid(8, 8, 8)[1]
+    cases = [(fake, -1.0, 2.0, other, need, sgwave.SG_EINVAL), (fake, 3.0, -0.5, other, need, sgwave.SG_EINVAL),
+             (None, 3.0, 2.0, other, need, sgwave.SG_EINVAL), (fake, 3.0, 2.0, fake, need, sgwave.SG_EINVAL),
+             (fake, 3.0, 2.0, other, need - 1, sgwave.SG_ENOSPACE)]
+    for noise, ell, p, out, nbytes, want in cases:
+        st = L.sg_grf(noise, 8, 8, 8, ell, ell, ell, p, out, ctypes.c_void_p(0x3000), nbytes, None)
+        assert st == want, (st, want, sgwave.sg_last_error())
