@@ -15,9 +15,10 @@ Contents
     of the paper (Ricker pulse, CFL and dispersion limits, temporal
     subsampling, band-passed wavelets) and the residual of the discretised
     wave operator on a stack of frames.
-  * ``builder.py``: the velocity-model builder modules Deposit, Squish, Fault
-    (smooth and rough surfaces, labels) and SaltSDT with their windowed-sinc
-    pull sampling and noise fields, in NumPy FP64.
+  * ``builder.py``: the velocity-model builder modules Deposit (boundary
+    path with value or simplex noise, sinusoidal mode), Squish, Fault (smooth
+    and rough surfaces, labels) and SaltSDT with its random field, their
+    windowed-sinc pull sampling and noise fields, in NumPy FP64.
 """
 from .wave import (  # noqa: F401
     Geometry,

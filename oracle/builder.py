@@ -1,5 +1,6 @@
 """FP64 reference of the velocity-model builder modules of SubsurfaceGen
-(arXiv 2605.30541, App. B): Deposit (Alg. 1, interbedded band), Squish
+(arXiv 2605.30541, App. B): Deposit (Alg. 1, interbedded band; its simplex
+noise fields and sinusoidal bedform mode from the module's prose), Squish
 (Alg. 2, vertical warping by a fractal-noise displacement), Fault (Alg. 3, one
 listric normal fault as a tapered rotation about a horizontal cylinder; sinc
 pull for velocities, nearest-neighbour pull for labels) and SaltSDT (Alg. 4,
@@ -268,6 +269,132 @@ def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vb
     zt = (z - start) * dz + np.asarray(tex_off, np.float64)[bed]
     eta = value_noise3d(tex_lattice, zt, np.broadcast_to(Y, zt.shape), np.broadcast_to(X, zt.shape), *lam)
     return (vbar + beta * z * dz) + tau(z) * ((vbed[bed] - vbar) + a_eta * eta)
+
+
+# The twelve gradients of 3D simplex noise: the midpoints of the cube's edges.
+SIMPLEX_GRADS = np.array([[1, 1, 0], [-1, 1, 0], [1, -1, 0], [-1, -1, 0], [1, 0, 1], [-1, 0, 1], [1, 0, -1],
+                          [-1, 0, -1], [0, 1, 1], [0, -1, 1], [0, 1, -1], [0, -1, -1]], np.float64)
+
+
+def simplex_noise3d(perm, a, b, c):
+    """3D simplex noise (Perlin's simplex noise in the formulation published
+    by Gustavson, "Simplex noise demystified", 2005) at lattice coordinates
+    (a, b, c) (arrays of one shape; this library passes (z, y, x) divided by
+    the wavelengths).  perm is a permutation of 0..255 (the random draw).
+
+    The point is skewed by F3 = 1/3 onto the cubic lattice, whose cells split
+    into six tetrahedra; the corners of the tetrahedron holding the point
+    each add (0.6 - |d|^2)^4 (g . d) where positive, d the unskewed offset
+    from the corner (G3 = 1/6) and g one of the twelve edge-midpoint
+    gradients, chosen by the corner's hash perm[i + perm[j + perm[k]]] mod 12
+    (indices mod 256); the sum is scaled by 32 (values in about [-1, 1]).
+    The field is 0 at every lattice corner and periodic with 256 lattice
+    cells on each skewed axis."""
+    P = np.asarray(perm, np.int64)
+    pts = [np.asarray(v, np.float64) for v in (a, b, c)]
+    s = (pts[0] + pts[1] + pts[2]) / 3.0
+    ijk = [np.floor(v + s) for v in pts]
+    t = (ijk[0] + ijk[1] + ijk[2]) / 6.0
+    d0 = [v - (i - t) for v, i in zip(pts, ijk)]
+    # rank the offsets: the tetrahedron's corners step one axis at a time,
+    # largest offset first (ties: the lower axis first)
+    ge01, ge02, ge12 = d0[0] >= d0[1], d0[0] >= d0[2], d0[1] >= d0[2]
+    first = [ge01 & ge02, ~ge01 & ge12, ~ge02 & ~ge12]
+    second = [ge01 | ge02, ~ge01 | ge12, ~ge02 | ~ge12]
+    second = [sec & ~fst for sec, fst in zip(second, first)]
+    steps = [[np.zeros_like(s)] * 3,
+             [f.astype(np.float64) for f in first],
+             [(f | g).astype(np.float64) for f, g in zip(first, second)],
+             [np.ones_like(s)] * 3]
+    ii = [i.astype(np.int64) & 255 for i in ijk]
+    total = np.zeros_like(s)
+    for k, o in enumerate(steps):
+        d = [d0[ax] - o[ax] + k / 6.0 for ax in range(3)]
+        w = 0.6 - (d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+        oi = [o[ax].astype(np.int64) for ax in range(3)]
+        h = P[(ii[0] + oi[0] + P[(ii[1] + oi[1] + P[(ii[2] + oi[2]) & 255]) & 255]) & 255] % 12
+        g = SIMPLEX_GRADS[h]
+        dot = g[..., 0] * d[0] + g[..., 1] * d[1] + g[..., 2] * d[2]
+        total += np.where(w > 0.0, np.maximum(w, 0.0) ** 4 * dot, 0.0)
+    return 32.0 * total
+
+
+def _deposit_taper(t, f_top, f_base):
+    def tau(z):
+        z = np.asarray(z, np.float64)
+        return np.minimum(z / (f_top * t), 1.0) * np.minimum((t - z) / (f_base * t), 1.0)
+    return tau
+
+
+def deposit_simplex(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vbed, beta: float,
+                    perm_b, lam_b, a_B: float, perm_t, lam_t, tex_off, a_eta: float, f_top: float,
+                    f_base: float):
+    """Alg. 1 (boundary path) with both noise fields from 3D simplex noise:
+    boundary i (i = 1..n-1, mean depth H_i = thick_0 + .. + thick_{i-1}
+    cells) moves by taper(H_i) a_B S_b(H_i dz / lam_b[0], y dy / lam_b[1],
+    x dx / lam_b[2]) -- the 3D field perm_b sampled on the plane at the
+    boundary's own depth, so close boundaries move together -- and is clamped
+    to [0, t-1]; the texture is a_eta S_t(((z - S_l) dz + tex_off_l) /
+    lam_t[0], y dy / lam_t[1], x dx / lam_t[2]) with the field perm_t.  The
+    rest (bed lookup, depth trend, taper) is `deposit`'s; lengths in metres,
+    a_B in cells, a_eta in m/s."""
+    thick = np.asarray(thick, np.float64)
+    vbed = np.asarray(vbed, np.float64)
+    n = thick.size
+    H = np.cumsum(thick)[:-1]
+    vbar = vbed.mean()
+    tau = _deposit_taper(t, f_top, f_base)
+    Yb = (np.arange(ny) * dy / lam_b[1])[None, :, None]
+    Xb = (np.arange(nx) * dx / lam_b[2])[None, None, :]
+    Zb = (H * dz / lam_b[0])[:, None, None]
+    shp = (n - 1, ny, nx)
+    eta_b = simplex_noise3d(perm_b, np.broadcast_to(Zb, shp), np.broadcast_to(Yb, shp), np.broadcast_to(Xb, shp))
+    Hyx = np.clip(H[:, None, None] + tau(H)[:, None, None] * a_B * eta_b, 0.0, t - 1.0)
+    z = np.arange(t, dtype=np.float64)[:, None, None]
+    le = Hyx[None, :, :, :] <= z[:, None, :, :]
+    bed = le.sum(axis=1)
+    start = np.where(le, Hyx[None], 0.0).max(axis=1, initial=0.0)
+    zt = ((z - start) * dz + np.asarray(tex_off, np.float64)[bed]) / lam_t[0]
+    Y = np.broadcast_to((np.arange(ny) * dy / lam_t[1])[None, :, None], zt.shape)
+    X = np.broadcast_to((np.arange(nx) * dx / lam_t[2])[None, None, :], zt.shape)
+    eta = simplex_noise3d(perm_t, zt, Y, X)
+    return (vbar + beta * z * dz) + tau(z) * ((vbed[bed] - vbar) + a_eta * eta)
+
+
+def warped_axis(freq_raw, sigma: float):
+    """The z-warped axis of Deposit's sinusoidal mode: the instantaneous
+    frequency freq_raw [t] (cycles per cell, the random draw) smoothed by a
+    Gaussian of sigma cells (SciPy's gaussian_filter1d, reflecting ends,
+    truncated at 4 sigma; sigma 0 leaves it), then summed: W[z] =
+    f[0] + .. + f[z-1] cycles above depth z (W[0] = 0)."""
+    from scipy import ndimage as nd
+    f = np.asarray(freq_raw, np.float64)
+    if sigma > 0:
+        f = nd.gaussian_filter1d(f, sigma, mode="reflect", truncate=4.0)
+    return np.concatenate([[0.0], np.cumsum(f)[:-1]])
+
+
+def deposit_sinusoidal(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, v0: float, beta: float,
+                       freq_raw, sigma: float, amp1: float, amp2: float, phase2: float, rug, a_r: float,
+                       perm_t, lam_t, a_eta: float, f_top: float, f_base: float):
+    """Deposit's sinusoidal bedform mode (the prose of App. B's Deposit):
+    phi(z, y, x) = 2 pi (W[z] + a_r rug(y, x)), W the warped axis of
+    `warped_axis(freq_raw, sigma)` and rug [ny, nx] a roughness field (e.g.
+    fractal noise of amplitude 1; a_r in cycles); then
+      V = (v0 + beta z dz) + taper(z) [amp1 sin(phi) + amp2 sin(2 phi + phase2)
+                                       + a_eta S_t(z dz / lam_t[0], y dy / lam_t[1], x dx / lam_t[2])]
+    with the taper of Alg. 1 and S_t the simplex field perm_t (the patchy
+    texture).  amp1, amp2, a_eta in m/s, beta in m/s per m."""
+    W = warped_axis(freq_raw, sigma)
+    tau = _deposit_taper(t, f_top, f_base)
+    z = np.arange(t, dtype=np.float64)[:, None, None]
+    phi = 2.0 * np.pi * (W[:, None, None] + a_r * np.asarray(rug, np.float64)[None, :, :])
+    shp = (t, ny, nx)
+    Z = np.broadcast_to(z * dz / lam_t[0], shp)
+    Y = np.broadcast_to((np.arange(ny) * dy / lam_t[1])[None, :, None], shp)
+    X = np.broadcast_to((np.arange(nx) * dx / lam_t[2])[None, None, :], shp)
+    eta = simplex_noise3d(perm_t, Z, Y, X)
+    return (v0 + beta * z * dz) + tau(z) * (amp1 * np.sin(phi) + amp2 * np.sin(2.0 * phi + phase2) + a_eta * eta)
 
 
 def salt_sdt(V, dz: float, dy: float, dx: float, centres, radii, rotations, grf, amplitude: float,

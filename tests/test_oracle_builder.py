@@ -519,3 +519,198 @@ def test_grf_spectrum_follows_p_of_k_in_every_band():
     edges = np.quantile(s[s2 > 0], np.linspace(0.0, 1.0, 13))
     bands = np.array([ratio[(s > a) & (s <= b)].mean() for a, b in zip(edges[:-1], edges[1:])])
     assert np.abs(bands / bands.mean() - 1.0).max() < 0.05, bands / bands.mean()
+
+
+# -- 3D simplex noise and the Deposit forms built on it ----------------------
+
+def _corner(i, j, k):
+    """Unskewed position of the skewed-lattice corner (i, j, k)."""
+    s = (i + j + k) / 6.0
+    return np.array([i - s, j - s, k - s], np.float64)
+
+
+def _simplex_grad_at(perm, c, h=1e-6):
+    """Central-difference gradient of the field at point c."""
+    g = np.zeros(3)
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        g[ax] = (B.simplex_noise3d(perm, *(c + e)) - B.simplex_noise3d(perm, *(c - e))) / (2 * h)
+    return g
+
+
+def test_simplex_noise_vanishes_at_corners_with_a_cube_edge_gradient_there():
+    """At every lattice corner the field is 0 (only the corner's own kernel
+    reaches it: the nearest other corners are sqrt(3/4) away, beyond the
+    radius sqrt(0.6)), and its gradient is 32 * 0.6^4 * g with g one of the
+    twelve edge midpoints (|g| = sqrt 2).  A wrong skew or unskew factor
+    moves the zeros; a wrong falloff radius, power or scale changes the
+    gradient."""
+    rng = np.random.default_rng(50)
+    perm = rng.permutation(256)
+    edges = {tuple(g) for g in ([a, b, 0] for a in (-1, 1) for b in (-1, 1))} | \
+            {tuple(g) for g in ([a, 0, b] for a in (-1, 1) for b in (-1, 1))} | \
+            {tuple(g) for g in ([0, a, b] for a in (-1, 1) for b in (-1, 1))}
+    seen = set()
+    for i, j, k in rng.integers(-300, 300, (60, 3)):
+        c = _corner(i, j, k)
+        assert abs(B.simplex_noise3d(perm, *c)) < 1e-13
+        g = _simplex_grad_at(perm, c) / (32.0 * 0.6 ** 4)
+        gr = tuple(int(v) for v in np.round(g))
+        assert np.abs(g - np.round(g)).max() < 1e-6 and gr in edges, g
+        seen.add(gr)
+    assert len(seen) >= 8
+
+
+def test_simplex_noise_is_the_sum_over_the_kuhn_tetrahedron_holding_the_point():
+    """Brute force: find, among the six tetrahedra of the skewed unit cube
+    {0, e_a, e_a + e_b, 1}, the one whose corners hold the point (barycentric
+    coordinates >= 0); take each corner's gradient from the field itself (as
+    measured at the corner) and add 32 max(0, 0.6 - |d|^2)^4 g.d over the four
+    corners, d the unskewed offset.  Equals the field to 1e-12 on random
+    points (a wrong corner order, unskew of the inner corners or corner hash
+    fails)."""
+    from itertools import permutations
+    rng = np.random.default_rng(51)
+    perm = rng.permutation(256)
+    for p in rng.uniform(-40, 40, (300, 3)):
+        u = p + p.sum() / 3.0                        # skewed coordinates
+        base = np.floor(u)
+        found = None
+        for order in permutations(range(3)):
+            ks = [base.copy()]
+            for ax in order:
+                nxt = ks[-1].copy()
+                nxt[ax] += 1
+                ks.append(nxt)
+            C = np.array([_corner(*kk) for kk in ks])
+            M = np.vstack([(C[1:] - C[0]).T])
+            lam = np.linalg.solve(M, p - C[0])
+            if lam.min() >= -1e-12 and lam.sum() <= 1 + 1e-12:
+                found = C
+                break
+        assert found is not None
+        ref = 0.0
+        for c in found:
+            d = p - c
+            w = 0.6 - d @ d
+            if w > 0:
+                ref += 32.0 * w ** 4 * (np.round(_simplex_grad_at(perm, c) / (32.0 * 0.6 ** 4)) @ d)
+        assert abs(B.simplex_noise3d(perm, *p) - ref) < 1e-12, (p, ref)
+
+
+def test_simplex_noise_periodicity_range_and_permutation_dependence():
+    """Shifting the skewed lattice by 256 cells along any axis leaves the
+    field unchanged (indices mod 256); values stay within [-1, 1] with mean
+    about 0; another permutation gives another field."""
+    rng = np.random.default_rng(52)
+    perm = rng.permutation(256)
+    pts = rng.uniform(-30, 30, (3, 2000))
+    v = B.simplex_noise3d(perm, *pts)
+    for ax in range(3):
+        sh = np.array([256.0 * (a == ax) for a in range(3)]) - 256.0 / 6.0
+        w = B.simplex_noise3d(perm, *(pts + sh[:, None]))
+        assert np.abs(w - v).max() < 1e-9
+    big = B.simplex_noise3d(perm, *rng.uniform(-100, 100, (3, 200000)))
+    assert np.abs(big).max() <= 1.0 and abs(big.mean()) < 0.01 and 0.3 < big.std() < 0.5
+    assert np.abs(B.simplex_noise3d(rng.permutation(256), *pts) - v).max() > 0.3
+
+
+def test_deposit_simplex_equals_the_boundary_path_with_plane_samples():
+    """deposit_simplex is Alg. 1's boundary path with eta_b the 3D simplex
+    field sampled on each boundary's own depth plane: with the texture off
+    it equals `deposit` given those plane samples; with both amplitudes 0
+    it is the plain bed model."""
+    rng = np.random.default_rng(53)
+    t, ny, nx, dz, dy, dx = 70, 5, 6, 4.0, 12.0, 9.0
+    thick = np.array([8.0, 11.0, 7.0, 12.0, 9.5, 10.0, 12.5])
+    vbed = rng.normal(2600, 150, 7)
+    pb, pt = rng.permutation(256), rng.permutation(256)
+    lam_b, lam_t = (60.0, 250.0, 180.0), (20.0, 90.0, 70.0)
+    H = np.cumsum(thick)[:-1]
+    Z = np.broadcast_to((H * dz / lam_b[0])[:, None, None], (6, ny, nx))
+    Y = np.broadcast_to((np.arange(ny) * dy / lam_b[1])[None, :, None], (6, ny, nx))
+    X = np.broadcast_to((np.arange(nx) * dx / lam_b[2])[None, None, :], (6, ny, nx))
+    eta_b = B.simplex_noise3d(pb, Z, Y, X)
+    off = rng.uniform(0, 500, 7)
+    a = B.deposit_simplex(t, ny, nx, dz, dy, dx, thick, vbed, 0.4, pb, lam_b, 3.0, pt, lam_t, off, 0.0, 0.2, 0.2)
+    b = B.deposit(t, ny, nx, dz, dy, dx, thick, vbed, 0.4, eta_b, 3.0, np.zeros((2, 2, 2)), lam_t, off, 0.0,
+                  0.2, 0.2)
+    assert np.abs(a - b).max() < 1e-9
+    c = B.deposit_simplex(t, ny, nx, dz, dy, dx, thick, vbed, 0.4, pb, lam_b, 0.0, pt, lam_t, off, 0.0, 0.2, 0.2)
+    d = B.deposit(t, ny, nx, dz, dy, dx, thick, vbed, 0.4, np.zeros((6, ny, nx)), 0.0, np.zeros((2, 2, 2)),
+                  lam_t, off, 0.0, 0.2, 0.2)
+    assert np.abs(c - d).max() < 1e-9
+
+
+def test_deposit_simplex_texture_restarts_at_each_bed_start():
+    """With flat contacts (a_B = 0) and two beds given the same offset, the
+    texture at k cells below the first bed's start equals the texture k
+    cells below the second's (sampling at absolute depth fails), and at a
+    bed start it is the field at (offset / lam_z, y dy / lam_y, x dx / lam_x)."""
+    rng = np.random.default_rng(54)
+    t, ny, nx, dz, dy, dx = 60, 4, 5, 5.0, 10.0, 10.0
+    thick = np.array([10.0, 20.0, 20.0, 10.0])
+    vbed = np.array([2500.0, 2500.0, 2500.0, 2500.0])
+    pt = rng.permutation(256)
+    lam_t = (35.0, 80.0, 60.0)
+    off = np.array([0.0, 123.0, 123.0, 40.0])
+    V = B.deposit_simplex(t, ny, nx, dz, dy, dx, thick, vbed, 0.0, pt, (1.0, 1.0, 1.0), 0.0, pt, lam_t, off, 50.0,
+                          1e-9, 1e-9)
+    tex = V - 2500.0                     # taper 1 below row 0, no trend, equal beds
+    assert np.abs(tex[10:30] - tex[30:50]).max() < 1e-9
+    assert np.abs(tex[10] - tex[25]).max() > 1.0
+    Y = np.broadcast_to((np.arange(ny) * dy / lam_t[1])[:, None], (ny, nx))
+    X = np.broadcast_to((np.arange(nx) * dx / lam_t[2])[None, :], (ny, nx))
+    ref = 50.0 * B.simplex_noise3d(pt, np.full((ny, nx), 123.0 / lam_t[0]), Y, X)
+    assert np.abs(tex[10] - ref).max() < 1e-9
+
+
+def test_warped_axis_sums_the_gaussian_smoothed_frequency():
+    """W[z] = sum of the smoothed frequency above z: sigma 0 gives the plain
+    prefix sum (a linear ramp gives the quadratic closed form); a constant
+    frequency is kept by the smoothing; a unit spike becomes the sampled
+    Gaussian exp(-m^2 / 2 sigma^2), normalised over |m| <= 4 sigma."""
+    t = 40
+    f = 0.05 + 0.002 * np.arange(t)
+    W = B.warped_axis(f, 0.0)
+    z = np.arange(t)
+    assert np.abs(W - (0.05 * z + 0.002 * z * (z - 1) / 2)).max() < 1e-12
+    assert np.abs(B.warped_axis(np.full(t, 0.1), 2.5) - 0.1 * z).max() < 1e-12
+    spike = np.zeros(t)
+    spike[20] = 1.0
+    sm = np.diff(B.warped_axis(spike, 2.0))          # smoothed values f[0..t-2]
+    m = np.arange(-8, 9)
+    g = np.exp(-m ** 2 / 8.0)
+    assert np.abs(sm[12:29] - g / g.sum()).max() < 1e-12
+
+
+def test_deposit_sinusoidal_closed_forms():
+    """Constant frequency f, no smoothing effect, no texture, taper 1: V is
+    v0 + beta z dz + amp1 sin(2 pi f z) + amp2 sin(4 pi f z + phase2); a
+    constant roughness c shifts the phase by 2 pi a_r c; the texture term
+    is a_eta times the simplex field at (z dz, y dy, x dx) / lam."""
+    rng = np.random.default_rng(55)
+    t, ny, nx, dz = 50, 3, 4, 2.0
+    f = 0.07
+    args = dict(v0=3000.0, beta=0.2, sigma=1.5, amp1=120.0, amp2=45.0, phase2=0.7)
+    pt = rng.permutation(256)
+    lam = (30.0, 70.0, 50.0)
+
+    def run(rug, a_r, a_eta):
+        return B.deposit_sinusoidal(t, ny, nx, dz, 10.0, 10.0, args["v0"], args["beta"], np.full(t, f),
+                                    args["sigma"], args["amp1"], args["amp2"], args["phase2"], rug, a_r, pt, lam,
+                                    a_eta, 1e-9, 1e-9)
+    z = np.arange(t)[:, None, None] * 1.0
+    V = run(np.zeros((ny, nx)), 0.0, 0.0)
+    ref = 3000.0 + 0.2 * z * dz + 120.0 * np.sin(2 * np.pi * f * z) + 45.0 * np.sin(4 * np.pi * f * z + 0.7)
+    assert np.abs(V[1:] - ref[1:]).max() < 1e-9
+    c = 0.3
+    V2 = run(np.full((ny, nx), c), 0.5, 0.0)
+    ph = 2 * np.pi * (f * z + 0.5 * c)
+    ref2 = 3000.0 + 0.2 * z * dz + 120.0 * np.sin(ph) + 45.0 * np.sin(2 * ph + 0.7)
+    assert np.abs(V2[1:] - ref2[1:]).max() < 1e-9
+    V3 = run(np.zeros((ny, nx)), 0.0, 25.0)
+    Z, Y, X = np.meshgrid(np.arange(t) * dz / lam[0], np.arange(ny) * 10.0 / lam[1], np.arange(nx) * 10.0 / lam[2],
+                          indexing="ij")
+    assert np.abs((V3 - V)[1:] - 25.0 * B.simplex_noise3d(pt, Z, Y, X)[1:]).max() < 1e-9
