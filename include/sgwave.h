@@ -438,6 +438,51 @@ sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, do
                      double lam_x, const float *tex_off, double a_eta, double f_top, double f_base, float *out,
                      void *stream);
 
+/* 3D simplex noise (the noise fields of Deposit, App. B: boundary surfaces
+ * and texture): Perlin's simplex noise as formulated by Gustavson (2005) --
+ * skew by 1/3, unskew by 1/6, the twelve cube-edge gradients chosen by the
+ * corner hash perm[i + perm[j + perm[k]]] mod 12 (indices mod 256), falloff
+ * (0.6 - d^2)^4, scale 32; values within about [-1, 1], 0 at lattice corners.
+ * perm: device int32 [256], a permutation of 0..255 (the random draw; entries
+ * are taken mod 256).  FP64 evaluation, FP32 output:
+ *   out[z][y][x] = amplitude S(oz + z sz, oy + y sy, ox + x sx)
+ * (coordinates in lattice cells, within 2^40).  SG_EINVAL for NULL pointers,
+ * non-positive sizes, non-finite arguments or coordinates beyond 2^40. */
+sg_status sg_simplex_noise3d(const int32_t *perm, int32_t nz, int32_t ny, int32_t nx, double oz, double oy, double ox,
+                             double sz, double sy, double sx, double amplitude, float *out, void *stream);
+
+/* Alg. 1 (Deposit, boundary path) with both noise fields from 3D simplex
+ * noise, as the module's prose describes: contact i (mean depth H_i =
+ * thick_0 + .. + thick_{i-1} cells) moves by taper(H_i) a_B S_b(H_i dz /
+ * lam_bz, y dy / lam_by, x dx / lam_bx) -- the field perm_b on the plane at
+ * the contact's depth -- and is clamped to [0, t-1]; the texture is
+ * a_eta S_t(((z - start) dz + tex_off_l) / lam_tz, y dy / lam_ty,
+ * x dx / lam_tx), the field perm_t (both perms device int32 [256]).  Bed
+ * lookup, depth trend and taper as sg_deposit; lengths in metres, a_B in
+ * cells, a_eta in m/s; nbeds in 1..129.  Errors as sg_deposit. */
+sg_status sg_deposit_simplex(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, int32_t nbeds,
+                             const float *thick, const float *vbed, double beta, const int32_t *perm_b,
+                             double lam_bz, double lam_by, double lam_bx, double a_B, const int32_t *perm_t,
+                             double lam_tz, double lam_ty, double lam_tx, const float *tex_off, double a_eta,
+                             double f_top, double f_base, float *out, void *stream);
+
+/* Deposit's sinusoidal bedform mode (the module's prose in App. B): freq
+ * [t] (device float, the raw instantaneous frequency in cycles per cell) is
+ * smoothed by the normalised Gaussian of sigma cells over |m| <= int(4 sigma +
+ * 0.5) with reflecting ends (sigma 0: unsmoothed) and summed into the warped
+ * axis W[z] = f[0] + .. + f[z-1]; with phi = 2 pi (W[z] + a_r rug[y][x])
+ * (rug device float [ny][nx], the rugosity field, may be NULL when a_r = 0):
+ *   out[z][y][x] = (v0 + beta z dz) + taper(z) [amp1 sin(phi)
+ *                  + amp2 sin(2 phi + phase2) + a_eta S_t(z dz / lam_tz, y dy / lam_ty, x dx / lam_tx)]
+ * with sg_deposit's taper and S_t the simplex field perm_t.  FP64 throughout,
+ * FP32 output.  t <= 4096, sigma in [0, 255].  SG_EINVAL for NULL pointers,
+ * sizes or spacings out of range, non-finite parameters. */
+sg_status sg_deposit_sinusoidal(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, double v0,
+                                double beta, const float *freq, double sigma, double amp1, double amp2,
+                                double phase2, const float *rug, double a_r, const int32_t *perm_t, double lam_tz,
+                                double lam_ty, double lam_tx, double a_eta, double f_top, double f_base, float *out,
+                                void *stream);
+
 /* Alg. 2, first step: the displacement field out [ny][nx] (metres, device)
  * as fractal value noise: per octave o = 0..noct-1 a periodic lattice
  * lattice[o] [gy][gx] (device floats, e.g. uniform in [-1, 1]), sampled with

@@ -330,16 +330,116 @@ __global__ void __launch_bounds__(256) k_fault_labels(const int32_t *__restrict_
     out[q] = lab[(int64_t)jz * plane + (int64_t)jy * nx + jx];
 }
 
+// 3D simplex noise (Perlin's simplex noise as formulated by Gustavson,
+// "Simplex noise demystified", 2005), FP64, at lattice coordinates (a, b, c):
+// skew by 1/3 onto the cubic lattice, pick the tetrahedron of the cube cell
+// by the order of the unskewed offsets, and add over its four corners
+// (0.6 - |d|^2)^4 (g . d) where positive, g the cube-edge midpoint chosen by
+// the corner's hash P[i + P[j + P[k]]] mod 12 (indices mod 256); times 32.
+// P: 256 entries in 0..255 (LDS).  With the published radius 0.6 a corner's
+// kernel reaches past the faces of its tetrahedron, so the field jumps
+// slightly across them; which tetrahedron a point on a face takes is decided
+// by IEEE operations without fusion (a sum, a division, floor, differences),
+// the same decision as any IEEE evaluation of the same coordinates.
+__device__ inline double simplex_corner(const int *P, int i, int j, int k, double x, double y, double z)
+{
+    const double w = 0.6 - (x * x + y * y + z * z);
+    if (!(w > 0.0)) return 0.0;
+    const int h = P[(i + P[(j + P[k & 255]) & 255]) & 255] % 12;
+    double dot;
+    switch (h) {
+    case 0: dot = x + y; break;
+    case 1: dot = -x + y; break;
+    case 2: dot = x - y; break;
+    case 3: dot = -x - y; break;
+    case 4: dot = x + z; break;
+    case 5: dot = -x + z; break;
+    case 6: dot = x - z; break;
+    case 7: dot = -x - z; break;
+    case 8: dot = y + z; break;
+    case 9: dot = -y + z; break;
+    case 10: dot = y - z; break;
+    default: dot = -y - z; break;
+    }
+    const double w2 = w * w;
+    return w2 * w2 * dot;
+}
+
+__device__ inline double simplex3(const int *P, double a, double b, double c)
+{
+    const double s = (a + b + c) / 3.0;
+    const double fi = floor(a + s), fj = floor(b + s), fk = floor(c + s);
+    const double t = (fi + fj + fk) / 6.0;
+    const double x0 = a - (fi - t), y0 = b - (fj - t), z0 = c - (fk - t);
+    // corners 1 and 2 step along the largest, then the two largest offsets
+    // (ties: the lower axis first)
+    int i1, j1, k1, i2, j2, k2;
+    if (x0 >= y0) {
+        if (y0 >= z0) { i1 = 1; j1 = 0; k1 = 0; i2 = 1; j2 = 1; k2 = 0; }
+        else if (x0 >= z0) { i1 = 1; j1 = 0; k1 = 0; i2 = 1; j2 = 0; k2 = 1; }
+        else { i1 = 0; j1 = 0; k1 = 1; i2 = 1; j2 = 0; k2 = 1; }
+    } else {
+        if (y0 < z0) { i1 = 0; j1 = 0; k1 = 1; i2 = 0; j2 = 1; k2 = 1; }
+        else if (x0 < z0) { i1 = 0; j1 = 1; k1 = 0; i2 = 0; j2 = 1; k2 = 1; }
+        else { i1 = 0; j1 = 1; k1 = 0; i2 = 1; j2 = 1; k2 = 0; }
+    }
+    const int i = (int)(int64_t)fi & 255, j = (int)(int64_t)fj & 255, k = (int)(int64_t)fk & 255;
+    double n = simplex_corner(P, i, j, k, x0, y0, z0);
+    n += simplex_corner(P, i + i1, j + j1, k + k1, x0 - i1 + 1.0 / 6.0, y0 - j1 + 1.0 / 6.0, z0 - k1 + 1.0 / 6.0);
+    n += simplex_corner(P, i + i2, j + j2, k + k2, x0 - i2 + 2.0 / 6.0, y0 - j2 + 2.0 / 6.0, z0 - k2 + 2.0 / 6.0);
+    n += simplex_corner(P, i + 1, j + 1, k + 1, x0 - 1.0 + 0.5, y0 - 1.0 + 0.5, z0 - 1.0 + 0.5);
+    return 32.0 * n;
+}
+
+// A permutation table into LDS (entries taken mod 256); all threads call it.
+__device__ inline void load_perm(const int32_t *perm, int *P)
+{
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) P[q] = perm[q] & 255;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_simplex3d(const int32_t *__restrict__ perm, int nz, int ny, int nx,
+                                                   double oz, double oy, double ox, double sz, double sy, double sx,
+                                                   double amplitude, float *__restrict__ out)
+{
+    __shared__ int P[256];
+    load_perm(perm, P);
+    const int64_t n = (int64_t)nz * ny * nx;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t zy = q / nx;
+        const int ix = (int)(q - zy * nx), iz = (int)(zy / ny), iy = (int)(zy - (int64_t)iz * ny);
+        // o + i s rounded twice, never fused: the published noise jumps across
+        // the tetrahedron faces, so the coordinates must round as specified
+        double a, b, c;
+        {
+#pragma clang fp contract(off)
+            a = oz + iz * sz;
+            b = oy + iy * sy;
+            c = ox + ix * sx;
+        }
+        out[q] = (float)(amplitude * simplex3(P, a, b, c));
+    }
+}
+
 // Deposit (Alg. 1, boundary path): one thread per (y, x) column, walking down
 // the band [t][ny][nx].  The contacts are the cumulative bed thicknesses
 // (summed in FP64 in bed order), each moved by taper x a_B x its noise and
 // clamped to the band; they are computed once per column into LDS (FP64,
 // [contact][lane]), and at every depth the voxel's bed is the number of
 // contacts at or above it, starting at the deepest of those; the texture is
-// value noise at the depth below that start plus the bed's offset.
+// sampled at the depth below that start plus the bed's offset.  SIMPLEX: the
+// contact noise is simplex noise (perm_b) on the plane at the contact's mean
+// depth and the texture simplex noise (perm_t); else the contact noise is an
+// input and the texture value noise on a lattice.
+template <bool SIMPLEX>
 __global__ void __launch_bounds__(kDepositThreads) k_deposit(DepositArgs A, float *__restrict__ out)
 {
     extern __shared__ double hcol[];   // [nbeds - 1][kDepositThreads]
+    __shared__ int Pb[SIMPLEX ? 256 : 1], Pt[SIMPLEX ? 256 : 1];
+    if (SIMPLEX) {
+        load_perm(A.perm_b, Pb);
+        load_perm(A.perm_t, Pt);
+    }
     const int64_t plane = (int64_t)A.ny * A.nx;
     const int64_t col = (int64_t)blockIdx.x * kDepositThreads + threadIdx.x;
     if (col >= plane) return;
@@ -355,17 +455,30 @@ __global__ void __launch_bounds__(kDepositThreads) k_deposit(DepositArgs A, floa
     auto fade = [](double u) { return u * u * u * (u * (u * 6.0 - 15.0) + 10.0); };
     auto wrap = [](double f, int g) { const int64_t i = (int64_t)f % g; return (int)(i < 0 ? i + g : i); };
     auto L = [&](int a, int b, int c) { return (double)A.lattice[((int64_t)a * A.gy + b) * A.gx + c]; };
-    const double py = iy * A.dy * A.inv_lam_y, px = ix * A.dx * A.inv_lam_x;
-    const double fy = floor(py), fx = floor(px);
-    const double ty = fade(py - fy), tx = fade(px - fx);
-    const int y0 = wrap(fy, A.gy), x0 = wrap(fx, A.gx);
-    const int y1 = (y0 + 1) % A.gy, x1 = (x0 + 1) % A.gx;
+    double ty = 0.0, tx = 0.0, by = 0.0, bx = 0.0;
+    int y0 = 0, x0 = 0, y1 = 0, x1 = 0;
+    if (SIMPLEX) {
+        ty = iy * A.dy / A.lam_t[1];
+        tx = ix * A.dx / A.lam_t[2];
+        by = iy * A.dy / A.lam_b[1];
+        bx = ix * A.dx / A.lam_b[2];
+    } else {
+        const double py = iy * A.dy * A.inv_lam_y, px = ix * A.dx * A.inv_lam_x;
+        const double fy = floor(py), fx = floor(px);
+        ty = fade(py - fy);
+        tx = fade(px - fx);
+        y0 = wrap(fy, A.gy);
+        x0 = wrap(fx, A.gx);
+        y1 = (y0 + 1) % A.gy;
+        x1 = (x0 + 1) % A.gx;
+    }
     {
         double H = 0.0;
         for (int i = 0; i + 1 < A.nbeds; ++i) {
             H += (double)A.thick[i];
-            hcol[i * kDepositThreads + threadIdx.x] =
-                fmin(fmax(H + tau(H) * A.a_B * (double)A.eta_b[(int64_t)i * plane + col], 0.0), t - 1.0);
+            const double eta =
+                SIMPLEX ? simplex3(Pb, H * A.dz / A.lam_b[0], by, bx) : (double)A.eta_b[(int64_t)i * plane + col];
+            hcol[i * kDepositThreads + threadIdx.x] = fmin(fmax(H + tau(H) * A.a_B * eta, 0.0), t - 1.0);
         }
     }
     for (int iz = 0; iz < A.t; ++iz) {
@@ -379,17 +492,116 @@ __global__ void __launch_bounds__(kDepositThreads) k_deposit(DepositArgs A, floa
                 start = fmax(start, h);
             }
         }
-        // texture: value noise at ((z - start) dz + offset, y dy, x dx)
-        const double pz = ((z - start) * A.dz + (double)A.tex_off[bed]) * A.inv_lam_z;
-        const double fz = floor(pz);
-        const double tz = fade(pz - fz);
-        const int z0 = wrap(fz, A.gz), z1 = (z0 + 1) % A.gz;
-        const double eta = (1 - tz) * ((1 - ty) * ((1 - tx) * L(z0, y0, x0) + tx * L(z0, y0, x1)) +
-                                       ty * ((1 - tx) * L(z0, y1, x0) + tx * L(z0, y1, x1))) +
-                           tz * ((1 - ty) * ((1 - tx) * L(z1, y0, x0) + tx * L(z1, y0, x1)) +
-                                 ty * ((1 - tx) * L(z1, y1, x0) + tx * L(z1, y1, x1)));
+        // texture at ((z - start) dz + offset, y dy, x dx)
+        double eta;
+        if (SIMPLEX) {
+            // (z - start) dz + offset rounded twice, never fused (see k_simplex3d)
+            double zt;
+            {
+#pragma clang fp contract(off)
+                zt = ((z - start) * A.dz + (double)A.tex_off[bed]) / A.lam_t[0];
+            }
+            eta = simplex3(Pt, zt, ty, tx);
+        } else {
+            const double pz = ((z - start) * A.dz + (double)A.tex_off[bed]) * A.inv_lam_z;
+            const double fz = floor(pz);
+            const double tz = fade(pz - fz);
+            const int z0 = wrap(fz, A.gz), z1 = (z0 + 1) % A.gz;
+            eta = (1 - tz) * ((1 - ty) * ((1 - tx) * L(z0, y0, x0) + tx * L(z0, y0, x1)) +
+                              ty * ((1 - tx) * L(z0, y1, x0) + tx * L(z0, y1, x1))) +
+                  tz * ((1 - ty) * ((1 - tx) * L(z1, y0, x0) + tx * L(z1, y0, x1)) +
+                        ty * ((1 - tx) * L(z1, y1, x0) + tx * L(z1, y1, x1)));
+        }
         out[(int64_t)iz * plane + col] =
             (float)((vbar + A.beta * z * A.dz) + tau(z) * (((double)A.vbed[bed] - vbar) + A.a_eta * eta));
+    }
+}
+
+// Deposit's sinusoidal mode: one thread per (y, x) column.  Each workgroup
+// first builds the warped axis in LDS: the raw frequency smoothed by the
+// normalised Gaussian over |m| <= int(4 sigma + 0.5) with reflecting ends,
+// then its prefix sum W[z] = f[0] + .. + f[z-1] (per-thread runs, the run
+// sums scanned by one thread).  Then every voxel takes
+//   (v0 + beta z dz) + taper(z) [amp1 sin(phi) + amp2 sin(2 phi + phase2) + a_eta S_t]
+// with phi = 2 pi (W[z] + a_r rug(y, x)), all in FP64.
+constexpr int kSinThreads = 256;
+
+__global__ void __launch_bounds__(kSinThreads) k_deposit_sin(DepositSinArgs A, float *__restrict__ out)
+{
+    __shared__ double W[kDepositSinMaxT];
+    __shared__ double G[1024 + 1];     // Gaussian weights 0..radius (normalised)
+    __shared__ double runs[kSinThreads];
+    __shared__ int P[256];
+    load_perm(A.perm_t, P);
+    const int T = A.t;
+    const int radius = A.sigma > 0.0 ? (int)(4.0 * A.sigma + 0.5) : 0;
+    // weights exp(-m^2 / (2 sigma^2)), normalised by their sum over -radius..radius
+    for (int m = threadIdx.x; m <= radius; m += kSinThreads)
+        G[m] = radius == 0 ? 1.0 : exp(-0.5 * (double)m * (double)m / (A.sigma * A.sigma));
+    __syncthreads();
+    if (threadIdx.x == 0 && radius > 0) {
+        double sum = G[0];
+        for (int m = 1; m <= radius; ++m) sum += 2.0 * G[m];
+        runs[0] = 1.0 / sum;
+    }
+    __syncthreads();
+    const double norm = radius > 0 ? runs[0] : 1.0;
+    __syncthreads();
+    // smoothed frequency into W (reflect: index i maps into [0, T) by the
+    // mirror about each end, period 2T)
+    auto refl = [&](int i) {
+        const int p2 = 2 * T;
+        int r = i % p2;
+        if (r < 0) r += p2;
+        return r >= T ? p2 - 1 - r : r;
+    };
+    for (int z = threadIdx.x; z < T; z += kSinThreads) {
+        double acc = G[0] * (double)A.freq[z];
+        for (int m = 1; m <= radius; ++m) acc += G[m] * ((double)A.freq[refl(z - m)] + (double)A.freq[refl(z + m)]);
+        W[z] = acc * norm;
+    }
+    __syncthreads();
+    // exclusive prefix sum: thread r sums its run [r c, (r+1) c)
+    const int chunk = (T + kSinThreads - 1) / kSinThreads;
+    const int z0 = threadIdx.x * chunk, z1 = min(z0 + chunk, T);
+    double run = 0.0;
+    for (int z = z0; z < z1; ++z) run += W[z];
+    runs[threadIdx.x] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int r = 0; r < kSinThreads; ++r) {
+            const double v = runs[r];
+            runs[r] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    {
+        double acc = runs[threadIdx.x];
+        for (int z = z0; z < z1; ++z) {
+            const double f = W[z];
+            W[z] = acc;
+            acc += f;
+        }
+    }
+    __syncthreads();
+    const int64_t plane = (int64_t)A.ny * A.nx;
+    const int64_t col = (int64_t)blockIdx.x * kSinThreads + threadIdx.x;
+    if (col >= plane) return;
+    const int iy = (int)(col / A.nx), ix = (int)(col - (int64_t)iy * A.nx);
+    const double t = A.t;
+    const double rt = 1.0 / (A.f_top * t), rb = 1.0 / (A.f_base * t);
+    const double rough = A.a_r * (A.rug ? (double)A.rug[col] : 0.0);
+    const double ty = iy * A.dy / A.lam_t[1], tx = ix * A.dx / A.lam_t[2];
+    const double two_pi = 6.283185307179586;
+    for (int iz = 0; iz < T; ++iz) {
+        const double z = iz;
+        const double tau = fmin(z * rt, 1.0) * fmin((t - z) * rb, 1.0);
+        const double phi = two_pi * (W[iz] + rough);
+        const double tex = A.a_eta != 0.0 ? A.a_eta * simplex3(P, z * A.dz / A.lam_t[0], ty, tx) : 0.0;
+        out[(int64_t)iz * plane + col] =
+            (float)((A.v0 + A.beta * z * A.dz) + tau * (A.amp1 * sin(phi) + A.amp2 * sin(2.0 * phi + A.phase2) + tex));
     }
 }
 
@@ -400,8 +612,31 @@ hipError_t launch_deposit(const DepositArgs &A, float *out, hipStream_t st)
     if (A.nbeds < 1 || A.nbeds > kDepositMaxBeds) return hipErrorInvalidValue;
     const int64_t n = (int64_t)A.ny * A.nx;
     const size_t lds = (size_t)std::max(A.nbeds - 1, 1) * kDepositThreads * sizeof(double);
-    hipLaunchKernelGGL(k_deposit, dim3((unsigned)((n + kDepositThreads - 1) / kDepositThreads)), dim3(kDepositThreads),
-                       lds, st, A, out);
+    const dim3 grid((unsigned)((n + kDepositThreads - 1) / kDepositThreads));
+    if (A.simplex)
+        hipLaunchKernelGGL(k_deposit<true>, grid, dim3(kDepositThreads), lds, st, A, out);
+    else
+        hipLaunchKernelGGL(k_deposit<false>, grid, dim3(kDepositThreads), lds, st, A, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_sinusoidal(const DepositSinArgs &A, float *out, hipStream_t st)
+{
+    if (A.t < 1 || A.t > kDepositSinMaxT || !(A.sigma >= 0.0 && A.sigma <= kDepositSinMaxSigma))
+        return hipErrorInvalidValue;
+    const int64_t n = (int64_t)A.ny * A.nx;
+    hipLaunchKernelGGL(k_deposit_sin, dim3((unsigned)((n + kSinThreads - 1) / kSinThreads)), dim3(kSinThreads), 0,
+                       st, A, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_simplex3d(const int32_t *perm, int nz, int ny, int nx, const double o[3], const double s[3],
+                            double amplitude, float *out, hipStream_t st)
+{
+    const int64_t n = (int64_t)nz * ny * nx;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_simplex3d, dim3((unsigned)blocks), dim3(256), 0, st, perm, nz, ny, nx, o[0], o[1], o[2],
+                       s[0], s[1], s[2], amplitude, out);
     return hipGetLastError();
 }
 

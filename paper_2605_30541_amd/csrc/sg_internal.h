@@ -224,9 +224,31 @@ struct DepositArgs {
     double dz, dy, dx, inv_lam_z, inv_lam_y, inv_lam_x;
     double beta, a_B, a_eta, f_top, f_base;
     const float *thick, *vbed, *tex_off, *eta_b, *lattice;
+    // simplex form: both noise fields from 3D simplex noise (perm tables of
+    // 256 entries; lengths in metres as (z, y, x)); eta_b and lattice unused
+    int simplex;
+    const int32_t *perm_b, *perm_t;
+    double lam_b[3], lam_t[3];
 };
 constexpr int kDepositMaxBeds = 129;   // contacts of a column held in LDS (128 x 64 lanes x 8 B)
 hipError_t launch_deposit(const DepositArgs &A, float *out, hipStream_t st);
+
+// Deposit's sinusoidal bedform mode.
+struct DepositSinArgs {
+    int t, ny, nx;
+    double dz, dy, dx, v0, beta, sigma, amp1, amp2, phase2, a_r, a_eta, f_top, f_base;
+    double lam_t[3];
+    const float *freq, *rug;
+    const int32_t *perm_t;
+};
+constexpr int kDepositSinMaxT = 4096;          // depths of a band (warped axis held in LDS)
+constexpr double kDepositSinMaxSigma = 255.0;  // smoothing radius int(4 sigma + 0.5) <= 1020
+hipError_t launch_deposit_sinusoidal(const DepositSinArgs &A, float *out, hipStream_t st);
+
+// out[z][y][x] = amplitude S(o[0] + z s[0], o[1] + y s[1], o[2] + x s[2]),
+// S the 3D simplex noise of the permutation perm[256].
+hipError_t launch_simplex3d(const int32_t *perm, int nz, int ny, int nx, const double o[3], const double s[3],
+                            double amplitude, float *out, hipStream_t st);
 hipError_t launch_fractal_noise2d(const float *lattice, int noct, int gy, int gx, int ny, int nx, double dy,
                                   double dx, double lam_y, double lam_x, double azimuth_rad, double amplitude,
                                   float *out, hipStream_t st);

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1979,6 +1980,111 @@ sg_status sg_deposit(int32_t t, int32_t ny, int32_t nx, double dz, double dy, do
     A.eta_b = eta_b;
     A.lattice = tex_lattice;
     SG_HIP(sg::launch_deposit(A, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_deposit_simplex(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, int32_t nbeds,
+                             const float *thick, const float *vbed, double beta, const int32_t *perm_b,
+                             double lam_bz, double lam_by, double lam_bx, double a_B, const int32_t *perm_t,
+                             double lam_tz, double lam_ty, double lam_tx, const float *tex_off, double a_eta,
+                             double f_top, double f_base, float *out, void *stream)
+{
+    if (!thick || !vbed || !perm_b || !perm_t || !tex_off || !out) return fail(SG_EINVAL, "NULL argument");
+    if (t < 1 || ny < 1 || nx < 1 || nbeds < 1) return fail(SG_EINVAL, "sizes must be >= 1");
+    if (nbeds > sg::kDepositMaxBeds) return fail(SG_EINVAL, "at most %d beds per band", sg::kDepositMaxBeds);
+    if ((int64_t)t * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "band too large");
+    for (double v : {dz, dy, dx, lam_bz, lam_by, lam_bx, lam_tz, lam_ty, lam_tx, f_top, f_base})
+        if (!positive_finite(v))
+            return fail(SG_EINVAL, "spacings, noise wavelengths and taper fractions must be finite and > 0");
+    if (!std::isfinite(beta) || !std::isfinite(a_B) || !std::isfinite(a_eta))
+        return fail(SG_EINVAL, "beta, a_B and a_eta must be finite");
+    sg::DepositArgs A{};
+    A.t = t;
+    A.ny = ny;
+    A.nx = nx;
+    A.nbeds = nbeds;
+    A.dz = dz;
+    A.dy = dy;
+    A.dx = dx;
+    A.beta = beta;
+    A.a_B = a_B;
+    A.a_eta = a_eta;
+    A.f_top = f_top;
+    A.f_base = f_base;
+    A.thick = thick;
+    A.vbed = vbed;
+    A.tex_off = tex_off;
+    A.simplex = 1;
+    A.perm_b = perm_b;
+    A.perm_t = perm_t;
+    A.lam_b[0] = lam_bz;
+    A.lam_b[1] = lam_by;
+    A.lam_b[2] = lam_bx;
+    A.lam_t[0] = lam_tz;
+    A.lam_t[1] = lam_ty;
+    A.lam_t[2] = lam_tx;
+    SG_HIP(sg::launch_deposit(A, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_deposit_sinusoidal(int32_t t, int32_t ny, int32_t nx, double dz, double dy, double dx, double v0,
+                                double beta, const float *freq, double sigma, double amp1, double amp2,
+                                double phase2, const float *rug, double a_r, const int32_t *perm_t, double lam_tz,
+                                double lam_ty, double lam_tx, double a_eta, double f_top, double f_base, float *out,
+                                void *stream)
+{
+    if (!freq || !perm_t || !out || (a_r != 0.0 && !rug)) return fail(SG_EINVAL, "NULL argument");
+    if (t < 1 || ny < 1 || nx < 1) return fail(SG_EINVAL, "sizes must be >= 1");
+    if (t > sg::kDepositSinMaxT) return fail(SG_EINVAL, "at most %d cells per band", sg::kDepositSinMaxT);
+    if ((int64_t)t * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "band too large");
+    for (double v : {dz, dy, dx, lam_tz, lam_ty, lam_tx, f_top, f_base})
+        if (!positive_finite(v))
+            return fail(SG_EINVAL, "spacings, noise wavelengths and taper fractions must be finite and > 0");
+    if (!(sigma >= 0.0 && sigma <= sg::kDepositSinMaxSigma))
+        return fail(SG_EINVAL, "sigma must be in [0, %g] cells", sg::kDepositSinMaxSigma);
+    for (double v : {v0, beta, amp1, amp2, phase2, a_r, a_eta})
+        if (!std::isfinite(v)) return fail(SG_EINVAL, "v0, beta, amplitudes, phase and a_r must be finite");
+    sg::DepositSinArgs A{};
+    A.t = t;
+    A.ny = ny;
+    A.nx = nx;
+    A.dz = dz;
+    A.dy = dy;
+    A.dx = dx;
+    A.v0 = v0;
+    A.beta = beta;
+    A.sigma = sigma;
+    A.amp1 = amp1;
+    A.amp2 = amp2;
+    A.phase2 = phase2;
+    A.a_r = a_r;
+    A.a_eta = a_eta;
+    A.f_top = f_top;
+    A.f_base = f_base;
+    A.lam_t[0] = lam_tz;
+    A.lam_t[1] = lam_ty;
+    A.lam_t[2] = lam_tx;
+    A.freq = freq;
+    A.rug = a_r != 0.0 ? rug : nullptr;
+    A.perm_t = perm_t;
+    SG_HIP(sg::launch_deposit_sinusoidal(A, out, (hipStream_t)stream));
+    return SG_OK;
+}
+
+sg_status sg_simplex_noise3d(const int32_t *perm, int32_t nz, int32_t ny, int32_t nx, double oz, double oy, double ox,
+                             double sz, double sy, double sx, double amplitude, float *out, void *stream)
+{
+    if (!perm || !out) return fail(SG_EINVAL, "NULL argument");
+    if (nz < 1 || ny < 1 || nx < 1) return fail(SG_EINVAL, "sizes must be >= 1");
+    if ((int64_t)nz * ny * nx >= ((int64_t)1 << 40)) return fail(SG_EINVAL, "volume too large");
+    for (double v : {oz, oy, ox, sz, sy, sx, amplitude})
+        if (!std::isfinite(v)) return fail(SG_EINVAL, "origin, steps and amplitude must be finite");
+    // lattice coordinates stay within +-2^40 (integer cell indices exact)
+    const double lim = 1099511627776.0;
+    for (auto [o, st, n] : {std::tuple<double, double, int>{oz, sz, nz}, {oy, sy, ny}, {ox, sx, nx}})
+        if (std::fabs(o) + std::fabs(st) * (n - 1) >= lim) return fail(SG_EINVAL, "coordinates beyond 2^40 cells");
+    const double o[3] = {oz, oy, ox}, st[3] = {sz, sy, sx};
+    SG_HIP(sg::launch_simplex3d(perm, nz, ny, nx, o, st, amplitude, out, (hipStream_t)stream));
     return SG_OK;
 }
 

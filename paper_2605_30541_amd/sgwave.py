@@ -157,6 +157,16 @@ _SIGS = {
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+    "sg_simplex_noise3d": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+                           + [ctypes.c_double] * 7 + [ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_deposit_simplex": (ctypes.c_int32, [ctypes.c_int32] * 3 + [ctypes.c_double] * 3
+                           + [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+                           + [ctypes.c_double] * 4 + [ctypes.c_void_p] + [ctypes.c_double] * 3
+                           + [ctypes.c_void_p] + [ctypes.c_double] * 3 + [ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_deposit_sinusoidal": (ctypes.c_int32, [ctypes.c_int32] * 3 + [ctypes.c_double] * 5
+                              + [ctypes.c_void_p] + [ctypes.c_double] * 4 + [ctypes.c_void_p, ctypes.c_double,
+                                                                             ctypes.c_void_p]
+                              + [ctypes.c_double] * 6 + [ctypes.c_void_p, ctypes.c_void_p]),
     "sg_squish": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sg_fault": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -590,6 +600,57 @@ def deposit(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vb
                             _ptr(eta_b) if eta_b is not None else None, a_B, _ptr(tex_lattice), gz, gy, gx,
                             lam[0], lam[1], lam[2], _ptr(tex_off), a_eta, f_top, f_base, _ptr(out),
                             _stream_ptr(stream)))
+    return out
+
+
+def simplex_noise3d(perm, shape, origin=(0.0, 0.0, 0.0), step=(1.0, 1.0, 1.0), amplitude: float = 1.0,
+                    stream=None):
+    """amplitude S(origin + index * step) on a [nz, ny, nx] grid (float32
+    device tensor), S the 3D simplex noise of perm (int32 device [256])."""
+    import torch
+    _need(perm, "perm", "int32", (256,))
+    nz, ny, nx = shape
+    out = torch.empty((nz, ny, nx), dtype=torch.float32, device=perm.device)
+    _check(lib().sg_simplex_noise3d(_ptr(perm), nz, ny, nx, origin[0], origin[1], origin[2], step[0], step[1],
+                                    step[2], amplitude, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def deposit_simplex(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, thick, vbed, beta: float, perm_b,
+                    lam_b, a_B: float, perm_t, lam_t, tex_off, a_eta: float, f_top: float, f_base: float,
+                    stream=None):
+    """Interbedded band [t, ny, nx] of Alg. 1 with simplex contact and
+    texture noise: thick/vbed/tex_off float32 [nbeds], perm_b/perm_t int32
+    [256] (device); lam_b, lam_t = (z, y, x) lengths in metres."""
+    import torch
+    _need(thick, "thick", "float32", (None,))
+    nbeds = thick.numel()
+    dev = thick.device
+    _need(vbed, "vbed", "float32", (nbeds,), dev)
+    _need(tex_off, "tex_off", "float32", (nbeds,), dev)
+    _need(perm_b, "perm_b", "int32", (256,), dev)
+    _need(perm_t, "perm_t", "int32", (256,), dev)
+    out = torch.empty((t, ny, nx), dtype=torch.float32, device=dev)
+    _check(lib().sg_deposit_simplex(t, ny, nx, dz, dy, dx, nbeds, _ptr(thick), _ptr(vbed), beta, _ptr(perm_b),
+                                    lam_b[0], lam_b[1], lam_b[2], a_B, _ptr(perm_t), lam_t[0], lam_t[1], lam_t[2],
+                                    _ptr(tex_off), a_eta, f_top, f_base, _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def deposit_sinusoidal(t: int, ny: int, nx: int, dz: float, dy: float, dx: float, v0: float, beta: float, freq,
+                       sigma: float, amp1: float, amp2: float, phase2: float, rug, a_r: float, perm_t, lam_t,
+                       a_eta: float, f_top: float, f_base: float, stream=None):
+    """Deposit's sinusoidal bedform band [t, ny, nx]: freq float32 [t], rug
+    float32 [ny, nx] (or None with a_r = 0), perm_t int32 [256], device."""
+    import torch
+    _need(freq, "freq", "float32", (t,))
+    dev = freq.device
+    _need(rug, "rug", "float32", (ny, nx), dev, optional=rug is None)
+    _need(perm_t, "perm_t", "int32", (256,), dev)
+    out = torch.empty((t, ny, nx), dtype=torch.float32, device=dev)
+    _check(lib().sg_deposit_sinusoidal(t, ny, nx, dz, dy, dx, v0, beta, _ptr(freq), sigma, amp1, amp2, phase2,
+                                       _ptr(rug) if rug is not None else None, a_r, _ptr(perm_t), lam_t[0], lam_t[1],
+                                       lam_t[2], a_eta, f_top, f_base, _ptr(out), _stream_ptr(stream)))
     return out
 
 

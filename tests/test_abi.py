@@ -261,6 +261,37 @@ def test_deposit_argument_errors_touch_nothing():
         assert L.sg_deposit(*args) == E, (i, bad)
 
 
+def test_simplex_deposit_argument_errors_touch_nothing():
+    """The simplex noise, the simplex Deposit and the sinusoidal mode reject
+    NULL pointers, sizes, spacings, lengths and parameters out of range
+    before any device work (fake device pointers)."""
+    L = sgwave.lib()
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    E = sgwave.SG_EINVAL
+    ok = [a, 4, 5, 6, 0.0, 0.0, 0.0, 0.1, 0.1, 0.1, 1.0, b, None]
+    for i, bad in ((0, None), (11, None), (1, 0), (3, -2), (4, float("nan")), (8, float("inf")), (10, float("nan")),
+                   (5, 2.0 ** 41), (9, 2.0 ** 40)):
+        args = list(ok)
+        args[i] = bad
+        assert L.sg_simplex_noise3d(*args) == E, (i, bad)
+    ok = [40, 3, 5, 5.0, 10.0, 10.0, 4, a, a, 0.5, a, 60.0, 200.0, 200.0, 2.0, a, 30.0, 100.0, 100.0, a, 10.0, 0.2,
+          0.2, b, None]
+    for i, bad in ((0, 0), (6, 0), (6, 130), (3, 0.0), (7, None), (10, None), (15, None), (19, None), (23, None),
+                   (11, 0.0), (13, -5.0), (16, float("inf")), (18, 0.0), (14, float("nan")), (20, float("nan")),
+                   (21, 0.0), (9, float("inf"))):
+        args = list(ok)
+        args[i] = bad
+        assert L.sg_deposit_simplex(*args) == E, (i, bad)
+    ok = [40, 3, 5, 5.0, 10.0, 10.0, 3000.0, 0.2, a, 2.0, 100.0, 30.0, 0.5, a, 0.1, a, 30.0, 100.0, 100.0, 10.0, 0.2,
+          0.2, b, None]
+    for i, bad in ((0, 0), (0, 4097), (2, 0), (8, None), (15, None), (22, None), (13, None), (9, -1.0), (9, 256.0),
+                   (9, float("nan")), (3, 0.0), (16, 0.0), (20, float("inf")), (6, float("nan")), (12, float("inf")),
+                   (14, float("nan"))):
+        args = list(ok)
+        args[i] = bad
+        assert L.sg_deposit_sinusoidal(*args) == E, (i, bad)
+
+
 def test_salt_argument_errors_touch_nothing():
     """SaltSDT validates sizes, body parameters and the workspace before any
     device work (fake device pointers; host body arrays are real)."""
