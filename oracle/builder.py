@@ -3,7 +3,8 @@
 noise fields and sinusoidal bedform mode from the module's prose), Squish
 (Alg. 2, vertical warping by a fractal-noise displacement), Fault (Alg. 3, one
 listric normal fault as a tapered rotation about a horizontal cylinder; sinc
-pull for velocities, nearest-neighbour pull for labels) and SaltSDT (Alg. 4,
+pull for velocities, nearest-neighbour pull for labels; subsidiary faults in
+Riedel-shear geometry) and SaltSDT (Alg. 4,
 salt bodies from perturbed signed distances).
 
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU
@@ -210,6 +211,74 @@ def fault_labels(L, dz: float, dy: float, dx: float, p: dict, fill: int):
     out = np.where(w == 0, L, out)
     out[(w != 0) & ((sz < 0) | (sz >= nz))] = fill
     return out
+
+
+RIEDEL_DEFAULTS = dict(synthetic_fraction=0.85, hangingwall_fraction=0.75, synthetic_offset_deg=15.0,
+                       antithetic_offset_deg=165.0)
+
+
+def riedel_subsidiaries(primary: dict, cfg: dict, uniforms):
+    """Subsidiary faults of a primary in simplified Riedel-shear geometry (the
+    Fault prose of App. B and the fault-array setting of App. C): candidate k
+    draws five uniforms u in [0, 1) (the random draw, an input [n, 5]) and is
+
+      * synthetic (an R-shear, strike turned by synthetic_offset_deg) when
+        u0 < synthetic_fraction, else antithetic (R', antithetic_offset_deg);
+      * in the hanging wall when u1 < hangingwall_fraction, else in the
+        footwall: the hanging wall is the side of the primary's trace towards
+        which it dips, -n with n = (sin a, cos a) in (y, x) the direction from
+        the primary's cylinder axis to its centre;
+      * centred at the primary's depth and at c_yx + along s + side across n
+        with along = (2 u2 - 1) along_strike, across = across_min + u3
+        (across_max - across_min), s = (cos a, -sin a) the primary's strike;
+      * a copy of the primary scaled by size_scale in radius, die_r and
+        die_strike, with slip = primary slip (slip_min + u4 (slip_max -
+        slip_min)), a smooth surface, the same dip, die-off angle and direction.
+
+    Candidates are taken in order; one whose centre lies closer than
+    min_distance (horizontally) to an accepted subsidiary's is rejected.
+    Returns the accepted subsidiaries (dicts like `primary`)."""
+    u = np.asarray(uniforms, np.float64).reshape(-1, 5)
+    a = math.radians(primary["azimuth_deg"])
+    n_y, n_x = math.sin(a), math.cos(a)
+    s_y, s_x = math.cos(a), -math.sin(a)
+    out = []
+    for k in range(u.shape[0]):
+        u0, u1, u2, u3, u4 = u[k]
+        synthetic = u0 < cfg["synthetic_fraction"]
+        side = -1.0 if u1 < cfg["hangingwall_fraction"] else 1.0
+        along = (2.0 * u2 - 1.0) * cfg["along_strike"]
+        across = cfg["across_min"] + u3 * (cfg["across_max"] - cfg["across_min"])
+        cy = primary["cy"] + along * s_y + side * across * n_y
+        cx = primary["cx"] + along * s_x + side * across * n_x
+        if cfg["min_distance"] > 0 and any(math.hypot(cy - q["cy"], cx - q["cx"]) < cfg["min_distance"]
+                                           for q in out):
+            continue
+        sub = dict(primary)
+        sub.update(cy=cy, cx=cx,
+                   azimuth_deg=primary["azimuth_deg"] + (cfg["synthetic_offset_deg"] if synthetic
+                                                         else cfg["antithetic_offset_deg"]),
+                   radius=primary["radius"] * cfg["size_scale"], die_r=primary["die_r"] * cfg["size_scale"],
+                   die_strike=primary["die_strike"] * cfg["size_scale"],
+                   slip=primary["slip"] * (cfg["slip_min"] + u4 * (cfg["slip_max"] - cfg["slip_min"])),
+                   rough_lattice=None)
+        out.append(sub)
+    return out
+
+
+def fault_sequence(V, dz: float, dy: float, dx: float, faults, fill: float):
+    """The faults applied one after another (a primary and its subsidiaries)."""
+    V = np.asarray(V, np.float64)
+    for p in faults:
+        V = fault(V, dz, dy, dx, p, fill)
+    return V
+
+
+def fault_labels_sequence(L, dz: float, dy: float, dx: float, faults, fill: int):
+    """Labels through the same faults one after another."""
+    for p in faults:
+        L = fault_labels(L, dz, dy, dx, p, fill)
+    return L
 
 
 def value_noise3d(lattice, z, y, x, lam_z: float, lam_y: float, lam_x: float):

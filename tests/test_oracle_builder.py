@@ -714,3 +714,95 @@ def test_deposit_sinusoidal_closed_forms():
     Z, Y, X = np.meshgrid(np.arange(t) * dz / lam[0], np.arange(ny) * 10.0 / lam[1], np.arange(nx) * 10.0 / lam[2],
                           indexing="ij")
     assert np.abs((V3 - V)[1:] - 25.0 * B.simplex_noise3d(pt, Z, Y, X)[1:]).max() < 1e-9
+
+
+# -- subsidiary faults (Riedel-shear geometry) --------------------------------
+
+PRIMARY = dict(cz=1200.0, cy=2500.0, cx=3000.0, azimuth_deg=25.0, dip_deg=60.0, radius=3000.0, slip=120.0,
+               direction=1, die_r=400.0, die_strike=2000.0, die_theta_deg=30.0)
+RIEDEL = dict(B.RIEDEL_DEFAULTS, along_strike=1500.0, across_min=100.0, across_max=700.0, size_scale=0.3,
+              slip_min=0.2, slip_max=0.5, min_distance=0.0)
+
+
+def _strike(az_deg):
+    a = math.radians(az_deg)
+    return np.array([math.cos(a), -math.sin(a)])
+
+
+def test_riedel_orientations_sides_and_draw_fractions():
+    """20000 candidates without the distance filter: every subsidiary's
+    strike makes 15 deg (synthetic) or 165 deg (antithetic) with the
+    primary's; the synthetic share is 0.85 and the hanging-wall share 0.75
+    (+-0.01); hanging-wall centres lie on the concave side of the primary's
+    listric surface (inside its cylinder, r < R, measured from the axis the
+    primary's dip and radius put at c - (R cos dip) n - (R sin dip) z), the
+    footwall ones outside, all across-strike distances in [100, 700] m and
+    along-strike offsets within +-1500 m; sizes and slips scaled as drawn."""
+    rng = np.random.default_rng(60)
+    u = rng.random((20000, 5))
+    subs = B.riedel_subsidiaries(PRIMARY, RIEDEL, u)
+    assert len(subs) == 20000
+    s0 = _strike(PRIMARY["azimuth_deg"])
+    n0 = np.array([s0[1] * -1.0, s0[0]])            # rotate strike by +90 deg: (sin a, cos a)
+    ang = np.array([math.degrees(math.acos(np.clip(_strike(q["azimuth_deg"]) @ s0, -1, 1))) for q in subs])
+    assert np.all((np.abs(ang - 15.0) < 1e-9) | (np.abs(ang - 165.0) < 1e-9))
+    assert abs(np.mean(ang < 90) - 0.85) < 0.01
+    a, dip, R = math.radians(PRIMARY["azimuth_deg"]), math.radians(PRIMARY["dip_deg"]), PRIMARY["radius"]
+    axis_yx = np.array([PRIMARY["cy"], PRIMARY["cx"]]) - R * math.cos(dip) * n0
+    axis_z = PRIMARY["cz"] - R * math.sin(dip)
+    hang = []
+    for q in subs:
+        d = np.array([q["cy"], q["cx"]]) - np.array([PRIMARY["cy"], PRIMARY["cx"]])
+        across, along = d @ n0, d @ s0
+        assert 100.0 - 1e-9 <= abs(across) <= 700.0 + 1e-9 and abs(along) <= 1500.0 + 1e-9
+        assert q["cz"] == PRIMARY["cz"]
+        r = math.hypot((np.array([q["cy"], q["cx"]]) - axis_yx) @ n0, q["cz"] - axis_z)
+        hang.append(r < R)
+        assert (r < R) == (across < 0)
+        assert q["radius"] == pytest.approx(0.3 * R) and q["die_r"] == pytest.approx(120.0)
+        assert 0.2 * 120.0 - 1e-9 <= q["slip"] <= 0.5 * 120.0 + 1e-9
+        assert q["dip_deg"] == 60.0 and q["direction"] == 1 and q["rough_lattice"] is None
+    assert abs(np.mean(hang) - 0.75) < 0.01
+
+
+def test_riedel_distance_filter_is_greedy_and_keeps_spacing():
+    """With min_distance 250 m: accepted centres are pairwise >= 250 m apart
+    (horizontally), every rejected candidate lies within 250 m of one
+    accepted before it, and the accepted ones are the unfiltered run's in
+    order (the filter drops, never alters)."""
+    rng = np.random.default_rng(61)
+    u = rng.random((60, 5))
+    cfg = dict(RIEDEL, min_distance=250.0)
+    kept = B.riedel_subsidiaries(PRIMARY, cfg, u)
+    allc = B.riedel_subsidiaries(PRIMARY, RIEDEL, u)
+    assert 5 < len(kept) < 60
+    xy = lambda q: np.array([q["cy"], q["cx"]])
+    for i in range(len(kept)):
+        for j in range(i):
+            assert np.linalg.norm(xy(kept[i]) - xy(kept[j])) >= 250.0
+    it = iter(kept)
+    nxt = next(it)
+    accepted = []
+    for q in allc:
+        if nxt is not None and q == nxt:
+            accepted.append(q)
+            nxt = next(it, None)
+        else:
+            assert min(np.linalg.norm(xy(q) - xy(p)) for p in accepted) < 250.0
+    assert nxt is None
+
+
+def test_fault_sequence_applies_the_faults_in_order():
+    """The sequence equals the faults applied one by one; a fault of zero
+    slip leaves the model, and the order matters for overlapping faults."""
+    rng = np.random.default_rng(62)
+    V = 2000.0 + 30.0 * np.arange(24)[:, None, None] + rng.normal(0, 5, (24, 10, 12))
+    p1 = dict(PRIMARY, cz=100.0, cy=50.0, cx=60.0, radius=300.0, slip=30.0, die_r=60.0, die_strike=200.0)
+    p2 = dict(p1, azimuth_deg=40.0, cx=70.0, slip=25.0)
+    seq = B.fault_sequence(V, 10.0, 10.0, 10.0, [p1, p2], 1500.0)
+    one = B.fault(B.fault(V, 10.0, 10.0, 10.0, p1, 1500.0), 10.0, 10.0, 10.0, p2, 1500.0)
+    assert np.abs(seq - one).max() == 0.0
+    rev = B.fault_sequence(V, 10.0, 10.0, 10.0, [p2, p1], 1500.0)
+    assert np.abs(seq - rev).max() > 1.0
+    still = B.fault_sequence(V, 10.0, 10.0, 10.0, [dict(p1, slip=0.0)], 1500.0)
+    assert np.abs(still - V).max() < 1e-9
