@@ -437,6 +437,22 @@ def builder_rate(passes=3):
     torch.cuda.synchronize()
     ms_fs = ev[0].elapsed_time(ev[1]) / passes
     del out3
+    # the primary and its Riedel-shear subsidiaries (25 candidates, the paper's 20-30 per primary;
+    # subsidiaries at 0.15 of the primary's size, 0.2-0.5 of its slip, 500 m apart) in one sequence
+    cfg = dict(synthetic_fraction=0.85, hangingwall_fraction=0.75, synthetic_offset_deg=15.0,
+               antithetic_offset_deg=165.0, along_strike=3000.0, across_min=300.0, across_max=2000.0,
+               size_scale=0.15, slip_min=0.2, slip_max=0.5, min_distance=500.0)
+    subs = sgwave.riedel_subsidiaries(fault, cfg, np.random.default_rng(17).random((25, 5)))
+    seq = [fault] + subs
+    ws = torch.empty_like(out)
+    out3 = sgwave.fault_sequence(out, h, h, h, seq, 1500.0, ws=ws)
+    torch.cuda.synchronize()
+    ev[0].record()
+    out3 = sgwave.fault_sequence(out, h, h, h, seq, 1500.0, ws=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_seq = ev[0].elapsed_time(ev[1])
+    del out3, ws
     nvox = nz * ny * nx
     moved = float((out2 != out).float().mean())
     del v, out, out2
@@ -458,6 +474,31 @@ def builder_rate(passes=3):
     torch.cuda.synchronize()
     ms_d = ev[0].elapsed_time(ev[1]) / passes
     del band, eta
+    # the same band with simplex contact and texture fields, and the sinusoidal bedform mode
+    perm_b = torch.randperm(256, device="cuda", generator=gen).to(torch.int32)
+    perm_t = torch.randperm(256, device="cuda", generator=gen).to(torch.int32)
+    sargs = (tb, ny, nx, h / 4, h, h, thick, vbed, 0.3, perm_b, (40.0, 1500.0, 2000.0), 3.0, perm_t,
+             (12.0, 400.0, 400.0), off, 50.0, 0.1, 0.1)
+    freq = torch.rand(tb, device="cuda", generator=gen) * 0.08 + 0.04
+    rug = sgwave.fractal_noise2d(torch.rand((3, 8, 8), device="cuda", generator=gen) * 2.0 - 1.0, ny, nx, h, h,
+                                 1500.0, 2000.0, 0.0, 1.0)
+    wargs = (tb, ny, nx, h / 4, h, h, 2600.0, 0.3, freq, 4.0, 150.0, 60.0, 0.8, rug, 0.1, perm_t,
+             (12.0, 400.0, 400.0), 50.0, 0.1, 0.1)
+    band = sgwave.deposit_simplex(*sargs)
+    band = sgwave.deposit_sinusoidal(*wargs)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(passes):
+        band = sgwave.deposit_simplex(*sargs)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(passes):
+        band = sgwave.deposit_sinusoidal(*wargs)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms_ds = ev[0].elapsed_time(ev[1]) / passes
+    ms_dw = ev[2].elapsed_time(ev[3]) / passes
+    del band, rug
     # SaltSDT: three rotated ellipsoids (radii 0.8-2 km); each body's field from
     # the GRF step (sg_grf: white noise on the 1024^3 periodic grid, spectral
     # exponent p = 2, correlation lengths l_k = max(r_k f_k, 5) cells with
@@ -504,7 +545,8 @@ def builder_rate(passes=3):
             "squish_ms": ms_sq, "squish_Gvoxel_per_s": nvox / (ms_sq / 1e3) / 1e9,
             "squish_frac_of_hbm_peak": 8.0 * nvox / (ms_sq / 1e3) / 1e9 / HBM_PEAK_GBS,
             "fault_ms": ms_f, "fault_Gvoxel_per_s": nvox / (ms_f / 1e3) / 1e9, "small_fault_ms": ms_fs,
-            "fault_moved_fraction": moved,
+            "fault_moved_fraction": moved, "fault_sequence_faults": len(seq), "fault_sequence_ms": ms_seq,
+            "deposit_simplex_ms": ms_ds, "deposit_sinusoidal_ms": ms_dw,
             "deposit_band": "200 x 1000 x 1000 cells (2.5 m vertical), 40 beds", "deposit_ms": ms_d,
             "deposit_Gvoxel_per_s": tb * ny * nx / (ms_d / 1e3) / 1e9}
 

@@ -544,6 +544,51 @@ typedef struct sg_fault_params {
 sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                    const sg_fault_params *p, float fill, float *out, void *stream);
 
+/* Faults applied one after another (a primary and its subsidiaries, App. B
+ * Fault prose): out = fault[n-1](... fault[0](v)), each as sg_fault; ws a
+ * second device volume [nz][ny][nx] (NULL allowed when nfaults <= 1), v, out
+ * and ws pairwise disjoint.  The steps alternate between out and ws; a fault
+ * whose reach is a box inside the volume costs that box plus a copy of the
+ * previous fault's box (never the whole volume after the second step).
+ * nfaults in 0..100000 (0 copies v).  A rough fault synchronises `stream`
+ * once, as in sg_fault.  Errors as sg_fault, plus SG_EINVAL for overlapping
+ * buffers or a missing ws. */
+sg_status sg_fault_sequence(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                            const sg_fault_params *faults, int32_t nfaults, float fill, float *out, float *ws,
+                            void *stream);
+
+/* Subsidiary faults of a primary in simplified Riedel-shear geometry (the
+ * Fault prose of App. B; App. C's fault-array setting gives R-shears at +15
+ * deg, R' at +165 deg, an 85 % synthetic and 75 % hanging-wall bias and a
+ * minimum-distance filter).  Host only, FP64.  Candidate k reads five
+ * uniforms in [0, 1] from uniforms[5 k ..] (the random draw, host) and is:
+ * synthetic (azimuth + synthetic_offset_deg) when u0 < synthetic_fraction,
+ * else antithetic (+ antithetic_offset_deg); on the hanging-wall side (-n, n =
+ * (sin a, cos a) in (y, x), the side the primary dips towards) when u1 <
+ * hangingwall_fraction, else the footwall side (+n); centred at the primary's
+ * depth, (2 u2 - 1) along_strike along the strike (cos a, -sin a) and
+ * across_min + u3 (across_max - across_min) across it; a smooth copy of the
+ * primary with radius, die_r and die_strike times size_scale and slip times
+ * slip_min + u4 (slip_max - slip_min).  Candidates are taken in order and one
+ * closer than min_distance (map view) to an accepted subsidiary is dropped.
+ * out: host [ncand] (the first *nout entries are written).  Each subsidiary is
+ * one more fault of a sequence.  SG_EINVAL for NULL pointers, ncand outside
+ * 0..1000000, fractions outside [0, 1], negative or non-finite distances,
+ * size_scale <= 0, uniforms outside [0, 1] or an invalid primary. */
+typedef struct sg_riedel_config {
+    double synthetic_fraction;     /* 0.85 */
+    double hangingwall_fraction;   /* 0.75 */
+    double synthetic_offset_deg;   /* 15 */
+    double antithetic_offset_deg;  /* 165 */
+    double along_strike;           /* half-length of the placement zone along strike [m] */
+    double across_min, across_max; /* distance from the primary's trace across strike [m] */
+    double size_scale;             /* radius and die-off lengths relative to the primary */
+    double slip_min, slip_max;     /* slip relative to the primary's */
+    double min_distance;           /* between subsidiary centres, map view [m] */
+} sg_riedel_config;
+sg_status sg_riedel_subsidiaries(const sg_fault_params *primary, const sg_riedel_config *cfg, int32_t ncand,
+                                 const double *uniforms, sg_fault_params *out, int32_t *nout);
+
 /* Alg. 3 for integer fields such as layer labels (the module resamples them
  * by nearest neighbour): the same fault and pull source as sg_fault, with
  * out(voxel) = labels at the voxel nearest the source (floor(s + 0.5) per axis
@@ -553,6 +598,12 @@ sg_status sg_fault(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz
  * labels.  Same argument errors as sg_fault. */
 sg_status sg_fault_labels(const int32_t *labels, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
                           const sg_fault_params *p, int32_t fill, int32_t *out, void *stream);
+
+/* Labels through a sequence of faults (nearest-neighbour pulls, as
+ * sg_fault_labels); buffers and errors as sg_fault_sequence. */
+sg_status sg_fault_labels_sequence(const int32_t *labels, int32_t nz, int32_t ny, int32_t nx, double dz, double dy,
+                                   double dx, const sg_fault_params *faults, int32_t nfaults, int32_t fill,
+                                   int32_t *out, int32_t *ws, void *stream);
 
 /* Alg. 4 (SaltSDT) on a device volume v [nz][ny][nx] (positions (z dz, y dy,
  * x dx) in metres).  Body i (host arrays): centre centres[3i..3i+2] and radii

@@ -774,4 +774,93 @@ hipError_t launch_fault_labels(const int32_t *lab, int nz, int ny, int nx, const
     return hipGetLastError();
 }
 
+namespace {
+
+// dst = src on the voxels of box B (rows of the box contiguous in x).
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_box(const T *__restrict__ src, int ny, int nx, VoxBox B,
+                                                  T *__restrict__ dst)
+{
+    const int64_t nb = (int64_t)B.bz * B.by * B.bx;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nb; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = q / B.bx;
+        const int x = (int)(q - row * B.bx), z = (int)(row / B.by), y = (int)(row - (int64_t)z * B.by);
+        const int64_t o = ((int64_t)(B.z0 + z) * ny + (B.y0 + y)) * nx + (B.x0 + x);
+        dst[o] = src[o];
+    }
+}
+
+template <typename T>
+hipError_t copy_box(const T *src, int ny, int nx, const VoxBox &B, T *dst, hipStream_t st)
+{
+    const int64_t nb = (int64_t)B.bz * B.by * B.bx;
+    const int64_t blocks = std::min<int64_t>((nb + 255) / 256, (int64_t)1 << 20);
+    hipLaunchKernelGGL(k_copy_box<T>, dim3((unsigned)blocks), dim3(256), 0, st, src, ny, nx, B, dst);
+    return hipGetLastError();
+}
+
+// The faults in order, alternating between out and ws so the last lands in
+// out.  Step k writes dst_k, which holds the state of step k-2 (garbage for
+// k < 2); that state differs from step k-1's only on the box fault k-1
+// wrote, so that box is copied over first (the whole volume for k < 2) when
+// fault k does not cover the volume itself; then fault k runs on its box.
+template <typename T, typename Launch>
+hipError_t fault_sequence(const T *v, int nz, int ny, int nx, const FaultFrame *F, int n, T *out, T *ws,
+                          hipStream_t st, Launch run_kernel)
+{
+    const VoxBox whole{0, 0, 0, nz, ny, nx};
+    const size_t bytes = (size_t)nz * ny * nx * sizeof(T);
+    if (n == 0) return hipMemcpyAsync(out, v, bytes, hipMemcpyDeviceToDevice, st);
+    const T *src = v;
+    VoxBox prev{};
+    bool prev_run = false;
+    for (int k = 0; k < n; ++k) {
+        T *dst = ((n - 1 - k) % 2 == 0) ? out : ws;
+        VoxBox B;
+        const bool run = fault_box(F[k], nz, ny, nx, B);
+        const bool partial = !run || B.bz < nz || B.by < ny || B.bx < nx;
+        hipError_t e = hipSuccess;
+        if (partial) {
+            if (k < 2)
+                e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+            else if (prev_run)
+                e = copy_box(src, ny, nx, prev, dst, st);
+        }
+        if (e != hipSuccess) return e;
+        if (run) {
+            const int64_t blocks = fault_blocks(B);
+            if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
+            run_kernel(src, B, F[k], dst, (unsigned)blocks);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        prev = run ? B : whole;
+        prev_run = run;
+        src = dst;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_fault_sequence(const float *v, int nz, int ny, int nx, const FaultFrame *F, int n, float fill,
+                                 float *out, float *ws, hipStream_t st)
+{
+    return fault_sequence(v, nz, ny, nx, F, n, out, ws, st,
+                          [&](const float *src, const VoxBox &B, const FaultFrame &f, float *dst, unsigned blocks) {
+                              hipLaunchKernelGGL(k_fault, dim3(blocks), dim3(256), 0, st, src, nz, ny, nx, B, f,
+                                                 fill, dst);
+                          });
+}
+
+hipError_t launch_fault_labels_sequence(const int32_t *lab, int nz, int ny, int nx, const FaultFrame *F, int n,
+                                        int32_t fill, int32_t *out, int32_t *ws, hipStream_t st)
+{
+    return fault_sequence(lab, nz, ny, nx, F, n, out, ws, st,
+                          [&](const int32_t *src, const VoxBox &B, const FaultFrame &f, int32_t *dst,
+                              unsigned blocks) {
+                              hipLaunchKernelGGL(k_fault_labels, dim3(blocks), dim3(256), 0, st, src, nz, ny, nx, B,
+                                                 f, fill, dst);
+                          });
+}
+
 }  // namespace sg

@@ -258,6 +258,12 @@ hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame
                         hipStream_t st);
 hipError_t launch_fault_labels(const int32_t *lab, int nz, int ny, int nx, const FaultFrame &F, int32_t fill,
                                int32_t *out, hipStream_t st);
+// Faults F[0..n-1] applied in order: the result in out, ws a second volume
+// (may be NULL when n <= 1); neither aliases v or the other.
+hipError_t launch_fault_sequence(const float *v, int nz, int ny, int nx, const FaultFrame *F, int n, float fill,
+                                 float *out, float *ws, hipStream_t st);
+hipError_t launch_fault_labels_sequence(const int32_t *lab, int nz, int ny, int nx, const FaultFrame *F, int n,
+                                        int32_t fill, int32_t *out, int32_t *ws, hipStream_t st);
 
 // One salt body of Alg. 4: centre and radii in metres as (z, y, x); R row-major,
 // taking world offsets to the body frame.

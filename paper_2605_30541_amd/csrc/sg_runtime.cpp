@@ -2193,6 +2193,116 @@ sg_status sg_fault_labels(const int32_t *labels, int32_t nz, int32_t ny, int32_t
     return SG_OK;
 }
 
+extern "C++" {
+namespace {
+bool overlap(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+template <typename T, typename Launch>
+sg_status fault_sequence_call(const T *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                              const sg_fault_params *faults, int32_t nfaults, T *out, T *ws, hipStream_t st,
+                              Launch launch)
+{
+    sg_status rc = volume_args(v, nz, ny, nx, out);
+    if (rc != SG_OK) return rc;
+    if (nfaults < 0 || nfaults > 100000) return fail(SG_EINVAL, "nfaults must be in 0..100000");
+    if (nfaults > 0 && !faults) return fail(SG_EINVAL, "NULL argument");
+    if (nfaults > 1 && !ws) return fail(SG_EINVAL, "ws is required for two or more faults");
+    const size_t bytes = (size_t)nz * ny * nx * sizeof(T);
+    if (overlap(v, out, bytes) || (nfaults > 1 && (overlap(v, ws, bytes) || overlap(out, ws, bytes))))
+        return fail(SG_EINVAL, "v, out and ws must not overlap");
+    std::vector<sg::FaultFrame> F((size_t)nfaults);
+    for (int32_t k = 0; k < nfaults; ++k)
+        if ((rc = fault_frame(&faults[k], dz, dy, dx, F[(size_t)k], st)) != SG_OK) return rc;
+    SG_HIP(launch(F.data()));
+    return SG_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+sg_status sg_fault_sequence(const float *v, int32_t nz, int32_t ny, int32_t nx, double dz, double dy, double dx,
+                            const sg_fault_params *faults, int32_t nfaults, float fill, float *out, float *ws,
+                            void *stream)
+{
+    const hipStream_t st = (hipStream_t)stream;
+    return fault_sequence_call(v, nz, ny, nx, dz, dy, dx, faults, nfaults, out, ws, st,
+                               [&](const sg::FaultFrame *F) {
+                                   return sg::launch_fault_sequence(v, nz, ny, nx, F, nfaults, fill, out, ws, st);
+                               });
+}
+
+sg_status sg_fault_labels_sequence(const int32_t *labels, int32_t nz, int32_t ny, int32_t nx, double dz, double dy,
+                                   double dx, const sg_fault_params *faults, int32_t nfaults, int32_t fill,
+                                   int32_t *out, int32_t *ws, void *stream)
+{
+    const hipStream_t st = (hipStream_t)stream;
+    return fault_sequence_call(labels, nz, ny, nx, dz, dy, dx, faults, nfaults, out, ws, st,
+                               [&](const sg::FaultFrame *F) {
+                                   return sg::launch_fault_labels_sequence(labels, nz, ny, nx, F, nfaults, fill, out,
+                                                                           ws, st);
+                               });
+}
+
+sg_status sg_riedel_subsidiaries(const sg_fault_params *primary, const sg_riedel_config *cfg, int32_t ncand,
+                                 const double *uniforms, sg_fault_params *out, int32_t *nout)
+{
+    if (!primary || !cfg || !nout || (ncand > 0 && (!uniforms || !out))) return fail(SG_EINVAL, "NULL argument");
+    if (ncand < 0 || ncand > 1000000) return fail(SG_EINVAL, "ncand must be in 0..1000000");
+    const sg_riedel_config &c = *cfg;
+    if (!(c.synthetic_fraction >= 0.0 && c.synthetic_fraction <= 1.0) ||
+        !(c.hangingwall_fraction >= 0.0 && c.hangingwall_fraction <= 1.0))
+        return fail(SG_EINVAL, "fractions must be in [0, 1]");
+    for (double x : {c.synthetic_offset_deg, c.antithetic_offset_deg})
+        if (!std::isfinite(x)) return fail(SG_EINVAL, "angle offsets must be finite");
+    for (double x : {c.along_strike, c.across_min, c.across_max, c.min_distance, c.slip_min, c.slip_max})
+        if (!(x >= 0.0 && std::isfinite(x))) return fail(SG_EINVAL, "distances and slip fractions must be finite and >= 0");
+    if (c.across_max < c.across_min || c.slip_max < c.slip_min)
+        return fail(SG_EINVAL, "across_max >= across_min and slip_max >= slip_min required");
+    if (!positive_finite(c.size_scale)) return fail(SG_EINVAL, "size_scale must be finite and > 0");
+    const sg_fault_params &p = *primary;
+    for (double x : {p.cz, p.cy, p.cx, p.azimuth_deg, p.dip_deg, p.slip})
+        if (!std::isfinite(x)) return fail(SG_EINVAL, "fault centre, azimuth, dip and slip must be finite");
+    for (double x : {p.radius, p.die_r, p.die_strike, p.die_theta_deg})
+        if (!positive_finite(x)) return fail(SG_EINVAL, "radius and die-off extents must be finite and > 0");
+    for (int64_t i = 0; i < (int64_t)ncand * 5; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] <= 1.0)) return fail(SG_EINVAL, "uniforms must be in [0, 1]");
+    const double deg = 3.14159265358979323846 / 180.0;
+    const double a = p.azimuth_deg * deg;
+    const double n_y = std::sin(a), n_x = std::cos(a), s_y = std::cos(a), s_x = -std::sin(a);
+    int32_t m = 0;
+    for (int32_t k = 0; k < ncand; ++k) {
+        const double *u = uniforms + (size_t)k * 5;
+        const bool synthetic = u[0] < c.synthetic_fraction;
+        const double side = u[1] < c.hangingwall_fraction ? -1.0 : 1.0;   // hanging wall: -n
+        const double along = (2.0 * u[2] - 1.0) * c.along_strike;
+        const double across = c.across_min + u[3] * (c.across_max - c.across_min);
+        const double cy = p.cy + along * s_y + side * across * n_y;
+        const double cx = p.cx + along * s_x + side * across * n_x;
+        bool keep = true;
+        if (c.min_distance > 0.0)
+            for (int32_t q = 0; q < m && keep; ++q)
+                keep = !(std::hypot(cy - out[q].cy, cx - out[q].cx) < c.min_distance);
+        if (!keep) continue;
+        sg_fault_params f = p;
+        f.cy = cy;
+        f.cx = cx;
+        f.azimuth_deg = p.azimuth_deg + (synthetic ? c.synthetic_offset_deg : c.antithetic_offset_deg);
+        f.radius = p.radius * c.size_scale;
+        f.die_r = p.die_r * c.size_scale;
+        f.die_strike = p.die_strike * c.size_scale;
+        f.slip = p.slip * (c.slip_min + u[4] * (c.slip_max - c.slip_min));
+        f.rough_lattice = nullptr;
+        f.rough_noct = f.rough_gd = f.rough_gs = 0;
+        f.rough_amplitude = f.rough_lam_strike = f.rough_lam_dip = 0.0;
+        out[m++] = f;
+    }
+    *nout = m;
+    return SG_OK;
+}
+
 namespace {
 sg_status salt_size_args(int32_t nz, int32_t ny, int32_t nx)
 {

@@ -82,12 +82,21 @@ class sg_fault_params(ctypes.Structure):
                 ("rough_lam_strike", ctypes.c_double), ("rough_lam_dip", ctypes.c_double)]
 
 
+class sg_riedel_config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("synthetic_fraction", "hangingwall_fraction", "synthetic_offset_deg",
+                                               "antithetic_offset_deg", "along_strike", "across_min", "across_max",
+                                               "size_scale", "slip_min", "slip_max", "min_distance")]
+
+
+_FAULT_FIELDS = ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip", "direction", "die_r", "die_strike",
+                 "die_theta_deg")
+
+
 def _fault_params(params: dict, device=None) -> sg_fault_params:
     """sg_fault_params from a dict of its fields; an optional rough surface is
     given by rough_lattice (a float32 device tensor [noct, gd, gs] on
     `device`), rough_amplitude, rough_lam_strike and rough_lam_dip."""
-    p = sg_fault_params(**{k: params[k] for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip",
-                                                  "direction", "die_r", "die_strike", "die_theta_deg")})
+    p = sg_fault_params(**{k: params[k] for k in _FAULT_FIELDS})
     lat = params.get("rough_lattice")
     if lat is not None:
         _need(lat, "rough_lattice", "float32", (None, None, None), device)
@@ -172,6 +181,17 @@ _SIGS = {
     "sg_fault": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(sg_fault_params), ctypes.c_float,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_fault_sequence": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.POINTER(sg_fault_params), ctypes.c_int32, ctypes.c_float,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_fault_labels_sequence": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.POINTER(sg_fault_params), ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_riedel_subsidiaries": (ctypes.c_int32, [ctypes.POINTER(sg_fault_params), ctypes.POINTER(sg_riedel_config),
+                                                ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(sg_fault_params), ctypes.POINTER(ctypes.c_int32)]),
     "sg_salt_workspace_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "sg_salt_sdt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -676,6 +696,59 @@ def fault(v, dz: float, dy: float, dx: float, params: dict, fill: float, stream=
     out = torch.empty_like(v)
     _check(lib().sg_fault(_ptr(v), nz, ny, nx, dz, dy, dx, ctypes.byref(p), fill, _ptr(out), _stream_ptr(stream)))
     return out
+
+
+def _fault_array(faults, device):
+    arr = (sg_fault_params * max(len(faults), 1))()
+    for k, f in enumerate(faults):
+        arr[k] = _fault_params(f, device)
+    return arr
+
+
+def fault_sequence(v, dz: float, dy: float, dx: float, faults, fill: float, ws=None, stream=None):
+    """v [nz, ny, nx] (float32 device) through the faults (a list of dicts as
+    for `fault`) in order; ws: a second float32 volume of v's shape (made
+    here when None and two or more faults are given)."""
+    import torch
+    _need(v, "v", "float32", (None, None, None))
+    nz, ny, nx = v.shape
+    if ws is None and len(faults) > 1:
+        ws = torch.empty_like(v)
+    _need(ws, "ws", "float32", tuple(v.shape), v.device, optional=ws is None)
+    arr = _fault_array(faults, v.device)
+    out = torch.empty_like(v)
+    _check(lib().sg_fault_sequence(_ptr(v), nz, ny, nx, dz, dy, dx, arr, len(faults), fill, _ptr(out), _ptr(ws),
+                                   _stream_ptr(stream)))
+    return out
+
+
+def fault_labels_sequence(labels, dz: float, dy: float, dx: float, faults, fill: int, ws=None, stream=None):
+    """int32 device labels through the faults in order (nearest-neighbour pulls)."""
+    import torch
+    _need(labels, "labels", "int32", (None, None, None))
+    nz, ny, nx = labels.shape
+    if ws is None and len(faults) > 1:
+        ws = torch.empty_like(labels)
+    _need(ws, "ws", "int32", tuple(labels.shape), labels.device, optional=ws is None)
+    arr = _fault_array(faults, labels.device)
+    out = torch.empty_like(labels)
+    _check(lib().sg_fault_labels_sequence(_ptr(labels), nz, ny, nx, dz, dy, dx, arr, len(faults), fill, _ptr(out),
+                                          _ptr(ws), _stream_ptr(stream)))
+    return out
+
+
+def riedel_subsidiaries(primary: dict, cfg: dict, uniforms):
+    """Subsidiary faults of `primary` (dict as for `fault`, smooth) from
+    uniforms [n, 5] (host) and cfg (the fields of sg_riedel_config); returns a
+    list of dicts."""
+    u = np.ascontiguousarray(uniforms, np.float64).reshape(-1, 5)
+    n = u.shape[0]
+    out = (sg_fault_params * max(n, 1))()
+    m = ctypes.c_int32(0)
+    c = sg_riedel_config(**{k: float(cfg[k]) for k, _ in sg_riedel_config._fields_})
+    _check(lib().sg_riedel_subsidiaries(ctypes.byref(_fault_params(primary)), ctypes.byref(c), n,
+                                        u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out, ctypes.byref(m)))
+    return [{k: getattr(out[i], k) for k in _FAULT_FIELDS} for i in range(m.value)]
 
 
 def sg_salt_workspace_size(nz: int, ny: int, nx: int) -> int:

@@ -371,3 +371,54 @@ def test_grf_grid_and_argument_errors():
     for noise, ell, p, out, nbytes, want in cases:
         st = L.sg_grf(noise, 8, 8, 8, ell, ell, ell, p, out, ctypes.c_void_p(0x3000), nbytes, None)
         assert st == want, (st, want, sgwave.sg_last_error())
+
+
+def test_riedel_subsidiaries_match_the_oracle():
+    """The host recipe equals the oracle's on the same draws (FP64, same
+    operation order), with and without the spacing filter; bad arguments
+    are rejected."""
+    from oracle import builder as OB
+    primary = dict(cz=1200.0, cy=2500.0, cx=3000.0, azimuth_deg=25.0, dip_deg=60.0, radius=3000.0, slip=120.0,
+                   direction=1, die_r=400.0, die_strike=2000.0, die_theta_deg=30.0)
+    cfg = dict(OB.RIEDEL_DEFAULTS, along_strike=1500.0, across_min=100.0, across_max=700.0, size_scale=0.3,
+               slip_min=0.2, slip_max=0.5, min_distance=250.0)
+    u = np.random.default_rng(70).random((30, 5))
+    for c in (cfg, dict(cfg, min_distance=0.0)):
+        got = sgwave.riedel_subsidiaries(primary, c, u)
+        ref = OB.riedel_subsidiaries(primary, c, u)
+        assert len(got) == len(ref) > 0
+        for g, r in zip(got, ref):
+            for k in ("cz", "cy", "cx", "azimuth_deg", "dip_deg", "radius", "slip", "direction", "die_r",
+                      "die_strike", "die_theta_deg"):
+                assert g[k] == pytest.approx(r[k], rel=1e-13, abs=1e-9), k
+    assert sgwave.riedel_subsidiaries(primary, cfg, np.zeros((0, 5))) == []
+    for bad_cfg in (dict(cfg, synthetic_fraction=1.5), dict(cfg, across_min=800.0), dict(cfg, size_scale=0.0),
+                    dict(cfg, min_distance=-1.0), dict(cfg, slip_max=0.1)):
+        with pytest.raises(SGError) as e:
+            sgwave.riedel_subsidiaries(primary, bad_cfg, u)
+        assert e.value.status == sgwave.SG_EINVAL
+    with pytest.raises(SGError):
+        sgwave.riedel_subsidiaries(primary, cfg, u + 1.0)
+    with pytest.raises(SGError):
+        sgwave.riedel_subsidiaries(dict(primary, radius=0.0), cfg, u)
+
+
+def test_fault_sequence_argument_errors_touch_nothing():
+    """Sequences reject NULL and overlapping buffers, a missing second volume
+    and bad fault parameters before any device work (fake pointers)."""
+    L = sgwave.lib()
+    f = sgwave._fault_params(dict(cz=100.0, cy=50.0, cx=60.0, azimuth_deg=0.0, dip_deg=60.0, radius=300.0,
+                                  slip=30.0, direction=1, die_r=60.0, die_strike=200.0, die_theta_deg=30.0))
+    arr = (sgwave.sg_fault_params * 3)(f, f, f)
+    bad = (sgwave.sg_fault_params * 3)(f, f, f)
+    bad[2].direction = 0
+    n = 10 * 12 * 14 * 4
+    v, out, ws = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    ok = [v, 10, 12, 14, 10.0, 10.0, 10.0, arr, 3, 1500.0, out, ws, None]
+    E = sgwave.SG_EINVAL
+    for i, badv in ((0, None), (10, None), (11, None), (8, -1), (1, 0), (4, 0.0), (7, None), (7, bad),
+                    (10, ctypes.c_void_p((1 << 20) + n - 4)), (11, ctypes.c_void_p((2 << 20) + 64))):
+        args = list(ok)
+        args[i] = badv
+        assert L.sg_fault_sequence(*args) == E, (i, badv)
+        assert L.sg_fault_labels_sequence(*args[:9], 0, *args[10:]) == E, (i, badv)
