@@ -70,6 +70,57 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     return LIB
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the
+# runtime (the C ABI's validation, table building and staging), for CPU test
+# runs: each sanitizer flag is scoped to the host pass, the kernels are the
+# regular objects.  Load it with SGWAVE_LIBRARY=<path> and the ASan runtime of
+# sanitizer_runtime() in LD_PRELOAD.
+SAN_DIR = os.path.join(OUT_DIR, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libsgwave.so")
+SAN_FLAGS = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def sanitizer_runtime() -> str | None:
+    """The shared ASan runtime of the ROCm clang (None if absent)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so") +
+                  glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Builds SAN_LIB: the regular kernel objects (built if missing) with the
+    host runtime compiled under ASan and UBSan."""
+    build(verbose, incremental=True)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = []
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith(".hip"):
+            objs.append(os.path.join(OUT_DIR, f + ".o"))
+        elif f.endswith(".cpp"):
+            obj = os.path.join(SAN_DIR, f + ".o")
+            cmd = [HIPCC, "-c", *SAN_FLAGS, *inc, os.path.join(CSRC, f), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            objs.append(obj)
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan",
+           "-Wl,--version-script=" + os.path.join(OUT_DIR, "exports.map"), *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     import sys
-    print(build(verbose=True, incremental="--incremental" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose=True))
+    else:
+        print(build(verbose=True, incremental="--incremental" in sys.argv))

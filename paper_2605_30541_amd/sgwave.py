@@ -17,7 +17,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libsgwave.so")
+# SGWAVE_LIBRARY selects another build of the same library (e.g. the host
+# sanitizer build of build.py --sanitize); there is no fallback either way
+LIB_PATH = os.environ.get("SGWAVE_LIBRARY") or os.path.join(_HERE, "_build", "libsgwave.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgwave.h")
 
 SG_OK, SG_EINVAL, SG_ECFL, SG_ENOSPACE, SG_EHIP, SG_EDIVERGED, SG_EUNSUPPORTED = range(7)
