@@ -49,9 +49,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=3)
     ap.add_argument("--shots-per-wave", type=int, default=25)
-    ap.add_argument("--grad-tuning", type=str, default="",
+    ap.add_argument("--grad-tuning", type=str, default="s128,96,3",
                     help="tuning of the forward and recompute passes of the 16-shot gradient, in the "
-                         "form of --batch-tuning (the adjoint always runs the tiled kernel)")
+                         "form of --batch-tuning (the adjoint always runs the tiled kernel; default: column "
+                         "sweep, 128-column strips, 96-row segments, time block 3, the fastest measured; "
+                         "'' = tiled)")
     ap.add_argument("--batched-grad-tuning", type=str, default="s256,160,3",
                     help="the same for the full-density batched gradient (default: column sweep, 256-column "
                          "strips, 160-row segments, time block 3, the fastest measured; '' = tiled)")
@@ -301,7 +303,8 @@ def gradient_rate(v, fwd_rate, tuning=None):
     sgwave.sg_check_finite(grad, ws)
     return {"workload": "forward with checkpoints + adjoint-state gradient, 16 shots on the 620x1001 "
                         "slice, nt 10000, checkpoints every 100 levels (segment recompute)",
-            "tuning": plan.get_tuning(nshot),
+            "tuning": {"forward_and_recompute": tuning or "tiled 128x64, time block 3",
+                       "adjoint": "tiled 128x64, time block 3"},
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
             "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 

@@ -258,9 +258,11 @@ __device__ __forceinline__ void sweep_body(const SliceDesc &s, const TileArgs &t
     };
 
     // steps j0 .. j1-1: guard rows outside [-4, Nz+4) read as the clamped
-    // guard row; the last step computes level n+TB at row zs1-1; the rings
-    // were zeroed before the first step's barrier
-    const int nsteps = zs1 + 4 * TB - j0;
+    // guard row; the last step computes level n+TB at row zs1-1, or later the
+    // last receiver sample (a receiver on the segment's last two rows is read
+    // 6 steps after its rows of level n+TB-1 are computed); the rings were
+    // zeroed before the first step's barrier
+    const int nsteps = max(zs1 + 4 * TB, rec_j1 + 1) - j0;
     const int j1 = j0 + (nsteps + kQ - 1) / kQ * kQ;
     for (int j = j0; j < j1; j += kQ) {
         step(std::integral_constant<int, 0>{}, j);

@@ -92,11 +92,14 @@ def test_uneven_slices_batched_full_length_against_oracle():
         assert e <= TOL
 
 
-def test_full_density_batched_gradient_against_stored_oracle_gradients():
+@pytest.mark.parametrize("tuning", [None, dict(variant=3, tile_x=256, tile_z=160, time_block=3)],
+                         ids=["tiled", "sweep-s256z160b3"])
+def test_full_density_batched_gradient_against_stored_oracle_gradients(tuning):
     """Two slices of the full-density batched-gradient workload (510 x 888
     with 4 shots including both edge shots, 593 x 973 with 2), 10000 levels,
     checkpoints every 100, two shots per slice per wave, through
-    sg_batch_adjoint_gradient.  The GPU forms each residual from its own FP32
+    sg_batch_adjoint_gradient: with the default tiling, and on the column
+    sweep (forward, recompute and adjoint) as the benchmark runs it.  The GPU forms each residual from its own FP32
     gathers on the true and start models; the reference gradients and misfits
     are the FP64 oracle's."""
     import torch
@@ -120,7 +123,7 @@ def test_full_density_batched_gradient_against_stored_oracle_gradients():
         misfits.append(0.5 * float((resid.double() ** 2).sum()))
         items.append((plan, vp, shots, resid, torch.full_like(vp, float("nan"))))
     ws = torch.empty(sgwave.sg_batch_grad_workspace_size(items, ckpt, 2), dtype=torch.uint8, device="cuda")
-    sgwave.sg_batch_adjoint_gradient(items, ws, ckpt, 2)
+    sgwave.sg_batch_adjoint_gradient(items, ws, ckpt, 2, tuning=tuning)
     torch.cuda.synchronize()
     for i, it in enumerate(items):
         e_m = abs(misfits[i] - float(ref["misfit%d" % i])) / float(ref["misfit%d" % i])

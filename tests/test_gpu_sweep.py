@@ -78,7 +78,8 @@ def test_sweep_equals_tiled_and_oracle(tuning, top):
     """A ragged field slice (91 x 301 at 10 m, 12-cell sponge), three shots:
     one on row 1, one off-grid at 23.4 m depth, one off-grid at 503.3 m;
     receivers on row 1 at every column plus off-grid ones from 17.5 m to 555.5
-    m depth and one on the last row; snapshots every 37 levels."""
+    m depth, one on the last row and a vertical array with a receiver in every
+    row (base rows on every segment's last rows); snapshots every 37 levels."""
     nz, nx, h, nt = 91, 301, 10.0, 260
     g = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=8e-4, nt=nt, nbl=12, vmax_hint=4500.0, top=top,
                  snap_every=37, snap_count=7)
@@ -86,7 +87,8 @@ def test_sweep_equals_tiled_and_oracle(tuning, top):
     src = np.array([[10.0, 400.0], [23.4, 1513.7], [503.3, 2907.0]])
     rec = np.concatenate([synth.surface_receivers(nx, h),
                           np.array([[17.5, 55.5], [41.0, 1777.7], [17.5, 2996.0], [0.0, 1200.0],
-                                    [400.0, 1500.0], [555.5, 2222.2], [899.0, 640.0]])])
+                                    [400.0, 1500.0], [555.5, 2222.2], [899.0, 640.0]]),
+                          np.stack([np.arange(nz - 1) * 10.0 + 2.5, np.full(nz - 1, 1733.3)], 1)])
     wl = np.stack([oracle.ricker(14.0 + 3 * k, g.dt, nt) for k in range(3)])
     check(g, v, src, rec, wl, tuning)
 
@@ -138,24 +140,50 @@ def test_sweep_batched_uneven_slices(tuning):
                 assert rel_l2(sa[k, j], os_[k, j]) <= TOL
 
 
+def _receivers(layout, nx):
+    """surface: every column at 10 m; vertical: off-grid ones plus a column
+    of eight receivers (more nodes in one column than a thread keeps);
+    dense: every column at three off-grid depths (more nodes per strip than
+    the adjoint sums in LDS)."""
+    surf = synth.surface_receivers(nx, 10.0)
+    if layout == "surface":
+        return surf
+    if layout == "vertical":
+        col = np.stack([np.arange(8) * 31.0 + 15.0, np.full(8, 733.0)], 1)
+        odd = np.array([[17.5, 55.5], [41.0, 1177.7], [0.0, 120.0], [555.5, 222.2], [689.0, 640.0]])
+        return np.concatenate([surf[::3], col, odd])
+    x = np.arange(nx - 1) * 10.0 + 3.3
+    return np.concatenate([np.stack([np.full(nx - 1, d), x], 1) for d in (12.5, 27.5, 44.0)])
+
+
 @pytest.mark.parametrize("tuning", [dict(variant=3, tile_x=128, time_block=4),
-                                    dict(variant=3, tile_x=256, tile_z=24, time_block=3)], ids=["s128b4", "s256z24b3"])
-def test_gradient_with_sweep_forward_and_recompute(tuning):
+                                    dict(variant=3, tile_x=256, tile_z=24, time_block=3),
+                                    dict(variant=3, tile_x=128, tile_z=8, time_block=6)],
+                         ids=["s128b4", "s256z24b3", "s128z8b6"])
+@pytest.mark.parametrize("layout,top", [("surface", sgwave.SG_TOP_FREE), ("vertical", sgwave.SG_TOP_FREE),
+                                        ("dense", sgwave.SG_TOP_ABSORBING), ("surface", sgwave.SG_TOP_ABSORBING),
+                                        ("dense", sgwave.SG_TOP_FREE)],
+                         ids=["surface", "vertical", "dense-absorbing", "surface-absorbing", "dense-free"])
+def test_gradient_with_sweep_forward_and_recompute(tuning, layout, top):
     """Forward with checkpoints and the segment recompute on the column sweep,
     the adjoint on the tiled kernel: gathers and gradient equal the all-tiled
-    gradient calls bit for bit (same ring values, same adjoint), and the
-    oracle's gradient to 1e-4."""
+    gradient calls bit for bit (same ring values, same adjoint) and the
+    oracle's gradient to 1e-4; the batched form (shot waves) equals the
+    all-tiled batched form bit for bit.  Receiver layouts: a surface line,
+    receivers at many depths incl. a column of eight, three dense off-grid
+    lines; both tops."""
     import torch
     nz, nx, nt, ckpt = 70, 150, 260, 29
-    g = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=8e-4, nt=nt, nbl=12, vmax_hint=4500.0, rec_every=2)
+    g = Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=8e-4, nt=nt, nbl=12, vmax_hint=4500.0, rec_every=2, top=top)
     v = synth.field_slice(31, nz, nx)
     src = np.array([[10.0, 300.0], [37.5, 1111.0]])
-    rec = synth.surface_receivers(nx, 10.0)
+    rec = _receivers(layout, nx)
     wl = np.stack([oracle.ricker(16.0, g.dt, nt), oracle.ricker(19.0, g.dt, nt)])
     w = torch.from_numpy(wl.astype(np.float32)).cuda()
     vp = torch.from_numpy(v).cuda()
     rng = np.random.default_rng(5)
-    resid_np = rng.standard_normal((2, g.nrow, nx)).astype(np.float32)
+    nrec = len(rec)
+    resid_np = rng.standard_normal((2, g.nrow, nrec)).astype(np.float32)
     resid = torch.from_numpy(resid_np).cuda()
     out = {}
     for name, tn in (("sweep", tuning), ("tiled", None)):
@@ -163,19 +191,22 @@ def test_gradient_with_sweep_forward_and_recompute(tuning):
         if tn:
             plan.set_tuning(**tn)
         sh = Shots(src, rec, w)
-        ws = torch.empty(sgwave.sg_grad_workspace_size(plan, 2, nx, ckpt), dtype=torch.uint8, device="cuda")
-        gathers = torch.empty((2, g.nrow, nx), device="cuda")
+        ws = torch.empty(sgwave.sg_grad_workspace_size(plan, 2, nrec, ckpt), dtype=torch.uint8, device="cuda")
+        gathers = torch.empty((2, g.nrow, nrec), device="cuda")
         grad = torch.empty_like(vp)
         sgwave.sg_forward_ckpt(plan, vp, sh, ckpt, gathers, ws)
         sgwave.sg_adjoint_gradient(plan, vp, sh, ckpt, resid, grad, ws)
         torch.cuda.synchronize()
         out[name] = (gathers.cpu().numpy(), grad.cpu().numpy())
     assert np.array_equal(out["sweep"][0], out["tiled"][0])
-    assert np.array_equal(out["sweep"][1], out["tiled"][1])
-    og = oracle.Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=g.dt, nt=nt, nbl=12)
+    og = oracle.Geometry(nz=nz, nx=nx, dz=10.0, dx=10.0, dt=g.dt, nt=nt, nbl=12,
+                         top_free=top == sgwave.SG_TOP_FREE)
     ref = oracle.gradient(og, v.astype(np.float64), src, wl, rec, resid_np.astype(np.float64), rec_every=2)
-    assert rel_l2(out["sweep"][1], ref) <= TOL
-    # batched form: the sweep tuning for the forward and recompute, in shot waves
+    e = rel_l2(out["sweep"][1], ref)
+    print("%s %s: gradient vs oracle %.2e" % (layout, tuning, e), flush=True)
+    assert np.array_equal(out["sweep"][1], out["tiled"][1])
+    assert e <= TOL
+    # batched form, one shot per wave
     items_out = []
     for tn in (tuning, None):
         plan = Plan(g)
