@@ -189,6 +189,10 @@ hipError_t launch_copy(float *dst, int64_t dst_shot, const float *src, int64_t s
                        hipStream_t st);
 // grad[iz][ix] (+)= 2 / (dt^2 v^3) * sum over shots and over the padded cells
 // whose velocity is copied from (iz, ix) of hsum
+// hsum += the adjoint launches' FP32 partial sums kept in ring slots first,
+// first - step, ... (nslot slots), in that order, for every shot of s.
+hipError_t launch_fold_partials(const SliceDesc &s, double *hsum, const float *ring, int64_t ring_shot, int first,
+                                int step, int nslot, hipStream_t st);
 hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const double *hsum,
                                 int64_t shot_stride, float dt, float *grad, hipStream_t st, bool accumulate = false);
 // Records level n held in frame `slot` of every shot: gather row (what & 1)

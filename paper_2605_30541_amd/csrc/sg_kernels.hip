@@ -259,7 +259,11 @@ struct TileShape {
 //             nodes of the new level; alongside h += mu^{k+1} D^k for k <= nt-2,
 //             D^k read from the ring (the velocity gradient is 2 / (dt^2 v^3) h:
 //             the damping terms of the exact derivative cancel because eta does
-//             not depend on v).
+//             not depend on v).  The launch's FP32 partial sum of h over its
+//             levels is stored in the ring slot of its first level t.n (D^{t.n}
+//             is dead once read; each output cell's slot is read and written by
+//             its own thread only), and k_fold_partials adds the partials of a
+//             segment to the FP64 accumulator in launch order.
 enum { kFwd = 0, kRing = 1, kAdj = 2 };
 
 template <int K, int NWX, int NWZ, int MODE, bool ISO, bool STREAM = false>
@@ -485,12 +489,11 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     }
     // adjoint: the second time difference D^k of the forward field for the
     // imaging term (read one sub-step ahead), and the partial sums of h.  Only
-    // the output rows are read (in bounds at the clamped column); only the
-    // output columns' sums are stored.
+    // the output cells are read and their sums stored.
     float pn[ADJ ? K : 1], hp[ADJ ? K : 1];
     const float *ringb = ADJ ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
     auto ring_level = [&](int L, float(&dst)[ADJ ? K : 1]) {
-        const bool h = L >= t.ring_lo && L <= t.ring_hi;
+        const bool h = xout && L >= t.ring_lo && L <= t.ring_hi;
         const float *rl = ringb + (int64_t)(h ? L - t.ring_lo : 0) * s.frame;
 #pragma unroll
         for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? gload_at(rl, rowb(k) + xc4) : 0.f;
@@ -664,17 +667,9 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
     // the newest level is in A after an even number of sub-steps, else in B
     const bool odd = t.nsteps & 1;
 
-    // ---- write the output tile: the last two levels; the adjoint adds this
-    // launch's partial imaging sums to the FP64 accumulator h of its cells
-    // (loads first, all in flight together)
-    double hsv[ADJ ? K : 1];
-    double *hs = ADJ ? t.hsum + (int64_t)shot * s.frame : nullptr;
-    // byte offset of a double in the accumulator: twice the float offset
-    if (ADJ) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            hsv[k] = (k >= k_lo && k < k_hi) ? gload_at(hs, 2u * (rowb(k) + xc4)) : 0.0;
-    }
+    // ---- write the output tile: the last two levels; the adjoint stores this
+    // launch's partial imaging sums in the ring slot of level t.n
+    float *hpart = ADJ ? t.ring + (int64_t)shot * t.ring_shot + (int64_t)(t.n - t.ring_lo) * s.frame : nullptr;
     // STREAM (a launch whose workgroups all run at once): the levels go out
     // with streaming (non-temporal) stores.  The next launch starts with cold
     // caches anyway, and the end of this one then has little dirty data left
@@ -692,7 +687,7 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
                     gstore_at(out_cur, ob, vc);
                     gstore_at(out_prev, ob, vp);
                 }
-                if (ADJ) gstore_at(hs, 2u * ob, hsv[k] + (double)hp[k]);
+                if (ADJ) gstore_nt_at(hpart, ob, hp[k]);
             }
         }
     }
@@ -777,6 +772,26 @@ __global__ void __launch_bounds__(256) k_fold_gradient(SliceDesc s, const float 
     const double v = vp[q];
     const float g = (float)(2.0 / ((double)dt * dt * v * v * v) * acc);
     grad[q] = accumulate ? grad[q] + g : g;
+}
+
+// h += the FP32 partial sums of a segment's adjoint launches, in launch order
+// (slots first, first - step, ...; nslot of them), per padded cell of every
+// shot: the same FP64 additions, in the same order, as adding each launch's
+// partial to h when the launch ends.
+__global__ void __launch_bounds__(256) k_fold_partials(SliceDesc s, double *hsum, const float *ring, int64_t ring_shot,
+                                                       int first, int step, int nslot)
+{
+    const int64_t per = (int64_t)s.Nz * s.Nx;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= per) return;
+    const int shot = blockIdx.y;
+    const int Z = (int)(q / s.Nx), X = (int)(q - (int64_t)Z * s.Nx);
+    const int64_t i = (int64_t)(Z + kGuard) * s.pitch + X + kGuard;
+    double *h = hsum + (int64_t)shot * s.frame + i;
+    const float *r = ring + (int64_t)shot * ring_shot + i;
+    double acc = *h;
+    for (int j = 0; j < nslot; ++j) acc += (double)r[(int64_t)(first - j * step) * s.frame];
+    *h = acc;
 }
 
 __global__ void __launch_bounds__(256) k_count_nonfinite(const float *x, size_t n, unsigned int *count)
@@ -966,6 +981,16 @@ hipError_t launch_fold_gradient(const SliceDesc &s, const float *vp, const doubl
     const unsigned blocks = (unsigned)((s.nz * s.nx + 255) / 256);
     hipLaunchKernelGGL(k_fold_gradient, dim3(blocks), dim3(256), 0, st, s, vp, hsum, shot_stride, dt, grad,
                        accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_partials(const SliceDesc &s, double *hsum, const float *ring, int64_t ring_shot, int first,
+                                int step, int nslot, hipStream_t st)
+{
+    if (nslot <= 0) return hipSuccess;
+    const int64_t per = (int64_t)s.Nz * s.Nx;
+    hipLaunchKernelGGL(k_fold_partials, dim3((unsigned)((per + 255) / 256), (unsigned)s.nshot), dim3(256), 0, st, s,
+                       hsum, ring, ring_shot, first, step, nslot);
     return hipGetLastError();
 }
 

@@ -1372,8 +1372,11 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
                              [](int, int) { return SG_OK; }, st);
             if (rc != SG_OK) return rc;
         }
-        // adjoint steps k = hi .. lo (mu^k from mu^{k+1}, mu^{k+2}) with imaging
+        // adjoint steps k = hi .. lo (mu^k from mu^{k+1}, mu^{k+2}) with imaging;
+        // each launch leaves its partial sums in the ring slot of its first level
+        int nlaunch = 0;
         for (int k0 = hi; k0 >= lo;) {
+            ++nlaunch;
             const int nsteps = std::min(c.t.time_block, k0 - lo + 1);
             sg::TileArgs a = tile_args(c.T, mu, k0, nsteps, mpair);
             a.ring = ring;
@@ -1388,6 +1391,7 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
             mpair ^= 1;
             k0 -= nsteps;
         }
+        SG_HIP(sg::launch_fold_partials(s, hsum, ring, ring_shot, hi - lo, c.t.time_block, nlaunch, st));
     }
     SG_HIP(sg::launch_fold_gradient(s, vp, hsum, F, (float)p->g.dt, grad, st));
     return SG_OK;
@@ -1848,13 +1852,18 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
                 fp ^= 1;
                 n += k;
             }
+            int nlaunch = 0;
             for (int k0 = hi; k0 >= lo;) {
+                ++nlaunch;
                 const int ns = std::min(t.time_block, k0 - lo + 1);
                 SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start_adj, k0, ns, mpair, config, iso, lo, last - 1,
                                                       st));
                 mpair ^= 1;
                 k0 -= ns;
             }
+            for (int q = 0; q < na; ++q)
+                SG_HIP(sg::launch_fold_partials(hb_adj[q].s, hb_adj[q].t.hsum, hb_adj[q].t.ring, hb_adj[q].t.ring_shot,
+                                                hi - lo, t.time_block, nlaunch, st));
         }
         for (int q = 0; q < na; ++q) {
             const sg_batch_grad_item &it = items[act[q]];
