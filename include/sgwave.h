@@ -301,7 +301,11 @@ sg_status sg_forward_noalloc(sg_plan *p, const float *vp, const sg_shots *shots,
  *   resid     device [nshot][ceil(nt/rec_every)][nrec] float, dJ/dd for any
  *             misfit J (for J = 1/2 |d - d_obs|^2 this is d - d_obs)
  *   grad      device [nz][nx] float, overwritten with dJ/dv summed over shots
- * Both calls must get the same plan, vp, shots, ckpt_every and ws.
+ * Both calls must get the same plan, vp, shots, ckpt_every and ws.  The
+ * gradient call also runs work on a second stream of the plan (created on
+ * first use, default priority) that it forks from and joins back into
+ * `stream` with events, so work enqueued on `stream` after the call sees the
+ * finished gradient; calls on one plan must not overlap.
  */
 sg_status sg_grad_workspace_size(const sg_plan *p, int32_t nshot, int32_t nrec,
                                  int32_t ckpt_every, size_t *bytes);
@@ -328,8 +332,9 @@ typedef struct {
 sg_status sg_batch_workspace_size(const sg_batch_item *items, int32_t nitems, size_t *bytes);
 
 /*
- * Runs every item as sg_forward would (same outputs), on the tiled kernel
- * with one tuning for the whole batch (NULL = the first item's plan tuning).
+ * Runs every item as sg_forward would (same outputs), on the tiled kernel or
+ * the column sweep, with one tuning for the whole batch (NULL = the first
+ * item's plan tuning).
  * Each time block of the whole batch is one launch over a flattened list of
  * (item, shot, tile) work; the sequence of launches is captured once into a
  * hipGraph per (workspace, batch shape) and replayed on later calls, unless
@@ -362,6 +367,10 @@ sg_status sg_batch_autotune(const sg_batch_item *items, int32_t nitems, int32_t 
  * adjoint), and adds its shots' contribution to the item's gradient.
  *   resid  device [nshot][ceil(nt/rec_every)][nrec] float, dJ/dd of the item
  *   grad   device [nz][nx] float, overwritten with dJ/dv summed over the item's shots
+ * A column-sweep tuning (variant 3) runs the forward and the recompute on the
+ * sweep; the adjoint always runs the tiled kernel.  Like sg_adjoint_gradient
+ * the call forks work onto the first item's plan's second stream and joins it
+ * back into `stream`.
  */
 typedef struct {
     sg_plan *plan;

@@ -790,7 +790,17 @@ __global__ void __launch_bounds__(256) k_fold_partials(SliceDesc s, double *hsum
     double *h = hsum + (int64_t)shot * s.frame + i;
     const float *r = ring + (int64_t)shot * ring_shot + i;
     double acc = *h;
-    for (int j = 0; j < nslot; ++j) acc += (double)r[(int64_t)(first - j * step) * s.frame];
+    // eight slots' loads in flight at a time, added in order
+    constexpr int kChunk = 8;
+    for (int j0 = 0; j0 < nslot; j0 += kChunk) {
+        float v[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+            v[c] = j0 + c < nslot ? r[(int64_t)(first - (j0 + c) * step) * s.frame] : 0.f;
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+            if (j0 + c < nslot) acc += (double)v[c];
+    }
     *h = acc;
 }
 

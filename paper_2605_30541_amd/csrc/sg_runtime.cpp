@@ -99,6 +99,10 @@ struct sg_plan {
     std::vector<hipEvent_t> prof_ev;
     int prof_used = 0;       // event pairs recorded by the last call
     int prof_launches = 0;   // time-stepping launches they bracket
+    // gradient calls: a second stream (default priority) on which a segment's
+    // partial sums are folded while the next segment runs, and its events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_seg = nullptr, ev_fold[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -108,14 +112,15 @@ namespace {
 // plan's pinned staging buffer in one copy.  With ckpt > 0 the layout also
 // holds the gradient state: checkpoints (levels jC-1, jC of every shot every
 // C = ckpt levels), the ring of one segment's recomputed second time
-// differences D^n (C levels), the adjoint field pairs, the FP64 accumulator
-// of the imaging sum,
+// differences D^n (C levels; two of them, used by alternate segments, so a
+// segment's partial imaging sums can be folded while the next segment runs),
+// the adjoint field pairs, the FP64 accumulator of the imaging sum,
 // and the residual-injection tables.
 struct Layout {
     size_t v2, w, a2, gx, gz, src_off, src_iz, src_ix, src_w, rec_off, rec_iz, rec_ix, rec_w, tile_rec, rec_list;
     size_t inj_tile, inj_lds, inj_iz, inj_ix, inj_pstart, inj_rid, inj_w;
     size_t tables_end, fields;
-    size_t ckpt, ring, mu, hsum, total;
+    size_t ckpt, ring, ring2, mu, hsum, total;
     int ckpt_every, nseg, ring_levels;
     int64_t inj_cap;   // capacity (cells and pairs) of the injection tables
 };
@@ -174,6 +179,7 @@ Layout layout_of(const sg_plan *p, int nshot, int nrec, int ckpt = 0)
         L.ring_levels = ckpt;                     // D^n of one segment
         L.ckpt = take((size_t)nshot * L.nseg * 2 * fr);
         L.ring = take((size_t)nshot * L.ring_levels * fr);
+        L.ring2 = take((size_t)nshot * L.ring_levels * fr);   // segments alternate between the two rings
         L.mu = take((size_t)nshot * sg::kFramesPerShot * fr);
         L.hsum = take((size_t)nshot * 2 * fr);     // doubles
     }
@@ -524,6 +530,17 @@ sg_status upload_tables(sg_plan *p, const Layout &L, char *ws, const sg_shots *s
     SG_HIP(hipMemcpyAsync(ws + L.gx, h, bytes, hipMemcpyHostToDevice, st));
     SG_HIP(hipEventRecord(slot.done, st));
     slot.pending = true;
+    return SG_OK;
+}
+
+// The plan's side stream and events for the gradient's folds (created on
+// first use; default priority, no blocking of the null stream).
+sg_status side_stream(sg_plan *p)
+{
+    if (!p->side) SG_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    if (!p->ev_seg) SG_HIP(hipEventCreateWithFlags(&p->ev_seg, hipEventDisableTiming));
+    for (hipEvent_t &e : p->ev_fold)
+        if (!e) SG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return SG_OK;
 }
 
@@ -1048,6 +1065,12 @@ sg_status sg_plan_destroy(sg_plan *p)
         if (sl.buf) (void)hipHostFree(sl.buf);
     }
     for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+    if (p->side) {
+        (void)hipStreamSynchronize(p->side);
+        (void)hipStreamDestroy(p->side);
+    }
+    for (hipEvent_t e : {p->ev_seg, p->ev_fold[0], p->ev_fold[1]})
+        if (e) (void)hipEventDestroy(e);
     delete p;
     return SG_OK;
 }
@@ -1343,7 +1366,8 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
     SG_HIP(sg::launch_prepare(s, vp, (float)(p->g.dt * p->g.dt), st));
     const int nshot = shots->nshot, nt = p->g.nt;
     const int64_t F = p->frame, fshot = (int64_t)sg::kFramesPerShot * F;
-    float *ck = (float *)(w + c.L.ckpt), *ring = (float *)(w + c.L.ring), *mu = (float *)(w + c.L.mu);
+    float *ck = (float *)(w + c.L.ckpt), *rings[2] = {(float *)(w + c.L.ring), (float *)(w + c.L.ring2)};
+    float *mu = (float *)(w + c.L.mu);
     double *hsum = (double *)(w + c.L.hsum);
     const int64_t ck_shot = (int64_t)c.L.nseg * 2 * F, ring_shot = (int64_t)c.L.ring_levels * F;
     SG_HIP(sg::launch_zero(mu, (size_t)nshot * fshot, st));
@@ -1358,10 +1382,15 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
     inj.rid = (const int32_t *)(w + c.L.inj_rid);
     inj.w = (const float *)(w + c.L.inj_w);
 
+    if ((rc = side_stream(p)) != SG_OK) return rc;
+    bool folding[2] = {false, false};
     int mpair = 0;   // adjoint pair: frame 0 = mu^{k+2}, frame 1 = mu^{k+1}
     p->prof_used = 0;
     for (int j = c.L.nseg - 1; j >= 0; --j) {
         const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
+        // this segment's ring; the fold of the segment that used it last must be done
+        float *ring = rings[j & 1];
+        if (folding[j & 1]) SG_HIP(hipStreamWaitEvent(st, p->ev_fold[j & 1], 0));
         // recompute levels lo+1 .. last from checkpoint j (levels lo-1, lo),
         // storing D^lo .. D^{last-1} in the ring
         const float *ckj = ck + (int64_t)j * 2 * F;
@@ -1391,8 +1420,16 @@ sg_status sg_adjoint_gradient(sg_plan *p, const float *vp, const sg_shots *shots
             mpair ^= 1;
             k0 -= nsteps;
         }
-        SG_HIP(sg::launch_fold_partials(s, hsum, ring, ring_shot, hi - lo, c.t.time_block, nlaunch, st));
+        // the fold runs on the side stream (in segment order) while the next
+        // segment recomputes into the other ring
+        SG_HIP(hipEventRecord(p->ev_seg, st));
+        SG_HIP(hipStreamWaitEvent(p->side, p->ev_seg, 0));
+        SG_HIP(sg::launch_fold_partials(s, hsum, ring, ring_shot, hi - lo, c.t.time_block, nlaunch, p->side));
+        SG_HIP(hipEventRecord(p->ev_fold[j & 1], p->side));
+        folding[j & 1] = true;
     }
+    // every fold is done (they run in order on the side stream)
+    SG_HIP(hipStreamWaitEvent(st, p->ev_fold[0], 0));
     SG_HIP(sg::launch_fold_gradient(s, vp, hsum, F, (float)p->g.dt, grad, st));
     return SG_OK;
 }
@@ -1656,7 +1693,7 @@ sg_status sg_batch_grad_workspace_size(const sg_batch_grad_item *items, int32_t 
         total += align_up(layout_of(items[i].plan, S, items[i].shots->nrec,
                                     ckpt_spacing(items[i].plan, ckpt_every)).total, 256);
     }
-    total += 2 * align_up((size_t)nitems * sizeof(sg::BatchItem), 256);
+    total += 4 * align_up((size_t)nitems * sizeof(sg::BatchItem), 256);   // forward / adjoint x two rings
     *bytes = total;
     return SG_OK;
 }
@@ -1779,15 +1816,30 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
         const int na = (int)act.size();
         // two device copies of the item table (forward fields, adjoint fields),
         // both uploaded once per wave in one copy
+        // four device copies of the item table: forward and adjoint fields,
+        // each with the first and with the second ring (segments alternate),
+        // uploaded once per wave in one copy
         const size_t tbl = align_up((size_t)nitems * sizeof(sg::BatchItem), 256);
-        sg::BatchItem *dev_fwd = (sg::BatchItem *)(w + need - 2 * tbl);
-        sg::BatchItem *dev_adj = (sg::BatchItem *)(w + need - tbl);
-        {
-            std::vector<char> both(2 * tbl, 0);
-            std::memcpy(both.data(), hb.data(), hb.size() * sizeof(sg::BatchItem));
-            std::memcpy(both.data() + tbl, hb_adj.data(), hb_adj.size() * sizeof(sg::BatchItem));
-            if ((rc = stage_upload(dev_fwd, both.data(), 2 * tbl, st)) != SG_OK) return rc;
+        sg::BatchItem *dev_fwd_r[2], *dev_adj_r[2];
+        dev_fwd_r[0] = (sg::BatchItem *)(w + need - 4 * tbl);
+        dev_adj_r[0] = (sg::BatchItem *)(w + need - 3 * tbl);
+        dev_fwd_r[1] = (sg::BatchItem *)(w + need - 2 * tbl);
+        dev_adj_r[1] = (sg::BatchItem *)(w + need - tbl);
+        std::vector<sg::BatchItem> hb2 = hb, hb_adj2 = hb_adj;
+        for (int q = 0; q < na; ++q) {
+            float *r2 = (float *)((char *)hb[q].t.ring - Ls[q].ring + Ls[q].ring2);
+            hb2[q].t.ring = r2;
+            hb_adj2[q].t.ring = r2;
         }
+        {
+            std::vector<char> all(4 * tbl, 0);
+            std::memcpy(all.data(), hb.data(), hb.size() * sizeof(sg::BatchItem));
+            std::memcpy(all.data() + tbl, hb_adj.data(), hb_adj.size() * sizeof(sg::BatchItem));
+            std::memcpy(all.data() + 2 * tbl, hb2.data(), hb2.size() * sizeof(sg::BatchItem));
+            std::memcpy(all.data() + 3 * tbl, hb_adj2.data(), hb_adj2.size() * sizeof(sg::BatchItem));
+            if ((rc = stage_upload(dev_fwd_r[0], all.data(), 4 * tbl, st)) != SG_OK) return rc;
+        }
+        sg::BatchItem *const dev_fwd = dev_fwd_r[0];
         auto copy_items = [&](auto dst_of, auto src_of, int64_t n) -> sg_status {
             for (int q = 0; q < na; ++q) {
                 const int64_t F = items[act[q]].plan->frame;
@@ -1826,11 +1878,18 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
                 if (rc != SG_OK) return rc;
             }
         }
-        // segments backwards: recompute into the ring, then the adjoint
+        // segments backwards: recompute into the segment's ring, then the
+        // adjoint; its partial sums are folded on the side stream while the
+        // next segment runs on the other ring
+        sg_plan *p0 = items[act[0]].plan;
+        if ((rc = side_stream(p0)) != SG_OK) return rc;
+        bool folding[2] = {false, false};
         int mpair = 0;
         const int nseg = Ls[0].nseg;
         for (int j = nseg - 1; j >= 0; --j) {
             const int lo = j * C, hi = std::min((j + 1) * C - 1, nt - 1), last = std::min(hi + 1, nt - 1);
+            const int rb = j & 1;
+            if (folding[rb]) SG_HIP(hipStreamWaitEvent(st, p0->ev_fold[rb], 0));
             rc = copy_items(
                 [&](int q, int64_t F, float **d, int64_t *ds) {
                     *d = hb[q].s.fields;
@@ -1846,9 +1905,9 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             for (int n = lo; n < last;) {
                 const int k = std::min(tf.time_block, last - n);
                 if (sweep_fwd)
-                    SG_HIP(sg::launch_sweep_batch(dev_fwd, na, start, n, k, fp, Tf[0].sweep_nw, st, true, lo));
+                    SG_HIP(sg::launch_sweep_batch(dev_fwd_r[rb], na, start, n, k, fp, Tf[0].sweep_nw, st, true, lo));
                 else
-                    SG_HIP(sg::launch_ring_tiled_batch(dev_fwd, na, start, n, k, fp, config, iso, lo, st));
+                    SG_HIP(sg::launch_ring_tiled_batch(dev_fwd_r[rb], na, start, n, k, fp, config, iso, lo, st));
                 fp ^= 1;
                 n += k;
             }
@@ -1856,15 +1915,23 @@ sg_status sg_batch_adjoint_gradient(const sg_batch_grad_item *items, int32_t nit
             for (int k0 = hi; k0 >= lo;) {
                 ++nlaunch;
                 const int ns = std::min(t.time_block, k0 - lo + 1);
-                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj, na, start_adj, k0, ns, mpair, config, iso, lo, last - 1,
-                                                      st));
+                SG_HIP(sg::launch_adjoint_tiled_batch(dev_adj_r[rb], na, start_adj, k0, ns, mpair, config, iso, lo,
+                                                      last - 1, st));
                 mpair ^= 1;
                 k0 -= ns;
             }
-            for (int q = 0; q < na; ++q)
-                SG_HIP(sg::launch_fold_partials(hb_adj[q].s, hb_adj[q].t.hsum, hb_adj[q].t.ring, hb_adj[q].t.ring_shot,
-                                                hi - lo, t.time_block, nlaunch, st));
+            SG_HIP(hipEventRecord(p0->ev_seg, st));
+            SG_HIP(hipStreamWaitEvent(p0->side, p0->ev_seg, 0));
+            for (int q = 0; q < na; ++q) {
+                const sg::BatchItem &ba = rb ? hb_adj2[q] : hb_adj[q];
+                SG_HIP(sg::launch_fold_partials(ba.s, ba.t.hsum, ba.t.ring, ba.t.ring_shot, hi - lo, t.time_block,
+                                                nlaunch, p0->side));
+            }
+            SG_HIP(hipEventRecord(p0->ev_fold[rb], p0->side));
+            folding[rb] = true;
         }
+        // every fold of this wave is done (in order on the side stream)
+        SG_HIP(hipStreamWaitEvent(st, p0->ev_fold[0], 0));
         for (int q = 0; q < na; ++q) {
             const sg_batch_grad_item &it = items[act[q]];
             SG_HIP(sg::launch_fold_gradient(hb[q].s, it.vp, hb[q].t.hsum, it.plan->frame,
