@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--batched-grad-tuning", type=str, default="s256,160,3",
                     help="the same for the full-density batched gradient (default: column sweep, 256-column "
                          "strips, 160-row segments, time block 3, the fastest measured; '' = tiled)")
+    ap.add_argument("--field-tuning", type=str, default="",
+                    help="tile_x,tile_z,time_block for the single field shot instead of the autotuner "
+                         "(profiling runs: keeps the autotuner's trial launches out of the counters)")
+    ap.add_argument("--field-steps", type=int, default=20, help="timed repetitions of the single field shot")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -217,10 +221,11 @@ def cpu_baseline(cases, nslices):
                       "(%.1f s wall)" % (nslices, cases[0][0].nt, sec)}
 
 
-def field_shot_rate(steps=20):
+def field_shot_rate(steps=20, tuning=None):
     """The field-scale single shot: a 620 x 1001 slice (seed 42) at 10 m with a
     40-cell sponge, dt 0.8 ms, nt 10000, a 12 Hz Ricker at (10 m, 5000 m), 1001
-    receivers, 63 snapshots every 100 levels; single-call path, autotuned."""
+    receivers, 63 snapshots every 100 levels; single-call path, autotuned
+    unless a tuning is given."""
     import numpy as np
     import torch
     from paper_2605_30541_amd import sgwave, synth
@@ -236,7 +241,10 @@ def field_shot_rate(steps=20):
     snaps = torch.empty((1, geom.snap_count, nz, nx), dtype=torch.float32, device="cuda")
     ws = torch.empty(sgwave.sg_forward_workspace_size(plan, 1, nx), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    sgwave.sg_autotune(plan, vp, shots, 64, ws, stream)
+    if tuning:
+        plan.set_tuning(**tuning)
+    else:
+        sgwave.sg_autotune(plan, vp, shots, 64, ws, stream)
     tuning = plan.get_tuning(1)
 
     def step():
@@ -610,7 +618,7 @@ def main():
     if args.only not in (None, "batch"):
         # a profiling run of one sub-workload: print its record only
         if args.only == "field_shot":
-            out["field_shot"], _ = field_shot_rate()
+            out["field_shot"], _ = field_shot_rate(args.field_steps, parse_tuning(args.field_tuning))
         elif args.only == "gradient":
             from paper_2605_30541_amd import synth
             out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None, parse_tuning(args.grad_tuning))
@@ -653,7 +661,7 @@ def main():
         "cpu_baseline": None,
     }
     if args.only is None:
-        out["field_shot"], v = field_shot_rate()
+        out["field_shot"], v = field_shot_rate(args.field_steps, parse_tuning(args.field_tuning))
         log("field shot: %.1f Gpt-updates/s" % out["field_shot"]["value"])
         out["gradient"] = gradient_rate(v, value, parse_tuning(args.grad_tuning))
         log("gradient: %.1f Gpt-steps/s" % out["gradient"]["value"])
