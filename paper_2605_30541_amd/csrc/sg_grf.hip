@@ -8,8 +8,8 @@
 // moves the transformed axis to the front, so after three the layout is
 // [z][y][x] again with every axis transformed.  The 1D FFTs are radix-2
 // Cooley-Tukey in LDS (bit-reversed load, log2 L butterfly stages, twiddles
-// from sincospif); neither direction is scaled (the final normalisation
-// removes every constant factor).
+// from a per-workgroup table of sincospif values); neither direction is
+// scaled (the final normalisation removes every constant factor).
 #include "sg_internal.h"
 
 namespace sg {
@@ -30,7 +30,13 @@ __global__ void __launch_bounds__(256) k_noise_to_complex(const float *noise, fl
 __global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, int logL, int64_t nlines, float sign)
 {
     __shared__ float2 buf[kFftLds];
+    __shared__ float2 tw[kFftLds / 2];   // exp(sign i 2 pi m / L), m < L/2: stage s uses m = j 2^(logL-s)
     const int L = 1 << logL;
+    for (int m = threadIdx.x; m < L / 2; m += kFftThreads) {
+        float sn, cs;
+        sincospif(sign * (float)m / (float)(L / 2), &sn, &cs);
+        tw[m] = make_float2(cs, sn);
+    }
     const int lpw = L >= kFftLds ? 1 : kFftLds / L;            // lines per workgroup
     const int64_t line0 = (int64_t)blockIdx.x * lpw;
     const int nl = (int)min((int64_t)lpw, nlines - line0);
@@ -51,8 +57,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, int log
             const int bb = b & ((L >> 1) - 1);
             const int g = bb >> (s - 1), j = bb & (half - 1);
             const int k = (ln << logL) + (g << s) + j;
-            float sn, cs;
-            sincospif(sign * (float)j / (float)half, &sn, &cs); // exp(sign i 2 pi j / 2 half)
+            const float2 w = tw[j << (logL - s)];                   // exp(sign i 2 pi j / 2 half)
+            const float cs = w.x, sn = w.y;
             const float2 u = buf[k], v = buf[k + half];
             const float2 t = make_float2(cs * v.x - sn * v.y, cs * v.y + sn * v.x);
             buf[k] = make_float2(u.x + t.x, u.y + t.y);
@@ -95,7 +101,8 @@ __global__ void __launch_bounds__(256) k_spectral_scale(float2 *a, int Pz, int P
         const double fy = (y < (Py + 1) / 2 ? y : y - Py) / (double)Py;
         const double fx = (x < (Px + 1) / 2 ? x : x - Px) / (double)Px;
         const double kz = two_pi * fz * lz, ky = two_pi * fy * ly, kx = two_pi * fx * lx;
-        const float amp = (float)pow(1.0 + kz * kz + ky * ky + kx * kx, -half_p);
+        // the power in FP32 (hardware log2 / exp2): the field is FP32 and is normalised afterwards
+        const float amp = exp2f(-(float)half_p * log2f((float)(1.0 + kz * kz + ky * ky + kx * kx)));
         float2 v = a[i];
         a[i] = make_float2(v.x * amp, v.y * amp);
     }
