@@ -61,6 +61,9 @@ def parse():
                     help="tile_x,tile_z,time_block for the single field shot instead of the autotuner "
                          "(profiling runs: keeps the autotuner's trial launches out of the counters)")
     ap.add_argument("--field-steps", type=int, default=20, help="timed repetitions of the single field shot")
+    ap.add_argument("--grad-levels", type=int, default=10000,
+                    help="time levels of the two gradient workloads (shorter runs for counter profiles: "
+                         "the launches and their grids are those of the full run)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size "
                          "reference kernel for hardware traffic counters)")
@@ -275,14 +278,14 @@ def field_shot_rate(steps=20, tuning=None):
             "hbm_algorithmic_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}, v
 
 
-def gradient_rate(v, fwd_rate, tuning=None):
+def gradient_rate(v, fwd_rate, tuning=None, nt=10000):
     """Forward with checkpoints + adjoint gradient: 16 shots on the field
     slice (1D-smoothed start model), checkpoints every 100 levels."""
     import numpy as np
     import torch
     from paper_2605_30541_amd import sgwave, synth
     from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
-    nz, nx, h, dt, nt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 10000, 16, 100
+    nz, nx, h, dt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 16, 100
     geom = Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, nbl=40, vmax_hint=4500.0)
     plan = Plan(geom)
     if tuning:
@@ -310,7 +313,7 @@ def gradient_rate(v, fwd_rate, tuning=None):
     rate = Nz * Nx * (nt - 1) * nshot / (ms / 1e3) / 1e9
     sgwave.sg_check_finite(grad, ws)
     return {"workload": "forward with checkpoints + adjoint-state gradient, 16 shots on the 620x1001 "
-                        "slice, nt 10000, checkpoints every 100 levels (segment recompute)",
+                        "slice, nt %d, checkpoints every 100 levels (segment recompute)" % nt,
             "tuning": {"forward_and_recompute": tuning or "tiled 128x64, time block 3",
                        "adjoint": "tiled 128x64, time block 3"},
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
@@ -562,7 +565,7 @@ def builder_rate(passes=3):
             "deposit_Gvoxel_per_s": tb * ny * nx / (ms_d / 1e3) / 1e9}
 
 
-def batched_gradient_rate(fwd_rate, shots_per_wave, tuning=None):
+def batched_gradient_rate(fwd_rate, shots_per_wave, tuning=None, nt=10000):
     """4 field slices of uneven size (nz 500-620, nx 801-1001) x 100 shots
     spread evenly over the full width, nt 10000 at 0.8 ms, receivers on every
     column: forward with checkpoints every 100 levels, segment recompute and
@@ -571,7 +574,7 @@ def batched_gradient_rate(fwd_rate, shots_per_wave, tuning=None):
     import torch
     from paper_2605_30541_amd import sgwave, synth
     from paper_2605_30541_amd.sgwave import Geometry, Plan, Shots
-    dt, nt, nshot, ckpt = 8e-4, 10000, 100, 100
+    dt, nshot, ckpt = 8e-4, 100, 100
     gen = torch.Generator(device="cuda")
     gen.manual_seed(7)
     items, pts = [], 0
@@ -597,9 +600,9 @@ def batched_gradient_rate(fwd_rate, shots_per_wave, tuning=None):
     for it in items:
         sgwave.sg_check_finite(it[4], ws)
     rate = pts * (nt - 1) / (ms / 1e3) / 1e9
-    return {"workload": "4 uneven field slices (nz 500-620, nx 801-1001, 40-cell sponge) x 100 shots, nt 10000, "
+    return {"workload": "4 uneven field slices (nz 500-620, nx 801-1001, 40-cell sponge) x 100 shots, nt %d, "
                         "forward with checkpoints every 100 levels + segment recompute + adjoint, "
-                        "%d shots per slice per wave" % shots_per_wave,
+                        "%d shots per slice per wave" % (nt, shots_per_wave),
             "ms": ms, "value": rate, "unit": "Gpt-steps/s (padded points x time steps x shots)",
             "forward_tuning": tuning, "workspace_GB": ws.numel() / 1e9, "ratio_to_forward_value": rate / fwd_rate if fwd_rate else None}
 
@@ -621,10 +624,11 @@ def main():
             out["field_shot"], _ = field_shot_rate(args.field_steps, parse_tuning(args.field_tuning))
         elif args.only == "gradient":
             from paper_2605_30541_amd import synth
-            out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None, parse_tuning(args.grad_tuning))
+            out["gradient"] = gradient_rate(synth.field_slice(42, 620, 1001), None, parse_tuning(args.grad_tuning),
+                                            args.grad_levels)
         elif args.only == "batched_gradient":
             out["batched_gradient"] = batched_gradient_rate(None, args.shots_per_wave,
-                                                            parse_tuning(args.batched_grad_tuning))
+                                                            parse_tuning(args.batched_grad_tuning), args.grad_levels)
         elif args.only == "paper":
             out["paper_workload"] = paper_workload_rate(None)
         elif args.only == "residual":
@@ -663,10 +667,10 @@ def main():
     if args.only is None:
         out["field_shot"], v = field_shot_rate(args.field_steps, parse_tuning(args.field_tuning))
         log("field shot: %.1f Gpt-updates/s" % out["field_shot"]["value"])
-        out["gradient"] = gradient_rate(v, value, parse_tuning(args.grad_tuning))
+        out["gradient"] = gradient_rate(v, value, parse_tuning(args.grad_tuning), args.grad_levels)
         log("gradient: %.1f Gpt-steps/s" % out["gradient"]["value"])
         out["batched_gradient"] = batched_gradient_rate(value, args.shots_per_wave,
-                                                        parse_tuning(args.batched_grad_tuning))
+                                                        parse_tuning(args.batched_grad_tuning), args.grad_levels)
         log("batched gradient: %.1f Gpt-steps/s" % out["batched_gradient"]["value"])
         out["paper_workload"] = paper_workload_rate(value)
         log("paper-shaped batch: %.1f Gpt-updates/s" % out["paper_workload"]["value"])
