@@ -11,10 +11,13 @@
 // so the 8 weights are computed once and the column streams through registers
 // in blocks of 8 rows: one load and 8 FMAs per voxel (HBM-bound, 8 B per voxel
 // read + written).
-// Fault: one thread per voxel, the volume walked in bricks (one XCD per
-// brick).  The pull source is computed in FP64 (the frame and the angles of
-// Alg. 3); voxels outside the taper are copied, the others take 8 x 8 x 8
-// taps (8 x 8 when ny = 1) with FP32 weights and sums.
+// Fault: a workgroup per brick of 4 x 4 rows of 64 voxels, four voxels per
+// thread, the bricks dealt to the XCDs in groups.  The pull source is
+// computed in FP64 (the frame and the angles of Alg. 3); voxels outside the
+// taper are copied, the others take 8 x 8 x 8 taps (8 x 8 when ny = 1) with
+// FP32 weights and sums.  The sinc weights are evaluated through identities
+// (one sine per axis, the window as a polynomial), which makes them cheap next
+// to the 512 taps.
 #include "sg_internal.h"
 
 #include <algorithm>
@@ -31,32 +34,34 @@ constexpr float kBeta = 6.f;
 constexpr int kBrickZ = 16, kBrickY = 16, kBrickRows = kBrickZ * kBrickY;   // fault kernel
 constexpr int kDepositThreads = 64;   // one wave per workgroup; its contacts fill up to 64 KB of LDS
 
-// I0 by its power series sum_k ((x/2)^2)^k / (k!)^2; for x <= 6 the terms
-// after k = 16 are below 1e-10 of the sum.
-__device__ inline float bessel_i0(float x)
-{
-    const float q = 0.25f * x * x;
-    float term = 1.f, sum = 1.f;
-#pragma unroll
-    for (int k = 1; k <= 16; ++k) {
-        term *= q * (1.f / (float)(k * k));   // constant reciprocal: no division
-        sum += term;
-    }
-    return sum;
-}
-
 // Normalised weights of the taps floor(s)-3 .. floor(s)+4 for the fractional
-// part f = s - floor(s): tap j sits at t = f + 3 - j from the sample.
+// part f = s - floor(s): tap j sits at t = f + 3 - j from the sample and
+// weighs sinc(t) I0(beta sqrt(1 - (t/4)^2)) before normalisation.  Evaluated
+// through identities, with one sine per axis: sin(pi t) = (-1)^(3-j) sin(pi f);
+// I0(beta sqrt(u)) = sum_k (beta^2 u / 4)^k / (k!)^2, a polynomial in u
+// (Horner; for beta = 6, where beta^2 u / 4 <= 9, the terms past k = 13 add
+// less than 1e-10 of the sum, far below FP32 rounding); the constant factors
+// 1/pi and 1/I0(beta) cancel in the normalisation.
 __device__ inline void sinc_weights(float f, float (&w)[kTaps])
 {
-    const float inv_i0b = 1.f / bessel_i0(kBeta);
+    constexpr int kTerms = 14;
+    // 1 / (k!)^2, k = 0 .. 13
+    constexpr float kInvFact2[kTerms] = {
+        1.f, 1.f, 0.25f, 2.7777777777777778e-2f, 1.7361111111111111e-3f, 6.9444444444444444e-5f,
+        1.9290123456790123e-6f, 3.9367598891408415e-8f, 6.1511873267825648e-10f, 7.5940584281266232e-12f,
+        7.5940584281266232e-14f, 6.2760813455591927e-16f, 4.3583898233049949e-18f, 2.5789288895295828e-20f};
+    const float q4 = 0.25f * kBeta * kBeta;
+    const float s1 = sinpif(f);
     float sum = 0.f;
 #pragma unroll
     for (int j = 0; j < kTaps; ++j) {
         const float t = f + 3.f - (float)j;
-        const float sc = t == 0.f ? 1.f : sinpif(t) / (3.14159265358979f * t);
-        const float u = 1.f - 0.0625f * t * t;
-        const float win = bessel_i0(kBeta * sqrtf(fmaxf(u, 0.f))) * inv_i0b;
+        // sinc(t) times pi; (-1)^(3-j) is +1 for odd j
+        const float sc = t == 0.f ? 3.14159265358979f : ((j & 1) ? s1 : -s1) * __builtin_amdgcn_rcpf(t);
+        const float q = q4 * fmaxf(1.f - 0.0625f * t * t, 0.f);
+        float win = kInvFact2[kTerms - 1];
+#pragma unroll
+        for (int k = kTerms - 2; k >= 0; --k) win = fmaf(win, q, kInvFact2[k]);
         w[j] = sc * win;
         sum += w[j];
     }
@@ -152,9 +157,15 @@ __device__ inline int fault_source(const FaultFrame &F, int nz, int iz, int iy, 
     const double h = qy * F.n_y + qx * F.n_x;
     const double az = qy * F.s_y + qx * F.s_x;
     const double r = sqrt(h * h + vv * vv);
+    const double rho_s = fabs(az) * F.inv_die_s;
+    // outside the taper along strike, or across it where the surface is
+    // certainly the smooth one (the same expressions as below: the voxel
+    // would be still), without the angle
+    if (rho_s >= 1.0) return kFaultStill;
+    if ((!F.rough || !(fabs(r - F.radius) < F.rough_reach)) && fabs(r - F.radius) * F.inv_die_r >= 1.0)
+        return kFaultStill;
     const double t_old = atan2(vv, h);
     const double rho_t = fabs(t_old - F.theta0) * F.inv_die_t;
-    const double rho_s = fabs(az) * F.inv_die_s;
     double R = F.radius;   // where the fault surface is, at this (along strike, down dip) position
     if (F.rough && rho_t < 1.0 && rho_s < 1.0 && fabs(r - F.radius) < F.rough_reach) {
         const double u = fmin(fmax(az * F.inv_lam_s, -1e12), 1e12);
@@ -205,30 +216,31 @@ __device__ inline bool brick_voxel(const VoxBox &B, int &iz, int &iy, int &ix)
     return lz < B.bz && ly < B.by && lx < B.bx;
 }
 
-__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, VoxBox B,
-                                               FaultFrame F, float fill, float *__restrict__ out)
+// The taps of a moved voxel: source index origin (z0, y0, x0) = floor(s) - 3
+// per axis (y and x bounded first), the FP32 fractions of s, and the voxel.
+struct FaultTaps {
+    int z0, y0, x0;
+    float fz, fy, fx;
+};
+
+__device__ inline FaultTaps fault_taps(double sz, double sy, double sx)
 {
-    int iz, iy, ix;
-    if (!brick_voxel(B, iz, iy, ix)) return;
-    const int64_t plane = (int64_t)ny * nx;
-    const int64_t q = (int64_t)iz * plane + (int64_t)iy * nx + ix;
-    double sz, sy, sx;
-    const int kind = fault_source(F, nz, iz, iy, ix, sz, sy, sx);
-    if (kind == kFaultStill) {   // w = 0: the source is the voxel itself
-        out[q] = v[q];
-        return;
-    }
-    if (kind == kFaultFill) {
-        out[q] = fill;
-        return;
-    }
     // (bounded before the integer casts; every tap index is clamped anyway)
-    const double fz = floor(sz), fy = floor(fmin(fmax(sy, -1e9), 1e9)), fx = floor(fmin(fmax(sx, -1e9), 1e9));
+    const double cy = fmin(fmax(sy, -1e9), 1e9), cx = fmin(fmax(sx, -1e9), 1e9);
+    const double fz = floor(sz), fy = floor(cy), fx = floor(cx);
+    return FaultTaps{(int)fz - 3, (int)fy - 3, (int)fx - 3, (float)(sz - fz), (float)(cy - fy), (float)(cx - fx)};
+}
+
+// The 8 x 8 x 8 pull from memory (8 x 8 on a one-row y axis): for each z tap
+// the sum over y rows of the 8-tap x sums, every index clamped to the volume.
+__device__ inline float fault_pull(const float *__restrict__ v, int nz, int ny, int nx, int z0, int y0, int x0,
+                                         float fz, float fy, float fx)
+{
+    const int64_t plane = (int64_t)ny * nx;
     float wz[kTaps], wy[kTaps], wx[kTaps];
-    sinc_weights((float)(sz - fz), wz);
-    sinc_weights((float)(fmin(fmax(sy, -1e9), 1e9) - fy), wy);
-    sinc_weights((float)(fmin(fmax(sx, -1e9), 1e9) - fx), wx);
-    const int z0 = (int)fz - 3, y0 = (int)fy - 3, x0 = (int)fx - 3;
+    sinc_weights(fz, wz);
+    sinc_weights(fy, wy);
+    sinc_weights(fx, wx);
     int jx[kTaps];
 #pragma unroll
     for (int c = 0; c < kTaps; ++c) jx[c] = min(max(x0 + c, 0), nx - 1);
@@ -254,45 +266,51 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
     };
     float acc = 0.f;
     if (x_inner && ny > 1) {
-        // the 16 row loads of a z tap are all issued before any is used (load
-        // latency overlaps across rows); same arithmetic order as row_taps
+        // the row loads of half a z tap (8 16-byte loads) are issued before
+        // any is used (load latency overlaps across rows); same arithmetic
+        // order as row_taps
+        constexpr int kHalf = kTaps / 2;
         int64_t ry[kTaps];
 #pragma unroll
         for (int b = 0; b < kTaps; ++b) ry[b] = (int64_t)min(max(y0 + b, 0), ny - 1) * nx + x0;
 #pragma unroll
         for (int a = 0; a < kTaps; ++a) {
             const float *pl = v + (int64_t)min(max(z0 + a, 0), nz - 1) * plane;
-            Float4u lo[kTaps], hi[kTaps];
-#pragma unroll
-            for (int b = 0; b < kTaps; ++b) {
-                lo[b] = *(const Float4u *)(pl + ry[b]);
-                hi[b] = *(const Float4u *)(pl + ry[b] + 4);
-            }
             float accy = 0.f;
 #pragma unroll
-            for (int b = 0; b < kTaps; ++b) {
-                float s = 0.f;
-                s = fmaf(wx[0], lo[b].x, s);
-                s = fmaf(wx[1], lo[b].y, s);
-                s = fmaf(wx[2], lo[b].z, s);
-                s = fmaf(wx[3], lo[b].w, s);
-                s = fmaf(wx[4], hi[b].x, s);
-                s = fmaf(wx[5], hi[b].y, s);
-                s = fmaf(wx[6], hi[b].z, s);
-                s = fmaf(wx[7], hi[b].w, s);
-                accy = fmaf(wy[b], s, accy);
+            for (int h = 0; h < kTaps; h += kHalf) {
+                Float4u lo[kHalf], hi[kHalf];
+#pragma unroll
+                for (int b = 0; b < kHalf; ++b) {
+                    lo[b] = *(const Float4u *)(pl + ry[h + b]);
+                    hi[b] = *(const Float4u *)(pl + ry[h + b] + 4);
+                }
+#pragma unroll
+                for (int b = 0; b < kHalf; ++b) {
+                    float s = 0.f;
+                    s = fmaf(wx[0], lo[b].x, s);
+                    s = fmaf(wx[1], lo[b].y, s);
+                    s = fmaf(wx[2], lo[b].z, s);
+                    s = fmaf(wx[3], lo[b].w, s);
+                    s = fmaf(wx[4], hi[b].x, s);
+                    s = fmaf(wx[5], hi[b].y, s);
+                    s = fmaf(wx[6], hi[b].z, s);
+                    s = fmaf(wx[7], hi[b].w, s);
+                    accy = fmaf(wy[h + b], s, accy);
+                }
             }
             acc = fmaf(wz[a], accy, acc);
         }
-        out[q] = acc;
-        return;
+        return acc;
     }
+#pragma unroll
     for (int a = 0; a < kTaps; ++a) {
         const int jz = min(max(z0 + a, 0), nz - 1);
         float accy = 0.f;
         if (ny == 1) {
             accy = row_taps(v + (int64_t)jz * plane);   // the y weights sum to 1 on a one-row axis
         } else {
+#pragma unroll
             for (int b = 0; b < kTaps; ++b) {
                 const int jy = min(max(y0 + b, 0), ny - 1);
                 accy = fmaf(wy[b], row_taps(v + (int64_t)jz * plane + (int64_t)jy * nx), accy);
@@ -300,7 +318,81 @@ __global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int 
         }
         acc = fmaf(wz[a], accy, acc);
     }
-    out[q] = acc;
+    return acc;
+}
+
+// Fault pull by bricks: a workgroup takes kSbZ x kSbY rows of 64 voxels (wave
+// w takes y row w of the brick, each thread its kSbZ voxels down z, in
+// columns 64 wide); each thread computes the pull
+// sources of its rows first (FP64; still and filled voxels are written at
+// once), keeping the taps of its moved voxels in LDS, then pulls them one
+// after another.  Bricks go to the XCDs in groups of kSbGroup x kSbGroup
+// bricks (y, z), so the source rows that neighbouring bricks share are
+// fetched into one L2.
+constexpr int kSbZ = 4, kSbY = 4, kSbPer = kSbZ * kSbY / 4, kSbGroup = 4;
+
+struct BrickGrid {
+    int nbx, ncy, ncz;   // bricks along x, brick groups along y and z
+};
+
+inline BrickGrid brick_grid(const VoxBox &B)
+{
+    const int nby = (B.by + kSbY - 1) / kSbY, nbz = (B.bz + kSbZ - 1) / kSbZ;
+    return BrickGrid{(B.bx + 63) / 64, (nby + kSbGroup - 1) / kSbGroup, (nbz + kSbGroup - 1) / kSbGroup};
+}
+
+inline int64_t brick_blocks(const VoxBox &B)
+{
+    const BrickGrid g = brick_grid(B);
+    const int64_t ngroup = (int64_t)g.nbx * g.ncy * g.ncz;
+    return (ngroup + 7) / 8 * 8 * (kSbGroup * kSbGroup);
+}
+
+__global__ void __launch_bounds__(256) k_fault(const float *__restrict__ v, int nz, int ny, int nx, VoxBox B,
+                                               BrickGrid G, FaultFrame F, float fill, float *__restrict__ out)
+{
+    __shared__ FaultTaps ptap[kSbPer][256];   // the taps of each thread's moved voxels
+    // the group of this workgroup: consecutive blocks of one XCD (every 8th
+    // block) take the kSbGroup^2 bricks of one group
+    const int64_t j = blockIdx.x / 8;
+    const int64_t group = (j / (kSbGroup * kSbGroup)) * 8 + blockIdx.x % 8;
+    if (group >= (int64_t)G.nbx * G.ncy * G.ncz) return;
+    const int r = (int)(j % (kSbGroup * kSbGroup));
+    const int gbx = (int)(group % G.nbx);
+    const int64_t rest = group / G.nbx;
+    const int by = (int)(rest % G.ncy) * kSbGroup + r % kSbGroup, bz = (int)(rest / G.ncy) * kSbGroup + r / kSbGroup;
+    if (by * kSbY >= B.by || bz * kSbZ >= B.bz) return;
+
+    const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+    const int64_t plane = (int64_t)ny * nx;
+    const int ix = B.x0 + gbx * 64 + lane;
+    // row k of this thread is z offset k, y offset w in the brick
+    const int iy = B.y0 + by * kSbY + w;
+    auto voxel = [&](int k) { return (int64_t)(B.z0 + bz * kSbZ + k) * plane + (int64_t)iy * nx + ix; };
+    if (iy >= B.y0 + B.by || ix >= B.x0 + B.bx) return;
+    unsigned moved = 0;   // bit k: row k's voxel takes the pull
+#pragma unroll
+    for (int k = 0; k < kSbPer; ++k) {
+        const int iz = B.z0 + bz * kSbZ + k;
+        if (iz >= B.z0 + B.bz) continue;
+        const int64_t q = voxel(k);
+        double sz, sy, sx;
+        const int kind = fault_source(F, nz, iz, iy, ix, sz, sy, sx);
+        if (kind == kFaultStill) {   // w = 0: the source is the voxel itself
+            out[q] = v[q];
+        } else if (kind == kFaultFill) {
+            out[q] = fill;
+        } else {
+            moved |= 1u << k;
+            ptap[k][threadIdx.x] = fault_taps(sz, sy, sx);
+        }
+    }
+#pragma unroll 1
+    for (int k = 0; k < kSbPer; ++k)
+        if (moved >> k & 1u) {
+            const FaultTaps P = ptap[k][threadIdx.x];
+            out[voxel(k)] = fault_pull(v, nz, ny, nx, P.z0, P.y0, P.x0, P.fz, P.fy, P.fx);
+        }
 }
 
 // Alg. 3 for integer fields (e.g. layer labels): the same pull source,
@@ -755,9 +847,10 @@ hipError_t launch_fault(const float *v, int nz, int ny, int nx, const FaultFrame
     bool run;
     hipError_t e = fault_prologue(v, nz, ny, nx, F, out, st, B, run);
     if (e != hipSuccess || !run) return e;
-    const int64_t blocks = fault_blocks(B);
+    const int64_t blocks = brick_blocks(B);
     if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, B, F, fill, out);
+    hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, v, nz, ny, nx, B, brick_grid(B), F, fill,
+                       out);
     return hipGetLastError();
 }
 
@@ -827,12 +920,7 @@ hipError_t fault_sequence(const T *v, int nz, int ny, int nx, const FaultFrame *
                 e = copy_box(src, ny, nx, prev, dst, st);
         }
         if (e != hipSuccess) return e;
-        if (run) {
-            const int64_t blocks = fault_blocks(B);
-            if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
-            run_kernel(src, B, F[k], dst, (unsigned)blocks);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+        if (run && (e = run_kernel(src, B, F[k], dst)) != hipSuccess) return e;
         prev = run ? B : whole;
         prev_run = run;
         src = dst;
@@ -846,9 +934,12 @@ hipError_t launch_fault_sequence(const float *v, int nz, int ny, int nx, const F
                                  float *out, float *ws, hipStream_t st)
 {
     return fault_sequence(v, nz, ny, nx, F, n, out, ws, st,
-                          [&](const float *src, const VoxBox &B, const FaultFrame &f, float *dst, unsigned blocks) {
-                              hipLaunchKernelGGL(k_fault, dim3(blocks), dim3(256), 0, st, src, nz, ny, nx, B, f,
-                                                 fill, dst);
+                          [&](const float *src, const VoxBox &B, const FaultFrame &f, float *dst) {
+                              const int64_t blocks = brick_blocks(B);
+                              if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
+                              hipLaunchKernelGGL(k_fault, dim3((unsigned)blocks), dim3(256), 0, st, src, nz, ny, nx,
+                                                 B, brick_grid(B), f, fill, dst);
+                              return hipGetLastError();
                           });
 }
 
@@ -856,10 +947,12 @@ hipError_t launch_fault_labels_sequence(const int32_t *lab, int nz, int ny, int 
                                         int32_t fill, int32_t *out, int32_t *ws, hipStream_t st)
 {
     return fault_sequence(lab, nz, ny, nx, F, n, out, ws, st,
-                          [&](const int32_t *src, const VoxBox &B, const FaultFrame &f, int32_t *dst,
-                              unsigned blocks) {
-                              hipLaunchKernelGGL(k_fault_labels, dim3(blocks), dim3(256), 0, st, src, nz, ny, nx, B,
-                                                 f, fill, dst);
+                          [&](const int32_t *src, const VoxBox &B, const FaultFrame &f, int32_t *dst) {
+                              const int64_t blocks = fault_blocks(B);
+                              if (blocks >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
+                              hipLaunchKernelGGL(k_fault_labels, dim3((unsigned)blocks), dim3(256), 0, st, src, nz,
+                                                 ny, nx, B, f, fill, dst);
+                              return hipGetLastError();
                           });
 }
 
