@@ -54,9 +54,9 @@ def parse():
                          "form of --batch-tuning (the adjoint always runs the tiled kernel; default: column "
                          "sweep, 128-column strips, 96-row segments, time block 3, the fastest measured; "
                          "'' = tiled)")
-    ap.add_argument("--batched-grad-tuning", type=str, default="s256,160,3",
+    ap.add_argument("--batched-grad-tuning", type=str, default="s256,160,4",
                     help="the same for the full-density batched gradient (default: column sweep, 256-column "
-                         "strips, 160-row segments, time block 3, the fastest measured; '' = tiled)")
+                         "strips, 160-row segments, time block 4, the fastest measured; '' = tiled)")
     ap.add_argument("--field-tuning", type=str, default="",
                     help="tile_x,tile_z,time_block for the single field shot instead of the autotuner "
                          "(profiling runs: keeps the autotuner's trial launches out of the counters)")

@@ -92,14 +92,17 @@ def test_uneven_slices_batched_full_length_against_oracle():
         assert e <= TOL
 
 
-@pytest.mark.parametrize("tuning", [None, dict(variant=3, tile_x=256, tile_z=160, time_block=3)],
-                         ids=["tiled", "sweep-s256z160b3"])
+@pytest.mark.parametrize("tuning", [None, dict(variant=3, tile_x=256, tile_z=160, time_block=3),
+                                    dict(variant=3, tile_x=256, tile_z=160, time_block=4)],
+                         ids=["tiled", "sweep-s256z160b3", "sweep-s256z160b4"])
 def test_full_density_batched_gradient_against_stored_oracle_gradients(tuning):
     """Two slices of the full-density batched-gradient workload (510 x 888
     with 4 shots including both edge shots, 593 x 973 with 2), 10000 levels,
     checkpoints every 100, two shots per slice per wave, through
-    sg_batch_adjoint_gradient: with the default tiling, and on the column
-    sweep (forward, recompute and adjoint) as the benchmark runs it.  The GPU forms each residual from its own FP32
+    sg_batch_adjoint_gradient: with the default tiling, and with the forward
+    and the recompute on the column sweep (the adjoint stays on the tiled
+    kernel) at time blocks 3 and 4, the latter as the benchmark runs it.  The
+    GPU forms each residual from its own FP32
     gathers on the true and start models; the reference gradients and misfits
     are the FP64 oracle's."""
     import torch
