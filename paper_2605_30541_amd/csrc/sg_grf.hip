@@ -9,7 +9,9 @@
 // [z][y][x] again with every axis transformed.  The 1D FFTs are radix-2
 // Cooley-Tukey in LDS (bit-reversed load, log2 L butterfly stages, twiddles
 // from a per-workgroup table of sincospif values); neither direction is
-// scaled (the final normalisation removes every constant factor).
+// scaled (the final normalisation removes every constant factor).  The real
+// noise enters in the first forward pass and the spectral factor in the first
+// inverse pass, as they load their lines.
 #include "sg_internal.h"
 
 namespace sg {
@@ -19,15 +21,45 @@ namespace {
 constexpr int kFftThreads = 256;
 constexpr int kFftLds = 1024;        // complex values held per workgroup (one line of 1024 or several shorter)
 
-__global__ void __launch_bounds__(256) k_noise_to_complex(const float *noise, float2 *a, int64_t n)
+// The spectral factor sqrt(P(k)) of cell (z, y, x) of the [Pz][Py][Px]
+// spectrum; k in radians per cell in the FFT's frequency order
+// (0, 1, .., P/2-1, -P/2, .., -1) / P.
+struct Spectrum {
+    int Pz, Py, Px;
+    double lz, ly, lx, half_p;
+};
+
+__device__ inline float spectral_amp(const Spectrum &S, int z, int y, int x)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = make_float2(noise[i], 0.f);
+    const double two_pi = 6.283185307179586;
+    const double fz = (z < (S.Pz + 1) / 2 ? z : z - S.Pz) / (double)S.Pz;
+    const double fy = (y < (S.Py + 1) / 2 ? y : y - S.Py) / (double)S.Py;
+    const double fx = (x < (S.Px + 1) / 2 ? x : x - S.Px) / (double)S.Px;
+    const double kz = two_pi * fz * S.lz, ky = two_pi * fy * S.ly, kx = two_pi * fx * S.lx;
+    // the power in FP32 (hardware log2 / exp2): the field is FP32 and is normalised afterwards
+    return exp2f(-(float)S.half_p * log2f((float)(1.0 + kz * kz + ky * ky + kx * kx)));
+}
+
+// One radix-2 butterfly: (u, v) -> (u + w v, u - w v).
+__device__ inline void butterfly(float2 &u, float2 &v, float2 w)
+{
+    const float cs = w.x, sn = w.y;
+    const float2 t = make_float2(cs * v.x - sn * v.y, cs * v.y + sn * v.x);
+    v = make_float2(u.x - t.x, u.y - t.y);
+    u = make_float2(u.x + t.x, u.y + t.y);
 }
 
 // FFT of every line of length L = 2^logL (lines contiguous): sign -1 forward,
-// +1 inverse.  A workgroup holds kFftLds / L lines (one when L = 1024).
-__global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, int logL, int64_t nlines, float sign)
+// +1 inverse.  A workgroup holds kFftLds / L lines (one when L = 1024).  The
+// input is `data`, or, when `real_in` is given, the real values real_in with
+// zero imaginary parts; with S.Pz > 0 every input value is first multiplied
+// by the spectral factor of its cell (the lines are then the x lines of the
+// [Pz][Py][Px] spectrum).  Two radix-2 stages per pass over LDS (the
+// butterflies of both stages on four values a thread holds), one last
+// radix-2 stage when logL is odd: the same butterflies, twiddles and order
+// of operations as stage after stage.
+__global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, const float *real_in, Spectrum S, int logL,
+                                                         int64_t nlines, float sign)
 {
     __shared__ float2 buf[kFftLds];
     __shared__ float2 tw[kFftLds / 2];   // exp(sign i 2 pi m / L), m < L/2: stage s uses m = j 2^(logL-s)
@@ -46,23 +78,48 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, int log
     for (int i = threadIdx.x; i < tot; i += kFftThreads) {
         const int ln = i >> logL, j = i & (L - 1);
         const int r = logL == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logL));
-        buf[(ln << logL) + r] = base[i];
+        float2 v = real_in ? make_float2(real_in[line0 * L + i], 0.f) : base[i];
+        if (S.Pz > 0) {
+            const int64_t line = line0 + ln;
+            const float amp = spectral_amp(S, (int)(line / S.Py), (int)(line % S.Py), j);
+            v = make_float2(v.x * amp, v.y * amp);
+        }
+        buf[(ln << logL) + r] = v;
     }
     __syncthreads();
-    const int nbf = tot >> 1;                                   // butterflies per stage
-    for (int s = 1; s <= logL; ++s) {
+    int s = 1;
+    for (; s + 1 <= logL; s += 2) {
+        // stages s and s + 1 on the groups of four values k, k + h, k + 2h, k + 3h
+        const int h = 1 << (s - 1);
+        for (int b = threadIdx.x; b < (tot >> 2); b += kFftThreads) {
+            const int ln = b >> (logL - 2);                     // line of this group
+            const int bb = b & ((L >> 2) - 1);
+            const int g = bb >> (s - 1), j = bb & (h - 1);
+            const int k = (ln << logL) + (g << (s + 1)) + j;
+            float2 x0 = buf[k], x1 = buf[k + h], x2 = buf[k + 2 * h], x3 = buf[k + 3 * h];
+            const float2 w1 = tw[j << (logL - s)];              // exp(sign i 2 pi j / 2h)
+            butterfly(x0, x1, w1);
+            butterfly(x2, x3, w1);
+            butterfly(x0, x2, tw[j << (logL - s - 1)]);         // exp(sign i 2 pi j / 4h)
+            butterfly(x1, x3, tw[(j + h) << (logL - s - 1)]);   // exp(sign i 2 pi (j + h) / 4h)
+            buf[k] = x0;
+            buf[k + h] = x1;
+            buf[k + 2 * h] = x2;
+            buf[k + 3 * h] = x3;
+        }
+        __syncthreads();
+    }
+    if (s == logL) {   // the last stage alone
         const int half = 1 << (s - 1);
-        for (int b = threadIdx.x; b < nbf; b += kFftThreads) {
+        for (int b = threadIdx.x; b < (tot >> 1); b += kFftThreads) {
             const int ln = b >> (logL - 1);                     // line of this butterfly
             const int bb = b & ((L >> 1) - 1);
             const int g = bb >> (s - 1), j = bb & (half - 1);
             const int k = (ln << logL) + (g << s) + j;
-            const float2 w = tw[j << (logL - s)];                   // exp(sign i 2 pi j / 2 half)
-            const float cs = w.x, sn = w.y;
-            const float2 u = buf[k], v = buf[k + half];
-            const float2 t = make_float2(cs * v.x - sn * v.y, cs * v.y + sn * v.x);
-            buf[k] = make_float2(u.x + t.x, u.y + t.y);
-            buf[k + half] = make_float2(u.x - t.x, u.y - t.y);
+            float2 u = buf[k], v = buf[k + half];
+            butterfly(u, v, tw[j << (logL - s)]);
+            buf[k] = u;
+            buf[k + half] = v;
         }
         __syncthreads();
     }
@@ -83,28 +140,6 @@ __global__ void __launch_bounds__(256) k_transpose(const float2 *in, float2 *out
     for (int k = ty; k < 32; k += 8) {
         const int64_t c = tc + k, r = tr + tx;
         if (r < R && c < C) out[c * R + r] = tile[tx][k];
-    }
-}
-
-// Multiply by sqrt(P(k)); k in radians per cell in the FFT's frequency
-// order (0, 1, .., P/2-1, -P/2, .., -1) / P.
-__global__ void __launch_bounds__(256) k_spectral_scale(float2 *a, int Pz, int Py, int Px, double lz, double ly,
-                                                       double lx, double half_p)
-{
-    const int64_t n = (int64_t)Pz * Py * Px;
-    const double two_pi = 6.283185307179586;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % Px);
-        const int64_t zy = i / Px;
-        const int y = (int)(zy % Py), z = (int)(zy / Py);
-        const double fz = (z < (Pz + 1) / 2 ? z : z - Pz) / (double)Pz;
-        const double fy = (y < (Py + 1) / 2 ? y : y - Py) / (double)Py;
-        const double fx = (x < (Px + 1) / 2 ? x : x - Px) / (double)Px;
-        const double kz = two_pi * fz * lz, ky = two_pi * fy * ly, kx = two_pi * fx * lx;
-        // the power in FP32 (hardware log2 / exp2): the field is FP32 and is normalised afterwards
-        const float amp = exp2f(-(float)half_p * log2f((float)(1.0 + kz * kz + ky * ky + kx * kx)));
-        float2 v = a[i];
-        a[i] = make_float2(v.x * amp, v.y * amp);
     }
 }
 
@@ -191,7 +226,8 @@ constexpr int kStatBlocks = 2048;
 
 // One 3D transform of a[Pz][Py][Px] (b: scratch of the same size); the
 // result is in a.
-hipError_t fft3(float2 *&a, float2 *&b, const int P[3], float sign, hipStream_t st)
+hipError_t fft3(float2 *&a, float2 *&b, const int P[3], float sign, const float *real_in, const Spectrum &S0,
+                hipStream_t st)
 {
     const int64_t n = (int64_t)P[0] * P[1] * P[2];
     int dims[3] = {P[0], P[1], P[2]};           // current layout [d0][d1][d2], d2 contiguous
@@ -200,9 +236,13 @@ hipError_t fft3(float2 *&a, float2 *&b, const int P[3], float sign, hipStream_t 
         const int logL = log2i(L);
         const int64_t nlines = n / L;
         const int lpw = L >= kFftLds ? 1 : kFftLds / L;
-        if (L > 1) {
+        // the first round takes the real input or the spectral factor (if given)
+        const float *rin = r == 0 ? real_in : nullptr;
+        const Spectrum S = r == 0 ? S0 : Spectrum{};
+        if (L > 1 || rin || S.Pz > 0) {
             const int64_t wgs = (nlines + lpw - 1) / lpw;
-            hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)wgs), dim3(kFftThreads), 0, st, a, logL, nlines, sign);
+            hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)wgs), dim3(kFftThreads), 0, st, a, rin, S, logL, nlines,
+                               sign);
         }
         const int64_t R = nlines, C = L;
         hipLaunchKernelGGL(k_transpose, dim3((unsigned)((R + 31) / 32), (unsigned)((C + 31) / 32)), dim3(256), 0, st,
@@ -243,11 +283,11 @@ hipError_t launch_grf(const float *noise, int nz, int ny, int nx, double lz, dou
     float2 *a = (float2 *)ws, *b = a + n;
     double *partials = (double *)(b + n);
     double *stats = partials + 2 * kStatBlocks;
-    hipLaunchKernelGGL(k_noise_to_complex, dim3(grid1d(n)), dim3(256), 0, st, noise, a, n);
-    hipError_t e = fft3(a, b, P, -1.f, st);
+    // forward transform of the real noise; the inverse one takes the spectral
+    // factor as it loads its first lines
+    hipError_t e = fft3(a, b, P, -1.f, noise, Spectrum{}, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spectral_scale, dim3(grid1d(n)), dim3(256), 0, st, a, P[0], P[1], P[2], lz, ly, lx, 0.5 * p);
-    if ((e = fft3(a, b, P, 1.f, st)) != hipSuccess) return e;
+    if ((e = fft3(a, b, P, 1.f, nullptr, Spectrum{P[0], P[1], P[2], lz, ly, lx, 0.5 * p}, st)) != hipSuccess) return e;
     const int64_t m = (int64_t)nz * ny * nx;
     hipLaunchKernelGGL(k_crop_real, dim3(kStatBlocks), dim3(256), 0, st, a, P[1], P[2], nz, ny, nx, out, partials);
     hipLaunchKernelGGL(k_grf_stats, dim3(1), dim3(256), 0, st, partials, kStatBlocks, m, stats);
