@@ -4,14 +4,13 @@
 // volume and scaled to zero mean and unit variance.
 //
 // A 3D transform is three rounds of [batched 1D FFTs along the contiguous
-// axis, then a 2D transpose of the (lines x length) matrix]: each round
-// moves the transformed axis to the front, so after three the layout is
-// [z][y][x] again with every axis transformed.  The 1D FFTs are radix-2
-// Cooley-Tukey in LDS (bit-reversed load, log2 L butterfly stages, twiddles
-// from a per-workgroup table of sincospif values); neither direction is
-// scaled (the final normalisation removes every constant factor).  The real
-// noise enters in the first forward pass and the spectral factor in the first
-// inverse pass, as they load their lines.
+// axis, written transposed so the next axis becomes the contiguous one]:
+// after three rounds the layout is [z][y][x] again with every axis
+// transformed.  Each round is one kernel (k_fft_t): radix-2 Cooley-Tukey in
+// LDS with twiddles from a per-workgroup table of sincospif values; neither
+// direction is scaled (the final normalisation removes every constant
+// factor).  The real noise enters in the first forward round and the spectral
+// factor in the first inverse round, as they load their lines.
 #include "sg_internal.h"
 
 namespace sg {
@@ -19,7 +18,8 @@ namespace sg {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftLds = 1024;        // complex values held per workgroup (one line of 1024 or several shorter)
+constexpr int kFftLds = 1024;        // longest line (the grid is at most 1024 per axis)
+constexpr int kFftRows = 4;          // lines per workgroup
 
 // The spectral factor sqrt(P(k)) of cell (z, y, x) of the [Pz][Py][Px]
 // spectrum; k in radians per cell in the FFT's frequency order
@@ -49,97 +49,113 @@ __device__ inline void butterfly(float2 &u, float2 &v, float2 w)
     u = make_float2(u.x + t.x, u.y + t.y);
 }
 
-// FFT of every line of length L = 2^logL (lines contiguous): sign -1 forward,
-// +1 inverse.  A workgroup holds kFftLds / L lines (one when L = 1024).  The
-// input is `data`, or, when `real_in` is given, the real values real_in with
-// zero imaginary parts; with S.Pz > 0 every input value is first multiplied
-// by the spectral factor of its cell (the lines are then the x lines of the
-// [Pz][Py][Px] spectrum).  Two radix-2 stages per pass over LDS (the
-// butterflies of both stages on four values a thread holds), one last
-// radix-2 stage when logL is odd: the same butterflies, twiddles and order
-// of operations as stage after stage.
-__global__ void __launch_bounds__(kFftThreads) k_fft_lines(float2 *data, const float *real_in, Spectrum S, int logL,
-                                                         int64_t nlines, float sign)
+// One round of the 3D transform in one pass: the FFT of every line of
+// in[D0][D1][L] (L = 2^logL; sign -1 forward, +1 inverse), written transposed to
+// out[L][D0][D1].  A workgroup takes kRows lines of one d0 and consecutive
+// d1, so every output row gets kRows consecutive values from it; its lines
+// sit in LDS padded (one value per 32, one per line), so the bit-reversed
+// stores, the butterflies' strides and the column-wise reads of the
+// transposed write spread over the banks.
+// The input is `in`, or, when `real_in` is given, the real values real_in
+// with zero imaginary parts; with S.Pz > 0 every input value is first
+// multiplied by the spectral factor of its cell (line / S.Py, line % S.Py,
+// position) (the lines are then the x lines of the [Pz][Py][Px] spectrum).
+// Radix-2 Cooley-Tukey in LDS: a bit-reversed load, then two butterfly
+// stages per pass (each thread does the four butterflies of two stages on
+// four values it holds: the butterflies and twiddles of stage after stage),
+// one last radix-2 stage when logL is odd.
+template <int kRows>
+__global__ void __launch_bounds__(kFftThreads) k_fft_t(const float2 *__restrict__ in, const float *__restrict__ real_in,
+                                                     Spectrum S, float2 *__restrict__ out, int logL, int D0, int D1,
+                                                     float sign)
 {
-    __shared__ float2 buf[kFftLds];
-    __shared__ float2 tw[kFftLds / 2];   // exp(sign i 2 pi m / L), m < L/2: stage s uses m = j 2^(logL-s)
-    const int L = 1 << logL;
+    __shared__ float2 buf[kRows * (kFftLds + kFftLds / 32 + 1)];
+    __shared__ float2 tw[kFftLds / 2];
+    // position r of line ln sits at ln * LS + r + r / 32: the pad breaks the
+    // bank conflicts of the bit-reversed stores and of the early stages' strides
+    const int L = 1 << logL, LS = L + L / 32 + 1;
+    auto at = [&](int ln, int r) { return ln * LS + r + (r >> 5); };
     for (int m = threadIdx.x; m < L / 2; m += kFftThreads) {
         float sn, cs;
         sincospif(sign * (float)m / (float)(L / 2), &sn, &cs);
         tw[m] = make_float2(cs, sn);
     }
-    const int lpw = L >= kFftLds ? 1 : kFftLds / L;            // lines per workgroup
-    const int64_t line0 = (int64_t)blockIdx.x * lpw;
-    const int nl = (int)min((int64_t)lpw, nlines - line0);
+    // consecutive blocks of work go to one XCD (the hardware deals workgroups
+    // to the 8 XCDs in turn), so the partial output rows that neighbouring
+    // blocks write meet in one L2
+    const int nblk = (int)gridDim.x, per = nblk >> 3, bid = (int)blockIdx.x;
+    const int blk = bid >= per * 8 ? bid : (bid & 7) * per + (bid >> 3);
+    const int nb1 = (D1 + kRows - 1) / kRows;
+    const int d0 = blk / nb1, d1s = (blk % nb1) * kRows;
+    const int nl = min(kRows, D1 - d1s);
     const int tot = nl * L;
-    float2 *base = data + line0 * L;
-    // load in bit-reversed order within each line
-    for (int i = threadIdx.x; i < tot; i += kFftThreads) {
-        const int ln = i >> logL, j = i & (L - 1);
-        const int r = logL == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logL));
-        float2 v = real_in ? make_float2(real_in[line0 * L + i], 0.f) : base[i];
-        if (S.Pz > 0) {
-            const int64_t line = line0 + ln;
-            const float amp = spectral_amp(S, (int)(line / S.Py), (int)(line % S.Py), j);
-            v = make_float2(v.x * amp, v.y * amp);
+    const int64_t line0 = (int64_t)d0 * D1 + d1s;
+    // load (bit-reversed within each line), eight values in flight per thread
+    constexpr int kBatch = 8;
+    for (int i0 = 0; i0 < tot; i0 += kFftThreads * kBatch) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = i0 + u * kFftThreads + threadIdx.x;
+            if (i < tot) v[u] = real_in ? make_float2(real_in[line0 * L + i], 0.f) : in[line0 * L + i];
         }
-        buf[(ln << logL) + r] = v;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int i = i0 + u * kFftThreads + threadIdx.x;
+            if (i >= tot) continue;
+            const int ln = i >> logL, j = i & (L - 1);
+            float2 x = v[u];
+            if (S.Pz > 0) {
+                const int64_t line = line0 + ln;
+                const float amp = spectral_amp(S, (int)(line / S.Py), (int)(line % S.Py), j);
+                x = make_float2(x.x * amp, x.y * amp);
+            }
+            const int r = logL == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logL));
+            buf[at(ln, r)] = x;
+        }
     }
     __syncthreads();
     int s = 1;
     for (; s + 1 <= logL; s += 2) {
-        // stages s and s + 1 on the groups of four values k, k + h, k + 2h, k + 3h
         const int h = 1 << (s - 1);
         for (int b = threadIdx.x; b < (tot >> 2); b += kFftThreads) {
-            const int ln = b >> (logL - 2);                     // line of this group
+            const int ln = b >> (logL - 2);
             const int bb = b & ((L >> 2) - 1);
             const int g = bb >> (s - 1), j = bb & (h - 1);
-            const int k = (ln << logL) + (g << (s + 1)) + j;
-            float2 x0 = buf[k], x1 = buf[k + h], x2 = buf[k + 2 * h], x3 = buf[k + 3 * h];
-            const float2 w1 = tw[j << (logL - s)];              // exp(sign i 2 pi j / 2h)
+            const int k = (g << (s + 1)) + j;
+            const int i0 = at(ln, k), i1 = at(ln, k + h), i2 = at(ln, k + 2 * h), i3 = at(ln, k + 3 * h);
+            float2 x0 = buf[i0], x1 = buf[i1], x2 = buf[i2], x3 = buf[i3];
+            const float2 w1 = tw[j << (logL - s)];
             butterfly(x0, x1, w1);
             butterfly(x2, x3, w1);
-            butterfly(x0, x2, tw[j << (logL - s - 1)]);         // exp(sign i 2 pi j / 4h)
-            butterfly(x1, x3, tw[(j + h) << (logL - s - 1)]);   // exp(sign i 2 pi (j + h) / 4h)
-            buf[k] = x0;
-            buf[k + h] = x1;
-            buf[k + 2 * h] = x2;
-            buf[k + 3 * h] = x3;
+            butterfly(x0, x2, tw[j << (logL - s - 1)]);
+            butterfly(x1, x3, tw[(j + h) << (logL - s - 1)]);
+            buf[i0] = x0;
+            buf[i1] = x1;
+            buf[i2] = x2;
+            buf[i3] = x3;
         }
         __syncthreads();
     }
-    if (s == logL) {   // the last stage alone
+    if (s == logL) {
         const int half = 1 << (s - 1);
         for (int b = threadIdx.x; b < (tot >> 1); b += kFftThreads) {
-            const int ln = b >> (logL - 1);                     // line of this butterfly
+            const int ln = b >> (logL - 1);
             const int bb = b & ((L >> 1) - 1);
             const int g = bb >> (s - 1), j = bb & (half - 1);
-            const int k = (ln << logL) + (g << s) + j;
-            float2 u = buf[k], v = buf[k + half];
+            const int k = (g << s) + j;
+            const int i0 = at(ln, k), i1 = at(ln, k + half);
+            float2 u = buf[i0], v = buf[i1];
             butterfly(u, v, tw[j << (logL - s)]);
-            buf[k] = u;
-            buf[k + half] = v;
+            buf[i0] = u;
+            buf[i1] = v;
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < tot; i += kFftThreads) base[i] = buf[i];
-}
-
-// out[c][r] = in[r][c] for an R x C matrix of complex values (32 x 32 tiles).
-__global__ void __launch_bounds__(256) k_transpose(const float2 *in, float2 *out, int64_t R, int64_t C)
-{
-    __shared__ float2 tile[32][33];
-    const int64_t tr = (int64_t)blockIdx.x * 32, tc = (int64_t)blockIdx.y * 32;   // rows on x: up to 2^25 tiles
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8 threads
-    for (int k = ty; k < 32; k += 8) {
-        const int64_t r = tr + k, c = tc + tx;
-        if (r < R && c < C) tile[k][tx] = in[r * C + c];
-    }
-    __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-        const int64_t c = tc + k, r = tr + tx;
-        if (r < R && c < C) out[c * R + r] = tile[tx][k];
+    // transposed write: position j of line ln goes to out[j][d0][d1s + ln]
+    for (int q = threadIdx.x; q < tot; q += kFftThreads) {
+        const int j = q / nl, ln = q - j * nl;
+        out[((int64_t)j * D0 + d0) * D1 + d1s + ln] = buf[at(ln, j)];
     }
 }
 
@@ -229,24 +245,15 @@ constexpr int kStatBlocks = 2048;
 hipError_t fft3(float2 *&a, float2 *&b, const int P[3], float sign, const float *real_in, const Spectrum &S0,
                 hipStream_t st)
 {
-    const int64_t n = (int64_t)P[0] * P[1] * P[2];
     int dims[3] = {P[0], P[1], P[2]};           // current layout [d0][d1][d2], d2 contiguous
     for (int r = 0; r < 3; ++r) {
         const int L = dims[2];
-        const int logL = log2i(L);
-        const int64_t nlines = n / L;
-        const int lpw = L >= kFftLds ? 1 : kFftLds / L;
         // the first round takes the real input or the spectral factor (if given)
         const float *rin = r == 0 ? real_in : nullptr;
         const Spectrum S = r == 0 ? S0 : Spectrum{};
-        if (L > 1 || rin || S.Pz > 0) {
-            const int64_t wgs = (nlines + lpw - 1) / lpw;
-            hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)wgs), dim3(kFftThreads), 0, st, a, rin, S, logL, nlines,
-                               sign);
-        }
-        const int64_t R = nlines, C = L;
-        hipLaunchKernelGGL(k_transpose, dim3((unsigned)((R + 31) / 32), (unsigned)((C + 31) / 32)), dim3(256), 0, st,
-                           a, b, R, C);
+        const int64_t wgs = (int64_t)dims[0] * ((dims[1] + kFftRows - 1) / kFftRows);
+        hipLaunchKernelGGL(k_fft_t<kFftRows>, dim3((unsigned)wgs), dim3(kFftThreads), 0, st, a, rin, S, b, log2i(L),
+                           dims[0], dims[1], sign);
         float2 *t = a;
         a = b;
         b = t;
