@@ -199,6 +199,11 @@ __device__ __forceinline__ void gstore_at(T *base, uint32_t byte_off, T v)
 }
 
 // Streaming store (no reuse expected before the data leaves the caches).
+// streaming load: data read once (it is not kept in the caches for reuse)
+__device__ __forceinline__ float gload_nt_at(const float *base, uint32_t byte_off)
+{
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) float *)((const char *)base + byte_off));
+}
 __device__ __forceinline__ void gstore_nt_at(float *base, uint32_t byte_off, float v)
 {
     __builtin_nontemporal_store(v, (__attribute__((address_space(1))) float *)((char *)base + byte_off));
@@ -488,15 +493,16 @@ __device__ __forceinline__ void tiled_body(const SliceDesc &s, const TileArgs &t
         }
     }
     // adjoint: the second time difference D^k of the forward field for the
-    // imaging term (read one sub-step ahead), and the partial sums of h.  Only
-    // the output cells are read and their sums stored.
+    // imaging term (read one sub-step ahead, with streaming loads: each value
+    // is read once), and the partial sums of h.  Only the output cells are
+    // read and their sums stored.
     float pn[ADJ ? K : 1], hp[ADJ ? K : 1];
     const float *ringb = ADJ ? t.ring + (int64_t)shot * t.ring_shot : nullptr;
     auto ring_level = [&](int L, float(&dst)[ADJ ? K : 1]) {
         const bool h = xout && L >= t.ring_lo && L <= t.ring_hi;
         const float *rl = ringb + (int64_t)(h ? L - t.ring_lo : 0) * s.frame;
 #pragma unroll
-        for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? gload_at(rl, rowb(k) + xc4) : 0.f;
+        for (int k = 0; k < K; ++k) dst[k] = (h && k >= k_lo && k < k_hi) ? gload_nt_at(rl, rowb(k) + xc4) : 0.f;
     };
     if (ADJ) {
         ring_level(t.n, pn);
