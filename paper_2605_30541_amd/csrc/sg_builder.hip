@@ -217,7 +217,7 @@ __device__ inline bool brick_voxel(const VoxBox &B, int &iz, int &iy, int &ix)
 }
 
 // The taps of a moved voxel: source index origin (z0, y0, x0) = floor(s) - 3
-// per axis (y and x bounded first), the FP32 fractions of s, and the voxel.
+// per axis (y and x bounded first) and the FP32 fractions of s.
 struct FaultTaps {
     int z0, y0, x0;
     float fz, fy, fx;
@@ -234,7 +234,7 @@ __device__ inline FaultTaps fault_taps(double sz, double sy, double sx)
 // The 8 x 8 x 8 pull from memory (8 x 8 on a one-row y axis): for each z tap
 // the sum over y rows of the 8-tap x sums, every index clamped to the volume.
 __device__ inline float fault_pull(const float *__restrict__ v, int nz, int ny, int nx, int z0, int y0, int x0,
-                                         float fz, float fy, float fx)
+                                  float fz, float fy, float fx)
 {
     const int64_t plane = (int64_t)ny * nx;
     float wz[kTaps], wy[kTaps], wx[kTaps];
