@@ -52,11 +52,14 @@ def _batch(full, tuning):
     return tuning
 
 
-def test_uneven_slices_batched_full_length_against_oracle():
+@pytest.mark.parametrize("given", [None, dict(variant=3, tile_x=256, tile_z=320, time_block=4)],
+                         ids=["autotuned", "sweep-s256z320b4"])
+def test_uneven_slices_batched_full_length_against_oracle(given):
     """Three slices of the batched forward's generator (419 x 681, 571 x 638,
     544 x 812) x 4 shots of each slice's 64-shot line (shots 0, 21, 42, 63), all
-    10000 levels in one batched call with the autotuned tiling: two shots of
-    the largest slice against the oracle, every shot of every slice finite and
+    10000 levels in one batched call with the autotuned tiling, and with the
+    tiling the benchmark's autotuner picks for the full batch: two shots of the
+    largest slice against the oracle, every shot of every slice finite and
     equal to its single-slice call under the same tiling."""
     import torch
     dt, nt, pick = 8e-4, 10000, [0, 21, 42, 63]
@@ -70,8 +73,8 @@ def test_uneven_slices_batched_full_length_against_oracle():
         gathers = torch.full((len(pick), g.nrow, nx), float("nan"), device="cuda")
         full.append((Plan(g), torch.from_numpy(v).cuda(), shots, gathers, None))
         cases.append((g, v, src, rec))
-    tuning = _batch(full, None)
-    print("autotuned batch tiling:", tuning, flush=True)
+    tuning = _batch(full, given)
+    print("batch tiling:", tuning, flush=True)
     for (plan, vp, shots, gathers, _), (g, v, src, rec) in zip(full, cases):
         assert torch.isfinite(gathers).all()
         plan.set_tuning(**tuning)
@@ -137,12 +140,15 @@ def test_full_density_batched_gradient_against_stored_oracle_gradients(tuning):
         assert e <= TOL
 
 
-def test_paper_shape_on_the_batched_path_against_oracle():
+@pytest.mark.parametrize("given", [None, dict(variant=3, tile_x=256, tile_z=0, time_block=5)],
+                         ids=["autotuned", "sweep-s256z0b5"])
+def test_paper_shape_on_the_batched_path_against_oracle(given):
     """Two 619 x 1000 slices (seeds 7 and 8) at 10 m, 60-cell sponge, dt 1 ms,
     8001 levels, 1000 receivers, gathers decimated by k = 14 (572 samples per
     trace) and snapshots every 14 levels over the first 5 s (358 frames), two
-    shots per slice in one batched call with the autotuned tiling: one shot per
-    slice against the oracle, its gathers and all 358 snapshots."""
+    shots per slice in one batched call with the autotuned tiling, and with
+    the tiling the benchmark's autotuner picks for the full paper-shaped batch:
+    one shot per slice against the oracle, its gathers and all 358 snapshots."""
     import torch
     nz, nx, h = 619, 1000, 10.0
     srcs = [synth.shot_line(64, 1100.0, (nx - 1) * h - 1100.0)[[5, 40]],
@@ -159,8 +165,8 @@ def test_paper_shape_on_the_batched_path_against_oracle():
         snaps = torch.empty((2, g.snap_count, nz, nx), dtype=torch.float32, device="cuda")
         full.append((Plan(g), torch.from_numpy(v).cuda(), shots, gathers, snaps))
         cases.append((g, v, srcs[i], rec))
-    tuning = _batch(full, None)
-    print("autotuned batch tiling:", tuning, flush=True)
+    tuning = _batch(full, given)
+    print("batch tiling:", tuning, flush=True)
     for i, k in ((0, 0), (1, 1)):
         g, v, src, rec = cases[i]
         og = oracle.Geometry(nz=nz, nx=nx, dz=h, dx=h, dt=g.dt, nt=g.nt, nbl=g.nbl)

@@ -141,14 +141,18 @@ def test_autograd_function_backward_equals_direct_call():
 GOLDEN_FIELD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "field_gradient_16shots.npz")
 
 
-def test_field_scale_gradient_sixteen_shots_full_length():
+@pytest.mark.parametrize("tuning", [None, dict(variant=3, tile_x=128, tile_z=96, time_block=3)],
+                         ids=["tiled", "sweep-s128z96b3"])
+def test_field_scale_gradient_sixteen_shots_full_length(tuning):
     """The differentiable workload at full size: the 620 x 1001 field slice
     (seed 42, 40-cell sponge, free surface), 16 shots at 10 m evenly spaced on
     [1.1, 8.9] km, 1001 receivers, 10000 levels of 0.8 ms, a 12 Hz Ricker,
     start model = lateral mean smoothed in depth (500 m), checkpoints every
     100 levels.  The GPU forms its residual from its own FP32 gathers on the
     true and start models; the reference is the FP64 oracle's gradient and
-    misfit stored by golden/make_field_gradient.py (oracle calls only)."""
+    misfit stored by golden/make_field_gradient.py (oracle calls only).  With
+    the default tiling, and with the forward and the recompute on the column
+    sweep (the adjoint stays tiled) as the benchmark runs it."""
     import torch
     ref = np.load(GOLDEN_FIELD)
     nz, nx, h, dt, nt, nshot, ckpt = 620, 1001, 10.0, 8e-4, 10000, 16, 100
@@ -161,6 +165,8 @@ def test_field_scale_gradient_sixteen_shots_full_length():
     ws = torch.empty(sgwave.sg_grad_workspace_size(plan, nshot, nx, ckpt), dtype=torch.uint8, device="cuda")
     d_obs = torch.empty((nshot, g.nrow, nx), dtype=torch.float32, device="cuda")
     sgwave.sg_forward(plan, torch.from_numpy(v_true).cuda(), shots, d_obs, None, ws)
+    if tuning:
+        plan.set_tuning(**tuning)
     vp = torch.from_numpy(v0).cuda()
     d = torch.empty_like(d_obs)
     sgwave.sg_forward_ckpt(plan, vp, shots, ckpt, d, ws)
